@@ -1,0 +1,205 @@
+/*
+ * gft.h -- C ABI of the MI355X fast graph Fourier transform library (libgft.so).
+ *
+ * What it computes (Lu & Ortega, "Fast Graph Fourier Transforms Based on Graph Symmetry
+ * and Bipartition"):
+ *   - The GFT of a graph signal x in R^n is c = U^T x, where L = U diag(lambda) U^T is the
+ *     eigendecomposition of the Laplacian L = D - W + S (Sec. II-B, eqs. def_laplacian and
+ *     l_from_sw), with the basis ordered by increasing eigenvalue (graph frequency).
+ *   - A plan factors U as a product of butterfly stages of Haar units (eq. B_phi, one
+ *     stage per node pairing phi, Sec. IV-B) and a block-diagonal set of small dense
+ *     sub-GFTs, the eigenbases of the leaf sub-graphs reached by the recursive
+ *     decomposition G -> (G+, G-) of Thm. decompose (Sec. IV-C).  Leaf sub-graphs are
+ *     further split into connected components (the G- of Fig. Gsk).
+ *   - gft_forward applies U^T to a batch of signals; gft_inverse applies U (the inverse
+ *     and the adjoint, since U is orthogonal and every B_phi is its own inverse, Sec. III).
+ *
+ * Conventions.
+ *   - Signals are signal-major: a batch of S signals is an S x n row-major array, the n
+ *     node values of one signal contiguous in node-label order.  Coefficients use the
+ *     same layout, in the plan's output order (ascending eigenvalue by default).
+ *   - Node labels are 0-based.
+ *   - Every function returns a gft_status.  No C++ exception crosses this boundary.  On
+ *     error, gft_last_error() returns a thread-local message naming the argument, stage
+ *     or node at fault.
+ *   - Host arrays passed in (graph, pairing, options) are borrowed for the call only; the
+ *     plan copies what it needs.  Device buffers (x, y) are owned by the caller.
+ *   - Streams are passed as void* and are hipStream_t values (NULL = the null stream).
+ *     Launches are asynchronous and stream-ordered; a device fault surfaces at the
+ *     caller's next synchronisation, not as a return code of the launching call.
+ */
+#ifndef GFT_H_
+#define GFT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GFT_OK = 0,
+  GFT_ERR_INVALID_ARG = 1,              /* NULL pointer, negative size, bad option value   */
+  GFT_ERR_GRAPH = 2,                    /* bad edge list: label out of range, i == j,      */
+                                        /* duplicate edge, non-finite weight or self-loop  */
+  GFT_ERR_NOT_INVOLUTION = 3,           /* phi(phi(i)) != i or phi(i) out of range         */
+  GFT_ERR_PAIRING_CROSSES_SUBGRAPH = 4, /* phi maps a node of one current sub-graph into   */
+                                        /* another (stages act inside G+ and G-)           */
+  GFT_ERR_NOT_SYMMETRIC = 5,            /* a current sub-graph is not phi-symmetric        */
+  GFT_ERR_EIGENSOLVE = 6,               /* leaf eigensolver did not converge               */
+  GFT_ERR_ORTHOGONALITY = 7,            /* plan-time check ||V^T V - I|| or residual failed*/
+  GFT_ERR_ALIGNMENT = 8,                /* device pointer not 16-byte aligned, or x and y  */
+                                        /* overlap without being equal                     */
+  GFT_ERR_UNSUPPORTED = 9,              /* shape or precision this build does not run      */
+  GFT_ERR_OOM = 10,                     /* host or device allocation failed                */
+  GFT_ERR_HIP = 11                      /* a HIP runtime call failed                       */
+} gft_status;
+
+/* Opaque plan.  Immutable after creation except for a per-device cache of its device
+ * image, filled on first use on each device (thread safe). */
+typedef struct gft_plan_s *gft_plan_t;
+
+/* Undirected weighted graph G(V, E, W) with self-loops s_i = w_ii (Sec. II-B).
+ * Each edge {src[e], dst[e]} (src != dst) is listed once with a finite real weight.
+ * self_loop is an array of n finite reals, or NULL for no self-loops.  Weights need not
+ * be positive: sub-graphs of the decomposition carry negative weights (Sec. IV-C). */
+typedef struct {
+  int32_t n;
+  int32_t num_edges;
+  const int32_t *src;
+  const int32_t *dst;
+  const double *weight;
+  const double *self_loop;
+} gft_graph;
+
+/* Node pairings, one involution per butterfly stage (Definition 1 and eq. p_phi;
+ * recursion of Sec. IV-C).  phi[s*n + i] is the partner of node i at stage s, i for a
+ * fixed node.  Stage s acts on each current sub-graph separately: it must map each
+ * sub-graph's node set onto itself, and each sub-graph it moves must be phi-symmetric
+ * (Definition 2).  A sub-graph left fixed by phi is not split at that stage.
+ * Of each pair, the smaller label joins V_X and its partner V_Y (eq. B_phi). */
+typedef struct {
+  int32_t num_stages;
+  const int32_t *phi;
+} gft_pairing;
+
+/* Arithmetic of the dense leaf blocks.  Haar stages always run in FP32. */
+typedef enum {
+  GFT_FP32 = 0,        /* FP32 products, FP32 accumulation (MFMA 16x16x4 f32)         */
+  GFT_BF16 = 1,        /* BF16 operands, FP32 accumulation                            */
+  GFT_FP16 = 2,        /* FP16 operands, FP32 accumulation                            */
+  GFT_SPLIT_BF16 = 3   /* hi+lo BF16 split, three products, FP32 accumulation         */
+} gft_precision;
+
+typedef enum {
+  GFT_ORDER_EIGENVALUE = 0,  /* ascending eigenvalue; ties by leaf-block order, then  */
+                             /* local index (any basis of an eigenspace is a GFT)     */
+  GFT_ORDER_BLOCK = 1        /* leaf-block order (depth first, G+ before G-), then    */
+                             /* ascending eigenvalue inside each block                */
+} gft_order;
+
+typedef struct {
+  int32_t precision;       /* gft_precision                                           */
+  int32_t order;           /* gft_order                                               */
+  int32_t tile_override;   /* 0 = tuned choice; else signals per tile (multiple of 16)*/
+  int32_t reserved;
+  double sym_tol;          /* relative tolerance of the phi-symmetry test on sub-graph*/
+                           /* Laplacians; <= 0 selects 1e-12                          */
+} gft_options;
+
+typedef struct {
+  int32_t n;
+  int32_t num_stages;      /* stages given                                            */
+  int32_t num_units;       /* Haar units over all stages                              */
+  int32_t num_blocks;      /* dense leaf blocks                                       */
+  int32_t max_block;       /* largest leaf block                                      */
+  int32_t num_z_scalings;  /* sum over stages of |V_Z| in the sub-graphs split        */
+  int64_t adds;            /* 2 * units + sum_b b(b-1)           (Table tab:runtime)  */
+  int64_t mults;           /* sum_b b^2 + num_z_scalings          (Table tab:runtime)  */
+  double max_residual;     /* max over blocks of ||L_b V_b - V_b Lambda_b||_F/||L_b||_F*/
+  double max_orth_error;   /* max over blocks of ||V_b^T V_b - I||_max                */
+} gft_plan_stats;
+
+/* Build a plan for one graph.  Validates the graph and every stage, forms the sub-graph
+ * Laplacians of Thm. decompose (eqs. blkdiag_G and Lpm), splits leaves into connected
+ * components, solves each leaf block's eigenproblem in FP64, checks orthogonality and
+ * residual, and orders the output.  opts may be NULL (FP32, eigenvalue order).
+ * Host-only: touches no GPU.  On success *out owns the plan (free with
+ * gft_plan_destroy). */
+gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing,
+                    const gft_options *opts, gft_plan_t *out);
+
+/* Build one plan covering num_graphs graphs (arrays of num_graphs graphs and pairings)
+ * for gft_forward_batch / gft_inverse_batch.  Each graph is planned as by gft_plan. */
+gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
+                          const gft_pairing *pairings, const gft_options *opts,
+                          gft_plan_t *out);
+
+/* y = U^T x for num_signals signals (coefficients; Sec. II-B).
+ * x: device, num_signals x n FP32, 16-byte aligned.  y: device, same shape, 16-byte
+ * aligned; y == x (in place) is allowed, other overlaps are rejected.
+ * num_signals == 0 is a no-op.  Single-graph plans only. */
+gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_signals,
+                       void *stream);
+
+/* x = U y (inverse and adjoint of gft_forward).  Same layout and rules. */
+gft_status gft_inverse(gft_plan_t plan, const void *y, void *x, int64_t num_signals,
+                       void *stream);
+
+/* Mixed batch in one persistent launch.  signal_offsets: device int64 array of
+ * num_graphs+1 non-decreasing entries, graph g owning signals [off[g], off[g+1]).
+ * Graph g's data starts at element sum_{h<g} (off[h+1]-off[h]) * n_h of x (and of y):
+ * the graphs' [S_g x n_g] arrays are packed back to back.  total_elements bounds that
+ * sum (the caller's buffer length in elements); the kernel never touches more.  The
+ * offsets are read on the device, so the call does not synchronise. */
+gft_status gft_forward_batch(gft_plan_t plan, const void *x, void *y,
+                             const int64_t *signal_offsets, int64_t total_elements,
+                             void *stream);
+gft_status gft_inverse_batch(gft_plan_t plan, const void *y, void *x,
+                             const int64_t *signal_offsets, int64_t total_elements,
+                             void *stream);
+
+/* Upload the plan's device image to the current device now (otherwise done on the first
+ * apply on each device, with a synchronous copy).  Call it before capturing an apply into
+ * a hipGraph.  Needs a GPU. */
+gft_status gft_plan_prepare(gft_plan_t plan);
+
+/* Statistics of graph `index` of a plan (0 for single-graph plans). */
+gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out);
+
+/* Number of graphs in the plan, and n of graph `index`. */
+gft_status gft_plan_num_graphs(gft_plan_t plan, int32_t *out);
+gft_status gft_plan_size(gft_plan_t plan, int32_t index, int32_t *n_out);
+
+/* Eigenvalues (n doubles, host) of graph `index` in output order. */
+gft_status gft_plan_eigenvalues(gft_plan_t plan, int32_t index, double *lambda);
+
+/* FP64 fast basis of graph `index` (n*n doubles, host, row-major): U[i*n + k] is node i
+ * of basis vector k, k in output order.  Computed on the host by running the plan's
+ * factorisation (stages and blocks) in FP64 on unit vectors. */
+gft_status gft_plan_basis(gft_plan_t plan, int32_t index, double *U);
+
+/* Apply the plan's factorisation in FP64 on the host (reference path of the plan's own
+ * algebra; no GPU).  x, y: host, num_signals x n doubles.  direction 0 = forward,
+ * 1 = inverse. */
+gft_status gft_plan_apply_host(gft_plan_t plan, int32_t index, int32_t direction,
+                               const double *x, double *y, int64_t num_signals);
+
+/* Leaf-block description of graph `index`: sizes[b] for b < num_blocks (num_blocks
+ * from gft_plan_info).  nodes, if not NULL, receives the n node labels grouped by block
+ * (block b's nodes contiguous, in block order). */
+gft_status gft_plan_blocks(gft_plan_t plan, int32_t index, int32_t *sizes, int32_t *nodes);
+
+gft_status gft_plan_destroy(gft_plan_t plan);
+
+/* Thread-local detail string of the last error on this thread ("" if none). */
+const char *gft_last_error(void);
+
+/* Library version string. */
+const char *gft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFT_H_ */

@@ -1,0 +1,362 @@
+// C ABI of libgft (include/gft.h): argument checking, plan ownership, per-device images.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gft.h"
+#include "launch.hpp"
+#include "plan.hpp"
+#include "program.hpp"
+
+using namespace gft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gft_status set_error(gft_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+gft_status ok() {
+  g_last_error.clear();
+  return GFT_OK;
+}
+
+// Device image of a plan on one GPU: one allocation holding every program's table and
+// fragments, and the programs with their device pointers filled in.
+struct DeviceImage {
+  int device = -1;
+  void *mem = nullptr;
+  std::vector<DevProgram> fwd, inv;
+  std::vector<int> grid_cap_fwd, grid_cap_inv;
+};
+
+}  // namespace
+
+struct gft_plan_s {
+  std::vector<GraphPlan> graphs;
+  gft_options opts{};
+  bool batch = false;
+  std::mutex mu;
+  std::map<int, std::unique_ptr<DeviceImage>> images;
+
+  ~gft_plan_s() {
+    for (auto &kv : images) {
+      if (kv.second && kv.second->mem) {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess) {
+          (void)hipSetDevice(kv.first);
+          (void)hipFree(kv.second->mem);
+          (void)hipSetDevice(cur);
+        }
+      }
+    }
+  }
+};
+
+namespace {
+
+gft_options default_options(const gft_options *o) {
+  gft_options d{};
+  d.precision = GFT_FP32;
+  d.order = GFT_ORDER_EIGENVALUE;
+  d.tile_override = 0;
+  d.sym_tol = 1e-12;
+  if (o) d = *o;
+  return d;
+}
+
+gft_status check_options(const gft_options &o) {
+  if (o.precision < GFT_FP32 || o.precision > GFT_SPLIT_BF16)
+    return set_error(GFT_ERR_INVALID_ARG, "options.precision is not a gft_precision value");
+  if (o.order != GFT_ORDER_EIGENVALUE && o.order != GFT_ORDER_BLOCK)
+    return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
+  if (o.tile_override != 0 && o.tile_override != 16 && o.tile_override != 32 &&
+      o.tile_override != 64 && o.tile_override != 128)
+    return set_error(GFT_ERR_INVALID_ARG, "options.tile_override must be 0, 16, 32, 64 or 128");
+  return GFT_OK;
+}
+
+// Get (building on first use) the image of `plan` on the current device.
+gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lock(plan->mu);
+  auto it = plan->images.find(dev);
+  if (it != plan->images.end()) {
+    *out = it->second.get();
+    return GFT_OK;
+  }
+  if (plan->opts.precision != GFT_FP32)
+    return set_error(GFT_ERR_UNSUPPORTED, "this build runs leaf blocks in FP32 only");
+  int max_lds = 0, cus = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(shared memory)");
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(CU count)");
+  const size_t budget = std::min<size_t>(kMaxLdsBytes, (size_t)max_lds);
+
+  std::vector<ProgramImage> imgs;
+  for (size_t g = 0; g < plan->graphs.size(); ++g)
+    for (int dir = 0; dir < 2; ++dir) {
+      ProgramImage im;
+      if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im))
+        return set_error(GFT_ERR_UNSUPPORTED,
+                         "graph " + std::to_string(g) + " (n = " + std::to_string(plan->graphs[g].n) +
+                             ") does not fit the LDS of one workgroup with this tile size");
+      imgs.push_back(std::move(im));
+    }
+  size_t bytes = 0;
+  std::vector<size_t> toff(imgs.size()), foff(imgs.size());
+  for (size_t i = 0; i < imgs.size(); ++i) {
+    toff[i] = bytes;
+    bytes += (imgs[i].table.size() * 4 + 255) & ~(size_t)255;
+    foff[i] = bytes;
+    bytes += (imgs[i].frag.size() * 4 + 255) & ~(size_t)255;
+  }
+  std::vector<char> host(bytes, 0);
+  for (size_t i = 0; i < imgs.size(); ++i) {
+    std::memcpy(host.data() + toff[i], imgs[i].table.data(), imgs[i].table.size() * 4);
+    std::memcpy(host.data() + foff[i], imgs[i].frag.data(), imgs[i].frag.size() * 4);
+  }
+  auto img = std::make_unique<DeviceImage>();
+  img->device = dev;
+  e = hipMalloc(&img->mem, bytes ? bytes : 256);
+  if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMalloc of the plan image failed");
+  e = hipMemcpy(img->mem, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(img->mem);
+    return set_error(GFT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  char *base = static_cast<char *>(img->mem);
+  for (size_t i = 0; i < imgs.size(); ++i) {
+    DevProgram P = imgs[i].prog;
+    P.table = reinterpret_cast<const int32_t *>(base + toff[i]);
+    P.frag = reinterpret_cast<const float *>(base + foff[i]);
+    const int cap = std::max(1, cus) * apply_occupancy(P);
+    if (i % 2 == 0) {
+      img->fwd.push_back(P);
+      img->grid_cap_fwd.push_back(cap);
+    } else {
+      img->inv.push_back(P);
+      img->grid_cap_inv.push_back(cap);
+    }
+  }
+  *out = img.get();
+  plan->images[dev] = std::move(img);
+  return GFT_OK;
+}
+
+gft_status check_buffers(const void *a, const void *b, int64_t bytes) {
+  if (!a || !b) return set_error(GFT_ERR_INVALID_ARG, "x and y must be non-NULL device pointers");
+  if ((reinterpret_cast<uintptr_t>(a) & 15) || (reinterpret_cast<uintptr_t>(b) & 15))
+    return set_error(GFT_ERR_ALIGNMENT, "x and y must be 16-byte aligned");
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  if (pa != pb && pa < pb + (uintptr_t)bytes && pb < pa + (uintptr_t)bytes)
+    return set_error(GFT_ERR_ALIGNMENT, "x and y overlap without being equal");
+  return GFT_OK;
+}
+
+gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S, void *stream) {
+  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->batch) return set_error(GFT_ERR_INVALID_ARG, "batch plans use gft_forward_batch / gft_inverse_batch");
+  if (S < 0) return set_error(GFT_ERR_INVALID_ARG, "num_signals must be >= 0");
+  if (S == 0) return ok();
+  const int64_t n = plan->graphs[0].n;
+  if (S > (int64_t(1) << 40) / n) return set_error(GFT_ERR_INVALID_ARG, "num_signals too large");
+  gft_status st = check_buffers(in, out, S * n * 4);
+  if (st != GFT_OK) return st;
+  DeviceImage *img = nullptr;
+  st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  const DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
+  const int cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
+  hipError_t e = launch_apply(P, static_cast<const float *>(in), static_cast<float *>(out), S,
+                              static_cast<hipStream_t>(stream), cap);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ok();
+}
+
+gft_status get_graph(gft_plan_t plan, int32_t index, const GraphPlan **g) {
+  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
+  if (index < 0 || index >= (int32_t)plan->graphs.size())
+    return set_error(GFT_ERR_INVALID_ARG, "graph index out of range");
+  *g = &plan->graphs[index];
+  return GFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing, const gft_options *opts,
+                    gft_plan_t *out) {
+  if (!out) return set_error(GFT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!graph) return set_error(GFT_ERR_INVALID_ARG, "graph is NULL");
+  const gft_options o = default_options(opts);
+  gft_status st = check_options(o);
+  if (st != GFT_OK) return st;
+  try {
+    auto p = std::make_unique<gft_plan_s>();
+    p->opts = o;
+    p->graphs.push_back(build_graph_plan(*graph, pairing, o));
+    *out = p.release();
+  } catch (const PlanError &err) {
+    return set_error(err.status, err.message);
+  } catch (const std::bad_alloc &) {
+    return set_error(GFT_ERR_OOM, "host allocation failed while planning");
+  } catch (const std::exception &ex) {
+    return set_error(GFT_ERR_INVALID_ARG, ex.what());
+  }
+  return ok();
+}
+
+gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs, const gft_pairing *pairings,
+                          const gft_options *opts, gft_plan_t *out) {
+  if (!out) return set_error(GFT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (num_graphs <= 0 || !graphs) return set_error(GFT_ERR_INVALID_ARG, "need num_graphs > 0 and graphs");
+  const gft_options o = default_options(opts);
+  gft_status st = check_options(o);
+  if (st != GFT_OK) return st;
+  try {
+    auto p = std::make_unique<gft_plan_s>();
+    p->opts = o;
+    p->batch = true;
+    for (int32_t g = 0; g < num_graphs; ++g) {
+      try {
+        p->graphs.push_back(build_graph_plan(graphs[g], pairings ? &pairings[g] : nullptr, o));
+      } catch (const PlanError &err) {
+        return set_error(err.status, "graph " + std::to_string(g) + ": " + err.message);
+      }
+    }
+    *out = p.release();
+  } catch (const std::bad_alloc &) {
+    return set_error(GFT_ERR_OOM, "host allocation failed while planning");
+  }
+  return ok();
+}
+
+gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_signals, void *stream) {
+  return apply(plan, 0, x, y, num_signals, stream);
+}
+
+gft_status gft_inverse(gft_plan_t plan, const void *y, void *x, int64_t num_signals, void *stream) {
+  return apply(plan, 1, y, x, num_signals, stream);
+}
+
+gft_status gft_forward_batch(gft_plan_t plan, const void *, void *, const int64_t *, int64_t, void *) {
+  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
+  return set_error(GFT_ERR_UNSUPPORTED, "batch apply is not built yet");
+}
+
+gft_status gft_inverse_batch(gft_plan_t plan, const void *, void *, const int64_t *, int64_t, void *) {
+  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
+  return set_error(GFT_ERR_UNSUPPORTED, "batch apply is not built yet");
+}
+
+gft_status gft_plan_prepare(gft_plan_t plan) {
+  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
+  DeviceImage *img = nullptr;
+  gft_status st = device_image(plan, &img);
+  return st != GFT_OK ? st : ok();
+}
+
+gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (!out) return set_error(GFT_ERR_INVALID_ARG, "out is NULL");
+  *out = g->stats;
+  return ok();
+}
+
+gft_status gft_plan_num_graphs(gft_plan_t plan, int32_t *out) {
+  if (!plan || !out) return set_error(GFT_ERR_INVALID_ARG, "plan and out must be non-NULL");
+  *out = (int32_t)plan->graphs.size();
+  return ok();
+}
+
+gft_status gft_plan_size(gft_plan_t plan, int32_t index, int32_t *n_out) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (!n_out) return set_error(GFT_ERR_INVALID_ARG, "n_out is NULL");
+  *n_out = g->n;
+  return ok();
+}
+
+gft_status gft_plan_eigenvalues(gft_plan_t plan, int32_t index, double *lambda) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (!lambda) return set_error(GFT_ERR_INVALID_ARG, "lambda is NULL");
+  std::memcpy(lambda, g->lambda_out.data(), sizeof(double) * g->n);
+  return ok();
+}
+
+gft_status gft_plan_basis(gft_plan_t plan, int32_t index, double *U) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (!U) return set_error(GFT_ERR_INVALID_ARG, "U is NULL");
+  const int n = g->n;
+  // column k = inverse transform of the unit coefficient vector e_k, run block-locally
+  std::vector<double> e(n, 0.0), col(n);
+  for (size_t i = 0; i < (size_t)n * n; ++i) U[i] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    e[k] = 1.0;
+    apply_host(*g, 1, e.data(), col.data(), 1);
+    e[k] = 0.0;
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + k] = col[i];
+  }
+  return ok();
+}
+
+gft_status gft_plan_apply_host(gft_plan_t plan, int32_t index, int32_t direction, const double *x,
+                               double *y, int64_t num_signals) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (direction != 0 && direction != 1) return set_error(GFT_ERR_INVALID_ARG, "direction must be 0 or 1");
+  if (num_signals < 0) return set_error(GFT_ERR_INVALID_ARG, "num_signals must be >= 0");
+  if (num_signals > 0 && (!x || !y)) return set_error(GFT_ERR_INVALID_ARG, "x and y must be non-NULL");
+  apply_host(*g, direction, x, y, num_signals);
+  return ok();
+}
+
+gft_status gft_plan_blocks(gft_plan_t plan, int32_t index, int32_t *sizes, int32_t *nodes) {
+  const GraphPlan *g = nullptr;
+  gft_status st = get_graph(plan, index, &g);
+  if (st != GFT_OK) return st;
+  if (!sizes) return set_error(GFT_ERR_INVALID_ARG, "sizes is NULL");
+  size_t pos = 0;
+  for (size_t b = 0; b < g->blocks.size(); ++b) {
+    sizes[b] = g->blocks[b].size;
+    if (nodes)
+      for (int32_t v : g->blocks[b].nodes) nodes[pos++] = v;
+  }
+  return ok();
+}
+
+gft_status gft_plan_destroy(gft_plan_t plan) {
+  delete plan;
+  return ok();
+}
+
+const char *gft_last_error(void) { return g_last_error.c_str(); }
+
+const char *gft_version(void) { return "libgft 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// Fused GFT kernels for gfx950 (CDNA4).
+//
+// One engine runs every plan: a tile of T = 16*mt signals (signal-major, contiguous in
+// HBM) is read with 16-byte coalesced loads into an LDS tile [T][stride]; the Haar stages
+// (eq. B_phi, unscaled add/sub plus sqrt(2) on V_Z) run in place in LDS; the dense leaf
+// blocks run as [T x K] * [K x N] products on v_mfma_f32_16x16x4_f32 with operands
+// gathered from LDS and results scattered to a second LDS tile in output order; the
+// tile is written back with 16-byte coalesced stores.  The inverse program runs blocks
+// first and stages after.  The kernel is persistent: each workgroup walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_program.hpp"
+#include "program.hpp"
+
+namespace gft {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr float kSqrt2f = 1.41421356237309504880f;
+
+// e / d from magic = ceil(2^32 / d) (0 encodes d == 1); exact while e * d < 2^32.
+__device__ __forceinline__ uint32_t fdiv(uint32_t e, uint32_t magic) {
+  return magic ? __umulhi(e, magic) : e;
+}
+
+struct LdsTables {
+  const int32_t *stages;  // 4 words per stage
+  const int32_t *ops;     // 2 words per op
+  const int32_t *blocks;  // 8 words per block
+  const int32_t *items;
+  const int32_t *gidx;
+  const int32_t *sidx;
+};
+
+__device__ __forceinline__ LdsTables carve(const DevProgram &P, const int32_t *base) {
+  LdsTables t;
+  t.stages = base;
+  t.ops = t.stages + 4 * (P.num_pre + P.num_post);
+  t.blocks = t.ops + 2 * P.total_ops;
+  t.items = t.blocks + 8 * P.num_blocks;
+  t.gidx = t.items + P.num_items;
+  t.sidx = t.gidx + P.gidx_len;
+  return t;
+}
+
+// Copy `count` floats (contiguous in HBM) into LDS rows of `stride` floats; rows at and
+// beyond count / n are zero-filled up to `rows`.
+__device__ __forceinline__ void load_tile(const float *g, int count, int rows, int n,
+                                          int stride, uint32_t magic_n, float *lds) {
+  const int tid = threadIdx.x;
+  const int nvec = count >> 2;
+  const float4 *g4 = reinterpret_cast<const float4 *>(g);
+  for (int v = tid; v < nvec; v += kThreads) {
+    const float4 val = g4[v];
+    const uint32_t e = 4u * (uint32_t)v;
+    uint32_t r = fdiv(e, magic_n);
+    uint32_t c = e - r * (uint32_t)n;
+    const float q[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lds[r * stride + c] = q[k];
+      if (++c == (uint32_t)n) {
+        c = 0;
+        ++r;
+      }
+    }
+  }
+  for (int e = 4 * nvec + tid; e < count; e += kThreads) {
+    const uint32_t r = fdiv((uint32_t)e, magic_n);
+    lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = g[e];
+  }
+  const int full = rows * n;
+  for (int e = count + tid; e < full; e += kThreads) {
+    const uint32_t r = fdiv((uint32_t)e, magic_n);
+    lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = 0.0f;
+  }
+}
+
+__device__ __forceinline__ void store_tile(const float *lds, int count, int n, int stride,
+                                           uint32_t magic_n, float *g) {
+  const int tid = threadIdx.x;
+  const int nvec = count >> 2;
+  float4 *g4 = reinterpret_cast<float4 *>(g);
+  for (int v = tid; v < nvec; v += kThreads) {
+    const uint32_t e = 4u * (uint32_t)v;
+    uint32_t r = fdiv(e, magic_n);
+    uint32_t c = e - r * (uint32_t)n;
+    float q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[k] = lds[r * stride + c];
+      if (++c == (uint32_t)n) {
+        c = 0;
+        ++r;
+      }
+    }
+    g4[v] = make_float4(q[0], q[1], q[2], q[3]);
+  }
+  for (int e = 4 * nvec + tid; e < count; e += kThreads) {
+    const uint32_t r = fdiv((uint32_t)e, magic_n);
+    g[e] = lds[r * stride + ((uint32_t)e - r * (uint32_t)n)];
+  }
+}
+
+// One butterfly stage over all T rows of an LDS tile (in place).
+__device__ __forceinline__ void haar_stage(const int32_t *st, const int32_t *ops, int rows,
+                                           int stride, float *lds) {
+  const int off = st[0];
+  const int cnt = st[1];
+  const uint32_t magic = (uint32_t)st[2];
+  const int items = rows * cnt;
+  for (int idx = threadIdx.x; idx < items; idx += kThreads) {
+    const uint32_t s = fdiv((uint32_t)idx, magic);
+    const int u = idx - (int)s * cnt;
+    const int i = ops[2 * (off + u)];
+    const int j = ops[2 * (off + u) + 1];
+    float *row = lds + s * stride;
+    if (j >= 0) {
+      const float a = row[i], b = row[j];
+      row[i] = a + b;
+      row[j] = a - b;
+    } else {
+      row[i] *= kSqrt2f;
+    }
+  }
+}
+
+// Dense leaf blocks: dst[:, sidx] = src[:, gidx] * M for every block, FP32 MFMA.
+// MFMA 16x16x4 f32 operand layout (one 16x16 block): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[4*(l/16) + v][l%16] in accumulator element v.
+template <int MT>
+__device__ __forceinline__ void block_products(const DevProgram &P, const LdsTables &t,
+                                               const float *src, float *dst) {
+  const int stride = P.stride;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int r = lane & 15;
+  for (int it = wave; it < P.num_items; it += kThreads / 64) {
+    const int item = t.items[it];
+    const int b = item >> 16;
+    const int nt = item & 0xffff;
+    const int32_t *B = t.blocks + 8 * b;
+    const int size = B[0], kchunks = B[1], ntiles = B[2];
+    const int32_t *gi = t.gidx + B[3];
+    const float *frag = P.frag + B[5] + nt * 64 + lane;
+    floatx4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < kchunks; ++kc) {
+      const float bm = frag[kc * ntiles * 64];
+      const int col = gi[4 * kc + g];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const float a = src[(16 * m + r) * stride + col];
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bm, acc[m], 0, 0, 0);
+      }
+    }
+    const int ncol = 16 * nt + r;
+    if (ncol < size) {
+      const int dcol = t.sidx[B[4] + ncol];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(16 * m + 4 * g + v) * stride + dcol] = acc[m][v];
+      }
+    }
+  }
+}
+
+template <int MT>
+__global__ __launch_bounds__(kThreads) void gft_apply_f32(DevProgram P, const float *in,
+                                                         float *out, int64_t S) {
+  extern __shared__ int32_t smem[];
+  constexpr int T = 16 * MT;
+  const int n = P.n;
+  const int stride = P.stride;
+  for (int i = threadIdx.x; i < P.table_words; i += kThreads) smem[i] = P.table[i];
+  const LdsTables t = carve(P, smem);
+  float *buf0 = reinterpret_cast<float *>(smem + ((P.table_words + 3) & ~3));
+  float *buf1 = buf0 + T * stride;
+  __syncthreads();
+  const int64_t num_tiles = (S + T - 1) / T;
+  for (int64_t tile = blockIdx.x; tile < num_tiles; tile += gridDim.x) {
+    const int64_t s0 = tile * T;
+    const int valid = (int)((S - s0) < T ? (S - s0) : T);
+    const float *gin = in + s0 * n;
+    float *gout = out + s0 * n;
+    load_tile(gin, valid * n, T, n, stride, P.magic_n, buf0);
+    __syncthreads();
+    for (int s = 0; s < P.num_pre; ++s) {
+      haar_stage(t.stages + 4 * s, t.ops, T, stride, buf0);
+      __syncthreads();
+    }
+    block_products<MT>(P, t, buf0, buf1);
+    __syncthreads();
+    for (int s = P.num_pre; s < P.num_pre + P.num_post; ++s) {
+      haar_stage(t.stages + 4 * s, t.ops, T, stride, buf1);
+      __syncthreads();
+    }
+    store_tile(buf1, valid * n, n, stride, P.magic_n, gout);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------- launch
+
+template <int MT>
+static hipError_t launch_mt(const DevProgram &P, const float *in, float *out, int64_t S,
+                            hipStream_t stream, int grid_cap) {
+  const size_t lds = program_lds_bytes(P);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)gft_apply_f32<MT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t T = 16 * MT;
+  const int64_t tiles = (S + T - 1) / T;
+  int grid = (int)(tiles < grid_cap ? tiles : grid_cap);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(gft_apply_f32<MT>, dim3(grid), dim3(kThreads), lds, stream, P, in, out, S);
+  return hipGetLastError();
+}
+
+int apply_occupancy(const DevProgram &P) {
+  const size_t lds = program_lds_bytes(P);
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (P.mt) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<1>, kThreads, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<2>, kThreads, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<4>, kThreads, lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<8>, kThreads, lds); break;
+    default: break;
+  }
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_t S,
+                        hipStream_t stream, int grid_cap) {
+  switch (P.mt) {
+    case 1: return launch_mt<1>(P, in, out, S, stream, grid_cap);
+    case 2: return launch_mt<2>(P, in, out, S, stream, grid_cap);
+    case 4: return launch_mt<4>(P, in, out, S, stream, grid_cap);
+    case 8: return launch_mt<8>(P, in, out, S, stream, grid_cap);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gft

@@ -1,0 +1,400 @@
+// Host plan builder: validation, recursive symmetric decomposition, leaf eigensolves,
+// output ordering and the FP64 host application of the factorisation.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <set>
+#include <sstream>
+#include <utility>
+
+#include "eigen.hpp"
+
+namespace gft {
+
+namespace {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+
+[[noreturn]] void fail(gft_status s, const std::string &msg) { throw PlanError{s, msg}; }
+
+// A current sub-graph of the decomposition: node labels (ascending) and its dense
+// Laplacian over them (m*m row-major).
+struct Sub {
+  std::vector<int32_t> nodes;
+  std::vector<double> L;
+  int32_t depth = 0;
+};
+
+void validate_graph(const gft_graph &g) {
+  if (g.n <= 0) fail(GFT_ERR_INVALID_ARG, "graph.n must be positive");
+  if (g.num_edges < 0) fail(GFT_ERR_INVALID_ARG, "graph.num_edges must be >= 0");
+  if (g.num_edges > 0 && (!g.src || !g.dst || !g.weight))
+    fail(GFT_ERR_INVALID_ARG, "graph.src/dst/weight must be non-NULL when num_edges > 0");
+  std::set<std::pair<int32_t, int32_t>> seen;
+  for (int32_t e = 0; e < g.num_edges; ++e) {
+    const int32_t a = g.src[e], b = g.dst[e];
+    std::ostringstream os;
+    if (a < 0 || a >= g.n || b < 0 || b >= g.n) {
+      os << "edge " << e << " (" << a << "," << b << ") has a label outside [0," << g.n << ")";
+      fail(GFT_ERR_GRAPH, os.str());
+    }
+    if (a == b) {
+      os << "edge " << e << " joins node " << a << " to itself; pass self-loops in self_loop";
+      fail(GFT_ERR_GRAPH, os.str());
+    }
+    if (!std::isfinite(g.weight[e])) {
+      os << "edge " << e << " has a non-finite weight";
+      fail(GFT_ERR_GRAPH, os.str());
+    }
+    if (!seen.insert({std::min(a, b), std::max(a, b)}).second) {
+      os << "edge " << e << " (" << a << "," << b << ") is listed twice";
+      fail(GFT_ERR_GRAPH, os.str());
+    }
+  }
+  if (g.self_loop)
+    for (int32_t i = 0; i < g.n; ++i)
+      if (!std::isfinite(g.self_loop[i])) {
+        std::ostringstream os;
+        os << "self_loop[" << i << "] is not finite";
+        fail(GFT_ERR_GRAPH, os.str());
+      }
+}
+
+// L = D - W + S (eqs. def_laplacian, l_from_sw).
+std::vector<double> dense_laplacian(const gft_graph &g) {
+  const size_t n = (size_t)g.n;
+  std::vector<double> L(n * n, 0.0);
+  for (int32_t e = 0; e < g.num_edges; ++e) {
+    const size_t a = (size_t)g.src[e], b = (size_t)g.dst[e];
+    const double w = g.weight[e];
+    L[a * n + b] -= w;
+    L[b * n + a] -= w;
+    L[a * n + a] += w;
+    L[b * n + b] += w;
+  }
+  if (g.self_loop)
+    for (size_t i = 0; i < n; ++i) L[i * n + i] += g.self_loop[i];
+  return L;
+}
+
+double max_abs(const std::vector<double> &v) {
+  double m = 0.0;
+  for (double x : v) m = std::max(m, std::fabs(x));
+  return m;
+}
+
+// Split sub-graph H by the local involution lp (Thm. decompose in matrix form, eq. Lpm):
+//   L+ over V_X u V_Z:  (L_XX + L_XY J | sqrt2 L_XZ ; sqrt2 L_ZX | L_ZZ)
+//   L- over V_Y:        L_YY - J L_XY
+// with V_X = {a : lp[a] > a}, V_Y = lp(V_X), V_Z = fixed points.
+void split(const Sub &H, const std::vector<int32_t> &lp, Sub &plus, Sub &minus,
+           HostStage &stage) {
+  const int m = (int)H.nodes.size();
+  std::vector<int> pl, mi;
+  std::vector<char> kind(m);  // 'x', 'y', 'z'
+  for (int a = 0; a < m; ++a) {
+    if (lp[a] == a) kind[a] = 'z';
+    else kind[a] = lp[a] > a ? 'x' : 'y';
+  }
+  for (int a = 0; a < m; ++a) {
+    if (kind[a] == 'y') mi.push_back(a);
+    else pl.push_back(a);
+    if (kind[a] == 'x') {
+      stage.pair_x.push_back(H.nodes[a]);
+      stage.pair_y.push_back(H.nodes[lp[a]]);
+    } else if (kind[a] == 'z') {
+      stage.znodes.push_back(H.nodes[a]);
+    }
+  }
+  auto Lh = [&](int a, int b) { return H.L[(size_t)a * m + b]; };
+  const int mp = (int)pl.size(), mm = (int)mi.size();
+  plus.nodes.resize(mp);
+  plus.L.assign((size_t)mp * mp, 0.0);
+  plus.depth = H.depth + 1;
+  for (int p = 0; p < mp; ++p) {
+    plus.nodes[p] = H.nodes[pl[p]];
+    for (int q = p; q < mp; ++q) {
+      const int a = pl[p], b = pl[q];
+      double v;
+      if (kind[a] == 'x' && kind[b] == 'x') v = Lh(a, b) + Lh(a, lp[b]);
+      else if (kind[a] == 'z' && kind[b] == 'z') v = Lh(a, b);
+      else v = kSqrt2 * Lh(a, b);
+      plus.L[(size_t)p * mp + q] = v;
+      plus.L[(size_t)q * mp + p] = v;
+    }
+  }
+  minus.nodes.resize(mm);
+  minus.L.assign((size_t)mm * mm, 0.0);
+  minus.depth = H.depth + 1;
+  for (int p = 0; p < mm; ++p) {
+    minus.nodes[p] = H.nodes[mi[p]];
+    for (int q = p; q < mm; ++q) {
+      const int a = mi[p], b = mi[q];
+      const double v = Lh(a, b) - Lh(lp[a], b);
+      minus.L[(size_t)p * mm + q] = v;
+      minus.L[(size_t)q * mm + p] = v;
+    }
+  }
+}
+
+// Connected components of a sub-graph (couplings with |l_ab| > tol), each ascending.
+std::vector<std::vector<int>> components(const Sub &H, double tol) {
+  const int m = (int)H.nodes.size();
+  std::vector<int> comp(m, -1);
+  std::vector<std::vector<int>> out;
+  for (int r = 0; r < m; ++r) {
+    if (comp[r] >= 0) continue;
+    std::vector<int> stack{r}, members;
+    comp[r] = (int)out.size();
+    while (!stack.empty()) {
+      const int v = stack.back();
+      stack.pop_back();
+      members.push_back(v);
+      for (int u = 0; u < m; ++u)
+        if (u != v && comp[u] < 0 && std::fabs(H.L[(size_t)v * m + u]) > tol) {
+          comp[u] = comp[r];
+          stack.push_back(u);
+        }
+    }
+    std::sort(members.begin(), members.end());
+    out.push_back(members);
+  }
+  return out;
+}
+
+}  // namespace
+
+GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
+                           const gft_options &opts) {
+  validate_graph(g);
+  const int32_t n = g.n;
+  const int32_t num_stages = pairing ? pairing->num_stages : 0;
+  if (num_stages < 0) fail(GFT_ERR_INVALID_ARG, "pairing.num_stages must be >= 0");
+  if (num_stages > 0 && !pairing->phi)
+    fail(GFT_ERR_INVALID_ARG, "pairing.phi must be non-NULL when num_stages > 0");
+  const double sym_tol = opts.sym_tol > 0 ? opts.sym_tol : 1e-12;
+
+  GraphPlan plan;
+  plan.n = n;
+  plan.num_stages_given = num_stages;
+
+  std::vector<Sub> subs(1);
+  subs[0].nodes.resize(n);
+  std::iota(subs[0].nodes.begin(), subs[0].nodes.end(), 0);
+  subs[0].L = dense_laplacian(g);
+  const double scale_L = std::max(max_abs(subs[0].L), 1e-300);
+
+  std::vector<int32_t> owner(n, 0), local(n, 0);
+  for (int32_t s = 0; s < num_stages; ++s) {
+    const int32_t *phi = pairing->phi + (size_t)s * n;
+    for (int32_t i = 0; i < n; ++i) {
+      if (phi[i] < 0 || phi[i] >= n || phi[phi[i]] != i) {
+        std::ostringstream os;
+        os << "stage " << s << ": pairing is not an involution at node " << i
+           << " (phi = " << phi[i] << ")";
+        fail(GFT_ERR_NOT_INVOLUTION, os.str());
+      }
+    }
+    for (size_t h = 0; h < subs.size(); ++h)
+      for (size_t a = 0; a < subs[h].nodes.size(); ++a) {
+        owner[subs[h].nodes[a]] = (int32_t)h;
+        local[subs[h].nodes[a]] = (int32_t)a;
+      }
+    HostStage stage;
+    std::vector<Sub> next;
+    next.reserve(subs.size() * 2);
+    for (size_t h = 0; h < subs.size(); ++h) {
+      Sub &H = subs[h];
+      const int m = (int)H.nodes.size();
+      bool moves = false;
+      std::vector<int32_t> lp(m);
+      for (int a = 0; a < m; ++a) {
+        const int32_t i = H.nodes[a], j = phi[i];
+        if (owner[j] != (int32_t)h) {
+          std::ostringstream os;
+          os << "stage " << s << ": node " << i << " is paired with node " << j
+             << ", which lies in a different sub-graph";
+          fail(GFT_ERR_PAIRING_CROSSES_SUBGRAPH, os.str());
+        }
+        lp[a] = local[j];
+        moves |= (j != i);
+      }
+      if (!moves) {
+        next.push_back(std::move(H));
+        continue;
+      }
+      // Definition 2 on the sub-graph: l_ab = l_{phi a, phi b} for all a, b
+      const double tol = sym_tol * std::max(max_abs(H.L), 1e-300 * scale_L);
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+          const double d = H.L[(size_t)a * m + b] - H.L[(size_t)lp[a] * m + lp[b]];
+          if (!(std::fabs(d) <= tol)) {
+            std::ostringstream os;
+            os << "stage " << s << ": sub-graph is not phi-symmetric at nodes (" << H.nodes[a]
+               << "," << H.nodes[b] << ") vs (" << H.nodes[lp[a]] << "," << H.nodes[lp[b]]
+               << "), difference " << d;
+            fail(GFT_ERR_NOT_SYMMETRIC, os.str());
+          }
+        }
+      Sub plus, minus;
+      split(H, lp, plus, minus, stage);
+      next.push_back(std::move(plus));
+      if (!minus.nodes.empty()) next.push_back(std::move(minus));
+    }
+    subs = std::move(next);
+    if (!stage.pair_x.empty()) plan.stages.push_back(std::move(stage));
+  }
+
+  // Leaves -> connected components -> dense blocks with FP64 eigensolves.
+  double max_res = 0.0, max_orth = 0.0;
+  for (const Sub &H : subs) {
+    const int m = (int)H.nodes.size();
+    const double tol = sym_tol * std::max(max_abs(H.L), 1e-300 * scale_L);
+    for (const std::vector<int> &comp : components(H, tol)) {
+      HostBlock B;
+      B.size = (int32_t)comp.size();
+      B.depth = H.depth;
+      B.scale = std::pow(0.5, 0.5 * H.depth);
+      const int b = B.size;
+      std::vector<double> Lb((size_t)b * b);
+      for (int p = 0; p < b; ++p) {
+        B.nodes.push_back(H.nodes[comp[p]]);
+        for (int q = 0; q < b; ++q) Lb[(size_t)p * b + q] = H.L[(size_t)comp[p] * m + comp[q]];
+      }
+      if (!symmetric_eigen(b, Lb, B.lambda, B.V)) {
+        std::ostringstream os;
+        os << "eigensolver did not converge on a leaf block of size " << b;
+        fail(GFT_ERR_EIGENSOLVE, os.str());
+      }
+      // plan-time checks: residual ||L V - V Lambda||_F / ||L||_F and orthogonality
+      double res2 = 0.0, nrm2 = 0.0, orth = 0.0;
+      for (int i = 0; i < b; ++i)
+        for (int k = 0; k < b; ++k) {
+          double s = 0.0, o = 0.0;
+          for (int j = 0; j < b; ++j) {
+            s += Lb[(size_t)i * b + j] * B.V[(size_t)j * b + k];
+            o += B.V[(size_t)j * b + i] * B.V[(size_t)j * b + k];
+          }
+          const double r = s - B.lambda[k] * B.V[(size_t)i * b + k];
+          res2 += r * r;
+          nrm2 += Lb[(size_t)i * b + k] * Lb[(size_t)i * b + k];
+          orth = std::max(orth, std::fabs(o - (i == k ? 1.0 : 0.0)));
+        }
+      const double res = std::sqrt(res2) / std::max(std::sqrt(nrm2), 1e-300);
+      max_res = std::max(max_res, nrm2 > 0 ? res : std::sqrt(res2));
+      max_orth = std::max(max_orth, orth);
+      if (orth > 1e-10 || (nrm2 > 0 ? res : std::sqrt(res2)) > 1e-10) {
+        std::ostringstream os;
+        os << "leaf block of size " << b << " failed the plan-time check (orthogonality "
+           << orth << ", residual " << res << ")";
+        fail(GFT_ERR_ORTHOGONALITY, os.str());
+      }
+      plan.blocks.push_back(std::move(B));
+    }
+  }
+
+  // Output order: ascending eigenvalue; eigenvalues within tau of their neighbour form
+  // one cluster, ordered by (block, local index).  Block order keeps block order.
+  struct Ent {
+    double lam;
+    int32_t b, k;
+  };
+  std::vector<Ent> ents;
+  double lam_max = 1.0;
+  for (int32_t b = 0; b < (int32_t)plan.blocks.size(); ++b)
+    for (int32_t k = 0; k < plan.blocks[b].size; ++k) {
+      ents.push_back({plan.blocks[b].lambda[k], b, k});
+      lam_max = std::max(lam_max, std::fabs(plan.blocks[b].lambda[k]));
+    }
+  if (opts.order == GFT_ORDER_EIGENVALUE) {
+    std::stable_sort(ents.begin(), ents.end(),
+                     [](const Ent &a, const Ent &b) { return a.lam < b.lam; });
+    const double tau = 1e-9 * lam_max;
+    size_t c0 = 0;
+    for (size_t i = 1; i <= ents.size(); ++i) {
+      if (i == ents.size() || ents[i].lam - ents[i - 1].lam > tau) {
+        std::sort(ents.begin() + c0, ents.begin() + i, [](const Ent &a, const Ent &b) {
+          return a.b != b.b ? a.b < b.b : a.k < b.k;
+        });
+        c0 = i;
+      }
+    }
+  } else if (opts.order != GFT_ORDER_BLOCK) {
+    fail(GFT_ERR_INVALID_ARG, "options.order must be 0 (eigenvalue) or 1 (block)");
+  }
+  for (auto &B : plan.blocks) B.out_pos.assign(B.size, -1);
+  plan.lambda_out.resize(n);
+  for (int32_t p = 0; p < (int32_t)ents.size(); ++p) {
+    plan.blocks[ents[p].b].out_pos[ents[p].k] = p;
+    plan.lambda_out[p] = ents[p].lam;
+  }
+
+  gft_plan_stats &st = plan.stats;
+  st.n = n;
+  st.num_stages = num_stages;
+  st.num_units = 0;
+  st.num_z_scalings = 0;
+  for (const HostStage &S : plan.stages) {
+    st.num_units += (int32_t)S.pair_x.size();
+    st.num_z_scalings += (int32_t)S.znodes.size();
+  }
+  st.num_blocks = (int32_t)plan.blocks.size();
+  st.max_block = 0;
+  int64_t sum_b2 = 0, sum_bb1 = 0;
+  for (const HostBlock &B : plan.blocks) {
+    st.max_block = std::max(st.max_block, B.size);
+    sum_b2 += (int64_t)B.size * B.size;
+    sum_bb1 += (int64_t)B.size * (B.size - 1);
+  }
+  st.adds = 2 * (int64_t)st.num_units + sum_bb1;
+  st.mults = sum_b2 + st.num_z_scalings;
+  st.max_residual = max_res;
+  st.max_orth_error = max_orth;
+  return plan;
+}
+
+void apply_host(const GraphPlan &p, int direction, const double *x, double *y, int64_t S) {
+  const int n = p.n;
+  std::vector<double> z(n), w(n);
+  for (int64_t s = 0; s < S; ++s) {
+    const double *xs = x + s * n;
+    double *ys = y + s * n;
+    if (direction == 0) {
+      std::copy(xs, xs + n, z.begin());
+      for (const HostStage &st : p.stages) {
+        for (size_t u = 0; u < st.pair_x.size(); ++u) {
+          const double a = z[st.pair_x[u]], b = z[st.pair_y[u]];
+          z[st.pair_x[u]] = a + b;
+          z[st.pair_y[u]] = a - b;
+        }
+        for (int32_t c : st.znodes) z[c] *= kSqrt2;
+      }
+      for (const HostBlock &B : p.blocks)
+        for (int k = 0; k < B.size; ++k) {
+          double acc = 0.0;
+          for (int j = 0; j < B.size; ++j) acc += B.V[(size_t)j * B.size + k] * z[B.nodes[j]];
+          ys[B.out_pos[k]] = B.scale * acc;
+        }
+    } else {
+      for (const HostBlock &B : p.blocks)
+        for (int j = 0; j < B.size; ++j) {
+          double acc = 0.0;
+          for (int k = 0; k < B.size; ++k) acc += B.V[(size_t)j * B.size + k] * xs[B.out_pos[k]];
+          w[B.nodes[j]] = B.scale * acc;
+        }
+      for (auto it = p.stages.rbegin(); it != p.stages.rend(); ++it) {
+        for (int32_t c : it->znodes) w[c] *= kSqrt2;
+        for (size_t u = 0; u < it->pair_x.size(); ++u) {
+          const double a = w[it->pair_x[u]], b = w[it->pair_y[u]];
+          w[it->pair_x[u]] = a + b;
+          w[it->pair_y[u]] = a - b;
+        }
+      }
+      std::copy(w.begin(), w.end(), ys);
+    }
+  }
+}
+
+}  // namespace gft

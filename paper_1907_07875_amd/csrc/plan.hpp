@@ -1,0 +1,60 @@
+// Host-side plan of the fast GFT: stages of Haar units and dense leaf blocks.
+//
+// A GraphPlan is the factorisation U = B_{phi_1} ... B_{phi_k} * P * diag(V_b) * Pi of the
+// paper (eq. left_gft applied recursively, Sec. IV-C), stored as
+//   - stages: for each pairing, the Haar units (i in V_X, j = phi(i) in V_Y) and the
+//     fixed nodes V_Z of every sub-graph the stage splits;
+//   - blocks: the connected components of the leaf sub-graphs, each with its node list,
+//     eigenvalues and FP64 eigenvectors V_b, and its depth (number of splits above it);
+//   - out_pos: the output position (coefficient index) of each block eigenvector.
+// Kernels run the stages unscaled (x_i + x_j, x_i - x_j, and sqrt(2) x_c on V_Z), which is
+// sqrt(2) B_phi on every split sub-graph; the 2^(-depth/2) factor is folded into the
+// block matrices.  This is the normalisation-absorption of Sec. III (Fig. haar).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gft.h"
+
+namespace gft {
+
+struct PlanError {
+  gft_status status;
+  std::string message;
+};
+
+struct HostStage {
+  std::vector<int32_t> pair_x;  // V_X member of each Haar unit
+  std::vector<int32_t> pair_y;  // its partner phi(x) in V_Y
+  std::vector<int32_t> znodes;  // fixed nodes of the sub-graphs split at this stage
+};
+
+struct HostBlock {
+  int32_t size = 0;
+  int32_t depth = 0;
+  double scale = 1.0;               // 2^(-depth/2)
+  std::vector<int32_t> nodes;       // node labels, ascending
+  std::vector<double> lambda;       // ascending
+  std::vector<double> V;            // size*size, V[j*size + k]
+  std::vector<int32_t> out_pos;     // output position of eigenvector k
+};
+
+struct GraphPlan {
+  int32_t n = 0;
+  int32_t num_stages_given = 0;
+  std::vector<HostStage> stages;    // stages that split something (others dropped)
+  std::vector<HostBlock> blocks;
+  std::vector<double> lambda_out;   // eigenvalues in output order
+  gft_plan_stats stats{};
+};
+
+// Build the plan of one graph.  Throws PlanError.
+GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
+                           const gft_options &opts);
+
+// FP64 host application of the factorisation (direction 0 forward, 1 inverse).
+void apply_host(const GraphPlan &p, int direction, const double *x, double *y, int64_t S);
+
+}  // namespace gft

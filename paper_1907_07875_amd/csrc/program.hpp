@@ -1,0 +1,31 @@
+// Host construction of the device programs of a plan (see device_program.hpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "device_program.hpp"
+#include "plan.hpp"
+
+namespace gft {
+
+// Host-side image of one program before upload: the LDS table and the matrix fragments.
+struct ProgramImage {
+  DevProgram prog{};          // pointers left null until upload
+  std::vector<int32_t> table;
+  std::vector<float> frag;
+};
+
+// Largest LDS bytes a workgroup of the apply kernel may use.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// Build the program of graph plan `p` for direction 0 (forward) or 1 (inverse).  The tile
+// size (16*mt signals) is `tile_override`/16 if nonzero, else the largest of 8,4,2,1
+// M-tiles whose LDS footprint fits `lds_budget` bytes.  Returns false if even one M-tile
+// does not fit.
+bool build_program(const GraphPlan &p, int direction, int tile_override, size_t lds_budget,
+                   ProgramImage &out);
+
+size_t program_lds_bytes(const DevProgram &P);
+
+}  // namespace gft

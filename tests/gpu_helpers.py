@@ -1,0 +1,33 @@
+"""Shared helpers of the GPU parity tests (no transform arithmetic of their own)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gft_oracle as O  # noqa: E402
+
+
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch.device("cuda:0")
+
+
+def gpu_basis(plan, dev):
+    """The basis the GPU applies: forward of the n unit vectors (row i = U^T e_i)."""
+    eye = torch.eye(plan.n, device=dev, dtype=torch.float32)
+    return plan.forward(eye).double().cpu().numpy()
+
+
+def aligned_oracle_basis(graph, Uhat, sv_tol=1e-5):
+    """Oracle eigenbasis rotated onto Uhat inside each eigenvalue cluster (sign / rotation
+    are free in a GFT); asserts Uhat spans the oracle's eigenspaces."""
+    L = O.laplacian_of(graph)
+    lam, U = O.gft(L)
+    Ua, min_sv = O.align(U, Uhat, lam)
+    assert min_sv > 1 - sv_tol, f"GPU basis leaves the oracle eigenspaces: min singular value {min_sv}"
+    return lam, Ua
+
+
+def to_np(t):
+    return t.double().cpu().numpy()

@@ -1,0 +1,166 @@
+"""GPU parity of the fast GFT kernels against the FP64 oracle (through the C ABI).
+
+The oracle's eigenbasis is aligned to the basis the GPU applies inside each eigenvalue
+cluster (sign and rotation within an eigenspace are free, Sec. III); the comparison then
+covers every coefficient of every signal.  FP32 tolerance: relative error <= 1e-5.
+"""
+import numpy as np
+import pytest
+
+import paper_1907_07875_amd as G
+import workloads as wl
+from oracle import gft_oracle as O
+from tests.gpu_helpers import aligned_oracle_basis, device, gpu_basis, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def _check_graph(g, X, tol=TOL_FP32):
+    dev = device()
+    plan = G.Plan.from_graph(g)
+    Uhat = gpu_basis(plan, dev)
+    lam, Ua = aligned_oracle_basis(g, Uhat)
+    Xd = X.astype(np.float64)
+    x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    y = plan.forward(x)
+    C_ref = O.forward(Xd, Ua)
+    err = O.relative_error(to_np(y), C_ref)
+    assert err <= tol, f"{g.name}: forward relative error {err:.3e}"
+    # inverse of the oracle's coefficients (FP32-rounded) reproduces the oracle's signal
+    C32 = C_ref.astype(np.float32)
+    xr = plan.inverse(torch.from_numpy(C32).to(dev))
+    err_i = O.relative_error(to_np(xr), O.inverse(C32.astype(np.float64), Ua))
+    assert err_i <= tol, f"{g.name}: inverse relative error {err_i:.3e}"
+    rt = O.relative_error(to_np(plan.inverse(y)), Xd)
+    assert rt <= tol, f"{g.name}: round trip error {rt:.3e}"
+    return plan, Uhat, lam
+
+
+def test_config1_path8_dct2():
+    """Path N=8 (one Haar stage, blocks 4+4): GPU basis is DCT-II up to sign."""
+    g = wl.config1_graph()
+    X = wl.gaussian(4096, 8, wl.rng_for(1), dtype=np.float64)
+    plan, Uhat, lam = _check_graph(g, X)
+    np.testing.assert_allclose(np.abs(Uhat.T @ O.dct2_matrix(8)), np.eye(8), atol=2e-6)
+    np.testing.assert_allclose(lam, O.path_eigenvalues(8), atol=1e-12)
+
+
+@pytest.mark.parametrize("S", [1, 15, 16, 17, 63, 64, 65, 1000, (1 << 14) + 37])
+def test_config2_grid8x8_ragged(S):
+    g = wl.config2_graph()
+    X = wl.ar1_field(S, 8, 8, 0.95, wl.rng_for(2, S))
+    _check_graph(g, X)
+
+
+def test_config2_grid8x8_full_size():
+    """2^20 AR(1) signals: the shape and launch configuration the benchmark times."""
+    g = wl.config2_graph()
+    X = wl.ar1_field(1 << 20, 8, 8, 0.95, wl.rng_for(2))
+    _check_graph(g, X)
+
+
+def test_config3_skeleton_fp32():
+    g = wl.config3_graph()
+    X = wl.skeleton_walks(8, 3, 40, wl.rng_for(3, 1)).reshape(-1, 25)
+    _check_graph(g, X)
+
+
+@pytest.mark.parametrize("g", [wl.path(4), wl.path(7), wl.path(64), wl.cycle(8), wl.cycle(13),
+                               wl.cycle(64), wl.grid(4, 4), wl.grid(5, 5), wl.grid(16, 16),
+                               wl.symmetric_bipartite(40, wl.rng_for(4, 40)),
+                               wl.symmetric_bipartite(128, wl.rng_for(4, 128))],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_config4_families_single(g):
+    X = wl.gaussian(3000, g.n, wl.rng_for(4, g.n, 7))
+    _check_graph(g, X)
+
+
+def test_no_symmetry_is_dense_gft():
+    """A plan with no stages is the dense GFT (one block)."""
+    g = wl.symmetric_bipartite(24, wl.rng_for(4, 99))
+    g.stages = []
+    X = wl.gaussian(500, g.n, wl.rng_for(4, 98))
+    _check_graph(g, X)
+
+
+def test_empty_batch_is_noop():
+    dev = device()
+    plan = G.Plan.from_graph(wl.config2_graph())
+    x = torch.zeros((0, 64), device=dev)
+    y = plan.forward(x)
+    assert y.shape == (0, 64)
+
+
+def test_in_place_forward():
+    dev = device()
+    g = wl.config2_graph()
+    plan = G.Plan.from_graph(g)
+    X = wl.gaussian(777, 64, wl.rng_for(2, 5))
+    x = torch.from_numpy(X).to(dev)
+    ref = plan.forward(x.clone())
+    plan.forward(x, out=x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, ref)
+
+
+def test_misaligned_and_overlapping_rejected():
+    dev = device()
+    plan = G.Plan.from_graph(wl.path(8))
+    buf = torch.zeros(8 * 101, device=dev)
+    with pytest.raises(G.GFTError) as e:
+        G.load_library()
+        import ctypes
+        G._check(G.load_library().gft_forward(plan.handle, ctypes.c_void_p(buf.data_ptr() + 4),
+                                              ctypes.c_void_p(buf.data_ptr() + 4096), 10, None))
+    assert e.value.status_name == "GFT_ERR_ALIGNMENT"
+    with pytest.raises(G.GFTError) as e:
+        import ctypes
+        G._check(G.load_library().gft_forward(plan.handle, ctypes.c_void_p(buf.data_ptr()),
+                                              ctypes.c_void_p(buf.data_ptr() + 64), 10, None))
+    assert e.value.status_name == "GFT_ERR_ALIGNMENT"
+
+
+def test_adjoint_dot_product():
+    """<U^T x, y> = <x, U y>: the inverse kernel is the adjoint of the forward kernel."""
+    dev = device()
+    g = wl.config3_graph()
+    plan = G.Plan.from_graph(g)
+    rng = wl.rng_for(3, 11)
+    x = torch.from_numpy(wl.gaussian(2048, 25, rng)).to(dev)
+    yv = torch.from_numpy(wl.gaussian(2048, 25, rng)).to(dev)
+    lhs = (plan.forward(x).double() * yv.double()).sum().item()
+    rhs = (x.double() * plan.inverse(yv).double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + (x.double().norm() * yv.double().norm()).item())
+
+
+def test_gpu_basis_matches_plan_basis():
+    dev = device()
+    for g in (wl.config2_graph(), wl.config3_graph(), wl.cycle(12)):
+        plan = G.Plan.from_graph(g)
+        np.testing.assert_allclose(gpu_basis(plan, dev), plan.basis(), atol=2e-6)
+
+
+def test_autograd_backward_is_inverse_kernel():
+    """Backward of GFTFunction (the adjoint kernel) vs finite differences and the oracle U g."""
+    dev = device()
+    g = wl.config3_graph()
+    plan = G.Plan.from_graph(g)
+    rng = wl.rng_for(3, 12)
+    x = torch.from_numpy(wl.gaussian(64, 25, rng)).to(dev).requires_grad_(True)
+    w = torch.from_numpy(wl.gaussian(64, 25, rng)).to(dev)
+    y = G.gft(x, plan)
+    (y * w).sum().backward()
+    Uhat = gpu_basis(plan, dev)
+    _, Ua = aligned_oracle_basis(g, Uhat)
+    # loss = sum(w * (x U)) -> grad_x = w U^T
+    np.testing.assert_allclose(to_np(x.grad), to_np(w) @ Ua.T, atol=2e-5)
+    # central finite differences with h = 1 are exact for a linear map up to rounding
+    xd = x.detach()
+    for (s, i) in ((0, 0), (5, 13), (63, 24)):
+        e = torch.zeros_like(xd)
+        e[s, i] = 1.0
+        fp = (plan.forward(xd + e) * w).double().sum().item()
+        fm = (plan.forward(xd - e) * w).double().sum().item()
+        assert abs((fp - fm) / 2 - x.grad[s, i].item()) <= 1e-3

@@ -1,0 +1,177 @@
+"""Host-side tests of the C ABI: exports, plan algebra vs the oracle, op counts, errors.
+
+No GPU is used: gft_plan is host-only and gft_plan_apply_host / gft_plan_basis run the
+plan's factorisation in FP64 on the host.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1907_07875_amd as G
+import workloads as wl
+from oracle import gft_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = G.load_library()
+    header = open(os.path.join(ROOT, "include", "gft.h")).read()
+    declared = set(re.findall(r"\b(gft_[a-z_]+)\s*\(", header))
+    assert declared, "no declarations parsed"
+    assert declared == set(G.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert "gfx950" in G.version()
+
+
+GRAPHS = [wl.config1_graph(), wl.config2_graph(), wl.config3_graph(), wl.cycle(12),
+          wl.cycle(13), wl.cycle(80), wl.grid(5, 5), wl.grid(4, 6), wl.path(33),
+          wl.symmetric_bipartite(48, wl.rng_for(4, 48)), wl.config5b_graph()]
+
+
+@pytest.mark.parametrize("g", GRAPHS, ids=lambda g: f"{g.name}{g.n}")
+def test_plan_basis_is_an_oracle_eigenbasis(g):
+    plan = G.Plan.from_graph(g)
+    lam, U = O.gft(O.laplacian_of(g))
+    lam_p = plan.eigenvalues()
+    scale = max(1.0, np.abs(lam).max())
+    np.testing.assert_allclose(lam_p, lam, atol=1e-10 * scale)
+    Uh = plan.basis()
+    np.testing.assert_allclose(Uh.T @ Uh, np.eye(g.n), atol=1e-12)
+    Ua, min_sv = O.align(U, Uh, lam)
+    assert min_sv > 1 - 1e-9
+    assert np.abs(Ua - Uh).max() < 1e-9
+    X = wl.gaussian(17, g.n, wl.rng_for(9, g.n), dtype=np.float64)
+    np.testing.assert_allclose(plan.apply_host(X, 0), O.forward(X, Ua), atol=1e-10)
+    np.testing.assert_allclose(plan.apply_host(O.forward(X, Ua), 1), X, atol=1e-10)
+    st = plan.info()
+    assert st["max_orth_error"] < 1e-12 and st["max_residual"] < 1e-12
+
+
+def test_config_op_counts():
+    """Fast op counts (Table tab:runtime convention) of the benchmark graphs."""
+    want = {"path8": (1, 4, 2, 32, 32), "grid8x8": (2, 64, 4, 1088, 1024),
+            "skeleton25": (1, 10, 3, 270, 280)}
+    for g in (wl.config1_graph(), wl.config2_graph(), wl.config3_graph()):
+        st = G.Plan.from_graph(g).info()
+        assert (st["num_stages"], st["num_units"], st["num_blocks"], st["adds"], st["mults"]) == want[g.name]
+
+
+def test_skeleton_minus_graph_splits_into_limbs():
+    """G- of the skeleton has two connected components (arm, leg), as in Fig. Gsk."""
+    plan = G.Plan.from_graph(wl.config3_graph())
+    sizes = sorted(len(b) for b in plan.blocks())
+    assert sizes == [5, 5, 15]
+
+
+def test_grid_recursive_64x64_blocks():
+    """64x64 grid, LR/UD reversals recursed on the + branch: 49 blocks b_i * b_j."""
+    g = wl.config5a_graph()
+    plan = G.Plan.from_graph(g)
+    st = plan.info()
+    assert st["num_blocks"] == 49 and st["max_block"] == 1024
+    sizes = sorted(len(b) for b in plan.blocks())
+    axis = [32, 16, 8, 4, 2, 1, 1]
+    assert sizes == sorted(a * b for a in axis for b in axis)
+    assert st["mults"] - st["num_z_scalings"] == 1366 ** 2
+
+
+def test_block_order_option():
+    g = wl.config2_graph()
+    p_eig = G.Plan.from_graph(g)
+    p_blk = G.Plan.from_graph(g, order=G.ORDER_BLOCK)
+    assert np.all(np.diff(p_eig.eigenvalues()) >= -1e-12)
+    lb = p_blk.eigenvalues()
+    assert not np.all(np.diff(lb) >= -1e-12)
+    np.testing.assert_allclose(np.sort(lb), p_eig.eigenvalues(), atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- errors
+
+def _status(fn):
+    with pytest.raises(G.GFTError) as e:
+        fn()
+    return e.value.status_name
+
+
+def test_error_not_involution():
+    g = wl.path(6)
+    assert _status(lambda: G.gft_plan(6, g.src, g.dst, g.weight, None, [np.array([1, 2, 0, 3, 4, 5])])) \
+        == "GFT_ERR_NOT_INVOLUTION"
+    assert _status(lambda: G.gft_plan(6, g.src, g.dst, g.weight, None, [np.array([0, 1, 2, 3, 4, 9])])) \
+        == "GFT_ERR_NOT_INVOLUTION"
+
+
+def test_error_not_symmetric_names_stage_and_nodes():
+    g = wl.path(6, weights=[1, 2, 3, 4, 5])
+    with pytest.raises(G.GFTError) as e:
+        G.Plan.from_graph(g)
+    assert e.value.status_name == "GFT_ERR_NOT_SYMMETRIC"
+    assert "stage 0" in str(e.value)
+
+
+def test_error_pairing_crosses_subgraph():
+    g = wl.path(8)
+    # after the reversal, {0..3} and {4..7} are separate sub-graphs; pairing 3 <-> 4 crosses
+    bad = wl.identity(8)
+    bad[3], bad[4] = 4, 3
+    assert _status(lambda: G.gft_plan(8, g.src, g.dst, g.weight, None, [wl.reversal(8), bad])) \
+        == "GFT_ERR_PAIRING_CROSSES_SUBGRAPH"
+
+
+def test_error_bad_graphs():
+    assert _status(lambda: G.gft_plan(3, [0, 1], [1, 5], [1.0, 1.0])) == "GFT_ERR_GRAPH"
+    assert _status(lambda: G.gft_plan(3, [0, 1], [1, 1], [1.0, 1.0])) == "GFT_ERR_GRAPH"
+    assert _status(lambda: G.gft_plan(3, [0, 1], [1, 0], [1.0, 1.0])) == "GFT_ERR_GRAPH"
+    assert _status(lambda: G.gft_plan(3, [0], [1], [np.nan])) == "GFT_ERR_GRAPH"
+    assert _status(lambda: G.gft_plan(3, [0], [1], [1.0], [0, np.inf, 0])) == "GFT_ERR_GRAPH"
+    assert _status(lambda: G.gft_plan(0, [], [], [])) == "GFT_ERR_INVALID_ARG"
+
+
+def test_error_bad_options():
+    g = wl.path(4)
+    assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, precision=7)) == "GFT_ERR_INVALID_ARG"
+    assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, order=3)) == "GFT_ERR_INVALID_ARG"
+    assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, tile=24)) == "GFT_ERR_INVALID_ARG"
+
+
+def test_null_arguments_rejected():
+    lib = G.load_library()
+    h = ctypes.c_void_p()
+    assert lib.gft_plan(None, None, None, ctypes.byref(h)) == 1
+    assert lib.gft_forward(None, None, None, 1, None) == 1
+    assert lib.gft_plan_info(None, 0, None) == 1
+    assert lib.gft_plan_destroy(None) == 0
+
+
+def test_negative_weights_accepted():
+    """Sub-graphs carry negative weights (Sec. IV-C); the input graph may too."""
+    g = wl.path(6, weights=[1.0, -0.5, 2.0, -0.5, 1.0])
+    plan = G.Plan.from_graph(g)
+    lam, U = O.gft(O.laplacian_of(g))
+    np.testing.assert_allclose(plan.eigenvalues(), lam, atol=1e-12)
+
+
+def test_single_node_and_no_edges():
+    for n, src, dst, w in ((1, [], [], []), (5, [], [], [])):
+        plan = G.gft_plan(n, src, dst, w)
+        X = np.arange(3 * n, dtype=np.float64).reshape(3, n)
+        np.testing.assert_allclose(np.abs(plan.apply_host(X, 0)).sum(axis=1), np.abs(X).sum(axis=1))
+
+
+def test_two_sparse_transposition_stage():
+    """A single transposition (Lemma 2sparse) is a one-unit stage; U- is 1x1."""
+    n = 6
+    g = wl._graph(n, [(0, j) for j in range(1, n)])
+    phi = wl.identity(n)
+    phi[2], phi[5] = 5, 2
+    plan = G.gft_plan(n, g.src, g.dst, g.weight, None, [phi])
+    st = plan.info()
+    assert st["num_units"] == 1 and sorted(len(b) for b in plan.blocks())[0] == 1
+    lam, U = O.gft(O.laplacian_of(g))
+    Ua, sv = O.align(U, plan.basis(), lam)
+    assert sv > 1 - 1e-10
