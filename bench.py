@@ -57,7 +57,7 @@ def cpu_baseline(X_sample, Y_gpu_sample, graph, basis_gpu):
         C = O.forward(Xd, U)
         Xr = O.inverse(C, U)
         reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 50:
+        if time.perf_counter() - t0 > 12.0:
             break
     dt = time.perf_counter() - t0
     values = 2.0 * Xd.shape[0] * Xd.shape[1] * reps
