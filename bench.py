@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--signals", type=int, default=S_FULL)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain device copy of the input size (counter calibration)")
     return ap.parse_args()
@@ -113,8 +114,10 @@ def main():
         return
 
     graph = wl.config2_graph()
-    plan = G.Plan.from_graph(graph)
+    plan = G.Plan.from_graph(graph, engine=args.engine)
     plan.prepare()
+    engine = plan.engine()
+    kernel_name = "gft_butterfly_f32<2,16,0>" if engine == "butterfly" else "gft_apply_f32<4>"
     stream = torch.cuda.current_stream()
     ya, yb = torch.empty_like(xa), torch.empty_like(xa)
     xr = torch.empty_like(xa)
@@ -156,6 +159,18 @@ def main():
     torch.cuda.synchronize()
     inv_avg_ms = e0.elapsed_time(e1) / args.steps
 
+    # plain device copy of the same bytes: the bandwidth a streaming kernel can reach here
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(3):
+        bufs[i & 1][1].copy_(bufs[i & 1][0])
+    c0.record(stream)
+    for i in range(args.steps):
+        bufs[i & 1][1].copy_(bufs[i & 1][0])
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / args.steps
+    copy_gbs = bytes_per_launch / (copy_ms * 1e-3) / 1e9
+
     result = {
         "metric": "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM roofline",
         "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": args.steps,
@@ -167,12 +182,15 @@ def main():
                    "precision": "fp32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "gft_apply_f32<4> (forward)",
+                     "kernel": kernel_name + " (forward)", "engine": engine,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": fwd_avg_ms},
         "forward_coeffs_per_s": S * n / (fwd_avg_ms * 1e-3),
         "inverse_values_per_s": S * n / (inv_avg_ms * 1e-3),
         "inverse_avg_launch_ms": inv_avg_ms,
+        "copy_reference": {"GB_per_s": copy_gbs, "avg_launch_ms": copy_ms,
+                           "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                           "forward_frac_of_copy": achieved / copy_gbs},
     }
 
     if not args.no_dense:

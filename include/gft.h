@@ -98,11 +98,22 @@ typedef enum {
                              /* ascending eigenvalue inside each block                */
 } gft_order;
 
+/* Kernel family.  AUTO picks the register-butterfly engine when the plan is a uniform
+ * hypercube (every stage pairs every node, 2^S equal connected leaf blocks, each Haar
+ * orbit holding one node of every block) and its shape is compiled in; otherwise the
+ * generic LDS-program engine. */
+typedef enum {
+  GFT_ENGINE_AUTO = 0,
+  GFT_ENGINE_GENERIC = 1,     /* always the generic engine                              */
+  GFT_ENGINE_BUTTERFLY = 2    /* require the register-butterfly engine (else          */
+                              /* GFT_ERR_UNSUPPORTED at the first apply)               */
+} gft_engine;
+
 typedef struct {
   int32_t precision;       /* gft_precision                                           */
   int32_t order;           /* gft_order                                               */
   int32_t tile_override;   /* 0 = tuned choice; else signals per tile (multiple of 16)*/
-  int32_t reserved;
+  int32_t engine;          /* gft_engine                                              */
   double sym_tol;          /* relative tolerance of the phi-symmetry test on sub-graph*/
                            /* Laplacians; <= 0 selects 1e-12                          */
 } gft_options;
@@ -163,6 +174,10 @@ gft_status gft_inverse_batch(gft_plan_t plan, const void *y, void *x,
  * apply on each device, with a synchronous copy).  Call it before capturing an apply into
  * a hipGraph.  Needs a GPU. */
 gft_status gft_plan_prepare(gft_plan_t plan);
+
+/* Engine (gft_engine: GFT_ENGINE_GENERIC or GFT_ENGINE_BUTTERFLY) the plan's image on
+ * the current device runs; builds the image like gft_plan_prepare.  Needs a GPU. */
+gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */
 gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out);

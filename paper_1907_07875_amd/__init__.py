@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgft.so")
 GFT_FP32, GFT_BF16, GFT_FP16, GFT_SPLIT_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": GFT_FP32, "bf16": GFT_BF16, "fp16": GFT_FP16, "split_bf16": GFT_SPLIT_BF16}
 ORDER_EIGENVALUE, ORDER_BLOCK = 0, 1
+ENGINES = {"auto": 0, "generic": 1, "butterfly": 2}
 
 STATUS = {
     0: "GFT_OK", 1: "GFT_ERR_INVALID_ARG", 2: "GFT_ERR_GRAPH", 3: "GFT_ERR_NOT_INVOLUTION",
@@ -30,7 +31,7 @@ STATUS = {
 # Every symbol include/gft.h declares.
 EXPORTS = [
     "gft_plan", "gft_plan_batch", "gft_forward", "gft_inverse", "gft_forward_batch",
-    "gft_inverse_batch", "gft_plan_prepare", "gft_plan_info", "gft_plan_num_graphs",
+    "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_info", "gft_plan_num_graphs",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version",
 ]
@@ -56,7 +57,7 @@ class _Pairing(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("tile_override", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_override", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("sym_tol", ctypes.c_double)]
 
 
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_forward_batch": ([P, P, P, P, i64, P], i32),
         "gft_inverse_batch": ([P, P, P, P, i64, P], i32),
         "gft_plan_prepare": ([P], i32),
+        "gft_plan_engine": ([P, ctypes.POINTER(i32)], i32),
         "gft_plan_info": ([P, i32, ctypes.POINTER(PlanStats)], i32),
         "gft_plan_num_graphs": ([P, ctypes.POINTER(i32)], i32),
         "gft_plan_size": ([P, i32, ctypes.POINTER(i32)], i32),
@@ -147,9 +149,10 @@ def _pairing_struct(n, stages, keep):
     return _Pairing(int(phi.shape[0]), phi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
 
 
-def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0):
+def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto"):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return _Options(prec, int(order), int(tile), 0, float(sym_tol))
+    eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    return _Options(prec, int(order), int(tile), eng, float(sym_tol))
 
 
 def _stream_ptr(stream):
@@ -170,10 +173,12 @@ class Plan:
 
     # -- construction ---------------------------------------------------------------
     @classmethod
-    def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0):
+    def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0,
+                   engine="auto"):
         """Plan one graph (an object with n, src, dst, weight, self_loop, stages)."""
         return gft_plan(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop,
-                        graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol)
+                        graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol,
+                        engine=engine)
 
     @property
     def n(self) -> int:
@@ -233,6 +238,12 @@ class Plan:
     def prepare(self):
         _check(load_library().gft_plan_prepare(self._h))
 
+    def engine(self) -> str:
+        """Kernel family the plan runs on the current device ("generic" or "butterfly")."""
+        e = ctypes.c_int32()
+        _check(load_library().gft_plan_engine(self._h, ctypes.byref(e)))
+        return {1: "generic", 2: "butterfly"}[e.value]
+
     # -- device apply ----------------------------------------------------------------
     def forward(self, x, out=None, stream=None):
         return gft_forward(self, x, out, stream)
@@ -242,20 +253,20 @@ class Plan:
 
 
 def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
-             order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0) -> Plan:
+             order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto") -> Plan:
     """Plan the fast GFT of one graph (C: ``gft_plan``)."""
     lib = load_library()
     keep = []
     g = _graph_struct(n, src, dst, weight, self_loop, keep)
     p = _pairing_struct(n, stages, keep)
-    o = _options(precision, order, tile, sym_tol)
+    o = _options(precision, order, tile, sym_tol, engine)
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision)
 
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
-                   sym_tol=0.0) -> Plan:
+                   sym_tol=0.0, engine="auto") -> Plan:
     """Plan several graphs for one persistent launch (C: ``gft_plan_batch``)."""
     lib = load_library()
     keep = []
@@ -264,7 +275,7 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     for i, gr in enumerate(graphs):
         G[i] = _graph_struct(gr.n, gr.src, gr.dst, gr.weight, gr.self_loop, keep)
         Pr[i] = _pairing_struct(gr.n, gr.stages, keep)
-    o = _options(precision, order, tile, sym_tol)
+    o = _options(precision, order, tile, sym_tol, engine)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(g.n) for g in graphs], True, precision)

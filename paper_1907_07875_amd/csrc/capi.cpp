@@ -35,9 +35,24 @@ gft_status ok() {
 // fragments, and the programs with their device pointers filled in.
 struct DeviceImage {
   int device = -1;
+  int num_cus = 1;
   void *mem = nullptr;
   std::vector<DevProgram> fwd, inv;
   std::vector<int> grid_cap_fwd, grid_cap_inv;
+  // register-butterfly programs (single-graph plans whose shape qualifies)
+  bool butterfly = false;
+  UProgram bfwd{}, binv{};
+};
+
+// Byte blob assembled on the host and uploaded in one copy; offsets are 256-aligned.
+struct Blob {
+  std::vector<char> bytes;
+  size_t add(const void *p, size_t n) {
+    const size_t off = bytes.size();
+    bytes.resize(off + ((n + 255) & ~(size_t)255), 0);
+    if (n) std::memcpy(bytes.data() + off, p, n);
+    return off;
+  }
 };
 
 }  // namespace
@@ -70,6 +85,7 @@ gft_options default_options(const gft_options *o) {
   d.precision = GFT_FP32;
   d.order = GFT_ORDER_EIGENVALUE;
   d.tile_override = 0;
+  d.engine = GFT_ENGINE_AUTO;
   d.sym_tol = 1e-12;
   if (o) d = *o;
   return d;
@@ -80,6 +96,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.precision is not a gft_precision value");
   if (o.order != GFT_ORDER_EIGENVALUE && o.order != GFT_ORDER_BLOCK)
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
+  if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_BUTTERFLY)
+    return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1 or 2");
   if (o.tile_override != 0 && o.tile_override != 16 && o.tile_override != 32 &&
       o.tile_override != 64 && o.tile_override != 128)
     return set_error(GFT_ERR_INVALID_ARG, "options.tile_override must be 0, 16, 32, 64 or 128");
@@ -106,34 +124,51 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(CU count)");
   const size_t budget = std::min<size_t>(kMaxLdsBytes, (size_t)max_lds);
 
+  // Register-butterfly engine for single-graph uniform hypercube plans.
+  UProgramImage ub[2];
+  bool use_bf = false;
+  if (!plan->batch && plan->opts.engine != GFT_ENGINE_GENERIC) {
+    use_bf = build_butterfly(plan->graphs[0], 0, ub[0]) && build_butterfly(plan->graphs[0], 1, ub[1]) &&
+             butterfly_supported(ub[0].prog.S, ub[0].prog.M);
+    if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
+      return set_error(GFT_ERR_UNSUPPORTED,
+                       "the register-butterfly engine does not cover this plan (needs a uniform "
+                       "hypercube with a compiled shape)");
+  }
+
   std::vector<ProgramImage> imgs;
   for (size_t g = 0; g < plan->graphs.size(); ++g)
     for (int dir = 0; dir < 2; ++dir) {
       ProgramImage im;
-      if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im))
+      if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im)) {
+        if (use_bf) continue;  // the butterfly engine serves this graph
         return set_error(GFT_ERR_UNSUPPORTED,
                          "graph " + std::to_string(g) + " (n = " + std::to_string(plan->graphs[g].n) +
                              ") does not fit the LDS of one workgroup with this tile size");
+      }
       imgs.push_back(std::move(im));
     }
-  size_t bytes = 0;
+  Blob blob;
   std::vector<size_t> toff(imgs.size()), foff(imgs.size());
   for (size_t i = 0; i < imgs.size(); ++i) {
-    toff[i] = bytes;
-    bytes += (imgs[i].table.size() * 4 + 255) & ~(size_t)255;
-    foff[i] = bytes;
-    bytes += (imgs[i].frag.size() * 4 + 255) & ~(size_t)255;
+    toff[i] = blob.add(imgs[i].table.data(), imgs[i].table.size() * 4);
+    foff[i] = blob.add(imgs[i].frag.data(), imgs[i].frag.size() * 4);
   }
-  std::vector<char> host(bytes, 0);
-  for (size_t i = 0; i < imgs.size(); ++i) {
-    std::memcpy(host.data() + toff[i], imgs[i].table.data(), imgs[i].table.size() * 4);
-    std::memcpy(host.data() + foff[i], imgs[i].frag.data(), imgs[i].frag.size() * 4);
-  }
+  size_t uoff[2][4] = {};
+  if (use_bf)
+    for (int d = 0; d < 2; ++d) {
+      uoff[d][0] = blob.add(ub[d].gcol.data(), ub[d].gcol.size() * 4);
+      uoff[d][1] = blob.add(ub[d].scol.data(), ub[d].scol.size() * 4);
+      uoff[d][2] = blob.add(ub[d].afrag.data(), ub[d].afrag.size() * 4);
+      uoff[d][3] = blob.add(ub[d].flips.data(), ub[d].flips.size() * 4);
+    }
+  const size_t bytes = blob.bytes.size();
   auto img = std::make_unique<DeviceImage>();
   img->device = dev;
+  img->num_cus = std::max(1, cus);
   e = hipMalloc(&img->mem, bytes ? bytes : 256);
   if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMalloc of the plan image failed");
-  e = hipMemcpy(img->mem, host.data(), bytes, hipMemcpyHostToDevice);
+  e = hipMemcpy(img->mem, blob.bytes.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(img->mem);
     return set_error(GFT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
@@ -143,13 +178,24 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     DevProgram P = imgs[i].prog;
     P.table = reinterpret_cast<const int32_t *>(base + toff[i]);
     P.frag = reinterpret_cast<const float *>(base + foff[i]);
-    const int cap = std::max(1, cus) * apply_occupancy(P);
+    const int cap = img->num_cus * apply_occupancy(P);
     if (i % 2 == 0) {
       img->fwd.push_back(P);
       img->grid_cap_fwd.push_back(cap);
     } else {
       img->inv.push_back(P);
       img->grid_cap_inv.push_back(cap);
+    }
+  }
+  if (use_bf) {
+    img->butterfly = true;
+    UProgram *dst[2] = {&img->bfwd, &img->binv};
+    for (int d = 0; d < 2; ++d) {
+      *dst[d] = ub[d].prog;
+      dst[d]->gcol = reinterpret_cast<const int32_t *>(base + uoff[d][0]);
+      dst[d]->scol = reinterpret_cast<const int32_t *>(base + uoff[d][1]);
+      dst[d]->afrag = reinterpret_cast<const float *>(base + uoff[d][2]);
+      dst[d]->flips = reinterpret_cast<const uint32_t *>(base + uoff[d][3]);
     }
   }
   *out = img.get();
@@ -179,10 +225,16 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   DeviceImage *img = nullptr;
   st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  const DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
-  const int cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
-  hipError_t e = launch_apply(P, static_cast<const float *>(in), static_cast<float *>(out), S,
-                              static_cast<hipStream_t>(stream), cap);
+  hipError_t e;
+  if (img->butterfly) {
+    e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, static_cast<const float *>(in),
+                         static_cast<float *>(out), S, static_cast<hipStream_t>(stream), img->num_cus);
+  } else {
+    const DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
+    const int cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
+    e = launch_apply(P, static_cast<const float *>(in), static_cast<float *>(out), S,
+                     static_cast<hipStream_t>(stream), cap);
+  }
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
 }
@@ -271,6 +323,15 @@ gft_status gft_plan_prepare(gft_plan_t plan) {
   DeviceImage *img = nullptr;
   gft_status st = device_image(plan, &img);
   return st != GFT_OK ? st : ok();
+}
+
+gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out) {
+  if (!plan || !engine_out) return set_error(GFT_ERR_INVALID_ARG, "plan and engine_out must be non-NULL");
+  DeviceImage *img = nullptr;
+  gft_status st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  *engine_out = img->butterfly ? GFT_ENGINE_BUTTERFLY : GFT_ENGINE_GENERIC;
+  return ok();
 }
 
 gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out) {

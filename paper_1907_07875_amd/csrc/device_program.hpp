@@ -47,10 +47,41 @@ struct DevProgram {
   int32_t sidx_len;
   uint32_t magic_n;   // ceil(2^32 / n)
   int32_t table_words;  // int32 words of the LDS-resident tables
+  int32_t frag_lds;     // 1: the fragments are copied to LDS after the tables (else read
+                        // from global memory)
+  int32_t frag_words;   // floats of `frag`
   // stages (4 words each) | ops (2 each) | blocks (8 each) | items | gidx | sidx,
   // contiguous; each workgroup copies it to LDS once
   const int32_t *table;
   const float *frag;
+};
+
+// Register-butterfly program (uniform hypercube plans): S stages, 2^S leaf blocks of M
+// nodes, n = M * 2^S; orbit o (o < M) holds node node(o, b) of every block b at block
+// position o, and stage t pairs slots b and b ^ 2^(S-1-t).  Lane l of a wave works on
+// signal l % 16 of a 16-signal tile and on lane group g = l / 16.
+//   gcol[g * Q + q] (Q = n/4): LDS column the lane gathers into data register q;
+//   scol[g * Q + q]: LDS column the lane scatters result register q to;
+//   afrag[f * 64 + l]: MFMA A-operand fragment f for lane l;
+//   flips[2g], flips[2g+1]: low and high words of the 64 sign-flip bits of group g.
+// A node enters at its initial slot and leaves stage S-1 at its final slot, which is its
+// leaf block.  At stage t every orbit combines slots (lo, hi = lo | 2^(S-1-t)) into
+// (lo + hi, +-(lo - hi)); the sign is flipped where the V_X node started in slot hi.
+// Flip bit of orbit register set j, stage t, lo-slot rank k: j * S * 2^(S-1) + t * 2^(S-1) + k,
+// where j = kc (forward) or nt * 4 + v (inverse).
+// Register order (forward): data q = kc * 2^S + b (orbit 4kc+g, slot b); results
+// q = (b * M/16 + nt) * 4 + v (coefficient 16nt+4g+v of block b).  Inverse: data
+// q = kc * 2^S + b (coefficient 4kc+g of block b); results q = (nt * 4 + v) * 2^S + b
+// (orbit 16nt+4g+v, slot b).  Fragment f = (b * M/16 + nt) * M/4 + kc.
+struct UProgram {
+  int32_t S;
+  int32_t M;
+  int32_t n;
+  int32_t dir;
+  const int32_t *gcol;
+  const int32_t *scol;
+  const uint32_t *flips;
+  const float *afrag;
 };
 
 }  // namespace gft

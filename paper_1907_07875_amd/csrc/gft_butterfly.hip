@@ -1,0 +1,230 @@
+// Register-butterfly GFT kernels for uniform hypercube plans (gfx950).
+//
+// A plan whose S butterfly stages each pair every node (eq. B_phi with V_Z empty), with
+// 2^S equal leaf blocks of M nodes, factors U^T as 2^S dense M x M sub-GFTs after S
+// stages of Haar units; every Haar orbit holds one node of every block (the grid of
+// Fig. grid_coords under LR then UD symmetry is the case n = 64, S = 2, M = 16).
+// Each wave works alone on tiles of 16 signals, with no workgroup barriers:
+//   HBM --16B loads, prefetched one tile ahead--> registers (native vector type: arrays
+//   of the HIP float4 struct are not promoted out of scratch) --> wave-private LDS tile
+//   --gather--> registers in MFMA operand order: lane (g, r) holds, for signal r, the
+//   2^S slots of the orbits assigned to lane group g
+//   --> Haar stages as register add/sub (forward) --> v_mfma_f32_16x16x4_f32 with the
+//   block matrices resident in registers --> Haar stages (inverse) --> scatter to the
+//   LDS tile in output order --> 16B stores.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_program.hpp"
+
+namespace gft {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+
+// x with its sign flipped when bit f is set.
+__device__ __forceinline__ float flip_sign(float x, uint32_t f) {
+  return __int_as_float(__float_as_int(x) ^ (int)(f << 31));
+}
+
+// Orders this wave's LDS accesses: every lane's earlier LDS operations complete (and the
+// compiler keeps them in place) before any later one.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace
+
+template <int S, int M, int DIR>
+__global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, const float *in,
+                                                                 float *out, int64_t nsig) {
+  constexpr int NB = 1 << S;      // leaf blocks = slots per orbit
+  constexpr int KC = M / 4;       // K chunks of a block
+  constexpr int NT = M / 16;      // 16-row tiles of a block
+  constexpr int N = M * NB;       // signal length
+  constexpr int Q = N / 4;        // values per lane
+  constexpr int STR = N + 4;      // LDS row stride: 16-byte rows, offset banks
+  constexpr int V4 = N / 16;      // float4 per lane per 16-signal tile
+  constexpr int NF = NB * NT * KC;
+  __shared__ float lds_all[kWaves * 16 * STR];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int r = lane & 15;
+  float *T = lds_all + wave * 16 * STR;
+
+  // LDS offsets of this lane's gathers and scatters
+  int gc[Q], sc[Q];
+  float af[NF];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    gc[q] = r * STR + P.gcol[g * Q + q];
+    sc[q] = r * STR + P.scol[g * Q + q];
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) af[f] = P.afrag[f * 64 + lane];
+  constexpr int PPS = NB / 2;
+  constexpr int FB = S * PPS;
+  const uint64_t flips = ((uint64_t)P.flips[2 * g + 1] << 32) | P.flips[2 * g];
+
+  const int64_t ntiles = (nsig + 15) / 16;
+  const int64_t step = (int64_t)gridDim.x * kWaves;
+  int64_t wt = (int64_t)blockIdx.x * kWaves + wave;
+
+  // Prefetch of a tile into registers.  The loads are unconditional, so that they stay in
+  // flight while the previous tile is computed: past the last valid signal a lane
+  // re-reads the tile's last float4 (lim >= N >= 32), whose rows are never stored.
+  floatx4 pre[V4];
+  auto issue = [&](int64_t t) {
+    const int64_t rem = nsig - 16 * t;
+    const int lim = (int)(rem < 16 ? rem : 16) * N;
+    const float *src = in + t * 16 * N;
+#pragma unroll
+    for (int k = 0; k < V4; ++k) {
+      const int e = 4 * (lane + 64 * k);
+      pre[k] = *reinterpret_cast<const floatx4 *>(src + (e < lim ? e : lim - 4));
+    }
+  };
+  if (wt < ntiles) issue(wt);
+
+  for (; wt < ntiles; wt += step) {
+    const int64_t rem = nsig - 16 * wt;
+    const int lim = (int)(rem < 16 ? rem : 16) * N;
+#pragma unroll
+    for (int k = 0; k < V4; ++k) {
+      const int e = 4 * (lane + 64 * k);
+      *reinterpret_cast<floatx4 *>(T + (e / N) * STR + (e % N)) = pre[k];
+    }
+    wave_lds_sync();
+    // next tile's loads (the last tile re-reads itself rather than branch around the loads)
+    const int64_t nxt = wt + step;
+    issue(nxt < ntiles ? nxt : ntiles - 1);
+
+    float d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) d[q] = T[gc[q]];
+
+    if (DIR == 0) {
+      // forward Haar stages, in stage order: slots lo and lo | bit, bit = 2^(S-1-t)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          const int bit = 1 << (S - 1 - t);
+          int k = 0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            if (!(b & bit)) {
+              const uint32_t f = (uint32_t)(flips >> (kc * FB + t * PPS + k)) & 1u;
+              const float a = d[kc * NB + b], c = d[kc * NB + (b | bit)];
+              d[kc * NB + b] = a + c;
+              d[kc * NB + (b | bit)] = flip_sign(a - c, f);
+              ++k;
+            }
+        }
+    }
+
+    float res[Q];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[(b * NT + nt) * KC + kc], d[kc * NB + b],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (DIR == 0) res[(b * NT + nt) * 4 + v] = acc[v];
+          else res[(nt * 4 + v) * NB + b] = acc[v];
+        }
+      }
+
+    if (DIR == 1) {
+      // inverse Haar stages, in reverse stage order, on each orbit's 2^S slots
+#pragma unroll
+      for (int o = 0; o < NT * 4; ++o)
+#pragma unroll
+        for (int t = S - 1; t >= 0; --t) {
+          const int bit = 1 << (S - 1 - t);
+          int k = 0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            if (!(b & bit)) {
+              const uint32_t f = (uint32_t)(flips >> (o * FB + t * PPS + k)) & 1u;
+              const float a = res[o * NB + b], c = flip_sign(res[o * NB + (b | bit)], f);
+              res[o * NB + b] = a + c;
+              res[o * NB + (b | bit)] = a - c;
+              ++k;
+            }
+        }
+    }
+
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) T[sc[q]] = res[q];
+    wave_lds_sync();
+    float *dst = out + wt * 16 * N;
+    floatx4 o4[V4];
+#pragma unroll
+    for (int k = 0; k < V4; ++k) {
+      const int e = 4 * (lane + 64 * k);
+      o4[k] = *reinterpret_cast<const floatx4 *>(T + (e / N) * STR + (e % N));
+    }
+    if (lim == 16 * N) {   // full tile (wave-uniform branch)
+#pragma unroll
+      for (int k = 0; k < V4; ++k) *reinterpret_cast<floatx4 *>(dst + 4 * (lane + 64 * k)) = o4[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < V4; ++k)
+        if (4 * (lane + 64 * k) < lim) *reinterpret_cast<floatx4 *>(dst + 4 * (lane + 64 * k)) = o4[k];
+    }
+    wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------- launch
+
+template <int S, int M, int DIR>
+static hipError_t launch_bf(const UProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR>,
+                                                   64 * kWaves, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  const int64_t ntiles = (nsig + 15) / 16;
+  const int64_t want = (ntiles + kWaves - 1) / kWaves;
+  const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
+  const int grid = (int)(want < cap ? want : cap);
+  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR>), dim3(grid > 0 ? grid : 1),
+                     dim3(64 * kWaves), 0, stream, P, in, out, nsig);
+  return hipGetLastError();
+}
+
+bool butterfly_supported(int S, int M) {
+  return (S == 1 && (M == 16 || M == 32)) || (S == 2 && M == 16) || (S == 3 && M == 16);
+}
+
+hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus) {
+#define GFT_BF_CASE(s, m)                                                                  \
+  if (P.S == s && P.M == m)                                                                \
+    return P.dir == 0 ? launch_bf<s, m, 0>(P, in, out, nsig, stream, num_cus)              \
+                      : launch_bf<s, m, 1>(P, in, out, nsig, stream, num_cus);
+  GFT_BF_CASE(1, 16)
+  GFT_BF_CASE(1, 32)
+  GFT_BF_CASE(2, 16)
+  GFT_BF_CASE(3, 16)
+#undef GFT_BF_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gft

@@ -47,28 +47,56 @@ __device__ __forceinline__ LdsTables carve(const DevProgram &P, const int32_t *b
   return t;
 }
 
-// Copy `count` floats (contiguous in HBM) into LDS rows of `stride` floats; rows at and
-// beyond count / n are zero-filled up to `rows`.
-__device__ __forceinline__ void load_tile(const float *g, int count, int rows, int n,
-                                          int stride, uint32_t magic_n, float *lds) {
-  const int tid = threadIdx.x;
+// Tile loads are split in two halves so the next tile's HBM reads overlap the current
+// tile's compute: issue_tile() starts up to kPrefetch float4 loads per thread into
+// registers; commit_tile() writes them to LDS rows of `stride` floats, loads whatever
+// did not fit in registers, and zero-fills rows at and beyond count / n up to `rows`.
+constexpr int kPrefetch = 4;
+
+// The prefetch loads are unconditional so that they stay in flight across the compute of
+// the previous tile (a guarded load is waited for inside its branch): lanes past the
+// tile's last float4 re-read it, and a tile with no whole float4 reads `spare`, 16 bytes
+// of valid device memory.  commit_tile() only stores the in-range ones.
+__device__ __forceinline__ void issue_tile(const float *g, int count, const floatx4 *spare,
+                                           floatx4 (&pre)[kPrefetch]) {
   const int nvec = count >> 2;
-  const float4 *g4 = reinterpret_cast<const float4 *>(g);
-  for (int v = tid; v < nvec; v += kThreads) {
-    const float4 val = g4[v];
-    const uint32_t e = 4u * (uint32_t)v;
-    uint32_t r = fdiv(e, magic_n);
-    uint32_t c = e - r * (uint32_t)n;
-    const float q[4] = {val.x, val.y, val.z, val.w};
+  const floatx4 *g4 = nvec > 0 ? reinterpret_cast<const floatx4 *>(g) : spare;
+  const int last = nvec > 0 ? nvec - 1 : 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      lds[r * stride + c] = q[k];
-      if (++c == (uint32_t)n) {
-        c = 0;
-        ++r;
-      }
+  for (int k = 0; k < kPrefetch; ++k) {
+    const int v = threadIdx.x + k * kThreads;
+    pre[k] = g4[v < last ? v : last];
+  }
+}
+
+__device__ __forceinline__ void put4(float *lds, uint32_t e, const floatx4 &val, int n,
+                                     int stride, uint32_t magic_n) {
+  uint32_t r = fdiv(e, magic_n);
+  uint32_t c = e - r * (uint32_t)n;
+  const float q[4] = {val[0], val[1], val[2], val[3]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    lds[r * stride + c] = q[k];
+    if (++c == (uint32_t)n) {
+      c = 0;
+      ++r;
     }
   }
+}
+
+__device__ __forceinline__ void commit_tile(const float *g, int count, int rows, int n,
+                                            int stride, uint32_t magic_n,
+                                            const floatx4 (&pre)[kPrefetch], float *lds) {
+  const int tid = threadIdx.x;
+  const int nvec = count >> 2;
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) {
+    const int v = tid + k * kThreads;
+    if (v < nvec) put4(lds, 4u * (uint32_t)v, pre[k], n, stride, magic_n);
+  }
+  const floatx4 *g4 = reinterpret_cast<const floatx4 *>(g);
+  for (int v = tid + kPrefetch * kThreads; v < nvec; v += kThreads)
+    put4(lds, 4u * (uint32_t)v, g4[v], n, stride, magic_n);
   for (int e = 4 * nvec + tid; e < count; e += kThreads) {
     const uint32_t r = fdiv((uint32_t)e, magic_n);
     lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = g[e];
@@ -134,7 +162,8 @@ __device__ __forceinline__ void haar_stage(const int32_t *st, const int32_t *ops
 // B[l/16][l%16]; it receives D[4*(l/16) + v][l%16] in accumulator element v.
 template <int MT>
 __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTables &t,
-                                               const float *src, float *dst) {
+                                               const float *fragbase, const float *src,
+                                               float *dst) {
   const int stride = P.stride;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -147,7 +176,7 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
     const int32_t *B = t.blocks + 8 * b;
     const int size = B[0], kchunks = B[1], ntiles = B[2];
     const int32_t *gi = t.gidx + B[3];
-    const float *frag = P.frag + B[5] + nt * 64 + lane;
+    const float *frag = fragbase + B[5] + nt * 64 + lane;
     floatx4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -173,7 +202,7 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
 }
 
 template <int MT>
-__global__ __launch_bounds__(kThreads) void gft_apply_f32(DevProgram P, const float *in,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 8 ? 2 : 4))) void gft_apply_f32(DevProgram P, const float *in,
                                                          float *out, int64_t S) {
   extern __shared__ int32_t smem[];
   constexpr int T = 16 * MT;
@@ -181,28 +210,40 @@ __global__ __launch_bounds__(kThreads) void gft_apply_f32(DevProgram P, const fl
   const int stride = P.stride;
   for (int i = threadIdx.x; i < P.table_words; i += kThreads) smem[i] = P.table[i];
   const LdsTables t = carve(P, smem);
-  float *buf0 = reinterpret_cast<float *>(smem + ((P.table_words + 3) & ~3));
+  float *lfrag = reinterpret_cast<float *>(smem + ((P.table_words + 3) & ~3));
+  if (P.frag_lds)
+    for (int i = threadIdx.x; i < P.frag_words; i += kThreads) lfrag[i] = P.frag[i];
+  const float *fragbase = P.frag_lds ? lfrag : P.frag;
+  float *buf0 = lfrag + (P.frag_lds ? ((P.frag_words + 3) & ~3) : 0);
   float *buf1 = buf0 + T * stride;
-  __syncthreads();
   const int64_t num_tiles = (S + T - 1) / T;
-  for (int64_t tile = blockIdx.x; tile < num_tiles; tile += gridDim.x) {
-    const int64_t s0 = tile * T;
-    const int valid = (int)((S - s0) < T ? (S - s0) : T);
-    const float *gin = in + s0 * n;
-    float *gout = out + s0 * n;
-    load_tile(gin, valid * n, T, n, stride, P.magic_n, buf0);
+  auto count_of = [&](int64_t tile) {
+    const int64_t rem = S - tile * T;
+    return (int)(rem < T ? rem : T) * n;
+  };
+  floatx4 pre[kPrefetch];
+  int64_t tile = blockIdx.x;
+  const floatx4 *spare = reinterpret_cast<const floatx4 *>(P.table);
+  if (tile < num_tiles) issue_tile(in + tile * T * n, count_of(tile), spare, pre);
+  __syncthreads();
+  for (; tile < num_tiles; tile += gridDim.x) {
+    const int count = count_of(tile);
+    commit_tile(in + tile * T * n, count, T, n, stride, P.magic_n, pre, buf0);
     __syncthreads();
+    // next tile's loads (the last tile re-reads itself rather than branch around the loads)
+    const int64_t next = tile + gridDim.x < num_tiles ? tile + gridDim.x : num_tiles - 1;
+    issue_tile(in + next * T * n, count_of(next), spare, pre);
     for (int s = 0; s < P.num_pre; ++s) {
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf0);
       __syncthreads();
     }
-    block_products<MT>(P, t, buf0, buf1);
+    block_products<MT>(P, t, fragbase, buf0, buf1);
     __syncthreads();
     for (int s = P.num_pre; s < P.num_pre + P.num_post; ++s) {
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf1);
       __syncthreads();
     }
-    store_tile(buf1, valid * n, n, stride, P.magic_n, gout);
+    store_tile(buf1, count, n, stride, P.magic_n, out + tile * T * n);
     __syncthreads();
   }
 }

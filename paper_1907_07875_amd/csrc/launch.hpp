@@ -16,4 +16,9 @@ hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_
 // Resident workgroups per CU of the apply kernel for this program's LDS footprint.
 int apply_occupancy(const DevProgram &P);
 
+// Register-butterfly engine (uniform hypercube plans).
+bool butterfly_supported(int S, int M);
+hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus);
+
 }  // namespace gft

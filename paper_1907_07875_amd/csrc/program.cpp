@@ -17,7 +17,8 @@ uint32_t magic_for(uint32_t d) {
 
 size_t program_lds_bytes(const DevProgram &P) {
   const size_t T = 16 * (size_t)P.mt;
-  return 4 * (size_t)((P.table_words + 3) & ~3) + 2 * T * (size_t)P.stride * 4;
+  const size_t frag = P.frag_lds ? 4 * (size_t)((P.frag_words + 3) & ~3) : 0;
+  return 4 * (size_t)((P.table_words + 3) & ~3) + frag + 2 * T * (size_t)P.stride * 4;
 }
 
 bool build_program(const GraphPlan &p, int direction, int tile_override, size_t lds_budget,
@@ -100,6 +101,10 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   t.insert(t.end(), gidx.begin(), gidx.end());
   t.insert(t.end(), sidx.begin(), sidx.end());
   P.table_words = (int32_t)t.size();
+  P.frag_words = (int32_t)frag.size();
+  // Fragments live in LDS when they are small: read from global memory their waits would
+  // also drain the in-flight prefetch of the next tile (the load counter is in order).
+  P.frag_lds = frag.size() * 4 <= 16 * 1024 ? 1 : 0;
 
   if (tile_override > 0) {
     P.mt = tile_override / 16;
@@ -114,6 +119,161 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   }
   P.mt = 1;
   return program_lds_bytes(P) <= lds_budget;
+}
+
+}  // namespace gft
+
+namespace gft {
+
+bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
+  const int n = p.n;
+  const int S = (int)p.stages.size();
+  if (S < 1 || S > 3) return false;
+  const int NB = 1 << S;
+  if ((int)p.blocks.size() != NB || n % NB) return false;
+  const int M = n / NB;
+  if (M % 16) return false;
+  for (const HostBlock &B : p.blocks)
+    if (B.size != M || B.depth != S) return false;
+  for (const HostStage &st : p.stages)
+    if (!st.znodes.empty() || (int)st.pair_x.size() * 2 != n) return false;
+
+  // final slot of a node = its leaf block; bit S-1-t of it is the node's side at stage t
+  std::vector<int> fslot(n, -1), pos(n, -1);
+  for (int b = 0; b < NB; ++b)
+    for (int k = 0; k < M; ++k) {
+      fslot[p.blocks[b].nodes[k]] = b;
+      pos[p.blocks[b].nodes[k]] = k;
+    }
+  std::vector<std::vector<int>> partner(S, std::vector<int>(n, -1));
+  std::vector<std::vector<char>> isx(S, std::vector<char>(n, 0));
+  for (int t = 0; t < S; ++t) {
+    const HostStage &st = p.stages[t];
+    for (size_t u = 0; u < st.pair_x.size(); ++u) {
+      partner[t][st.pair_x[u]] = st.pair_y[u];
+      partner[t][st.pair_y[u]] = st.pair_x[u];
+      isx[t][st.pair_x[u]] = 1;
+    }
+    for (int i = 0; i < n; ++i)
+      if (partner[t][i] < 0 || ((fslot[i] >> (S - 1 - t)) & 1) != (isx[t][i] ? 0 : 1)) return false;
+  }
+  // Slot bit of each node before stage t (pb[t][i]): stage-t partners differ in it, and
+  // partners at any earlier stage agree in it (they must share every bit but their own).
+  std::vector<std::vector<int>> pb(S, std::vector<int>(n, -1));
+  for (int t = 0; t < S; ++t) {
+    std::vector<int> &c = pb[t];
+    for (int s0 = 0; s0 < n; ++s0) {
+      if (c[s0] >= 0) continue;
+      c[s0] = 0;
+      std::vector<int> stack{s0};
+      while (!stack.empty()) {
+        const int v = stack.back();
+        stack.pop_back();
+        for (int t2 = 0; t2 <= t; ++t2) {
+          const int w = partner[t2][v];
+          const int want = t2 == t ? 1 - c[v] : c[v];
+          if (c[w] < 0) {
+            c[w] = want;
+            stack.push_back(w);
+          } else if (c[w] != want) {
+            return false;
+          }
+        }
+      }
+    }
+  }
+  std::vector<int> islot(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < S; ++t) islot[i] |= pb[t][i] << (S - 1 - t);
+
+  // orbits: one node per final slot and per initial slot, numbered by block-0 position
+  std::vector<int> parent(n);
+  for (int i = 0; i < n; ++i) parent[i] = i;
+  auto find = [&](int v) {
+    while (parent[v] != v) v = parent[v] = parent[parent[v]];
+    return v;
+  };
+  for (int t = 0; t < S; ++t)
+    for (int i = 0; i < n; ++i) parent[find(i)] = find(partner[t][i]);
+  std::vector<int> orbit_id(n, -1);
+  for (int k = 0; k < M; ++k) orbit_id[find(p.blocks[0].nodes[k])] = k;
+  std::vector<int> node_fin((size_t)M * NB, -1), node_ini((size_t)M * NB, -1);
+  for (int i = 0; i < n; ++i) {
+    const int o = orbit_id[find(i)];
+    if (o < 0) return false;
+    int &cf = node_fin[(size_t)o * NB + fslot[i]];
+    int &ci = node_ini[(size_t)o * NB + islot[i]];
+    if (cf >= 0 || ci >= 0) return false;
+    cf = ci = i;
+  }
+  // Sign flips: at stage t the pair (x, y) sits in slots (lo, lo | bit); when x (the V_X
+  // node) starts in the upper slot the difference lands negated and is flipped back.
+  const int PPS = NB / 2;  // pairs per stage within an orbit
+  std::vector<uint64_t> oflip(M, 0);
+  for (int t = 0; t < S; ++t) {
+    const int bp = S - 1 - t;
+    for (int x = 0; x < n; ++x) {
+      if (!isx[t][x]) continue;
+      // slot of x before stage t: final bits above t, initial bits from t down
+      const int hi_mask = ~((1 << (bp + 1)) - 1) & (NB - 1);
+      const int pre = (fslot[x] & hi_mask) | (islot[x] & ((1 << (bp + 1)) - 1));
+      const int lo = pre & ~(1 << bp);
+      const int k = ((lo >> (bp + 1)) << bp) | (lo & ((1 << bp) - 1));
+      if (pb[t][x]) oflip[orbit_id[find(x)]] |= (uint64_t)1 << (t * PPS + k);
+    }
+  }
+
+  const int Q = n / 4, KC = M / 4, NT = M / 16;
+  const int FB = S * PPS;  // flip bits per orbit
+  if (KC * FB > 64 || NT * 4 * FB > 64) return false;
+  UProgramImage im;
+  im.prog.S = S;
+  im.prog.M = M;
+  im.prog.n = n;
+  im.prog.dir = direction;
+  im.gcol.assign((size_t)4 * Q, 0);
+  im.scol.assign((size_t)4 * Q, 0);
+  im.flips.assign(8, 0);
+  for (int g = 0; g < 4; ++g) {
+    uint64_t fw = 0;
+    for (int kc = 0; kc < KC; ++kc)
+      for (int b = 0; b < NB; ++b)
+        im.gcol[(size_t)g * Q + kc * NB + b] =
+            direction == 0 ? node_ini[(size_t)(4 * kc + g) * NB + b]
+                           : p.blocks[b].out_pos[4 * kc + g];
+    if (direction == 0)
+      for (int kc = 0; kc < KC; ++kc) fw |= oflip[4 * kc + g] << (kc * FB);
+    for (int nt = 0; nt < NT; ++nt)
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * nt + 4 * g + v;
+        for (int b = 0; b < NB; ++b) {
+          if (direction == 0)
+            im.scol[(size_t)g * Q + (b * NT + nt) * 4 + v] = p.blocks[b].out_pos[c];
+          else
+            im.scol[(size_t)g * Q + (nt * 4 + v) * NB + b] = node_ini[(size_t)c * NB + b];
+        }
+        if (direction == 1) fw |= oflip[c] << ((nt * 4 + v) * FB);
+      }
+    im.flips[2 * g] = (uint32_t)(fw & 0xffffffffu);
+    im.flips[2 * g + 1] = (uint32_t)(fw >> 32);
+  }
+  im.afrag.assign((size_t)NB * NT * KC * 64, 0.0f);
+  for (int b = 0; b < NB; ++b) {
+    const HostBlock &B = p.blocks[b];
+    for (int nt = 0; nt < NT; ++nt)
+      for (int kc = 0; kc < KC; ++kc)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = 16 * nt + lane % 16, k = 4 * kc + lane / 16;
+          // forward: A[c][o] = V_b[pos(node(o,b))][c]; inverse: A[o][k] = V_b[pos(node(o,b))][k]
+          const int o = direction == 0 ? k : row;
+          const int c = direction == 0 ? row : k;
+          const int node = node_fin[(size_t)o * NB + b];
+          im.afrag[((size_t)(b * NT + nt) * KC + kc) * 64 + lane] =
+              (float)(B.scale * B.V[(size_t)pos[node] * M + c]);
+        }
+  }
+  out = std::move(im);
+  return true;
 }
 
 }  // namespace gft

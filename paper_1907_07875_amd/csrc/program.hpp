@@ -28,4 +28,20 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
 
 size_t program_lds_bytes(const DevProgram &P);
 
+// Host image of a register-butterfly program (see UProgram).
+struct UProgramImage {
+  UProgram prog{};
+  std::vector<int32_t> gcol, scol;
+  std::vector<uint32_t> flips;
+  std::vector<float> afrag;
+};
+
+// Build the register-butterfly program of `p` if the plan is a uniform hypercube: every
+// stage pairs every node (no V_Z), 2^S leaf blocks of equal size M (a multiple of 16),
+// and each Haar orbit can be laid out on 2^S register slots so that every stage-t pair
+// differs only in slot bit S-1-t (a 2-colouring per stage; orientation is fixed by a
+// per-orbit sign flip).  The leaf block of a node is its slot after the last stage.
+// Returns false (out untouched) otherwise.
+bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out);
+
 }  // namespace gft

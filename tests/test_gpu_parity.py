@@ -17,9 +17,9 @@ pytestmark = pytest.mark.gpu
 TOL_FP32 = 1e-5
 
 
-def _check_graph(g, X, tol=TOL_FP32):
+def _check_graph(g, X, tol=TOL_FP32, engine="auto"):
     dev = device()
-    plan = G.Plan.from_graph(g)
+    plan = G.Plan.from_graph(g, engine=engine)
     Uhat = gpu_basis(plan, dev)
     lam, Ua = aligned_oracle_basis(g, Uhat)
     Xd = X.astype(np.float64)
@@ -47,18 +47,44 @@ def test_config1_path8_dct2():
     np.testing.assert_allclose(lam, O.path_eigenvalues(8), atol=1e-12)
 
 
+@pytest.mark.parametrize("engine", ["generic", "butterfly"])
 @pytest.mark.parametrize("S", [1, 15, 16, 17, 63, 64, 65, 1000, (1 << 14) + 37])
-def test_config2_grid8x8_ragged(S):
+def test_config2_grid8x8_ragged(S, engine):
     g = wl.config2_graph()
     X = wl.ar1_field(S, 8, 8, 0.95, wl.rng_for(2, S))
-    _check_graph(g, X)
+    _check_graph(g, X, engine=engine)
 
 
-def test_config2_grid8x8_full_size():
+@pytest.mark.parametrize("engine", ["auto", "generic"])
+def test_config2_grid8x8_full_size(engine):
     """2^20 AR(1) signals: the shape and launch configuration the benchmark times."""
     g = wl.config2_graph()
     X = wl.ar1_field(1 << 20, 8, 8, 0.95, wl.rng_for(2))
-    _check_graph(g, X)
+    _check_graph(g, X, engine=engine)
+
+
+@pytest.mark.parametrize("g", [wl.path(32), wl.path(64), wl.cycle(32), wl.cycle_two_stage(64),
+                               wl.grid(4, 16), wl.grid3d(4, 4, 8)],
+                         ids=lambda g: f"{g.name}{g.n}s{len(g.stages)}")
+def test_butterfly_engine_shapes(g):
+    """Uniform hypercube plans on the register-butterfly engine (S = 1, 2, 3 stages)."""
+    X = wl.gaussian(2000, g.n, wl.rng_for(4, g.n, 3))
+    _check_graph(g, X, engine="butterfly")
+
+
+def test_auto_engine_choice():
+    device()
+    assert G.Plan.from_graph(wl.config2_graph()).engine() == "butterfly"
+    assert G.Plan.from_graph(wl.config3_graph()).engine() == "generic"
+    assert G.Plan.from_graph(wl.config2_graph(), engine="generic").engine() == "generic"
+
+
+def test_butterfly_engine_rejects_non_uniform_plan():
+    dev = device()
+    plan = G.Plan.from_graph(wl.config3_graph(), engine="butterfly")
+    with pytest.raises(G.GFTError) as e:
+        plan.forward(torch.zeros((16, 25), device=dev))
+    assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
 
 
 def test_config3_skeleton_fp32():

@@ -125,6 +125,47 @@ def grid(N1: int, N2: Optional[int] = None, name="grid") -> Graph:
     return _graph(N1 * N2, grid_edges(N1, N2), None, None, stages, name)
 
 
+def grid3d(A: int, B: int, C: int, name="grid3d") -> Graph:
+    """Unit-weight 6-connected A x B x C grid, node (a,b,c) -> (a*B + b)*C + c; one
+    reversal stage per axis (c, then b, then a)."""
+    def v(a, b, c):
+        return (a * B + b) * C + c
+    edges = []
+    for a in range(A):
+        for b in range(B):
+            for c in range(C):
+                if c + 1 < C:
+                    edges.append((v(a, b, c), v(a, b, c + 1)))
+                if b + 1 < B:
+                    edges.append((v(a, b, c), v(a, b + 1, c)))
+                if a + 1 < A:
+                    edges.append((v(a, b, c), v(a + 1, b, c)))
+    n = A * B * C
+    stages = []
+    for axis in range(3):
+        phi = identity(n)
+        for a in range(A):
+            for b in range(B):
+                for c in range(C):
+                    t = [a, b, c]
+                    t[2 - axis] = [A, B, C][2 - axis] - 1 - t[2 - axis]
+                    phi[v(a, b, c)] = v(*t)
+        stages.append(phi)
+    return _graph(n, edges, None, None, stages, name)
+
+
+def cycle_two_stage(n: int, name="cycle2") -> Graph:
+    """n-cycle (4 | n) with the reversal and then a reversal inside each half: both halves
+    are symmetric paths (the + half plain, the - half with a self-loop 2 at each end)."""
+    g = cycle(n, name)
+    h = n // 2
+    phi = identity(n)
+    phi[:h] = np.arange(h - 1, -1, -1)
+    phi[h:] = np.arange(n - 1, h - 1, -1)
+    g.stages.append(phi)
+    return g
+
+
 def _halving_chain(m: int):
     """Nested index ranges [0, m), [0, m/2), ... used by the recursive reversal stages."""
     ranges = []
