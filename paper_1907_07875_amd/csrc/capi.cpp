@@ -115,8 +115,6 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     *out = it->second.get();
     return GFT_OK;
   }
-  if (plan->opts.precision != GFT_FP32)
-    return set_error(GFT_ERR_UNSUPPORTED, "this build runs leaf blocks in FP32 only");
   int max_lds = 0, cus = 0;
   e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(shared memory)");
@@ -127,7 +125,10 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   // Register-butterfly engine for single-graph uniform hypercube plans.
   UProgramImage ub[2];
   bool use_bf = false;
-  if (!plan->batch && plan->opts.engine != GFT_ENGINE_GENERIC) {
+  if (plan->opts.engine == GFT_ENGINE_BUTTERFLY && (plan->batch || plan->opts.precision != GFT_FP32))
+    return set_error(GFT_ERR_UNSUPPORTED,
+                     "the register-butterfly engine runs single-graph FP32 plans only");
+  if (!plan->batch && plan->opts.engine != GFT_ENGINE_GENERIC && plan->opts.precision == GFT_FP32) {
     use_bf = build_butterfly(plan->graphs[0], 0, ub[0]) && build_butterfly(plan->graphs[0], 1, ub[1]) &&
              butterfly_supported(ub[0].prog.S, ub[0].prog.M);
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
@@ -140,7 +141,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   for (size_t g = 0; g < plan->graphs.size(); ++g)
     for (int dir = 0; dir < 2; ++dir) {
       ProgramImage im;
-      if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im)) {
+      if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im,
+                         plan->opts.precision)) {
         if (use_bf) continue;  // the butterfly engine serves this graph
         return set_error(GFT_ERR_UNSUPPORTED,
                          "graph " + std::to_string(g) + " (n = " + std::to_string(plan->graphs[g].n) +
@@ -177,7 +179,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   for (size_t i = 0; i < imgs.size(); ++i) {
     DevProgram P = imgs[i].prog;
     P.table = reinterpret_cast<const int32_t *>(base + toff[i]);
-    P.frag = reinterpret_cast<const float *>(base + foff[i]);
+    P.frag = reinterpret_cast<const uint32_t *>(base + foff[i]);
     const int cap = img->num_cus * apply_occupancy(P);
     if (i % 2 == 0) {
       img->fwd.push_back(P);

@@ -19,11 +19,15 @@ struct DevStage {
   int32_t pad;
 };
 
-// A dense leaf block, applied as a [T x K] * [K x N] product on MFMA 16x16x4 f32 tiles.
-// gidx[gidx_off + k], k < 4*kchunks: source column of input k (padding points at a valid
-// column; its matrix row is zero).  sidx[sidx_off + c], c < size: destination column of
-// output c.  The matrix is stored as per-lane fragments: frag[frag_off +
-// ((kc * ntiles) + nt) * 64 + lane] = M[4*kc + lane/16][16*nt + lane%16] (zero padded).
+// A dense leaf block, applied as a [T x K] * [K x N] product on 16x16 MFMA tiles whose K
+// step is KS = 4 (FP32, v_mfma_f32_16x16x4_f32) or 16 (BF16/FP16/split, the 16x16x16
+// MFMAs).  gidx[gidx_off + k], k < KS*kchunks: source column of input k (padding points at
+// a valid column; its matrix row is zero).  sidx[sidx_off + c], c < size: destination
+// column of output c.  The matrix is stored as per-lane fragments, at 32-bit word offset
+// frag_off, one fragment per (kc, nt) in the order (kc * ntiles + nt):
+//   FP32:   1 word per lane:  M[4*kc + lane/16][16*nt + lane%16];
+//   16-bit: 2 words per lane: M[16*kc + 4*(lane/16) + j][16*nt + lane%16], j = 0..3;
+//   split:  4 words per lane: the hi fragment's 2 words, then the lo fragment's 2 words.
 struct DevBlock {
   int32_t size;
   int32_t kchunks;
@@ -49,11 +53,12 @@ struct DevProgram {
   int32_t table_words;  // int32 words of the LDS-resident tables
   int32_t frag_lds;     // 1: the fragments are copied to LDS after the tables (else read
                         // from global memory)
-  int32_t frag_words;   // floats of `frag`
+  int32_t frag_words;   // 32-bit words of `frag`
+  int32_t prec;         // gft_precision of the leaf blocks
   // stages (4 words each) | ops (2 each) | blocks (8 each) | items | gidx | sidx,
   // contiguous; each workgroup copies it to LDS once
   const int32_t *table;
-  const float *frag;
+  const uint32_t *frag;
 };
 
 // Register-butterfly program (uniform hypercube plans): S stages, 2^S leaf blocks of M

@@ -18,6 +18,24 @@
 namespace gft {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// gft_precision values (include/gft.h)
+constexpr int kFP32 = 0, kBF16 = 1, kFP16 = 2, kSPLIT = 3;
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const u32x2 w = {a | (b << 16), c | (d << 16)};
+  return __builtin_bit_cast(bf16x4, w);
+}
 
 constexpr int kThreads = 256;
 constexpr float kSqrt2f = 1.41421356237309504880f;
@@ -157,13 +175,19 @@ __device__ __forceinline__ void haar_stage(const int32_t *st, const int32_t *ops
   }
 }
 
-// Dense leaf blocks: dst[:, sidx] = src[:, gidx] * M for every block, FP32 MFMA.
-// MFMA 16x16x4 f32 operand layout (one 16x16 block): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives D[4*(l/16) + v][l%16] in accumulator element v.
-template <int MT>
+// Dense leaf blocks: dst[:, sidx] = src[:, gidx] * M for every block.
+// MFMA operand layouts (one 16x16 block; D in both: lane l receives D[4*(l/16) + v][l%16]):
+//   16x16x4 f32:  lane l supplies A[l%16][l/16] and B[l/16][l%16];
+//   16x16x16 bf16/f16: lane l supplies A[l%16][4*(l/16) + j] and B[4*(l/16) + j][l%16], j < 4.
+// A = signal values gathered from LDS (rows = signals), B = block-matrix fragments.
+// Split precision: x = x_hi + x_lo in BF16 for both operands, three products
+// hi*hi + hi*lo + lo*hi accumulated in FP32.
+template <int MT, int PREC>
 __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTables &t,
-                                               const float *fragbase, const float *src,
+                                               const uint32_t *fragbase, const float *src,
                                                float *dst) {
+  constexpr int WPL = PREC == kFP32 ? 1 : (PREC == kSPLIT ? 4 : 2);
+  constexpr int KS = PREC == kFP32 ? 4 : 16;
   const int stride = P.stride;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -176,17 +200,54 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
     const int32_t *B = t.blocks + 8 * b;
     const int size = B[0], kchunks = B[1], ntiles = B[2];
     const int32_t *gi = t.gidx + B[3];
-    const float *frag = fragbase + B[5] + nt * 64 + lane;
+    const uint32_t *frag = fragbase + B[5] + (nt * 64 + lane) * WPL;
     floatx4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < kchunks; ++kc) {
-      const float bm = frag[kc * ntiles * 64];
-      const int col = gi[4 * kc + g];
+      const uint32_t *fw = frag + kc * ntiles * 64 * WPL;
+      if constexpr (PREC == kFP32) {
+        const float bm = __uint_as_float(fw[0]);
+        const int col = gi[KS * kc + g];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const float a = src[(16 * m + r) * stride + col];
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bm, acc[m], 0, 0, 0);
+        for (int m = 0; m < MT; ++m) {
+          const float a = src[(16 * m + r) * stride + col];
+          acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bm, acc[m], 0, 0, 0);
+        }
+      } else {
+        const u32x2 bw = {fw[0], fw[1]};
+        int col[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) col[j] = gi[KS * kc + 4 * g + j];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const float *row = src + (16 * m + r) * stride;
+          float x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = row[col[j]];
+          if constexpr (PREC == kFP16) {
+            const halfx4 a = {(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, __builtin_bit_cast(halfx4, bw),
+                                                           acc[m], 0, 0, 0);
+          } else {
+            uint32_t h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h[j] = bf16_bits(x[j]);
+            const bf16x4 ahi = pack_bf16(h[0], h[1], h[2], h[3]);
+            const bf16x4 bhi = __builtin_bit_cast(bf16x4, bw);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[m], 0, 0, 0);
+            if constexpr (PREC == kSPLIT) {
+              uint32_t l[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) l[j] = bf16_bits(x[j] - __uint_as_float(h[j] << 16));
+              const bf16x4 alo = pack_bf16(l[0], l[1], l[2], l[3]);
+              const u32x2 bwl = {fw[2], fw[3]};
+              const bf16x4 blo = __builtin_bit_cast(bf16x4, bwl);
+              acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[m], 0, 0, 0);
+              acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[m], 0, 0, 0);
+            }
+          }
+        }
       }
     }
     const int ncol = 16 * nt + r;
@@ -201,20 +262,20 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
   }
 }
 
-template <int MT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 8 ? 2 : 4))) void gft_apply_f32(DevProgram P, const float *in,
-                                                         float *out, int64_t S) {
+template <int MT, int PREC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 8 ? 2 : 4))) void gft_apply(
+    DevProgram P, const float *in, float *out, int64_t S) {
   extern __shared__ int32_t smem[];
   constexpr int T = 16 * MT;
   const int n = P.n;
   const int stride = P.stride;
   for (int i = threadIdx.x; i < P.table_words; i += kThreads) smem[i] = P.table[i];
   const LdsTables t = carve(P, smem);
-  float *lfrag = reinterpret_cast<float *>(smem + ((P.table_words + 3) & ~3));
+  uint32_t *lfrag = reinterpret_cast<uint32_t *>(smem + ((P.table_words + 3) & ~3));
   if (P.frag_lds)
     for (int i = threadIdx.x; i < P.frag_words; i += kThreads) lfrag[i] = P.frag[i];
-  const float *fragbase = P.frag_lds ? lfrag : P.frag;
-  float *buf0 = lfrag + (P.frag_lds ? ((P.frag_words + 3) & ~3) : 0);
+  const uint32_t *fragbase = P.frag_lds ? lfrag : P.frag;
+  float *buf0 = reinterpret_cast<float *>(lfrag + (P.frag_lds ? ((P.frag_words + 3) & ~3) : 0));
   float *buf1 = buf0 + T * stride;
   const int64_t num_tiles = (S + T - 1) / T;
   auto count_of = [&](int64_t tile) {
@@ -237,7 +298,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf0);
       __syncthreads();
     }
-    block_products<MT>(P, t, fragbase, buf0, buf1);
+    block_products<MT, PREC>(P, t, fragbase, buf0, buf1);
     __syncthreads();
     for (int s = P.num_pre; s < P.num_pre + P.num_post; ++s) {
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf1);
@@ -250,12 +311,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
 
 // ---------------------------------------------------------------------------- launch
 
-template <int MT>
+template <int MT, int PREC>
 static hipError_t launch_mt(const DevProgram &P, const float *in, float *out, int64_t S,
                             hipStream_t stream, int grid_cap) {
   const size_t lds = program_lds_bytes(P);
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)gft_apply_f32<MT>,
+    hipError_t e = hipFuncSetAttribute((const void *)gft_apply<MT, PREC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
@@ -263,32 +324,55 @@ static hipError_t launch_mt(const DevProgram &P, const float *in, float *out, in
   const int64_t tiles = (S + T - 1) / T;
   int grid = (int)(tiles < grid_cap ? tiles : grid_cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(gft_apply_f32<MT>, dim3(grid), dim3(kThreads), lds, stream, P, in, out, S);
+  hipLaunchKernelGGL((gft_apply<MT, PREC>), dim3(grid), dim3(kThreads), lds, stream, P, in, out, S);
   return hipGetLastError();
 }
 
-int apply_occupancy(const DevProgram &P) {
+template <int PREC>
+static int occupancy_p(const DevProgram &P) {
   const size_t lds = program_lds_bytes(P);
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (P.mt) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<1>, kThreads, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<2>, kThreads, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<4>, kThreads, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_f32<8>, kThreads, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<1, PREC>, kThreads, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<2, PREC>, kThreads, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<4, PREC>, kThreads, lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<8, PREC>, kThreads, lds); break;
     default: break;
   }
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
+int apply_occupancy(const DevProgram &P) {
+  switch (P.prec) {
+    case kFP32: return occupancy_p<kFP32>(P);
+    case kBF16: return occupancy_p<kBF16>(P);
+    case kFP16: return occupancy_p<kFP16>(P);
+    case kSPLIT: return occupancy_p<kSPLIT>(P);
+    default: return 1;
+  }
+}
+
+template <int PREC>
+static hipError_t launch_p(const DevProgram &P, const float *in, float *out, int64_t S,
+                           hipStream_t stream, int grid_cap) {
+  switch (P.mt) {
+    case 1: return launch_mt<1, PREC>(P, in, out, S, stream, grid_cap);
+    case 2: return launch_mt<2, PREC>(P, in, out, S, stream, grid_cap);
+    case 4: return launch_mt<4, PREC>(P, in, out, S, stream, grid_cap);
+    case 8: return launch_mt<8, PREC>(P, in, out, S, stream, grid_cap);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_t S,
                         hipStream_t stream, int grid_cap) {
-  switch (P.mt) {
-    case 1: return launch_mt<1>(P, in, out, S, stream, grid_cap);
-    case 2: return launch_mt<2>(P, in, out, S, stream, grid_cap);
-    case 4: return launch_mt<4>(P, in, out, S, stream, grid_cap);
-    case 8: return launch_mt<8>(P, in, out, S, stream, grid_cap);
+  switch (P.prec) {
+    case kFP32: return launch_p<kFP32>(P, in, out, S, stream, grid_cap);
+    case kBF16: return launch_p<kBF16>(P, in, out, S, stream, grid_cap);
+    case kFP16: return launch_p<kFP16>(P, in, out, S, stream, grid_cap);
+    case kSPLIT: return launch_p<kSPLIT>(P, in, out, S, stream, grid_cap);
     default: return hipErrorInvalidValue;
   }
 }

@@ -2,10 +2,51 @@
 #include "program.hpp"
 
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 
 namespace gft {
 
+uint16_t to_bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t to_f16_bits(float x) {
+  // IEEE binary16, round to nearest even (finite inputs of block matrices: |x| <= 1)
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t sign = (u >> 16) & 0x8000u;
+  const int exp = (int)((u >> 23) & 0xff) - 127 + 15;
+  uint32_t mant = u & 0x7fffffu;
+  if (((u >> 23) & 0xff) == 0xff) return (uint16_t)(sign | 0x7c00u | (mant ? 0x200u : 0u));
+  if (exp >= 31) return (uint16_t)(sign | 0x7c00u);
+  if (exp <= 0) {  // subnormal half (or zero)
+    if (exp < -10) return (uint16_t)sign;
+    mant |= 0x800000u;
+    const int shift = 14 - exp;
+    uint32_t h = mant >> shift;
+    const uint32_t rem = mant & ((1u << shift) - 1), half = 1u << (shift - 1);
+    if (rem > half || (rem == half && (h & 1u))) ++h;
+    return (uint16_t)(sign | h);
+  }
+  uint32_t h = ((uint32_t)exp << 10) | (mant >> 13);
+  const uint32_t rem = mant & 0x1fffu;
+  if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;
+  return (uint16_t)(sign | h);
+}
+
 namespace {
+
+float bf16_to_float(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
 
 uint32_t magic_for(uint32_t d) {
   // ceil(2^32 / d): floor(e * magic / 2^32) == e / d whenever e * d < 2^32.
@@ -22,7 +63,7 @@ size_t program_lds_bytes(const DevProgram &P) {
 }
 
 bool build_program(const GraphPlan &p, int direction, int tile_override, size_t lds_budget,
-                   ProgramImage &out) {
+                   ProgramImage &out, int precision) {
   const int n = p.n;
   DevProgram &P = out.prog;
   P = DevProgram{};
@@ -31,8 +72,11 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   P.magic_n = magic_for((uint32_t)n);
 
   std::vector<int32_t> stages, ops, blocks, items, gidx, sidx;
-  std::vector<float> &frag = out.frag;
+  std::vector<uint32_t> &frag = out.frag;
   frag.clear();
+  P.prec = precision;
+  const int KS = precision == GFT_FP32 ? 4 : 16;                  // K per MFMA
+  const int WPL = precision == GFT_FP32 ? 1 : (precision == GFT_SPLIT_BF16 ? 4 : 2);
 
   // Haar stages: forward in plan order before the blocks; inverse in reverse after them.
   const int ns = (int)p.stages.size();
@@ -63,22 +107,45 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   for (int b = 0; b < (int)p.blocks.size(); ++b) {
     const HostBlock &B = p.blocks[b];
     const int sz = B.size;
-    const int kchunks = (sz + 3) / 4;
+    const int kchunks = (sz + KS - 1) / KS;
     const int ntiles = (sz + 15) / 16;
     const int g_off = (int)gidx.size(), s_off = (int)sidx.size(), f_off = (int)frag.size();
     const std::vector<int32_t> &kin = direction == 0 ? B.nodes : B.out_pos;
     const std::vector<int32_t> &nout = direction == 0 ? B.out_pos : B.nodes;
-    for (int k = 0; k < 4 * kchunks; ++k) gidx.push_back(kin[k < sz ? k : 0]);
+    for (int k = 0; k < KS * kchunks; ++k) gidx.push_back(kin[k < sz ? k : 0]);
     for (int c = 0; c < sz; ++c) sidx.push_back(nout[c]);
-    frag.resize(frag.size() + (size_t)kchunks * ntiles * 64, 0.0f);
+    auto mat = [&](int k, int c) -> double {   // M[k][c] of this direction, zero padded
+      if (k >= sz || c >= sz) return 0.0;
+      return B.scale * (direction == 0 ? B.V[(size_t)k * sz + c] : B.V[(size_t)c * sz + k]);
+    };
+    frag.resize(frag.size() + (size_t)kchunks * ntiles * 64 * WPL, 0u);
     for (int kc = 0; kc < kchunks; ++kc)
       for (int nt = 0; nt < ntiles; ++nt)
         for (int lane = 0; lane < 64; ++lane) {
-          const int k = 4 * kc + lane / 16, c = 16 * nt + lane % 16;
-          double v = 0.0;
-          if (k < sz && c < sz)
-            v = direction == 0 ? B.V[(size_t)k * sz + c] : B.V[(size_t)c * sz + k];
-          frag[f_off + ((size_t)kc * ntiles + nt) * 64 + lane] = (float)(B.scale * v);
+          uint32_t *w = &frag[f_off + (((size_t)kc * ntiles + nt) * 64 + lane) * WPL];
+          const int c = 16 * nt + lane % 16;
+          if (precision == GFT_FP32) {
+            const float v = (float)mat(4 * kc + lane / 16, c);
+            std::memcpy(w, &v, 4);
+            continue;
+          }
+          uint16_t hi[4], lo[4];
+          for (int j = 0; j < 4; ++j) {
+            const double v = mat(16 * kc + 4 * (lane / 16) + j, c);
+            if (precision == GFT_FP16) {
+              hi[j] = to_f16_bits((float)v);
+              lo[j] = 0;
+            } else {
+              hi[j] = to_bf16_bits((float)v);
+              lo[j] = to_bf16_bits((float)(v - (double)bf16_to_float(hi[j])));
+            }
+          }
+          w[0] = (uint32_t)hi[0] | ((uint32_t)hi[1] << 16);
+          w[1] = (uint32_t)hi[2] | ((uint32_t)hi[3] << 16);
+          if (precision == GFT_SPLIT_BF16) {
+            w[2] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+            w[3] = (uint32_t)lo[2] | ((uint32_t)lo[3] << 16);
+          }
         }
     blocks.insert(blocks.end(), {sz, kchunks, ntiles, g_off, s_off, f_off, 0, 0});
     for (int nt = 0; nt < ntiles; ++nt) items.push_back((b << 16) | nt);

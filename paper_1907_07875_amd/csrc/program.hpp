@@ -13,7 +13,7 @@ namespace gft {
 struct ProgramImage {
   DevProgram prog{};          // pointers left null until upload
   std::vector<int32_t> table;
-  std::vector<float> frag;
+  std::vector<uint32_t> frag; // 32-bit words (FP32 values or packed 16-bit pairs)
 };
 
 // Largest LDS bytes a workgroup of the apply kernel may use.
@@ -24,7 +24,11 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // M-tiles whose LDS footprint fits `lds_budget` bytes.  Returns false if even one M-tile
 // does not fit.
 bool build_program(const GraphPlan &p, int direction, int tile_override, size_t lds_budget,
-                   ProgramImage &out);
+                   ProgramImage &out, int precision = GFT_FP32);
+
+// Round-to-nearest-even conversions used for the 16-bit block fragments.
+uint16_t to_bf16_bits(float x);
+uint16_t to_f16_bits(float x);
 
 size_t program_lds_bytes(const DevProgram &P);
 
