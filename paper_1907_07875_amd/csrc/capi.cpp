@@ -37,11 +37,16 @@ struct DeviceImage {
   int device = -1;
   int num_cus = 1;
   void *mem = nullptr;
+  void *mem2 = nullptr;
   std::vector<DevProgram> fwd, inv;
   std::vector<int> grid_cap_fwd, grid_cap_inv;
   // register-butterfly programs (single-graph plans whose shape qualifies)
   bool butterfly = false;
   UProgram bfwd{}, binv{};
+  // batch plans: device arrays of the G forward and G inverse programs
+  const DevProgram *dev_fwd = nullptr, *dev_inv = nullptr;
+  size_t batch_lds = 0;
+  int batch_grid = 1;
 };
 
 // Byte blob assembled on the host and uploaded in one copy; offsets are 256-aligned.
@@ -71,6 +76,7 @@ struct gft_plan_s {
         if (hipGetDevice(&cur) == hipSuccess) {
           (void)hipSetDevice(kv.first);
           (void)hipFree(kv.second->mem);
+          if (kv.second->mem2) (void)hipFree(kv.second->mem2);
           (void)hipSetDevice(cur);
         }
       }
@@ -120,7 +126,14 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(shared memory)");
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(CU count)");
-  const size_t budget = std::min<size_t>(kMaxLdsBytes, (size_t)max_lds);
+  size_t budget = std::min<size_t>(kMaxLdsBytes, (size_t)max_lds);
+  const int G = (int)plan->graphs.size();
+  if (plan->batch) {
+    // the batch kernel keeps G+1 element offsets and 257 partial sums in LDS as well
+    const size_t fixed = batch_lds_bytes(G, 0) + 8 * 257 + 256;
+    if (fixed + 4096 > budget) return set_error(GFT_ERR_UNSUPPORTED, "too many graphs in one batch plan");
+    budget -= fixed;
+  }
 
   // Register-butterfly engine for single-graph uniform hypercube plans.
   UProgramImage ub[2];
@@ -199,6 +212,35 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       dst[d]->afrag = reinterpret_cast<const float *>(base + uoff[d][2]);
       dst[d]->flips = reinterpret_cast<const uint32_t *>(base + uoff[d][3]);
     }
+  }
+  if (plan->batch) {
+    std::vector<DevProgram> arr;
+    size_t maxlds = 0;
+    for (int g = 0; g < G; ++g) {
+      arr.push_back(img->fwd[g]);
+      maxlds = std::max(maxlds, program_lds_bytes(img->fwd[g]));
+    }
+    for (int g = 0; g < G; ++g) {
+      arr.push_back(img->inv[g]);
+      maxlds = std::max(maxlds, program_lds_bytes(img->inv[g]));
+    }
+    void *parr = nullptr;
+    e = hipMalloc(&parr, arr.size() * sizeof(DevProgram));
+    if (e != hipSuccess) {
+      (void)hipFree(img->mem);
+      return set_error(GFT_ERR_OOM, "hipMalloc of the batch program array failed");
+    }
+    e = hipMemcpy(parr, arr.data(), arr.size() * sizeof(DevProgram), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(parr);
+      (void)hipFree(img->mem);
+      return set_error(GFT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    img->mem2 = parr;
+    img->dev_fwd = static_cast<const DevProgram *>(parr);
+    img->dev_inv = img->dev_fwd + G;
+    img->batch_lds = batch_lds_bytes(G, maxlds);
+    img->batch_grid = img->num_cus * batch_occupancy(plan->opts.precision, img->batch_lds);
   }
   *out = img.get();
   plan->images[dev] = std::move(img);
@@ -310,14 +352,35 @@ gft_status gft_inverse(gft_plan_t plan, const void *y, void *x, int64_t num_sign
   return apply(plan, 1, y, x, num_signals, stream);
 }
 
-gft_status gft_forward_batch(gft_plan_t plan, const void *, void *, const int64_t *, int64_t, void *) {
+static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *out,
+                              const int64_t *signal_offsets, int64_t total_elements, void *stream) {
   if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
-  return set_error(GFT_ERR_UNSUPPORTED, "batch apply is not built yet");
+  if (!plan->batch) return set_error(GFT_ERR_INVALID_ARG, "single-graph plans use gft_forward / gft_inverse");
+  if (total_elements < 0) return set_error(GFT_ERR_INVALID_ARG, "total_elements must be >= 0");
+  if (total_elements == 0) return ok();
+  if (!signal_offsets) return set_error(GFT_ERR_INVALID_ARG, "signal_offsets is NULL");
+  if (total_elements > (int64_t(1) << 40)) return set_error(GFT_ERR_INVALID_ARG, "total_elements too large");
+  gft_status st = check_buffers(in, out, total_elements * 4);
+  if (st != GFT_OK) return st;
+  DeviceImage *img = nullptr;
+  st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  hipError_t e = launch_apply_batch(plan->opts.precision, dir == 0 ? img->dev_fwd : img->dev_inv,
+                                    (int)plan->graphs.size(), signal_offsets, total_elements,
+                                    static_cast<const float *>(in), static_cast<float *>(out),
+                                    img->batch_lds, img->batch_grid, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ok();
 }
 
-gft_status gft_inverse_batch(gft_plan_t plan, const void *, void *, const int64_t *, int64_t, void *) {
-  if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
-  return set_error(GFT_ERR_UNSUPPORTED, "batch apply is not built yet");
+gft_status gft_forward_batch(gft_plan_t plan, const void *x, void *y, const int64_t *signal_offsets,
+                             int64_t total_elements, void *stream) {
+  return apply_batch(plan, 0, x, y, signal_offsets, total_elements, stream);
+}
+
+gft_status gft_inverse_batch(gft_plan_t plan, const void *y, void *x, const int64_t *signal_offsets,
+                             int64_t total_elements, void *stream) {
+  return apply_batch(plan, 1, y, x, signal_offsets, total_elements, stream);
 }
 
 gft_status gft_plan_prepare(gft_plan_t plan) {

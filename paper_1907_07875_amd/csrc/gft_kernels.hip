@@ -309,6 +309,143 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
   }
 }
 
+// ---------------------------------------------------------------------------- mixed batch
+
+// One tile of T = 16*mt signals of one program: load -> pre stages -> blocks -> post stages
+// -> store.  The program's tables (and fragments, when LDS-resident) are already in LDS.
+template <int MT, int PREC>
+__device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t,
+                                         const uint32_t *fragbase, const float *gin,
+                                         float *gout, int count, float *buf0, float *buf1,
+                                         const floatx4 *spare) {
+  constexpr int T = 16 * MT;
+  floatx4 pre[kPrefetch];
+  issue_tile(gin, count, spare, pre);
+  commit_tile(gin, count, T, P.n, P.stride, P.magic_n, pre, buf0);
+  __syncthreads();
+  for (int s = 0; s < P.num_pre; ++s) {
+    haar_stage(t.stages + 4 * s, t.ops, T, P.stride, buf0);
+    __syncthreads();
+  }
+  block_products<MT, PREC>(P, t, fragbase, buf0, buf1);
+  __syncthreads();
+  for (int s = P.num_pre; s < P.num_pre + P.num_post; ++s) {
+    haar_stage(t.stages + 4 * s, t.ops, T, P.stride, buf1);
+    __syncthreads();
+  }
+  store_tile(buf1, count, P.n, P.stride, P.magic_n, gout);
+  __syncthreads();
+}
+
+// Many graphs in one persistent launch.  Graph g owns signals [off[g], off[g+1]) and its
+// data starts at element elem[g] = sum_{h<g} (off[h+1]-off[h]) * n_h of in/out; each
+// workgroup first rebuilds elem[] in LDS from the device offsets (no host sync, no
+// workspace), then takes the tiles whose first element falls in its 1/gridDim share of
+// [0, elem[G]): a byte-balanced, contiguous partition.  Graphs whose data would end past
+// total_elems are skipped.  A workgroup reloads a program's tables into LDS only when it
+// moves to another graph.
+template <int PREC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void gft_apply_batch(
+    const DevProgram *__restrict__ progs, int G, const int64_t *__restrict__ sig_off,
+    int64_t total_elems, const float *in, float *out) {
+  extern __shared__ int32_t smem[];
+  int64_t *elem = reinterpret_cast<int64_t *>(smem);          // G + 1 entries
+  int32_t *area = smem + 2 * ((G + 2) & ~1);                   // program area
+  // per-thread partial sums over contiguous chunks of graphs, then a serial scan of the
+  // kThreads partials by thread 0 and a second pass
+  __shared__ int64_t part[kThreads + 1];
+  const int per = (G + kThreads - 1) / kThreads;
+  const int g0 = threadIdx.x * per, g1 = g0 + per < G ? g0 + per : G;
+  int64_t acc = 0;
+  for (int g = g0; g < g1; ++g) {
+    const int64_t ns = sig_off[g + 1] - sig_off[g];
+    acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kThreads; ++i) {
+      const int64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    part[kThreads] = run;
+  }
+  __syncthreads();
+  acc = part[threadIdx.x];
+  for (int g = g0; g < g1; ++g) {
+    elem[g] = acc;
+    const int64_t ns = sig_off[g + 1] - sig_off[g];
+    acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+  }
+  if (threadIdx.x == 0) elem[G] = part[kThreads];
+  __syncthreads();
+
+  const int64_t E = elem[G];
+  const int64_t W = gridDim.x;
+  const int64_t e0 = (int64_t)(((__int128)E * blockIdx.x) / W);
+  const int64_t e1 = (int64_t)(((__int128)E * (blockIdx.x + 1)) / W);
+  if (e0 >= e1) return;
+  // graph holding element e0: last g with elem[g] <= e0
+  int lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (elem[mid] <= e0) lo = mid;
+    else hi = mid;
+  }
+  int g = lo;
+  int loaded = -1;
+  DevProgram P{};
+  LdsTables tabs{};
+  const uint32_t *fragbase = nullptr;
+  float *buf0 = nullptr, *buf1 = nullptr;
+  int64_t t = -1;
+  while (g < G) {
+    const int64_t gbeg = elem[g], gend = elem[g + 1];
+    if (gend <= gbeg || gend > total_elems) {
+      ++g;
+      t = 0;
+      if (elem[g < G ? g : G] >= e1) break;
+      continue;
+    }
+    const int n = progs[g].n;
+    const int T = 16 * progs[g].mt;
+    const int64_t tile_elems = (int64_t)T * n;
+    if (t < 0) t = (e0 - gbeg + tile_elems - 1) / tile_elems;   // first tile starting >= e0
+    const int64_t start = gbeg + t * tile_elems;
+    if (start >= gend) {   // this graph has no tile left for us: the next one may
+      ++g;
+      t = 0;
+      continue;
+    }
+    if (start >= e1) break;
+    if (loaded != g) {
+      P = progs[g];
+      for (int i = threadIdx.x; i < P.table_words; i += kThreads) area[i] = P.table[i];
+      tabs = carve(P, area);
+      uint32_t *lfrag = reinterpret_cast<uint32_t *>(area + ((P.table_words + 3) & ~3));
+      if (P.frag_lds)
+        for (int i = threadIdx.x; i < P.frag_words; i += kThreads) lfrag[i] = P.frag[i];
+      fragbase = P.frag_lds ? lfrag : P.frag;
+      buf0 = reinterpret_cast<float *>(lfrag + (P.frag_lds ? ((P.frag_words + 3) & ~3) : 0));
+      buf1 = buf0 + T * P.stride;
+      loaded = g;
+      __syncthreads();
+    }
+    const int64_t rem = gend - start;
+    const int count = (int)(rem < tile_elems ? rem : tile_elems);
+    const floatx4 *spare = reinterpret_cast<const floatx4 *>(P.table);
+    switch (P.mt) {
+      case 1: run_tile<1, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
+      case 2: run_tile<2, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
+      case 4: run_tile<4, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
+      default: run_tile<8, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
+    }
+    ++t;
+  }
+}
+
 // ---------------------------------------------------------------------------- launch
 
 template <int MT, int PREC>
@@ -373,6 +510,50 @@ hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_
     case kBF16: return launch_p<kBF16>(P, in, out, S, stream, grid_cap);
     case kFP16: return launch_p<kFP16>(P, in, out, S, stream, grid_cap);
     case kSPLIT: return launch_p<kSPLIT>(P, in, out, S, stream, grid_cap);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t batch_lds_bytes(int G, size_t max_program_lds) {
+  return 8 * (size_t)((G + 2) & ~1) + max_program_lds;
+}
+
+template <int PREC>
+static hipError_t launch_batch_p(const DevProgram *progs, int G, const int64_t *sig_off,
+                                 int64_t total_elems, const float *in, float *out,
+                                 size_t lds, int grid, hipStream_t stream) {
+  if (lds + 8 * (kThreads + 1) > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((gft_apply_batch<PREC>), dim3(grid), dim3(kThreads), lds, stream, progs, G,
+                     sig_off, total_elems, in, out);
+  return hipGetLastError();
+}
+
+int batch_occupancy(int prec, size_t lds) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (prec) {
+    case kFP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP32>, kThreads, lds); break;
+    case kBF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kBF16>, kThreads, lds); break;
+    case kFP16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP16>, kThreads, lds); break;
+    case kSPLIT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kSPLIT>, kThreads, lds); break;
+    default: break;
+  }
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const int64_t *sig_off,
+                              int64_t total_elems, const float *in, float *out, size_t lds,
+                              int grid, hipStream_t stream) {
+  switch (prec) {
+    case kFP32: return launch_batch_p<kFP32>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
+    case kBF16: return launch_batch_p<kBF16>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
+    case kFP16: return launch_batch_p<kFP16>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
+    case kSPLIT: return launch_batch_p<kSPLIT>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

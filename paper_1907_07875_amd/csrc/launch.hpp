@@ -16,6 +16,13 @@ hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_
 // Resident workgroups per CU of the apply kernel for this program's LDS footprint.
 int apply_occupancy(const DevProgram &P);
 
+// Mixed batch: G programs (device array `progs`) in one persistent launch.
+size_t batch_lds_bytes(int G, size_t max_program_lds);
+int batch_occupancy(int prec, size_t lds);
+hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const int64_t *sig_off,
+                              int64_t total_elems, const float *in, float *out, size_t lds,
+                              int grid, hipStream_t stream);
+
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(int S, int M);
 hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,
