@@ -1,17 +1,24 @@
-"""Benchmark of the fast GFT on one MI355X: 8x8 grid, 2^20 AR(1) signals, FP32.
+"""Benchmark of the fast GFT on one MI355X.
 
+Default workload (the headline line): 8x8 4-neighbour grid, 2^20 AR(1) signals, FP32.
 One step = forward GFT (y = U^T x) + inverse GFT (x' = U y) of the whole batch, inputs
-resident in HBM.  ``value`` counts the values both transforms produce (2 * S * n) per
-second.  Also reported: the dominant kernel's achieved HBM bandwidth against the 8 TB/s
-peak (HIP events on the launch stream), the dense-GFT GEMM (torch.matmul, FP32, no TF32)
-on the same GPU and basis, and the FP64 oracle timed on host cores on a bounded sample.
+resident in HBM; ``value`` counts the values both transforms produce (2 * S * n) per
+second.  Also reported: the dominant (forward) kernel's achieved HBM bandwidth against the
+8 TB/s peak (HIP events on the launch stream), the dense-GFT GEMM (torch.matmul, FP32 and
+BF16) on the same GPU and basis, a plain device copy of the same bytes, and the FP64
+oracle timed on host cores on a bounded sample (with the GPU's relative error there).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Other workloads (``--workload``): ``skeleton`` (25-joint skeleton, 16384 x 3 x 300
+signals, BF16 leaf blocks) and ``mixed`` (the ~150-graph uneven batch, one persistent
+launch per direction).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid8x8]
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -22,15 +29,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM roofline"
 
-# HBM bytes per forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the same
-# counters on a 256 MiB device copy (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for
-# the kernel source it was measured on: reported as null once that file changes.
+# HBM bytes per forward launch of the 8x8-grid workload from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE, scaled by the same counters on a 256 MiB device copy
+# (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for the kernel source it was measured
+# on: reported as null once that file changes.
 PROFILED_TRAFFIC = {"source": "paper_1907_07875_amd/csrc/gft_butterfly.hip",
-                    "sha256_16": "80803b11fea3051c", "bytes_per_launch": 2.0 * 131134 * 1024 + 262144 * 1024}
-S_FULL = 1 << 20
-N1 = N2 = 8
-RHO = 0.95
+                    "sha256_16": "80803b11fea3051c",
+                    "bytes_per_launch": 2.0 * 131134 * 1024 + 262144 * 1024}
 
 
 def parse():
@@ -38,48 +45,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--signals", type=int, default=S_FULL)
+    ap.add_argument("--workload", default="grid8x8", choices=["grid8x8", "skeleton", "mixed"])
+    ap.add_argument("--signals", type=int, default=None, help="override the signal count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "split_bf16"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain device copy of the input size (counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(X_sample, Y_gpu_sample, graph, basis_gpu):
-    """FP64 oracle on the host: eigendecomposition + dense apply, forward and inverse."""
-    import numpy as np
-    from oracle import gft_oracle as O
+def _threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
-        threads = os.cpu_count() or 1
-    Xd = X_sample.astype(np.float64)
-    t0 = time.perf_counter()
-    L = O.laplacian_of(graph)
-    lam, U = O.gft(L)
-    reps = 0
-    while True:
-        C = O.forward(Xd, U)
-        Xr = O.inverse(C, U)
-        reps += 1
-        if time.perf_counter() - t0 > 12.0:
-            break
-    dt = time.perf_counter() - t0
-    values = 2.0 * Xd.shape[0] * Xd.shape[1] * reps
-    # relative error of the GPU's forward on this sample, oracle basis aligned to the GPU's
-    Ua, min_sv = O.align(U, basis_gpu, lam)
-    err = O.relative_error(Y_gpu_sample, O.forward(Xd, Ua))
-    return {
-        "value": values / dt, "unit": "coeffs/s", "cores": int(threads), "kind": "oracle",
-        "sample": f"{Xd.shape[0]} signals of the same AR(1) workload (first rows of the batch), "
-                  f"Laplacian + eigh once then {reps} x (forward + inverse) FP64 NumPy/LAPACK, "
-                  f"{dt:.1f} s",
-        "gpu_forward_rel_err_vs_oracle": err, "gpu_basis_min_singular_value": min_sv,
-        "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
-    }
+        return os.cpu_count() or 1
 
 
 def _cpu_model():
@@ -92,26 +74,95 @@ def _cpu_model():
     return "unknown"
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU: every signal is "
-                          "independent, so N GPUs would each run this same kernel on 1/N of the "
-                          "batch with no exchange; multi-GPU runs are not part of this build"}))
-        sys.exit(2)
+def cpu_baseline(samples, desc):
+    """FP64 oracle on the host on a bounded sample: Laplacian + eigh once per graph, then
+    forward + inverse repeatedly for ~12 s; also the GPU's relative error on the sample.
 
+    samples: list of (graph, X_sample [s, n] float32, Y_gpu_sample [s, n], plan_basis).
+    """
     import numpy as np
+    from oracle import gft_oracle as O
+    t0 = time.perf_counter()
+    bases = []
+    for g, X, _, _ in samples:
+        lam, U = O.gft(O.laplacian_of(g))
+        bases.append((lam, U, X.astype(np.float64)))
+    reps, values = 0, 0.0
+    while True:
+        for lam, U, Xd in bases:
+            C = O.forward(Xd, U)
+            O.inverse(C, U)
+            values += 2.0 * Xd.size
+        reps += 1
+        if time.perf_counter() - t0 > 12.0:
+            break
+    dt = time.perf_counter() - t0
+    num = den = 0.0
+    min_sv = 1.0
+    for (g, X, Yg, Ub), (lam, U, Xd) in zip(samples, bases):
+        Ua, sv = O.align(U, Ub, lam)
+        min_sv = min(min_sv, sv)
+        ref = O.forward(Xd, Ua)
+        num += float(np.sum((Yg - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+    return {
+        "value": values / dt, "unit": "coeffs/s", "cores": int(_threads()), "kind": "oracle",
+        "sample": f"{desc}; Laplacian + eigh once per graph, then {reps} x (forward + inverse) "
+                  f"FP64 NumPy/LAPACK, {dt:.1f} s",
+        "gpu_forward_rel_err_vs_oracle": (num / den) ** 0.5 if den > 0 else 0.0,
+        "plan_basis_min_singular_value": min_sv,
+        "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+    }
+
+
+def avg_ms(torch, stream, fn, reps):
+    """Average duration of `reps` back-to-back launches, by HIP events on `stream`."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(reps):
+        fn(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_steps(torch, stream, fwd, inv, steps, warmup):
+    """Warm up, then time `steps` steps of forward + inverse (wall clock, synchronised on
+    both sides) with HIP events around every forward launch."""
+    import numpy as np
+    for i in range(warmup):
+        fwd(i)
+        inv(i)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        fwd(i)
+        evs[i][1].record(stream)
+        inv(i)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return ms_step, fwd_ms
+
+
+def _c(ptr):
+    return ctypes.c_void_p(ptr)
+
+
+def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, sample_desc,
+                 kernel_names=None):
+    """Shared body of the single-graph workloads."""
     import torch
 
     import paper_1907_07875_amd as G
-    import workloads as wl
 
     dev = torch.device("cuda:0")
-    S, n = args.signals, N1 * N2
-    X = wl.ar1_field(S, N1, N2, RHO, wl.rng_for(2))
-    xa = torch.from_numpy(X).to(dev)
+    S, n = X_host.shape
+    xa = torch.from_numpy(X_host).to(dev)
     xb = torch.roll(xa, shifts=1, dims=0).contiguous()   # second buffer: defeats the 256 MB cache
-
     if args.profile_copy:
         out = torch.empty_like(xa)
         for _ in range(max(1, args.steps)):
@@ -120,143 +171,217 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * xa.numel() * 4}))
         return
 
-    graph = wl.config2_graph()
-    plan = G.Plan.from_graph(graph, engine=args.engine)
+    plan = G.Plan.from_graph(graph, engine=args.engine, precision=precision)
     plan.prepare()
-    engine = plan.engine()
-    kernel_name = "gft_butterfly_f32<2,16,0>" if engine == "butterfly" else "gft_apply_f32<4>"
+    eng = plan.engine()
     stream = torch.cuda.current_stream()
-    ya, yb = torch.empty_like(xa), torch.empty_like(xa)
-    xr = torch.empty_like(xa)
+    ya, yb, xr = torch.empty_like(xa), torch.empty_like(xa), torch.empty_like(xa)
     bufs = [(xa, ya), (xb, yb)]
+    # the timed loops call the C ABI directly with pre-marshalled arguments, so that host
+    # overhead between the timing events and the launches stays at a few microseconds
+    lib, h, sp = G.load_library(), plan.handle, _c(int(stream.cuda_stream))
+    P = {id(t): _c(t.data_ptr()) for t in (xa, xb, ya, yb, xr)}
 
-    # The timed loops call the C ABI directly with pre-marshalled arguments, so that host
-    # overhead between the timing events and the launches stays at a few microseconds.
-    lib = G.load_library()
-    hplan = plan.handle
-    sptr = ctypes.c_void_p(int(stream.cuda_stream))
-    ptr = {id(t): ctypes.c_void_p(t.data_ptr()) for t in (xa, xb, ya, yb, xr)}
-
-    def fwd(x, y):
-        st = lib.gft_forward(hplan, ptr[id(x)], ptr[id(y)], S, sptr)
-        if st:
-            G._check(st)
-
-    def inv(y, x):
-        st = lib.gft_inverse(hplan, ptr[id(y)], ptr[id(x)], S, sptr)
-        if st:
-            G._check(st)
-
-    def step(i, ev=None):
+    def fwd(i):
         x, y = bufs[i & 1]
-        if ev is not None:
-            ev[0].record(stream)
-        fwd(x, y)
-        if ev is not None:
-            ev[1].record(stream)
-        inv(y, xr)
+        st = lib.gft_forward(h, P[id(x)], P[id(y)], S, sp)
+        if st:
+            G._check(st)
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fwd_ms = [a.elapsed_time(b) for a, b in evs]
-    fwd_avg_ms = float(np.mean(fwd_ms))
-    bytes_per_launch = 2.0 * S * n * 4           # read x, write y (algorithmic)
-    achieved = bytes_per_launch / (fwd_avg_ms * 1e-3) / 1e9
-    value = 2.0 * S * n / (ms_per_step * 1e-3)
+    def inv(i):
+        st = lib.gft_inverse(h, P[id(bufs[i & 1][1])], P[id(xr)], S, sp)
+        if st:
+            G._check(st)
 
-    # inverse kernel time on its own
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(args.steps):
-        inv(bufs[i & 1][1], xr)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    inv_avg_ms = e0.elapsed_time(e1) / args.steps
-
-    # plain device copy of the same bytes: the bandwidth a streaming kernel can reach here
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for i in range(3):
-        bufs[i & 1][1].copy_(bufs[i & 1][0])
-    c0.record(stream)
-    for i in range(args.steps):
-        bufs[i & 1][1].copy_(bufs[i & 1][0])
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_ms = c0.elapsed_time(c1) / args.steps
+    ms_step, fwd_ms = run_steps(torch, stream, fwd, inv, args.steps, args.warmup)
+    inv_ms = avg_ms(torch, stream, inv, args.steps)
+    copy_ms = avg_ms(torch, stream, lambda i: bufs[i & 1][1].copy_(bufs[i & 1][0]), args.steps)
+    bytes_per_launch = 2.0 * S * n * 4
+    achieved = bytes_per_launch / (fwd_ms * 1e-3) / 1e9
     copy_gbs = bytes_per_launch / (copy_ms * 1e-3) / 1e9
+    kname = (kernel_names or {}).get(eng, f"{eng} engine kernel")
 
-    import hashlib
     traffic = None
     try:
         src = open(os.path.join(ROOT, PROFILED_TRAFFIC["source"]), "rb").read()
-        if engine == "butterfly" and hashlib.sha256(src).hexdigest()[:16] == PROFILED_TRAFFIC["sha256_16"]:
+        if (args.workload == "grid8x8" and eng == "butterfly" and S == 1 << 20
+                and hashlib.sha256(src).hexdigest()[:16] == PROFILED_TRAFFIC["sha256_16"]):
             traffic = PROFILED_TRAFFIC["bytes_per_launch"]
     except OSError:
         pass
 
     result = {
-        "metric": "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM roofline",
-        "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "grid8x8_ar1_fwd_inv", "graph": "8x8 4-neighbour grid, unit weights",
-                   "stages": "LR then UD (2 x 32 Haar units), 4 leaf blocks of 16",
-                   "signals": S, "n": n, "rho": RHO, "values_per_step": 2 * S * n,
-                   "precision": "fp32"},
+        "metric": METRIC,
+        "value": 2.0 * S * n / (ms_step * 1e-3), "unit": "coeffs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else f"f32 io, {precision} blocks, f32 acc",
+        "data": "synthetic",
+        "config": dict(workload_cfg, signals=S, n=n, values_per_step=2 * S * n, precision=precision),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel_name + " (forward)", "engine": engine,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": fwd_avg_ms},
-        "forward_coeffs_per_s": S * n / (fwd_avg_ms * 1e-3),
-        "inverse_values_per_s": S * n / (inv_avg_ms * 1e-3),
-        "inverse_avg_launch_ms": inv_avg_ms,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
+                     "kernel": kname + " (forward)", "engine": eng,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms},
+        "forward_coeffs_per_s": S * n / (fwd_ms * 1e-3),
+        "inverse_values_per_s": S * n / (inv_ms * 1e-3), "inverse_avg_launch_ms": inv_ms,
         "copy_reference": {"GB_per_s": copy_gbs, "avg_launch_ms": copy_ms,
                            "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
                            "forward_frac_of_copy": achieved / copy_gbs},
     }
 
     if not args.no_dense:
-        # dense GFT as one GEMM on the same GPU, same basis, FP32 without TF32
+        # dense GFT as one GEMM on the same GPU, same basis (rows of U = forward(e_i))
         torch.backends.cuda.matmul.allow_tf32 = False
-        eye = torch.eye(n, device=dev)
-        Ud = G.gft_forward(plan, eye)                 # rows of U^T e_i = rows of U
-        UdT = Ud.t().contiguous()
-        for _ in range(3):
-            torch.matmul(xa, Ud, out=ya)
-            torch.matmul(ya, UdT, out=xr)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            x, y = bufs[i & 1]
-            torch.matmul(x, Ud, out=y)
-            torch.matmul(y, UdT, out=xr)
-        torch.cuda.synchronize()
-        dms = (time.perf_counter() - t0) * 1e3 / args.steps
-        yf = G.gft_forward(plan, xa)
-        diff = (torch.matmul(xa, Ud) - yf).double().norm() / yf.double().norm()
-        result["dense_gemm"] = {"value": 2.0 * S * n / (dms * 1e-3), "unit": "coeffs/s",
-                                "ms_per_step": dms, "impl": "torch.matmul FP32 (hipBLASLt/rocBLAS), no TF32",
-                                "rel_diff_vs_fast": float(diff)}
-        result["speedup_vs_dense"] = result["value"] / result["dense_gemm"]["value"]
+        Ud = G.gft_forward(plan, torch.eye(n, device=dev))
+        dense = {}
+        for dt_name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+            U1 = Ud.to(dt).contiguous()
+            U2 = Ud.t().contiguous().to(dt)
+            xs = [b[0].to(dt) for b in bufs]
+            ys = [torch.empty_like(xs[0]) for _ in range(2)]
+            xo = torch.empty_like(xs[0])
+
+            def dfwd(i):
+                torch.matmul(xs[i & 1], U1, out=ys[i & 1])
+
+            def dinv(i):
+                torch.matmul(ys[i & 1], U2, out=xo)
+
+            d_step, d_fwd = run_steps(torch, stream, dfwd, dinv, args.steps, 3)
+            dense[dt_name] = {"value": 2.0 * S * n / (d_step * 1e-3), "unit": "coeffs/s",
+                              "ms_per_step": d_step, "forward_avg_launch_ms": d_fwd,
+                              "impl": f"torch.matmul {dt_name} (hipBLASLt/rocBLAS)" +
+                                      (", no TF32" if dt_name == "fp32" else "")}
+            del xs, ys, xo
+        result["dense_gemm"] = dense
+        result["speedup_vs_dense_fp32"] = result["value"] / dense["fp32"]["value"]
 
     if not args.no_cpu_baseline:
-        ns = 1 << 16
-        Yg = G.gft_forward(plan, xa[:ns]).double().cpu().numpy()
-        basis = G.gft_forward(plan, torch.eye(n, device=dev)).double().cpu().numpy()
-        result["cpu_baseline"] = cpu_baseline(X[:ns], Yg, graph, basis)
-
+        rows = slice(0, sample_rows)
+        Yg = G.gft_forward(plan, xa[rows]).double().cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline([(graph, X_host[rows], Yg, plan.basis())], sample_desc)
     print(json.dumps(result), flush=True)
+
+
+def bench_grid(args):
+    import workloads as wl
+    S = args.signals or (1 << 20)
+    X = wl.ar1_field(S, 8, 8, 0.95, wl.rng_for(2))
+    bench_single(args, wl.config2_graph(), X, args.precision or "fp32",
+                 {"workload": "grid8x8_ar1_fwd_inv", "graph": "8x8 4-neighbour grid, unit weights",
+                  "stages": "LR then UD (2 x 32 Haar units), 4 leaf blocks of 16", "rho": 0.95},
+                 1 << 16, "65536 signals of the same AR(1) workload (first rows of the batch)",
+                 kernel_names={"butterfly": "gft_butterfly_f32<2,16,0>", "generic": "gft_apply<4,fp32>"})
+
+
+def bench_skeleton(args):
+    import workloads as wl
+    seqs = (args.signals // 900) if args.signals else 16384
+    X = wl.skeleton_walks_chunked(seqs).reshape(-1, 25)
+    bench_single(args, wl.config3_graph(), X, args.precision or "bf16",
+                 {"workload": "skeleton25_walks_fwd_inv",
+                  "graph": "25-node skeleton: 5-node spine, 4 limbs of 5, unit weights",
+                  "stages": "left/right limb swap (10 Haar units), leaf blocks 15 + 5 + 5",
+                  "shape": f"[{seqs}, 3, 300, 25]"},
+                 8 * 900, "first 8 sequences (7200 signals) of the same skeleton workload",
+                 kernel_names={"generic": f"gft_apply<8,{args.precision or 'bf16'}>"})
+
+
+def bench_mixed(args):
+    import numpy as np
+    import torch
+
+    import paper_1907_07875_amd as G
+    import workloads as wl
+
+    dev = torch.device("cuda:0")
+    precision = args.precision or "fp32"
+    graphs = wl.config4_graphs(wl.rng_for(4))
+    counts = wl.config4_signal_counts(len(graphs), wl.rng_for(4, 1))
+    rng = wl.rng_for(4, 2)
+    xs = [wl.gaussian(int(s), g.n, rng) for g, s in zip(graphs, counts)]
+    flat = np.concatenate([x.reshape(-1) for x in xs])
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    E = flat.size
+    plan = G.gft_plan_batch(graphs, precision=precision)
+    plan.prepare()
+    xa = torch.from_numpy(flat).to(dev)
+    xb = torch.roll(xa, shifts=1).contiguous()
+    ya, yb, xr = torch.empty_like(xa), torch.empty_like(xa), torch.empty_like(xa)
+    offs = torch.from_numpy(off).to(dev)
+    stream = torch.cuda.current_stream()
+    lib, h, sp = G.load_library(), plan.handle, _c(int(stream.cuda_stream))
+    bufs = [(xa, ya), (xb, yb)]
+    P = {id(t): _c(t.data_ptr()) for t in (xa, xb, ya, yb, xr, offs)}
+
+    def fwd(i):
+        x, y = bufs[i & 1]
+        st = lib.gft_forward_batch(h, P[id(x)], P[id(y)], P[id(offs)], E, sp)
+        if st:
+            G._check(st)
+
+    def inv(i):
+        st = lib.gft_inverse_batch(h, P[id(bufs[i & 1][1])], P[id(xr)], P[id(offs)], E, sp)
+        if st:
+            G._check(st)
+
+    ms_step, fwd_ms = run_steps(torch, stream, fwd, inv, args.steps, args.warmup)
+    bytes_per_launch = 2.0 * E * 4
+    achieved = bytes_per_launch / (fwd_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": 2.0 * E / (ms_step * 1e-3), "unit": "coeffs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else f"f32 io, {precision} blocks",
+        "data": "synthetic",
+        "config": {"workload": "mixed_batch_fwd_inv", "graphs": len(graphs),
+                   "families": "paths 4..64, cycles 8..64, grids 4x4..16x16, bipartite 16..128",
+                   "signals": int(counts.sum()), "elements": int(E), "precision": precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"gft_apply_batch<{precision}> (forward)",
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms},
+    }
+    if not args.no_dense:
+        # the same batch as one dense GEMM launch per graph (FP32, same bases)
+        torch.backends.cuda.matmul.allow_tf32 = False
+        Us = [G.gft_forward(G.Plan.from_graph(g), torch.eye(g.n, device=dev)) for g in graphs]
+        pos = np.concatenate([[0], np.cumsum(counts * np.array([g.n for g in graphs]))])
+        views = [(xa[pos[i]:pos[i + 1]].view(-1, g.n), ya[pos[i]:pos[i + 1]].view(-1, g.n))
+                 for i, g in enumerate(graphs)]
+
+        def dfwd(i):
+            for (xv, yv), U in zip(views, Us):
+                if xv.shape[0]:
+                    torch.matmul(xv, U, out=yv)
+
+        d_step, _ = run_steps(torch, stream, dfwd, dfwd, args.steps, 2)
+        result["dense_gemm"] = {"value": 2.0 * E / (d_step * 1e-3), "unit": "coeffs/s",
+                                "ms_per_step": d_step,
+                                "impl": f"torch.matmul FP32, one launch per graph ({len(graphs)} per direction)"}
+    if not args.no_cpu_baseline:
+        samples = []
+        for i in (0, 60, 118, 125, 140):
+            g = graphs[i]
+            s = min(int(counts[i]), 4096)
+            Xs = xs[i][:s]
+            Yg = G.gft_forward(G.Plan.from_graph(g, engine="generic"),
+                               torch.from_numpy(Xs).to(dev)).double().cpu().numpy()
+            samples.append((g, Xs, Yg, plan.basis(i)))
+        result["cpu_baseline"] = cpu_baseline(
+            samples, "5 graphs of the batch (path, cycle, grid, 2 bipartite), up to 4096 signals each")
+    print(json.dumps(result), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: every signal is "
+                          "independent, so N GPUs would each run this same kernel on 1/N of the "
+                          "batch with no exchange; multi-GPU runs are not part of this build"}))
+        sys.exit(2)
+    {"grid8x8": bench_grid, "skeleton": bench_skeleton, "mixed": bench_mixed}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -295,6 +295,17 @@ def ar1_field(S: int, N1: int, N2: int, rho: float, rng: np.random.Generator,
     return out
 
 
+def skeleton_walks_chunked(seqs: int, channels: int = 3, frames: int = 300, chunk: int = 512,
+                           dtype=np.float32) -> np.ndarray:
+    """Config 3 signals [seqs, channels, frames, 25], generated in chunks of ``chunk``
+    sequences, chunk k from its own stream rng_for(3, 100 + k) (any chunk can be rebuilt)."""
+    out = np.empty((seqs, channels, frames, 25), dtype=dtype)
+    for k, a in enumerate(range(0, seqs, chunk)):
+        b = min(seqs, a + chunk)
+        out[a:b] = skeleton_walks(b - a, channels, frames, rng_for(3, 100 + k), dtype)
+    return out
+
+
 def skeleton_walks(seqs: int, channels: int, frames: int, rng: np.random.Generator,
                    dtype=np.float32) -> np.ndarray:
     """Smooth random-walk motion on the 25-joint skeleton, shape [seqs, channels, frames, 25].
@@ -315,7 +326,7 @@ def skeleton_walks(seqs: int, channels: int, frames: int, rng: np.random.Generat
     walk = pose[:, :, None, :] + np.cumsum(steps, axis=2)
     k = np.ones(5) / 5.0
     cs = np.cumsum(np.concatenate([np.zeros((seqs, channels, 1, 25)), walk], axis=2), axis=2)
-    smooth = (cs[:, :, 5:, :] - cs[:, :, :-5, :]) * k[0] * 1.0
+    smooth = (cs[:, :, 5:, :] - cs[:, :, :-5, :]) * k[0]
     return smooth[:, :, :frames, :].astype(dtype)
 
 
