@@ -166,6 +166,58 @@ def cycle_two_stage(n: int, name="cycle2") -> Graph:
     return g
 
 
+def bidiagonal_grid(N: int, a: float = 0.5, name="grid6conn") -> Graph:
+    """6-connected N x N grid: unit horizontal/vertical edges plus diagonal edges
+    (k,l)-(k+1,l+1) of weight a.  Symmetric about both diagonals (Fig. grid_bidiag).
+    Stages: diagonal symmetry (k,l) <-> (l,k), then anti-diagonal (k,l) <-> (N-1-l, N-1-k)."""
+    edges = grid_edges(N, N)
+    w = [1.0] * len(edges)
+    for k in range(N - 1):
+        for l in range(N - 1):
+            edges.append((k * N + l, (k + 1) * N + l + 1))
+            w.append(a)
+    diag = identity(N * N)
+    anti = identity(N * N)
+    for k in range(N):
+        for l in range(N):
+            diag[k * N + l] = l * N + k
+            anti[k * N + l] = (N - 1 - l) * N + (N - 1 - k)
+    return _graph(N * N, edges, w, None, [diag, anti], name)
+
+
+def zshaped_grid(N: int, w: float = 2.0, name="zgrid") -> Graph:
+    """N x N grid with unit horizontal edges and anti-diagonal edges (k,l)-(k+1,l-1) of
+    weight w (Fig. z4x4); centrosymmetric, one stage phi(i) = n-1-i."""
+    edges, ws = [], []
+    for k in range(N):
+        for l in range(N):
+            if l + 1 < N:
+                edges.append((k * N + l, k * N + l + 1))
+                ws.append(1.0)
+            if k + 1 < N and l >= 1:
+                edges.append((k * N + l, (k + 1) * N + l - 1))
+                ws.append(w)
+    return _graph(N * N, edges, ws, None, [reversal(N * N)], name)
+
+
+def skeleton(spine: int, arm: int, leg: int, arm_at: int, leg_at: int, name="skeleton") -> Graph:
+    """Skeleton tree: a spine path 0..spine-1 and two mirror-symmetric arms (attached at
+    spine node arm_at) and legs (attached at leg_at); labels: spine, left arm, left leg,
+    right arm, right leg.  One stage swaps left and right limbs (Fig. Gsk)."""
+    edges = [(i, i + 1) for i in range(spine - 1)]
+    n, limbs = spine, []
+    for length, at in ((arm, arm_at), (leg, leg_at), (arm, arm_at), (leg, leg_at)):
+        edges.append((at, n))
+        edges += [(n + i, n + i + 1) for i in range(length - 1)]
+        limbs.append((n, length))
+        n += length
+    phi = identity(n)
+    for (b1, l1), (b2, _) in ((limbs[0], limbs[2]), (limbs[1], limbs[3])):
+        for i in range(l1):
+            phi[b1 + i], phi[b2 + i] = b2 + i, b1 + i
+    return _graph(n, edges, None, None, [phi], name)
+
+
 def _halving_chain(m: int):
     """Nested index ranges [0, m), [0, m/2), ... used by the recursive reversal stages."""
     ranges = []
