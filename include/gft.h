@@ -98,15 +98,20 @@ typedef enum {
                              /* ascending eigenvalue inside each block                */
 } gft_order;
 
-/* Kernel family.  AUTO picks the register-butterfly engine when the plan is a uniform
- * hypercube (every stage pairs every node, 2^S equal connected leaf blocks, each Haar
- * orbit holding one node of every block) and its shape is compiled in; otherwise the
- * generic LDS-program engine. */
+/* Kernel family.  AUTO picks, for single-graph plans: the register-butterfly engine when
+ * the plan is a uniform hypercube (every stage pairs every node, 2^S equal connected leaf
+ * blocks, each Haar orbit holding one node of every block), its shape is compiled in and
+ * the blocks are FP32; else the large-signal engine when a tile of 16 signals does not fit
+ * a workgroup's LDS or a leaf block has 192 nodes or more; else the generic engine.  Batch
+ * plans always run the generic engine. */
 typedef enum {
   GFT_ENGINE_AUTO = 0,
-  GFT_ENGINE_GENERIC = 1,     /* always the generic engine                              */
-  GFT_ENGINE_BUTTERFLY = 2    /* require the register-butterfly engine (else          */
-                              /* GFT_ERR_UNSUPPORTED at the first apply)               */
+  GFT_ENGINE_GENERIC = 1,     /* LDS-program engine (one fused kernel)                  */
+  GFT_ENGINE_BUTTERFLY = 2,   /* register-butterfly engine (else GFT_ERR_UNSUPPORTED at  */
+                              /* the first apply)                                       */
+  GFT_ENGINE_LARGE = 3        /* large-signal engine: Haar stages and permutations in    */
+                              /* streaming passes, leaf blocks as MFMA GEMM tiles over a */
+                              /* stream-ordered workspace of 2*S*n floats (hipMallocAsync)*/
 } gft_engine;
 
 typedef struct {

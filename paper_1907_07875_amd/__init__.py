@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgft.so")
 GFT_FP32, GFT_BF16, GFT_FP16, GFT_SPLIT_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": GFT_FP32, "bf16": GFT_BF16, "fp16": GFT_FP16, "split_bf16": GFT_SPLIT_BF16}
 ORDER_EIGENVALUE, ORDER_BLOCK = 0, 1
-ENGINES = {"auto": 0, "generic": 1, "butterfly": 2}
+ENGINES = {"auto": 0, "generic": 1, "butterfly": 2, "large": 3}
 
 STATUS = {
     0: "GFT_OK", 1: "GFT_ERR_INVALID_ARG", 2: "GFT_ERR_GRAPH", 3: "GFT_ERR_NOT_INVOLUTION",
@@ -242,7 +242,7 @@ class Plan:
         """Kernel family the plan runs on the current device ("generic" or "butterfly")."""
         e = ctypes.c_int32()
         _check(load_library().gft_plan_engine(self._h, ctypes.byref(e)))
-        return {1: "generic", 2: "butterfly"}[e.value]
+        return {1: "generic", 2: "butterfly", 3: "large"}[e.value]
 
     # -- device apply ----------------------------------------------------------------
     def forward(self, x, out=None, stream=None):

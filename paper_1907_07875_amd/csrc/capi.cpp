@@ -43,6 +43,9 @@ struct DeviceImage {
   // register-butterfly programs (single-graph plans whose shape qualifies)
   bool butterfly = false;
   UProgram bfwd{}, binv{};
+  // large-signal engine (single-graph plans)
+  bool large = false;
+  LargeImage lg[2];
   // batch plans: device arrays of the G forward and G inverse programs
   const DevProgram *dev_fwd = nullptr, *dev_inv = nullptr;
   size_t batch_lds = 0;
@@ -102,8 +105,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.precision is not a gft_precision value");
   if (o.order != GFT_ORDER_EIGENVALUE && o.order != GFT_ORDER_BLOCK)
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
-  if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_BUTTERFLY)
-    return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1 or 2");
+  if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_LARGE)
+    return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2 or 3");
   if (o.tile_override != 0 && o.tile_override != 16 && o.tile_override != 32 &&
       o.tile_override != 64 && o.tile_override != 128)
     return set_error(GFT_ERR_INVALID_ARG, "options.tile_override must be 0, 16, 32, 64 or 128");
@@ -150,13 +153,27 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                        "hypercube with a compiled shape)");
   }
 
+  // Large-signal engine: signals whose 16-signal tile does not fit LDS, or big leaf blocks.
+  bool use_large = false;
+  if (!plan->batch && !use_bf && plan->opts.engine != GFT_ENGINE_GENERIC) {
+    ProgramImage probe;
+    const bool fits = build_program(plan->graphs[0], 0, 0, budget, probe, plan->opts.precision);
+    use_large = plan->opts.engine == GFT_ENGINE_LARGE ||
+                (plan->opts.engine == GFT_ENGINE_AUTO &&
+                 (!fits || plan->graphs[0].stats.max_block >= 192));
+    if (use_large && plan->opts.precision == GFT_FP16)
+      return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine runs FP32, BF16 or split BF16 blocks");
+  }
+  if (plan->opts.engine == GFT_ENGINE_LARGE && plan->batch)
+    return set_error(GFT_ERR_UNSUPPORTED, "batch plans run the generic engine");
+
   std::vector<ProgramImage> imgs;
   for (size_t g = 0; g < plan->graphs.size(); ++g)
     for (int dir = 0; dir < 2; ++dir) {
       ProgramImage im;
       if (!build_program(plan->graphs[g], dir, plan->opts.tile_override, budget, im,
                          plan->opts.precision)) {
-        if (use_bf) continue;  // the butterfly engine serves this graph
+        if (use_bf || use_large) continue;  // another engine serves this graph
         return set_error(GFT_ERR_UNSUPPORTED,
                          "graph " + std::to_string(g) + " (n = " + std::to_string(plan->graphs[g].n) +
                              ") does not fit the LDS of one workgroup with this tile size");
@@ -177,6 +194,25 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       uoff[d][2] = blob.add(ub[d].afrag.data(), ub[d].afrag.size() * 4);
       uoff[d][3] = blob.add(ub[d].flips.data(), ub[d].flips.size() * 4);
     }
+  LargeImage lgi[2];
+  size_t loff[2][7] = {};
+  if (use_large)
+    for (int d = 0; d < 2; ++d) {
+      build_large(plan->graphs[0], d, lgi[d]);
+      for (int k = 0; k < 2; ++k) {
+        loff[d][2 * k] = blob.add(lgi[d].scatter[k].data(), lgi[d].scatter[k].size() * 4);
+        loff[d][2 * k + 1] = blob.add(lgi[d].gather[k].data(), lgi[d].gather[k].size() * 4);
+      }
+      const int sp = d == 0 ? 0 : 1;   // pass holding the stages
+      loff[d][4] = blob.add(lgi[d].stages[sp].data(), lgi[d].stages[sp].size() * 4);
+      loff[d][5] = blob.add(lgi[d].ops[sp].data(), lgi[d].ops[sp].size() * 4);
+      loff[d][6] = blob.add(lgi[d].blocks.data(), lgi[d].blocks.size() * sizeof(LBlock));
+      lgi[d].block_sizes.shrink_to_fit();
+      // matrices last (largest)
+    }
+  size_t lmat[2] = {};
+  if (use_large)
+    for (int d = 0; d < 2; ++d) lmat[d] = blob.add(lgi[d].mats.data(), lgi[d].mats.size() * 4);
   const size_t bytes = blob.bytes.size();
   auto img = std::make_unique<DeviceImage>();
   img->device = dev;
@@ -211,6 +247,24 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       dst[d]->scol = reinterpret_cast<const int32_t *>(base + uoff[d][1]);
       dst[d]->afrag = reinterpret_cast<const float *>(base + uoff[d][2]);
       dst[d]->flips = reinterpret_cast<const uint32_t *>(base + uoff[d][3]);
+    }
+  }
+  if (use_large) {
+    img->large = true;
+    for (int d = 0; d < 2; ++d) {
+      LargeImage &L = img->lg[d];
+      L = std::move(lgi[d]);
+      for (int k = 0; k < 2; ++k) {
+        PermPass &P = L.pass[k];
+        P.scatter = L.scatter[k].empty() ? nullptr : reinterpret_cast<const int32_t *>(base + loff[d][2 * k]);
+        P.gather = L.gather[k].empty() ? nullptr : reinterpret_cast<const int32_t *>(base + loff[d][2 * k + 1]);
+        P.stages = reinterpret_cast<const int32_t *>(base + loff[d][4]);
+        P.ops = reinterpret_cast<const int32_t *>(base + loff[d][5]);
+      }
+      L.dev_blocks = reinterpret_cast<const LBlock *>(base + loff[d][6]);
+      L.dev_mats = reinterpret_cast<const float *>(base + lmat[d]);
+      L.mats.clear();
+      L.mats.shrink_to_fit();
     }
   }
   if (plan->batch) {
@@ -270,7 +324,32 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   st = device_image(plan, &img);
   if (st != GFT_OK) return st;
   hipError_t e;
-  if (img->butterfly) {
+  if (img->large) {
+    const LargeImage &L = img->lg[dir];
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t ws_bytes = 2 * (size_t)S * (size_t)L.ldw * 4;
+    void *ws = nullptr;
+    e = hipMallocAsync(&ws, ws_bytes, st);
+    if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
+    float *W1 = static_cast<float *>(ws), *W2 = W1 + (size_t)S * L.ldw;
+    const int budget_rows[2] = {std::max(1, std::min(32, (96 * 1024) / (4 * L.stride[0]))),
+                                std::max(1, std::min(32, (96 * 1024) / (4 * L.stride[1])))};
+    auto grid_for = [&](int rows) {
+      const int64_t tiles = (S + rows - 1) / rows;
+      return (int)std::min<int64_t>(tiles, (int64_t)img->num_cus * 4);
+    };
+    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, S, budget_rows[0],
+                              L.stride[0], grid_for(budget_rows[0]), st);
+    if (e == hipSuccess)
+      e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
+                            (int)L.blocks.size(), L.dev_mats, W1, W2, S, L.ldw,
+                            block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S), st);
+    if (e == hipSuccess)
+      e = launch_permute_stages(L.pass[1], W2, static_cast<float *>(out), S, budget_rows[1],
+                                L.stride[1], grid_for(budget_rows[1]), st);
+    const hipError_t ef = hipFreeAsync(ws, st);
+    if (e == hipSuccess) e = ef;
+  } else if (img->butterfly) {
     e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, static_cast<const float *>(in),
                          static_cast<float *>(out), S, static_cast<hipStream_t>(stream), img->num_cus);
   } else {
@@ -395,7 +474,7 @@ gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out) {
   DeviceImage *img = nullptr;
   gft_status st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  *engine_out = img->butterfly ? GFT_ENGINE_BUTTERFLY : GFT_ENGINE_GENERIC;
+  *engine_out = img->butterfly ? GFT_ENGINE_BUTTERFLY : (img->large ? GFT_ENGINE_LARGE : GFT_ENGINE_GENERIC);
   return ok();
 }
 

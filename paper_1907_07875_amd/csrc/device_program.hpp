@@ -89,4 +89,33 @@ struct UProgram {
   const float *afrag;
 };
 
+// Large-signal engine (signals that do not fit a workgroup's LDS tile, or large leaf
+// blocks): three passes through a block-contiguous workspace W with row stride ldw.
+//   pass 1 (permute + stages): each tile of signals is scattered into an LDS tile, the
+//     Haar stages run on it, and the tile is gathered out:
+//       tile[r][scatter[c]] = in[r * ld_in + c]   (scatter[c] < 0: column ignored)
+//       out[r * ld_out + c] = gather[c] < 0 ? 0 : tile[r][gather[c]]
+//   pass 2 (grouped GEMM): W2[:, off_b : off_b + b] = W[:, off_b : off_b + b] * M_b for
+//     every leaf block b (M_b row-major b x b with row stride ld_b), MFMA tiles;
+//   pass 3 (permute only).
+// Forward: x -[stages]-> W (block layout) -[GEMM]-> W2 -[permute]-> y (output order).
+// Inverse: y -[permute]-> W (block layout) -[GEMM]-> W2 -[stages reversed]-> x.
+struct PermPass {
+  int32_t n_tile;           // LDS row length (node or coefficient space)
+  int32_t in_cols, ld_in;   // columns read per row and input row stride
+  int32_t out_cols, ld_out; // columns written per row and output row stride
+  int32_t num_stages;       // Haar stages applied to the LDS tile
+  const int32_t *scatter;   // in_cols entries, or nullptr for identity
+  const int32_t *gather;    // out_cols entries, or nullptr for identity
+  const int32_t *stages;    // 2 words per stage: op offset, op count
+  const int32_t *ops;       // 2 words per op: (i, j) or (c, -1)
+};
+
+struct LBlock {
+  int32_t size;     // b
+  int32_t col;      // column offset in the workspace (multiple of 4)
+  int32_t mat;      // offset of M_b in the matrix array (elements, multiple of 4)
+  int32_t ld;       // row stride of M_b (multiple of 4, >= b)
+};
+
 }  // namespace gft

@@ -23,6 +23,14 @@ hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const in
                               int64_t total_elems, const float *in, float *out, size_t lds,
                               int grid, hipStream_t stream);
 
+// Large-signal engine.
+hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
+                                 int rows, int stride, int grid, hipStream_t stream);
+int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
+hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const float *mats,
+                             const float *A, float *C, int64_t S, int ld, int64_t grid,
+                             hipStream_t stream);
+
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(int S, int M);
 hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,

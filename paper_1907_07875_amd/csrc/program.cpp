@@ -344,3 +344,75 @@ bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
 }
 
 }  // namespace gft
+
+namespace gft {
+
+void build_large(const GraphPlan &p, int direction, LargeImage &out) {
+  LargeImage im;
+  const int n = p.n;
+  im.n = n;
+  // block-contiguous workspace layout, each block's span padded to a multiple of 4
+  std::vector<int32_t> col_node, col_coef;   // per workspace column (or -1 for padding)
+  int col = 0;
+  size_t mat = 0;
+  for (const HostBlock &B : p.blocks) {
+    const int ld = (B.size + 3) & ~3;
+    im.blocks.push_back({B.size, col, (int32_t)mat, ld});
+    im.block_sizes.push_back(B.size);
+    for (int k = 0; k < ld; ++k) {
+      col_node.push_back(k < B.size ? B.nodes[k] : -1);
+      col_coef.push_back(k < B.size ? B.out_pos[k] : -1);
+    }
+    col += ld;
+    mat += (size_t)B.size * ld;
+  }
+  im.ldw = col;
+  im.mats.assign(mat, 0.0f);
+  for (size_t b = 0; b < p.blocks.size(); ++b) {
+    const HostBlock &B = p.blocks[b];
+    const LBlock &L = im.blocks[b];
+    for (int k = 0; k < B.size; ++k)
+      for (int c = 0; c < B.size; ++c)  // forward M[k][c] = V[k][c]; inverse M[k][j] = V[j][k]
+        im.mats[(size_t)L.mat + (size_t)k * L.ld + c] =
+            (float)(B.scale * (direction == 0 ? B.V[(size_t)k * B.size + c] : B.V[(size_t)c * B.size + k]));
+  }
+  // stage program (forward order for the forward, reversed for the inverse)
+  std::vector<int32_t> st, ops;
+  const int ns = (int)p.stages.size();
+  for (int q = 0; q < ns; ++q) {
+    const HostStage &S = p.stages[direction == 0 ? q : ns - 1 - q];
+    const int off = (int)(ops.size() / 2);
+    for (size_t u = 0; u < S.pair_x.size(); ++u) {
+      ops.push_back(S.pair_x[u]);
+      ops.push_back(S.pair_y[u]);
+    }
+    for (int32_t c : S.znodes) {
+      ops.push_back(c);
+      ops.push_back(-1);
+    }
+    st.push_back(off);
+    st.push_back((int)(ops.size() / 2) - off);
+  }
+  const int stages_pass = direction == 0 ? 0 : 1;   // forward: stages in pass 1; inverse: pass 3
+  im.stages[stages_pass] = st;
+  im.ops[stages_pass] = ops;
+  for (int k = 0; k < 2; ++k) {
+    PermPass &P = im.pass[k];
+    P.n_tile = n;
+    im.stride[k] = n | 1;
+    P.num_stages = k == stages_pass ? ns : 0;
+    const bool first = k == 0;
+    if (first) {          // n-wide input -> workspace layout
+      P.in_cols = P.ld_in = n;
+      P.out_cols = P.ld_out = im.ldw;
+      im.gather[k] = direction == 0 ? col_node : col_coef;
+    } else {              // workspace layout -> n-wide output
+      P.in_cols = P.ld_in = im.ldw;
+      P.out_cols = P.ld_out = n;
+      im.scatter[k] = direction == 0 ? col_coef : col_node;
+    }
+  }
+  out = std::move(im);
+}
+
+}  // namespace gft

@@ -48,4 +48,20 @@ struct UProgramImage {
 // Returns false (out untouched) otherwise.
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out);
 
+// Host image of the large-signal engine for one direction (see PermPass, LBlock).
+struct LargeImage {
+  int32_t n = 0, ldw = 0;
+  int32_t stride[2] = {0, 0};  // LDS row stride of passes 1 and 3
+  PermPass pass[2]{};          // pointers left null until upload
+  std::vector<int32_t> scatter[2], gather[2], stages[2], ops[2];
+  std::vector<LBlock> blocks;
+  std::vector<int32_t> block_sizes;
+  std::vector<float> mats;
+  const LBlock *dev_blocks = nullptr;   // device copies, set at upload
+  const float *dev_mats = nullptr;
+};
+
+// Build the large-signal engine image of `p` for direction 0 (forward) or 1 (inverse).
+void build_large(const GraphPlan &p, int direction, LargeImage &out);
+
 }  // namespace gft
