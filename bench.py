@@ -9,8 +9,11 @@ BF16) on the same GPU and basis, a plain device copy of the same bytes, and the 
 oracle timed on host cores on a bounded sample (with the GPU's relative error there).
 
 Other workloads (``--workload``): ``skeleton`` (25-joint skeleton, 16384 x 3 x 300
-signals, BF16 leaf blocks) and ``mixed`` (the ~150-graph uneven batch, one persistent
-launch per direction).
+signals, BF16 leaf blocks), ``mixed`` (the ~150-graph uneven batch, one persistent launch
+per direction), ``grid64`` (64x64 grid, 12 stages, 65536 signals) and ``wpath1024``
+(weighted symmetric path, n = 1024, 65536 signals); the last two run the large-signal
+engine (stage/permutation passes + grouped MFMA GEMM) and are reported against the MFMA
+roofline of their precision.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid8x8]
 """
@@ -29,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0,
+                    "split_bf16": 2500.0 / 3.0}   # split: three BF16 products per product
 METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM roofline"
 
 # HBM bytes per forward launch of the 8x8-grid workload from rocprofv3 FETCH_SIZE /
@@ -45,7 +50,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="grid8x8", choices=["grid8x8", "skeleton", "mixed"])
+    ap.add_argument("--workload", default="grid8x8",
+                    choices=["grid8x8", "skeleton", "mixed", "grid64", "wpath1024"])
     ap.add_argument("--signals", type=int, default=None, help="override the signal count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
@@ -153,7 +159,7 @@ def _c(ptr):
 
 
 def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, sample_desc,
-                 kernel_names=None):
+                 kernel_names=None, flops_per_signal=None):
     """Shared body of the single-graph workloads."""
     import torch
 
@@ -210,6 +216,17 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     except OSError:
         pass
 
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
+            "kernel": kname + " (forward)", "engine": eng,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms}
+    if flops_per_signal is not None:
+        tflops = flops_per_signal * S / (fwd_ms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[precision]
+        roof.update({"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": tflops / peak, "algorithmic_flops_per_launch": flops_per_signal * S,
+                     "hbm_GB_per_s": achieved, "hbm_frac": achieved / HBM_PEAK_GBS})
     result = {
         "metric": METRIC,
         "value": 2.0 * S * n / (ms_step * 1e-3), "unit": "coeffs/s", "n_gpus": 1,
@@ -218,11 +235,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
         "dtype": "f32" if precision == "fp32" else f"f32 io, {precision} blocks, f32 acc",
         "data": "synthetic",
         "config": dict(workload_cfg, signals=S, n=n, values_per_step=2 * S * n, precision=precision),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
-                     "kernel": kname + " (forward)", "engine": eng,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms},
+        "roofline": roof,
         "forward_coeffs_per_s": S * n / (fwd_ms * 1e-3),
         "inverse_values_per_s": S * n / (inv_ms * 1e-3), "inverse_avg_launch_ms": inv_ms,
         "copy_reference": {"GB_per_s": copy_gbs, "avg_launch_ms": copy_ms,
@@ -286,6 +299,36 @@ def bench_skeleton(args):
                   "shape": f"[{seqs}, 3, 300, 25]"},
                  8 * 900, "first 8 sequences (7200 signals) of the same skeleton workload",
                  kernel_names={"generic": f"gft_apply<8,{args.precision or 'bf16'}>"})
+
+
+def _large_workload(args, graph, S, name, desc):
+    import numpy as np
+    import paper_1907_07875_amd as G
+    import workloads as wl
+    X = wl.gaussian(S, graph.n, wl.rng_for(5, 7))
+    st = G.Plan.from_graph(graph).info()
+    sum_b2 = st["mults"] - st["num_z_scalings"]
+    # per signal: 2 flops per block multiply-add, plus the Haar units' add/sub
+    flops = 2.0 * sum_b2 + 2.0 * st["num_units"]
+    bench_single(args, graph, X, args.precision or "fp32",
+                 {"workload": name, "graph": desc, "stages": st["num_stages"],
+                  "leaf_blocks": st["num_blocks"], "max_block": st["max_block"],
+                  "dense_flops_per_signal": 2.0 * graph.n * graph.n, "fast_flops_per_signal": flops},
+                 256, "first 256 signals of the same workload",
+                 kernel_names={"large": "large engine: permute_stages + block_gemm + permute_stages"},
+                 flops_per_signal=flops)
+
+
+def bench_grid64(args):
+    import workloads as wl
+    _large_workload(args, wl.config5a_graph(), args.signals or 65536, "grid64x64_fwd_inv",
+                    "64x64 grid, LR/UD reversals recursed on the + branch (12 stages)")
+
+
+def bench_wpath(args):
+    import workloads as wl
+    _large_workload(args, wl.config5b_graph(), args.signals or 65536, "wpath1024_fwd_inv",
+                    "weighted symmetric path, n = 1024, mirrored weights and self-loops")
 
 
 def bench_mixed(args):
@@ -381,7 +424,8 @@ def main():
                           "independent, so N GPUs would each run this same kernel on 1/N of the "
                           "batch with no exchange; multi-GPU runs are not part of this build"}))
         sys.exit(2)
-    {"grid8x8": bench_grid, "skeleton": bench_skeleton, "mixed": bench_mixed}[args.workload](args)
+    {"grid8x8": bench_grid, "skeleton": bench_skeleton, "mixed": bench_mixed,
+     "grid64": bench_grid64, "wpath1024": bench_wpath}[args.workload](args)
 
 
 if __name__ == "__main__":

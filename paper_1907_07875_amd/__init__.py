@@ -83,6 +83,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libgft.so not found at {path}; run paper_1907_07875_amd/build.py "
                           "(or __graft_entry__.build()) first")
+    # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading torch first makes
+    # libgft bind to that instance: one HIP runtime per process, shared streams and memory.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64

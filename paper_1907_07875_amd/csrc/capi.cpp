@@ -332,11 +332,13 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
     e = hipMallocAsync(&ws, ws_bytes, st);
     if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
     float *W1 = static_cast<float *>(ws), *W2 = W1 + (size_t)S * L.ldw;
-    const int budget_rows[2] = {std::max(1, std::min(32, (96 * 1024) / (4 * L.stride[0]))),
-                                std::max(1, std::min(32, (96 * 1024) / (4 * L.stride[1])))};
+    // stage passes: tiles of a few rows (about 32 KB of LDS) for occupancy; gather-only
+    // passes: a grid of about 16 workgroups per CU walking the elements
+    const int budget_rows[2] = {std::max(1, std::min(16, (32 * 1024) / (4 * L.stride[0]))),
+                                std::max(1, std::min(16, (32 * 1024) / (4 * L.stride[1])))};
     auto grid_for = [&](int rows) {
       const int64_t tiles = (S + rows - 1) / rows;
-      return (int)std::min<int64_t>(tiles, (int64_t)img->num_cus * 4);
+      return (int)std::min<int64_t>(tiles, (int64_t)img->num_cus * 16);
     };
     e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, S, budget_rows[0],
                               L.stride[0], grid_for(budget_rows[0]), st);

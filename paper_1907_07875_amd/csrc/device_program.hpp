@@ -91,22 +91,24 @@ struct UProgram {
 
 // Large-signal engine (signals that do not fit a workgroup's LDS tile, or large leaf
 // blocks): three passes through a block-contiguous workspace W with row stride ldw.
-//   pass 1 (permute + stages): each tile of signals is scattered into an LDS tile, the
-//     Haar stages run on it, and the tile is gathered out:
-//       tile[r][scatter[c]] = in[r * ld_in + c]   (scatter[c] < 0: column ignored)
-//       out[r * ld_out + c] = gather[c] < 0 ? 0 : tile[r][gather[c]]
+//   pass 1 / pass 3 (gather, optional Haar stages): per signal row,
+//       tile[j] = scatter[j] < 0 ? 0 : in[row * ld_in + scatter[j]]    (j < n_tile)
+//       stages on the tile (pass with num_stages > 0 only; the tile lives in LDS)
+//       out[row * ld_out + c] = gather[c] < 0 ? 0 : tile[gather[c]]    (c < out_cols)
+//     (`scatter` names the input column each tile entry is read from; null = identity;
+//     with no stages the tile is not materialised and out[c] = in[scatter[gather[c]]],
+//     the host passing a composed `gather`);
 //   pass 2 (grouped GEMM): W2[:, off_b : off_b + b] = W[:, off_b : off_b + b] * M_b for
-//     every leaf block b (M_b row-major b x b with row stride ld_b), MFMA tiles;
-//   pass 3 (permute only).
+//     every leaf block b (M_b row-major b x b with row stride ld_b), MFMA tiles.
 // Forward: x -[stages]-> W (block layout) -[GEMM]-> W2 -[permute]-> y (output order).
 // Inverse: y -[permute]-> W (block layout) -[GEMM]-> W2 -[stages reversed]-> x.
 struct PermPass {
-  int32_t n_tile;           // LDS row length (node or coefficient space)
-  int32_t in_cols, ld_in;   // columns read per row and input row stride
+  int32_t n_tile;           // tile row length (node or coefficient space)
+  int32_t in_cols, ld_in;   // input columns and row stride
   int32_t out_cols, ld_out; // columns written per row and output row stride
-  int32_t num_stages;       // Haar stages applied to the LDS tile
-  const int32_t *scatter;   // in_cols entries, or nullptr for identity
-  const int32_t *gather;    // out_cols entries, or nullptr for identity
+  int32_t num_stages;       // Haar stages applied to the tile
+  const int32_t *scatter;   // n_tile entries: input column of each tile entry (or null)
+  const int32_t *gather;    // out_cols entries: tile entry of each output column (or null)
   const int32_t *stages;    // 2 words per stage: op offset, op count
   const int32_t *ops;       // 2 words per op: (i, j) or (c, -1)
 };

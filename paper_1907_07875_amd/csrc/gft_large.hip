@@ -36,27 +36,36 @@ __device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, 
 
 // ---------------------------------------------------------------------------- pass 1/3
 
-// Tiles of `rows` signals: scatter-load into an LDS tile [rows][stride], run the stages,
-// gather-store.  stride = odd >= n_tile.  Columns of the tile that no input column
-// scatters to are zero.
+// Rows of `rows` signals per tile: tile[r][j] = in[r * ld_in + (scatter-inverse) ...].
+// The pass is given in gather form on both sides:
+//   load:  tile[r][j] = gin[j] < 0 ? 0 : in[r * ld_in + gin[j]]        (j < n_tile)
+//   store: out[r * ld_out + c] = gout[c] < 0 ? 0 : tile[r][gout[c]]    (c < out_cols)
+// (gin / gout null = identity).  With no stages the tile is skipped altogether: each
+// output element gathers its input directly (a row is a few KB, so the gathered reads stay
+// in L2 while writes are coalesced).
 __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const float *in,
                                                                float *out, int64_t S,
                                                                int rows, int stride) {
+  const int tid = threadIdx.x;
+  if (P.num_stages == 0) {
+    const int64_t total = S * (int64_t)P.out_cols;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + tid; e < total; e += (int64_t)gridDim.x * kThreads) {
+      const int64_t r = e / P.out_cols;
+      const int c = (int)(e - r * P.out_cols);
+      const int src = P.gather ? P.gather[c] : c;
+      out[r * P.ld_out + c] = src >= 0 ? in[r * P.ld_in + src] : 0.0f;
+    }
+    return;
+  }
   extern __shared__ float tile[];
   const int64_t ntiles = (S + rows - 1) / rows;
-  const int tid = threadIdx.x;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t r0 = t * rows;
     const int nr = (int)((S - r0) < rows ? (S - r0) : rows);
-    for (int i = tid; i < rows * stride; i += kThreads) tile[i] = 0.0f;
-    __syncthreads();
-    for (int r = 0; r < nr; ++r) {
-      const float *src = in + (r0 + r) * (int64_t)P.ld_in;
-      float *dst = tile + r * stride;
-      for (int c = tid; c < P.in_cols; c += kThreads) {
-        const int d = P.scatter ? P.scatter[c] : c;
-        if (d >= 0) dst[d] = src[c];
-      }
+    for (int idx = tid; idx < nr * P.n_tile; idx += kThreads) {
+      const int r = idx / P.n_tile, j = idx - r * P.n_tile;
+      const int src = P.scatter ? P.scatter[j] : j;
+      tile[r * stride + j] = src >= 0 ? in[(r0 + r) * (int64_t)P.ld_in + src] : 0.0f;
     }
     __syncthreads();
     for (int s = 0; s < P.num_stages; ++s) {
@@ -75,13 +84,10 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
       }
       __syncthreads();
     }
-    for (int r = 0; r < nr; ++r) {
-      float *dst = out + (r0 + r) * (int64_t)P.ld_out;
-      const float *src = tile + r * stride;
-      for (int c = tid; c < P.out_cols; c += kThreads) {
-        const int g = P.gather ? P.gather[c] : c;
-        dst[c] = g >= 0 ? src[g] : 0.0f;
-      }
+    for (int idx = tid; idx < nr * P.out_cols; idx += kThreads) {
+      const int r = idx / P.out_cols, c = idx - r * P.out_cols;
+      const int g = P.gather ? P.gather[c] : c;
+      out[(r0 + r) * (int64_t)P.ld_out + c] = g >= 0 ? tile[r * stride + g] : 0.0f;
     }
     __syncthreads();
   }
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
 
 hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
                                  int rows, int stride, int grid, hipStream_t stream) {
-  const size_t lds = (size_t)rows * stride * 4;
+  const size_t lds = P.num_stages ? (size_t)rows * stride * 4 : 0;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_permute_stages,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

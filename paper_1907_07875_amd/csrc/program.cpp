@@ -396,20 +396,30 @@ void build_large(const GraphPlan &p, int direction, LargeImage &out) {
   const int stages_pass = direction == 0 ? 0 : 1;   // forward: stages in pass 1; inverse: pass 3
   im.stages[stages_pass] = st;
   im.ops[stages_pass] = ops;
+  // Both passes in gather form: tile entry j reads input column src[j]; output column c
+  // reads tile entry dst[c].  Workspace column col holds node col_node[col] (coefficient
+  // col_coef[col]) of its block, or padding (-1).
+  auto inverse_of = [&](const std::vector<int32_t> &cols, int nvals) {
+    std::vector<int32_t> inv(nvals, -1);   // value -> workspace column
+    for (int c = 0; c < (int)cols.size(); ++c)
+      if (cols[c] >= 0) inv[cols[c]] = c;
+    return inv;
+  };
   for (int k = 0; k < 2; ++k) {
     PermPass &P = im.pass[k];
     P.n_tile = n;
     im.stride[k] = n | 1;
     P.num_stages = k == stages_pass ? ns : 0;
-    const bool first = k == 0;
-    if (first) {          // n-wide input -> workspace layout
+    const std::vector<int32_t> &map = (direction == 0) == (k == 0) ? col_node : col_coef;
+    if (k == 0) {          // n-wide input -> workspace layout
       P.in_cols = P.ld_in = n;
       P.out_cols = P.ld_out = im.ldw;
-      im.gather[k] = direction == 0 ? col_node : col_coef;
-    } else {              // workspace layout -> n-wide output
+      im.gather[k] = map;                            // tile (n-space) entry of each ws column
+    } else {               // workspace layout -> n-wide output
       P.in_cols = P.ld_in = im.ldw;
       P.out_cols = P.ld_out = n;
-      im.scatter[k] = direction == 0 ? col_coef : col_node;
+      if (P.num_stages) im.scatter[k] = inverse_of(map, n);   // ws column of each tile entry
+      else im.gather[k] = inverse_of(map, n);                 // composed: ws column of output c
     }
   }
   out = std::move(im);
