@@ -198,11 +198,11 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   size_t loff[2][7] = {};
   if (use_large)
     for (int d = 0; d < 2; ++d) {
-      build_large(plan->graphs[0], d, lgi[d]);
-      for (int k = 0; k < 2; ++k) {
-        loff[d][2 * k] = blob.add(lgi[d].scatter[k].data(), lgi[d].scatter[k].size() * 4);
+      if (!build_large(plan->graphs[0], d, lgi[d]))
+        return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine takes at most " +
+                                                  std::to_string(kLargeMaxCols) + " workspace columns");
+      for (int k = 0; k < 2; ++k)
         loff[d][2 * k + 1] = blob.add(lgi[d].gather[k].data(), lgi[d].gather[k].size() * 4);
-      }
       const int sp = d == 0 ? 0 : 1;   // pass holding the stages
       loff[d][4] = blob.add(lgi[d].stages[sp].data(), lgi[d].stages[sp].size() * 4);
       loff[d][5] = blob.add(lgi[d].ops[sp].data(), lgi[d].ops[sp].size() * 4);
@@ -256,10 +256,9 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       L = std::move(lgi[d]);
       for (int k = 0; k < 2; ++k) {
         PermPass &P = L.pass[k];
-        P.scatter = L.scatter[k].empty() ? nullptr : reinterpret_cast<const int32_t *>(base + loff[d][2 * k]);
         P.gather = L.gather[k].empty() ? nullptr : reinterpret_cast<const int32_t *>(base + loff[d][2 * k + 1]);
         P.stages = reinterpret_cast<const int32_t *>(base + loff[d][4]);
-        P.ops = reinterpret_cast<const int32_t *>(base + loff[d][5]);
+        P.ops = reinterpret_cast<const uint32_t *>(base + loff[d][5]);
       }
       L.dev_blocks = reinterpret_cast<const LBlock *>(base + loff[d][6]);
       L.dev_mats = reinterpret_cast<const float *>(base + lmat[d]);
@@ -332,23 +331,13 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
     e = hipMallocAsync(&ws, ws_bytes, st);
     if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
     float *W1 = static_cast<float *>(ws), *W2 = W1 + (size_t)S * L.ldw;
-    // stage passes: tiles of a few rows (about 32 KB of LDS) for occupancy; gather-only
-    // passes: a grid of about 16 workgroups per CU walking the elements
-    const int budget_rows[2] = {std::max(1, std::min(16, (32 * 1024) / (4 * L.stride[0]))),
-                                std::max(1, std::min(16, (32 * 1024) / (4 * L.stride[1])))};
-    auto grid_for = [&](int rows) {
-      const int64_t tiles = (S + rows - 1) / rows;
-      return (int)std::min<int64_t>(tiles, (int64_t)img->num_cus * 16);
-    };
-    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, S, budget_rows[0],
-                              L.stride[0], grid_for(budget_rows[0]), st);
+    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, S, img->num_cus, st);
     if (e == hipSuccess)
       e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
                             (int)L.blocks.size(), L.dev_mats, W1, W2, S, L.ldw,
                             block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S), st);
     if (e == hipSuccess)
-      e = launch_permute_stages(L.pass[1], W2, static_cast<float *>(out), S, budget_rows[1],
-                                L.stride[1], grid_for(budget_rows[1]), st);
+      e = launch_permute_stages(L.pass[1], W2, static_cast<float *>(out), S, img->num_cus, st);
     const hipError_t ef = hipFreeAsync(ws, st);
     if (e == hipSuccess) e = ef;
   } else if (img->butterfly) {

@@ -91,33 +91,29 @@ struct UProgram {
 
 // Large-signal engine (signals that do not fit a workgroup's LDS tile, or large leaf
 // blocks): three passes through a block-contiguous workspace W with row stride ldw.
-//   pass 1 / pass 3 (gather, optional Haar stages): per signal row,
-//       tile[j] = scatter[j] < 0 ? 0 : in[row * ld_in + scatter[j]]    (j < n_tile)
-//       stages on the tile (pass with num_stages > 0 only; the tile lives in LDS)
-//       out[row * ld_out + c] = gather[c] < 0 ? 0 : tile[gather[c]]    (c < out_cols)
-//     (`scatter` names the input column each tile entry is read from; null = identity;
-//     with no stages the tile is not materialised and out[c] = in[scatter[gather[c]]],
-//     the host passing a composed `gather`);
+//   pass 1 / pass 3 (stage + gather): a tile of a few signal rows is copied as is into LDS
+//     (row stride in_cols), the Haar stages run on it (pass with num_stages > 0 only; the
+//     op indices are tile columns), and output column c of each row takes tile column
+//     gather[c] (-1: zero; gather null: identity);
 //   pass 2 (grouped GEMM): W2[:, off_b : off_b + b] = W[:, off_b : off_b + b] * M_b for
-//     every leaf block b (M_b row-major b x b with row stride ld_b), MFMA tiles.
-// Forward: x -[stages]-> W (block layout) -[GEMM]-> W2 -[permute]-> y (output order).
-// Inverse: y -[permute]-> W (block layout) -[GEMM]-> W2 -[stages reversed]-> x.
+//     every leaf block b, MFMA tiles.  M_b is stored transposed (row c of the stored
+//     matrix is column c of M_b, row stride ld_b), so both operands are contiguous in k.
+// Forward: x -[stages, gather]-> W (block layout) -[GEMM]-> W2 -[gather]-> y (output order).
+// Inverse: y -[gather]-> W (block layout) -[GEMM]-> W2 -[stages, gather]-> x.
 struct PermPass {
-  int32_t n_tile;           // tile row length (node or coefficient space)
-  int32_t in_cols, ld_in;   // input columns and row stride
-  int32_t out_cols, ld_out; // columns written per row and output row stride
+  int32_t in_cols;          // input row length = input row stride = tile row stride
+  int32_t out_cols;         // output row length = output row stride
   int32_t num_stages;       // Haar stages applied to the tile
-  const int32_t *scatter;   // n_tile entries: input column of each tile entry (or null)
-  const int32_t *gather;    // out_cols entries: tile entry of each output column (or null)
+  const int32_t *gather;    // out_cols entries: tile column of each output column (or null)
   const int32_t *stages;    // 2 words per stage: op offset, op count
-  const int32_t *ops;       // 2 words per op: (i, j) or (c, -1)
+  const uint32_t *ops;      // per op: i | j << 16 (tile columns); j = 0xffff: scale i by sqrt 2
 };
 
 struct LBlock {
   int32_t size;     // b
   int32_t col;      // column offset in the workspace (multiple of 4)
-  int32_t mat;      // offset of M_b in the matrix array (elements, multiple of 4)
-  int32_t ld;       // row stride of M_b (multiple of 4, >= b)
+  int32_t mat;      // offset of M_b^T in the matrix array (elements, multiple of 4)
+  int32_t ld;       // row stride of M_b^T (multiple of 4, >= b)
 };
 
 }  // namespace gft

@@ -17,6 +17,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr float kSqrt2f = 1.41421356237309504880f;
@@ -32,62 +33,97 @@ __device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, 
   return __builtin_bit_cast(bf16x4, w);
 }
 
+// BF16 k values 4s .. 4s+3 of an 8-value fragment
+__device__ __forceinline__ bf16x4 half_of(u32x4 w, int s) {
+  const u32x2 h = s == 0 ? u32x2{w[0], w[1]} : u32x2{w[2], w[3]};
+  return __builtin_bit_cast(bf16x4, h);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- pass 1/3
 
-// Rows of `rows` signals per tile: tile[r][j] = in[r * ld_in + (scatter-inverse) ...].
-// The pass is given in gather form on both sides:
-//   load:  tile[r][j] = gin[j] < 0 ? 0 : in[r * ld_in + gin[j]]        (j < n_tile)
-//   store: out[r * ld_out + c] = gout[c] < 0 ? 0 : tile[r][gout[c]]    (c < out_cols)
-// (gin / gout null = identity).  With no stages the tile is skipped altogether: each
-// output element gathers its input directly (a row is a few KB, so the gathered reads stay
-// in L2 while writes are coalesced).
+// One tile = `rows` consecutive signal rows.  Rows are contiguous in memory and in LDS
+// (tile row stride = in_cols), so the load is a straight copy of rows x in_cols floats
+// (float4 when in_cols is a multiple of 4).  Each Haar op is then applied to every row of
+// the tile by one thread (the ops of a stage are disjoint), and the store gathers each
+// output column from its tile column, threads owning columns (float4 stores when out_cols
+// is a multiple of 4) so each index-table entry is read once per tile.
 __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const float *in,
                                                                float *out, int64_t S,
-                                                               int rows, int stride) {
+                                                               int rows) {
+  extern __shared__ __attribute__((aligned(16))) float tile[];
   const int tid = threadIdx.x;
-  if (P.num_stages == 0) {
-    const int64_t total = S * (int64_t)P.out_cols;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + tid; e < total; e += (int64_t)gridDim.x * kThreads) {
-      const int64_t r = e / P.out_cols;
-      const int c = (int)(e - r * P.out_cols);
-      const int src = P.gather ? P.gather[c] : c;
-      out[r * P.ld_out + c] = src >= 0 ? in[r * P.ld_in + src] : 0.0f;
-    }
-    return;
-  }
-  extern __shared__ float tile[];
+  const int ic = P.in_cols, oc = P.out_cols;
   const int64_t ntiles = (S + rows - 1) / rows;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t r0 = t * rows;
     const int nr = (int)((S - r0) < rows ? (S - r0) : rows);
-    for (int idx = tid; idx < nr * P.n_tile; idx += kThreads) {
-      const int r = idx / P.n_tile, j = idx - r * P.n_tile;
-      const int src = P.scatter ? P.scatter[j] : j;
-      tile[r * stride + j] = src >= 0 ? in[(r0 + r) * (int64_t)P.ld_in + src] : 0.0f;
+    // load
+    const float *src = in + r0 * ic;
+    if ((ic & 3) == 0) {
+      const int tot = nr * (ic >> 2);
+      const floatx4 *s4 = reinterpret_cast<const floatx4 *>(src);
+      floatx4 *t4 = reinterpret_cast<floatx4 *>(tile);
+      int e = tid;
+      for (; e + 3 * kThreads < tot; e += 4 * kThreads) {
+        floatx4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = s4[e + q * kThreads];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t4[e + q * kThreads] = v[q];
+      }
+      for (; e < tot; e += kThreads) t4[e] = s4[e];
+    } else {
+      const int tot = nr * ic;
+      for (int e = tid; e < tot; e += kThreads) tile[e] = src[e];
     }
     __syncthreads();
+    // Haar stages
     for (int s = 0; s < P.num_stages; ++s) {
       const int off = P.stages[2 * s], cnt = P.stages[2 * s + 1];
-      for (int idx = tid; idx < nr * cnt; idx += kThreads) {
-        const int r = idx / cnt, u = idx - r * cnt;
-        const int i = P.ops[2 * (off + u)], j = P.ops[2 * (off + u) + 1];
-        float *row = tile + r * stride;
-        if (j >= 0) {
-          const float a = row[i], b = row[j];
-          row[i] = a + b;
-          row[j] = a - b;
+      for (int u = tid; u < cnt; u += kThreads) {
+        const uint32_t op = P.ops[off + u];
+        const int i = (int)(op & 0xffffu), j = (int)(op >> 16);
+        if (j != 0xffff) {
+          for (int r = 0; r < nr; ++r) {
+            float *row = tile + r * ic;
+            const float a = row[i], b = row[j];
+            row[i] = a + b;
+            row[j] = a - b;
+          }
         } else {
-          row[i] *= kSqrt2f;
+          for (int r = 0; r < nr; ++r) tile[r * ic + i] *= kSqrt2f;
         }
       }
       __syncthreads();
     }
-    for (int idx = tid; idx < nr * P.out_cols; idx += kThreads) {
-      const int r = idx / P.out_cols, c = idx - r * P.out_cols;
-      const int g = P.gather ? P.gather[c] : c;
-      out[(r0 + r) * (int64_t)P.ld_out + c] = g >= 0 ? tile[r * stride + g] : 0.0f;
+    // gather + store
+    float *dst = out + r0 * oc;
+    if ((oc & 3) == 0) {
+      for (int c = 4 * tid; c < oc; c += 4 * kThreads) {
+        int g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = P.gather ? P.gather[c + q] : c + q;
+#pragma unroll 4
+        for (int r = 0; r < nr; ++r) {
+          floatx4 v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float x = tile[r * ic + (g[q] >= 0 ? g[q] : 0)];
+            v[q] = g[q] >= 0 ? x : 0.0f;
+          }
+          *reinterpret_cast<floatx4 *>(dst + (int64_t)r * oc + c) = v;
+        }
+      }
+    } else {
+      for (int c = tid; c < oc; c += kThreads) {
+        const int g = P.gather ? P.gather[c] : c;
+        for (int r = 0; r < nr; ++r) {
+          const float x = tile[r * ic + (g >= 0 ? g : 0)];
+          dst[(int64_t)r * oc + c] = g >= 0 ? x : 0.0f;
+        }
+      }
     }
     __syncthreads();
   }
@@ -95,28 +131,50 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
 
 // ---------------------------------------------------------------------------- pass 2
 
-// Grouped GEMM over leaf blocks: C[:, col_b + j] = sum_k A[:, col_b + k] * M_b[k][j].
-// Workgroup tile 128 signals x 128 columns, K step 16, four waves of 64 x 64 each
-// (4 x 4 MFMA 16x16 tiles).  A and B tiles are prefetched into registers while the
-// previous tile is multiplied out of LDS (A stored k-major so that MFMA operand reads are
-// conflict-free); the prefetch is unconditional (the last tile is re-read) because loads
-// under a branch are waited for inside it.  PREC: 0 = FP32 (16x16x4 f32), 1 = BF16, 3 = split BF16 hi+lo (16x16x16
-// bf16; three products for split).
-constexpr int kBM = 128, kBN = 128, kBK = 16, kPad = 4;
+// Grouped GEMM over leaf blocks: C[:, col_b + j] = sum_k A[:, col_b + k] * M_b[k][j], M_b
+// read from its stored transpose.  Workgroup tile 128 signals x 128 columns, four waves of
+// 64 x 64 (4 x 4 MFMA 16x16 tiles).  Both operands sit in LDS with k contiguous per row
+// (As[m][k], Bs[n][k], rows padded by 16 bytes).  The contraction sums over k, so the k that
+// a lane supplies to each MFMA may be permuted as long as A and B agree: per 16 (FP32) or
+// 32 (BF16) k, lane (g, r) takes the consecutive k = 4g .. 4g+3 (four 16x16x4 steps) or
+// 8g .. 8g+7 (two 16x16x16 steps) and reads each fragment with one 16-byte LDS load.  BF16 operands are rounded once,
+// when the tile is written to LDS (split BF16: hi and lo planes, three products).  LDS is
+// double buffered, so one barrier per K step; the next global tile is loaded into registers
+// (unconditionally: the last tile is re-read, since loads under a branch are waited for
+// inside it) while the current one is multiplied.
+//
+// Tiles are numbered block by block, m tile by m tile, n tiles fastest.  Workgroup i runs
+// on XCD i mod 8, so within each window of 64 workgroups the numbering is regrouped to give
+// every XCD 8 consecutive tiles (those that share an A panel then share one L2) while the
+// windows keep the work spread evenly over the XCDs, whatever the block sizes.
+constexpr int kBM = 128, kBN = 128;
 
-template <int PREC>
+template <int PREC, int BK_> struct GemmCfg {
+  static constexpr int BK = BK_;                            // K step
+  static constexpr int row_bytes = BK * (PREC == 0 ? 4 : 2) + 16;  // LDS row, padded
+  static constexpr int planes = PREC == 3 ? 2 : 1;          // split: hi + lo
+  static constexpr int plane_bytes = kBM * row_bytes;       // one operand tile
+  static constexpr int buf_bytes = 2 * planes * plane_bytes;
+  static constexpr int lds_bytes = 2 * buf_bytes;           // double buffered
+};
+
+template <int PREC, int BK>
 __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restrict__ blocks,
                                                            int nblocks, const float *mats,
                                                            const float *A, float *C, int64_t S,
                                                            int ld) {
-  __shared__ __attribute__((aligned(16))) float As[kBK][kBM + kPad];
-  __shared__ __attribute__((aligned(16))) float Bs[kBK][kBN + kPad];
+  using Cfg = GemmCfg<PREC, BK>;
+  constexpr int NQ = BK / 4, NLD = BK / 8;                  // float4 per row, loads per thread
+  constexpr int kRowBytes = Cfg::row_bytes;
+  constexpr int KS = PREC == 0 ? 4 : 8;                     // k per lane per fragment load
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
-  // locate (block, m tile, n tile) of this workgroup
-  const int64_t mtiles = (S + kBM - 1) / kBM;
+
   int64_t id = blockIdx.x;
+  if (id < (int64_t)(gridDim.x & ~63u)) id = (id & ~63ll) + ((id & 7) << 3) + ((id >> 3) & 7);
+  const int64_t mtiles = (S + kBM - 1) / kBM;
   int b = 0;
   for (; b < nblocks; ++b) {
     const int64_t nt = (blocks[b].size + kBN - 1) / kBN;
@@ -130,42 +188,60 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
   const int col0 = (int)(id % ntb) * kBN;
   const int K = blk.size;
   const float *Ab = A + blk.col;
-  const float *Bm = mats + blk.mat;
+  const float *Bt = mats + blk.mat;
 
-  // register prefetch of one K tile: A 128x16 (2 float4 per thread), B 16x128 (2 float4)
-  floatx4 ra[2], rb[2];
+  // global -> registers: NLD float4 of A (row m, k quad kq) and of B^T (row n, k quad kq)
+  floatx4 ra[NLD], rb[NLD];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NLD; ++i) {
       const int idx = tid + kThreads * i;
-      const int m = idx >> 2, kq = (idx & 3) * 4;
+      const int m = idx / NQ, kq = (idx % NQ) * 4;
+      const int k = k0 + kq;
+      const int kc = k < K ? k : 0;                        // rows are padded to 4: in bounds
       int64_t row = row0 + m;
       row = row < S ? row : S - 1;                         // clamped: never stored
-      const int k = k0 + kq;
-      floatx4 v = *reinterpret_cast<const floatx4 *>(Ab + row * ld + (k < K ? k : 0));
+      floatx4 v = *reinterpret_cast<const floatx4 *>(Ab + row * ld + kc);
+      const int c = col0 + m;
+      floatx4 w = *reinterpret_cast<const floatx4 *>(Bt + (int64_t)(c < K ? c : K - 1) * blk.ld + kc);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         if (k + j >= K) v[j] = 0.0f;
+        if (k + j >= K || c >= K) w[j] = 0.0f;
+      }
       ra[i] = v;
-      const int kb = idx >> 5, nq = (idx & 31) * 4;
-      const int kr = k0 + kb < K ? k0 + kb : K - 1;
-      const int c = col0 + nq;
-      floatx4 w = *reinterpret_cast<const floatx4 *>(Bm + (int64_t)kr * blk.ld + (c < blk.ld ? c : 0));
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (k0 + kb >= K || c + j >= K) w[j] = 0.0f;
       rb[i] = w;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
+    char *base = smem + buf * Cfg::buf_bytes;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NLD; ++i) {
       const int idx = tid + kThreads * i;
-      const int m = idx >> 2, kq = (idx & 3) * 4;
+      const int m = idx / NQ, kq = (idx % NQ) * 4;
+      if constexpr (PREC == 0) {
+        *reinterpret_cast<floatx4 *>(base + m * kRowBytes + kq * 4) = ra[i];
+        *reinterpret_cast<floatx4 *>(base + Cfg::plane_bytes + m * kRowBytes + kq * 4) = rb[i];
+      } else {
+        uint32_t ah[4], bh[4], al[4], bl[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) As[kq + j][m] = ra[i][j];
-      const int kb = idx >> 5, nq = (idx & 31) * 4;
-      *reinterpret_cast<floatx4 *>(&Bs[kb][nq]) = rb[i];
+        for (int j = 0; j < 4; ++j) {
+          ah[j] = bf16_bits(ra[i][j]);
+          bh[j] = bf16_bits(rb[i][j]);
+          al[j] = bf16_bits(ra[i][j] - __uint_as_float(ah[j] << 16));
+          bl[j] = bf16_bits(rb[i][j] - __uint_as_float(bh[j] << 16));
+        }
+        const int off = m * kRowBytes + kq * 2;
+        *reinterpret_cast<u32x2 *>(base + off) = u32x2{ah[0] | (ah[1] << 16), ah[2] | (ah[3] << 16)};
+        *reinterpret_cast<u32x2 *>(base + Cfg::plane_bytes + off) =
+            u32x2{bh[0] | (bh[1] << 16), bh[2] | (bh[3] << 16)};
+        if constexpr (PREC == 3) {
+          *reinterpret_cast<u32x2 *>(base + 2 * Cfg::plane_bytes + off) =
+              u32x2{al[0] | (al[1] << 16), al[2] | (al[3] << 16)};
+          *reinterpret_cast<u32x2 *>(base + 3 * Cfg::plane_bytes + off) =
+              u32x2{bl[0] | (bl[1] << 16), bl[2] | (bl[3] << 16)};
+        }
+      }
     }
   };
 
@@ -175,64 +251,58 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  const int nk = (K + kBK - 1) / kBK;
+  const int nk = (K + BK - 1) / BK;
   load(0);
+  store(0);
+  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    store();
-    __syncthreads();
-    load((kt + 1 < nk ? kt + 1 : kt) * kBK);   // unconditional: see the prefetch note
-    if constexpr (PREC == 0) {
+    load((kt + 1 < nk ? kt + 1 : kt) * BK);    // unconditional: see the prefetch note
+    const char *base = smem + (kt & 1) * Cfg::buf_bytes;
 #pragma unroll
-      for (int kk = 0; kk < kBK / 4; ++kk) {
-        float a[4], bb[4];
+    for (int h = 0; h < BK / (4 * KS); ++h) {     // 16-byte fragments: k = 4*KS*h + KS*g + ...
+      const int aoff = (wm * 64 + r) * kRowBytes + 16 * (4 * h + g);
+      const int boff = Cfg::plane_bytes + (wn * 64 + r) * kRowBytes + 16 * (4 * h + g);
+      if constexpr (PREC == 0) {
+        floatx4 a4[4], b4[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As[4 * kk + g][wm * 64 + 16 * i + r];
+        for (int i = 0; i < 4; ++i) a4[i] = *reinterpret_cast<const floatx4 *>(base + aoff + i * 16 * kRowBytes);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bb[j] = Bs[4 * kk + g][wn * 64 + 16 * j + r];
+        for (int j = 0; j < 4; ++j) b4[j] = *reinterpret_cast<const floatx4 *>(base + boff + j * 16 * kRowBytes);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      // 16x16x16 bf16: lane (g, r) supplies A[r][4g + q] and B[4g + q][r], q < 4
-      bf16x4 ahi[4], alo[4], bhi[4], blo[4];
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        uint32_t h[4], l[4];
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[i][kk], b4[j][kk], acc[i][j], 0, 0, 0);
+      } else {
+        u32x4 ah[4], bh[4], al[4], bl[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x = As[4 * g + q][wm * 64 + 16 * i + r];
-          h[q] = bf16_bits(x);
-          l[q] = bf16_bits(x - __uint_as_float(h[q] << 16));
+        for (int i = 0; i < 4; ++i) {
+          ah[i] = *reinterpret_cast<const u32x4 *>(base + aoff + i * 16 * kRowBytes);
+          if constexpr (PREC == 3) al[i] = *reinterpret_cast<const u32x4 *>(base + 2 * Cfg::plane_bytes + aoff + i * 16 * kRowBytes);
         }
-        ahi[i] = pack_bf16(h[0], h[1], h[2], h[3]);
-        alo[i] = pack_bf16(l[0], l[1], l[2], l[3]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        uint32_t h[4], l[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x = Bs[4 * g + q][wn * 64 + 16 * j + r];
-          h[q] = bf16_bits(x);
-          l[q] = bf16_bits(x - __uint_as_float(h[q] << 16));
-        }
-        bhi[j] = pack_bf16(h[0], h[1], h[2], h[3]);
-        blo[j] = pack_bf16(l[0], l[1], l[2], l[3]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
-          if constexpr (PREC == 3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], acc[i][j], 0, 0, 0);
-          }
+          bh[j] = *reinterpret_cast<const u32x4 *>(base + boff + j * 16 * kRowBytes);
+          if constexpr (PREC == 3) bl[j] = *reinterpret_cast<const u32x4 *>(base + 2 * Cfg::plane_bytes + boff + j * 16 * kRowBytes);
         }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const bf16x4 a = half_of(ah[i], s), bb = half_of(bh[j], s);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
+              if constexpr (PREC == 3) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, half_of(bl[j], s), acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(half_of(al[i], s), bb, acc[i][j], 0, 0, 0);
+              }
+            }
+      }
     }
+    store((kt + 1) & 1);     // the other buffer: last read before the previous barrier
     __syncthreads();
   }
   // epilogue: lane (g, r) holds rows 4g + v, column r of each 16x16 tile
@@ -252,16 +322,26 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
 
 // ---------------------------------------------------------------------------- launch
 
+int permute_rows(const PermPass &P) {
+  // about 40 KB of LDS per tile (four workgroups per CU), 1 to 16 rows
+  const int rows = (40 * 1024) / (4 * P.in_cols);
+  return rows < 1 ? 1 : (rows > 16 ? 16 : rows);
+}
+
 hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
-                                 int rows, int stride, int grid, hipStream_t stream) {
-  const size_t lds = P.num_stages ? (size_t)rows * stride * 4 : 0;
+                                 int num_cus, hipStream_t stream) {
+  const int rows = permute_rows(P);
+  const size_t lds = (size_t)rows * P.in_cols * 4;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_permute_stages,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  const int64_t tiles = (S + rows - 1) / rows;
+  const int64_t cap = (int64_t)num_cus * 8;
+  const int grid = (int)(tiles < cap ? tiles : cap);
   hipLaunchKernelGGL(gft_permute_stages, dim3(grid), dim3(kThreads), lds, stream, P, in, out, S,
-                     rows, stride);
+                     rows);
   return hipGetLastError();
 }
 
@@ -272,21 +352,32 @@ int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S) {
   return tiles;
 }
 
+template <int PREC, int BK>
+static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const float *mats,
+                                   const float *A, float *C, int64_t S, int ld, int64_t grid,
+                                   hipStream_t stream) {
+  const int lds = GemmCfg<PREC, BK>::lds_bytes;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)gft_block_gemm<PREC, BK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((gft_block_gemm<PREC, BK>), dim3((unsigned)grid), dim3(kThreads), lds, stream,
+                     blocks, nblocks, mats, A, C, S, ld);
+  return hipGetLastError();
+}
+
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const float *mats,
                              const float *A, float *C, int64_t S, int ld, int64_t grid,
                              hipStream_t stream) {
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   switch (prec) {
-    case 0: hipLaunchKernelGGL(gft_block_gemm<0>, dim3((unsigned)grid), dim3(kThreads), 0, stream,
-                               blocks, nblocks, mats, A, C, S, ld); break;
-    case 1: hipLaunchKernelGGL(gft_block_gemm<1>, dim3((unsigned)grid), dim3(kThreads), 0, stream,
-                               blocks, nblocks, mats, A, C, S, ld); break;
-    case 3: hipLaunchKernelGGL(gft_block_gemm<3>, dim3((unsigned)grid), dim3(kThreads), 0, stream,
-                               blocks, nblocks, mats, A, C, S, ld); break;
+    case 0: return launch_gemm_prec<0, 16>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
+    case 1: return launch_gemm_prec<1, 32>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
+    case 3: return launch_gemm_prec<3, 32>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace gft

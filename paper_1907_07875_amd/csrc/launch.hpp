@@ -24,8 +24,9 @@ hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const in
                               int grid, hipStream_t stream);
 
 // Large-signal engine.
+int permute_rows(const PermPass &P);   // signal rows per LDS tile of a stage/gather pass
 hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
-                                 int rows, int stride, int grid, hipStream_t stream);
+                                 int num_cus, hipStream_t stream);
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const float *mats,
                              const float *A, float *C, int64_t S, int ld, int64_t grid,

@@ -347,7 +347,7 @@ bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
 
 namespace gft {
 
-void build_large(const GraphPlan &p, int direction, LargeImage &out) {
+bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   LargeImage im;
   const int n = p.n;
   im.n = n;
@@ -367,62 +367,59 @@ void build_large(const GraphPlan &p, int direction, LargeImage &out) {
     mat += (size_t)B.size * ld;
   }
   im.ldw = col;
+  if (im.ldw > kLargeMaxCols || mat > (size_t)INT32_MAX) return false;
   im.mats.assign(mat, 0.0f);
   for (size_t b = 0; b < p.blocks.size(); ++b) {
     const HostBlock &B = p.blocks[b];
     const LBlock &L = im.blocks[b];
     for (int k = 0; k < B.size; ++k)
-      for (int c = 0; c < B.size; ++c)  // forward M[k][c] = V[k][c]; inverse M[k][j] = V[j][k]
-        im.mats[(size_t)L.mat + (size_t)k * L.ld + c] =
+      for (int c = 0; c < B.size; ++c)  // stored transposed: Mt[c][k] = M[k][c], with
+        // forward M[k][c] = V[k][c] and inverse M[k][j] = V[j][k]
+        im.mats[(size_t)L.mat + (size_t)c * L.ld + k] =
             (float)(B.scale * (direction == 0 ? B.V[(size_t)k * B.size + c] : B.V[(size_t)c * B.size + k]));
   }
-  // stage program (forward order for the forward, reversed for the inverse)
-  std::vector<int32_t> st, ops;
-  const int ns = (int)p.stages.size();
-  for (int q = 0; q < ns; ++q) {
-    const HostStage &S = p.stages[direction == 0 ? q : ns - 1 - q];
-    const int off = (int)(ops.size() / 2);
-    for (size_t u = 0; u < S.pair_x.size(); ++u) {
-      ops.push_back(S.pair_x[u]);
-      ops.push_back(S.pair_y[u]);
-    }
-    for (int32_t c : S.znodes) {
-      ops.push_back(c);
-      ops.push_back(-1);
-    }
-    st.push_back(off);
-    st.push_back((int)(ops.size() / 2) - off);
-  }
-  const int stages_pass = direction == 0 ? 0 : 1;   // forward: stages in pass 1; inverse: pass 3
-  im.stages[stages_pass] = st;
-  im.ops[stages_pass] = ops;
-  // Both passes in gather form: tile entry j reads input column src[j]; output column c
-  // reads tile entry dst[c].  Workspace column col holds node col_node[col] (coefficient
-  // col_coef[col]) of its block, or padding (-1).
+  // Workspace column col holds node col_node[col] (coefficient col_coef[col]) of its block,
+  // or padding (-1).
   auto inverse_of = [&](const std::vector<int32_t> &cols, int nvals) {
     std::vector<int32_t> inv(nvals, -1);   // value -> workspace column
     for (int c = 0; c < (int)cols.size(); ++c)
       if (cols[c] >= 0) inv[cols[c]] = c;
     return inv;
   };
+  const std::vector<int32_t> wcol_node = inverse_of(col_node, n);
+  // stage program (forward order for the forward, reversed for the inverse); the forward
+  // runs it on x (tile columns = nodes), the inverse on W2 (tile columns = workspace)
+  const int stages_pass = direction == 0 ? 0 : 1;
+  auto tcol = [&](int32_t v) { return (uint32_t)(direction == 0 ? v : wcol_node[v]); };
+  std::vector<int32_t> st;
+  std::vector<uint32_t> ops;
+  const int ns = (int)p.stages.size();
+  for (int q = 0; q < ns; ++q) {
+    const HostStage &S = p.stages[direction == 0 ? q : ns - 1 - q];
+    const int off = (int)ops.size();
+    for (size_t u = 0; u < S.pair_x.size(); ++u) ops.push_back(tcol(S.pair_x[u]) | (tcol(S.pair_y[u]) << 16));
+    for (int32_t c : S.znodes) ops.push_back(tcol(c) | (0xffffu << 16));
+    st.push_back(off);
+    st.push_back((int)ops.size() - off);
+  }
+  im.stages[stages_pass] = st;
+  im.ops[stages_pass] = ops;
   for (int k = 0; k < 2; ++k) {
     PermPass &P = im.pass[k];
-    P.n_tile = n;
-    im.stride[k] = n | 1;
     P.num_stages = k == stages_pass ? ns : 0;
     const std::vector<int32_t> &map = (direction == 0) == (k == 0) ? col_node : col_coef;
     if (k == 0) {          // n-wide input -> workspace layout
-      P.in_cols = P.ld_in = n;
-      P.out_cols = P.ld_out = im.ldw;
-      im.gather[k] = map;                            // tile (n-space) entry of each ws column
+      P.in_cols = n;
+      P.out_cols = im.ldw;
+      im.gather[k] = map;                        // node / coefficient of each ws column
     } else {               // workspace layout -> n-wide output
-      P.in_cols = P.ld_in = im.ldw;
-      P.out_cols = P.ld_out = n;
-      if (P.num_stages) im.scatter[k] = inverse_of(map, n);   // ws column of each tile entry
-      else im.gather[k] = inverse_of(map, n);                 // composed: ws column of output c
+      P.in_cols = im.ldw;
+      P.out_cols = n;
+      im.gather[k] = inverse_of(map, n);         // ws column of each node / coefficient
     }
   }
   out = std::move(im);
+  return true;
 }
 
 }  // namespace gft

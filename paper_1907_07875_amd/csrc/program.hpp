@@ -51,9 +51,9 @@ bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out);
 // Host image of the large-signal engine for one direction (see PermPass, LBlock).
 struct LargeImage {
   int32_t n = 0, ldw = 0;
-  int32_t stride[2] = {0, 0};  // LDS row stride of passes 1 and 3
   PermPass pass[2]{};          // pointers left null until upload
-  std::vector<int32_t> scatter[2], gather[2], stages[2], ops[2];
+  std::vector<int32_t> gather[2], stages[2];
+  std::vector<uint32_t> ops[2];
   std::vector<LBlock> blocks;
   std::vector<int32_t> block_sizes;
   std::vector<float> mats;
@@ -61,7 +61,11 @@ struct LargeImage {
   const float *dev_mats = nullptr;
 };
 
+// Largest tile row (workspace columns) of the large-signal engine: op indices are 16-bit.
+constexpr int kLargeMaxCols = 65535;
+
 // Build the large-signal engine image of `p` for direction 0 (forward) or 1 (inverse).
-void build_large(const GraphPlan &p, int direction, LargeImage &out);
+// Returns false when the workspace row would exceed kLargeMaxCols.
+bool build_large(const GraphPlan &p, int direction, LargeImage &out);
 
 }  // namespace gft
