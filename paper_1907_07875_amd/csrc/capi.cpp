@@ -211,8 +211,11 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       // matrices last (largest)
     }
   size_t lmat[2] = {};
+  const bool mats16 = plan->opts.precision == GFT_BF16;   // the GEMM reads one of the two
   if (use_large)
-    for (int d = 0; d < 2; ++d) lmat[d] = blob.add(lgi[d].mats.data(), lgi[d].mats.size() * 4);
+    for (int d = 0; d < 2; ++d)
+      lmat[d] = mats16 ? blob.add(lgi[d].mats16.data(), lgi[d].mats16.size() * 2)
+                       : blob.add(lgi[d].mats.data(), lgi[d].mats.size() * 4);
   const size_t bytes = blob.bytes.size();
   auto img = std::make_unique<DeviceImage>();
   img->device = dev;
@@ -261,9 +264,12 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
         P.ops = reinterpret_cast<const uint32_t *>(base + loff[d][5]);
       }
       L.dev_blocks = reinterpret_cast<const LBlock *>(base + loff[d][6]);
-      L.dev_mats = reinterpret_cast<const float *>(base + lmat[d]);
+      L.dev_mats = mats16 ? nullptr : reinterpret_cast<const float *>(base + lmat[d]);
+      L.dev_mats16 = mats16 ? reinterpret_cast<const uint16_t *>(base + lmat[d]) : nullptr;
       L.mats.clear();
       L.mats.shrink_to_fit();
+      L.mats16.clear();
+      L.mats16.shrink_to_fit();
     }
   }
   if (plan->batch) {
@@ -331,13 +337,15 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
     e = hipMallocAsync(&ws, ws_bytes, st);
     if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
     float *W1 = static_cast<float *>(ws), *W2 = W1 + (size_t)S * L.ldw;
-    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, S, img->num_cus, st);
+    const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
+    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st);
     if (e == hipSuccess)
       e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
-                            (int)L.blocks.size(), L.dev_mats, W1, W2, S, L.ldw,
+                            (int)L.blocks.size(), ws16 ? (const void *)L.dev_mats16 : (const void *)L.dev_mats,
+                            W1, W2, S, L.ldw,
                             block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S), st);
     if (e == hipSuccess)
-      e = launch_permute_stages(L.pass[1], W2, static_cast<float *>(out), S, img->num_cus, st);
+      e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st);
     const hipError_t ef = hipFreeAsync(ws, st);
     if (e == hipSuccess) e = ef;
   } else if (img->butterfly) {

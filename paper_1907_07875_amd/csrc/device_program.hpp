@@ -96,7 +96,8 @@ struct UProgram {
 //     op indices are tile columns), and output column c of each row takes tile column
 //     gather[c] (-1: zero; gather null: identity);
 //   pass 2 (grouped GEMM): W2[:, off_b : off_b + b] = W[:, off_b : off_b + b] * M_b for
-//     every leaf block b, MFMA tiles.  M_b is stored transposed (row c of the stored
+//     every leaf block b, MFMA tiles.  With BF16 blocks, W and the matrices are stored in
+//     BF16 (pass 1 rounds its output), W2 stays FP32.  M_b is stored transposed (row c of the stored
 //     matrix is column c of M_b, row stride ld_b), so both operands are contiguous in k.
 // Forward: x -[stages, gather]-> W (block layout) -[GEMM]-> W2 -[gather]-> y (output order).
 // Inverse: y -[gather]-> W (block layout) -[GEMM]-> W2 -[stages, gather]-> x.
@@ -111,9 +112,9 @@ struct PermPass {
 
 struct LBlock {
   int32_t size;     // b
-  int32_t col;      // column offset in the workspace (multiple of 4)
-  int32_t mat;      // offset of M_b^T in the matrix array (elements, multiple of 4)
-  int32_t ld;       // row stride of M_b^T (multiple of 4, >= b)
+  int32_t col;      // column offset in the workspace (multiple of 8)
+  int32_t mat;      // offset of M_b^T in the matrix array (elements, multiple of 8)
+  int32_t ld;       // row stride of M_b^T (multiple of 8, >= b)
 };
 
 }  // namespace gft

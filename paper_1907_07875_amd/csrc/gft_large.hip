@@ -48,9 +48,11 @@ __device__ __forceinline__ bf16x4 half_of(u32x4 w, int s) {
 // (float4 when in_cols is a multiple of 4).  Each Haar op is then applied to every row of
 // the tile by one thread (the ops of a stage are disjoint), and the store gathers each
 // output column from its tile column, threads owning columns (float4 stores when out_cols
-// is a multiple of 4) so each index-table entry is read once per tile.
+// is a multiple of 4) so each index-table entry is read once per tile.  OUT16: the output
+// is rounded to BF16 (round to nearest even), the workspace of BF16 leaf blocks.
+template <bool OUT16>
 __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const float *in,
-                                                               float *out, int64_t S,
+                                                               void *out_raw, int64_t S,
                                                                int rows) {
   extern __shared__ __attribute__((aligned(16))) float tile[];
   const int tid = threadIdx.x;
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
       __syncthreads();
     }
     // gather + store
-    float *dst = out + r0 * oc;
+    float *dst = static_cast<float *>(out_raw) + r0 * oc;
+    uint16_t *dst16 = static_cast<uint16_t *>(out_raw) + r0 * oc;
     if ((oc & 3) == 0) {
       for (int c = 4 * tid; c < oc; c += 4 * kThreads) {
         int g[4];
@@ -113,15 +116,22 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
             const float x = tile[r * ic + (g[q] >= 0 ? g[q] : 0)];
             v[q] = g[q] >= 0 ? x : 0.0f;
           }
-          *reinterpret_cast<floatx4 *>(dst + (int64_t)r * oc + c) = v;
+          if constexpr (OUT16)
+            *reinterpret_cast<u32x2 *>(dst16 + (int64_t)r * oc + c) =
+                u32x2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)};
+          else
+            *reinterpret_cast<floatx4 *>(dst + (int64_t)r * oc + c) = v;
         }
       }
     } else {
       for (int c = tid; c < oc; c += kThreads) {
         const int g = P.gather ? P.gather[c] : c;
         for (int r = 0; r < nr; ++r) {
-          const float x = tile[r * ic + (g >= 0 ? g : 0)];
-          dst[(int64_t)r * oc + c] = g >= 0 ? x : 0.0f;
+          const float x = g >= 0 ? tile[r * ic + (g >= 0 ? g : 0)] : 0.0f;
+          if constexpr (OUT16)
+            dst16[(int64_t)r * oc + c] = (uint16_t)bf16_bits(x);
+          else
+            dst[(int64_t)r * oc + c] = x;
         }
       }
     }
@@ -160,11 +170,10 @@ template <int PREC, int BK_> struct GemmCfg {
 
 template <int PREC, int BK>
 __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restrict__ blocks,
-                                                           int nblocks, const float *mats,
-                                                           const float *A, float *C, int64_t S,
+                                                           int nblocks, const void *mats_raw,
+                                                           const void *A_raw, float *C, int64_t S,
                                                            int ld) {
   using Cfg = GemmCfg<PREC, BK>;
-  constexpr int NQ = BK / 4, NLD = BK / 8;                  // float4 per row, loads per thread
   constexpr int kRowBytes = Cfg::row_bytes;
   constexpr int KS = PREC == 0 ? 4 : 8;                     // k per lane per fragment load
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -187,27 +196,42 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
   const int64_t row0 = (id / ntb) * kBM;
   const int col0 = (int)(id % ntb) * kBN;
   const int K = blk.size;
-  const float *Ab = A + blk.col;
-  const float *Bt = mats + blk.mat;
 
-  // global -> registers: NLD float4 of A (row m, k quad kq) and of B^T (row n, k quad kq)
-  floatx4 ra[NLD], rb[NLD];
+  // global -> registers.  FP32 storage (PREC 0, 3): NLD float4 of A (row m, k quad kq) and
+  // of B^T (row m of the n tile); BF16 storage (PREC 1): NLD 16-byte groups of 8 k.
+  constexpr int EPL = PREC == 1 ? 8 : 4;                   // elements per 16-byte load
+  constexpr int NQ = BK / EPL, NLD = kBM * NQ / kThreads;  // loads per row, per thread
+  typedef __attribute__((ext_vector_type(4))) uint32_t vec4;
+  vec4 ra[NLD], rb[NLD];
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
       const int idx = tid + kThreads * i;
-      const int m = idx / NQ, kq = (idx % NQ) * 4;
+      const int m = idx / NQ, kq = (idx % NQ) * EPL;
       const int k = k0 + kq;
-      const int kc = k < K ? k : 0;                        // rows are padded to 4: in bounds
+      const int kc = k < K ? k : 0;                        // rows are padded to 8: in bounds
       int64_t row = row0 + m;
       row = row < S ? row : S - 1;                         // clamped: never stored
-      floatx4 v = *reinterpret_cast<const floatx4 *>(Ab + row * ld + kc);
       const int c = col0 + m;
-      floatx4 w = *reinterpret_cast<const floatx4 *>(Bt + (int64_t)(c < K ? c : K - 1) * blk.ld + kc);
+      const int64_t boff = blk.mat + (int64_t)(c < K ? c : K - 1) * blk.ld + kc;
+      vec4 v, w;
+      if constexpr (PREC == 1) {
+        v = *reinterpret_cast<const vec4 *>(static_cast<const uint16_t *>(A_raw) + row * ld + blk.col + kc);
+        w = *reinterpret_cast<const vec4 *>(static_cast<const uint16_t *>(mats_raw) + boff);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (k + j >= K) v[j] = 0.0f;
-        if (k + j >= K || c >= K) w[j] = 0.0f;
+        for (int h = 0; h < 4; ++h) {                      // word h holds k + 2h, k + 2h + 1
+          const uint32_t mask = k + 2 * h >= K ? 0u : (k + 2 * h + 1 >= K ? 0xffffu : 0xffffffffu);
+          v[h] &= mask;
+          w[h] &= c < K ? mask : 0u;
+        }
+      } else {
+        v = *reinterpret_cast<const vec4 *>(static_cast<const float *>(A_raw) + row * ld + blk.col + kc);
+        w = *reinterpret_cast<const vec4 *>(static_cast<const float *>(mats_raw) + boff);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= K) v[j] = 0u;
+          if (k + j >= K || c >= K) w[j] = 0u;
+        }
       }
       ra[i] = v;
       rb[i] = w;
@@ -218,29 +242,31 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
       const int idx = tid + kThreads * i;
-      const int m = idx / NQ, kq = (idx % NQ) * 4;
+      const int m = idx / NQ, kq = (idx % NQ) * EPL;
       if constexpr (PREC == 0) {
-        *reinterpret_cast<floatx4 *>(base + m * kRowBytes + kq * 4) = ra[i];
-        *reinterpret_cast<floatx4 *>(base + Cfg::plane_bytes + m * kRowBytes + kq * 4) = rb[i];
+        *reinterpret_cast<vec4 *>(base + m * kRowBytes + kq * 4) = ra[i];
+        *reinterpret_cast<vec4 *>(base + Cfg::plane_bytes + m * kRowBytes + kq * 4) = rb[i];
+      } else if constexpr (PREC == 1) {
+        *reinterpret_cast<vec4 *>(base + m * kRowBytes + kq * 2) = ra[i];
+        *reinterpret_cast<vec4 *>(base + Cfg::plane_bytes + m * kRowBytes + kq * 2) = rb[i];
       } else {
         uint32_t ah[4], bh[4], al[4], bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          ah[j] = bf16_bits(ra[i][j]);
-          bh[j] = bf16_bits(rb[i][j]);
-          al[j] = bf16_bits(ra[i][j] - __uint_as_float(ah[j] << 16));
-          bl[j] = bf16_bits(rb[i][j] - __uint_as_float(bh[j] << 16));
+          const float xa = __uint_as_float(ra[i][j]), xb = __uint_as_float(rb[i][j]);
+          ah[j] = bf16_bits(xa);
+          bh[j] = bf16_bits(xb);
+          al[j] = bf16_bits(xa - __uint_as_float(ah[j] << 16));
+          bl[j] = bf16_bits(xb - __uint_as_float(bh[j] << 16));
         }
         const int off = m * kRowBytes + kq * 2;
         *reinterpret_cast<u32x2 *>(base + off) = u32x2{ah[0] | (ah[1] << 16), ah[2] | (ah[3] << 16)};
         *reinterpret_cast<u32x2 *>(base + Cfg::plane_bytes + off) =
             u32x2{bh[0] | (bh[1] << 16), bh[2] | (bh[3] << 16)};
-        if constexpr (PREC == 3) {
-          *reinterpret_cast<u32x2 *>(base + 2 * Cfg::plane_bytes + off) =
-              u32x2{al[0] | (al[1] << 16), al[2] | (al[3] << 16)};
-          *reinterpret_cast<u32x2 *>(base + 3 * Cfg::plane_bytes + off) =
-              u32x2{bl[0] | (bl[1] << 16), bl[2] | (bl[3] << 16)};
-        }
+        *reinterpret_cast<u32x2 *>(base + 2 * Cfg::plane_bytes + off) =
+            u32x2{al[0] | (al[1] << 16), al[2] | (al[3] << 16)};
+        *reinterpret_cast<u32x2 *>(base + 3 * Cfg::plane_bytes + off) =
+            u32x2{bl[0] | (bl[1] << 16), bl[2] | (bl[3] << 16)};
       }
     }
   };
@@ -328,20 +354,24 @@ int permute_rows(const PermPass &P) {
   return rows < 1 ? 1 : (rows > 16 ? 16 : rows);
 }
 
-hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
-                                 int num_cus, hipStream_t stream) {
+hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
+                                 int64_t S, int num_cus, hipStream_t stream) {
   const int rows = permute_rows(P);
   const size_t lds = (size_t)rows * P.in_cols * 4;
+  const void *fn = out16 ? (const void *)gft_permute_stages<true> : (const void *)gft_permute_stages<false>;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)gft_permute_stages,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const int64_t tiles = (S + rows - 1) / rows;
   const int64_t cap = (int64_t)num_cus * 8;
   const int grid = (int)(tiles < cap ? tiles : cap);
-  hipLaunchKernelGGL(gft_permute_stages, dim3(grid), dim3(kThreads), lds, stream, P, in, out, S,
-                     rows);
+  if (out16)
+    hipLaunchKernelGGL(gft_permute_stages<true>, dim3(grid), dim3(kThreads), lds, stream, P, in,
+                       out, S, rows);
+  else
+    hipLaunchKernelGGL(gft_permute_stages<false>, dim3(grid), dim3(kThreads), lds, stream, P, in,
+                       out, S, rows);
   return hipGetLastError();
 }
 
@@ -353,8 +383,8 @@ int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S) {
 }
 
 template <int PREC, int BK>
-static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const float *mats,
-                                   const float *A, float *C, int64_t S, int ld, int64_t grid,
+static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const void *mats,
+                                   const void *A, float *C, int64_t S, int ld, int64_t grid,
                                    hipStream_t stream) {
   const int lds = GemmCfg<PREC, BK>::lds_bytes;
   if (lds > 64 * 1024) {
@@ -367,8 +397,8 @@ static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const floa
   return hipGetLastError();
 }
 
-hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const float *mats,
-                             const float *A, float *C, int64_t S, int ld, int64_t grid,
+hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
+                             const void *A, float *C, int64_t S, int ld, int64_t grid,
                              hipStream_t stream) {
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;

@@ -25,11 +25,12 @@ hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const in
 
 // Large-signal engine.
 int permute_rows(const PermPass &P);   // signal rows per LDS tile of a stage/gather pass
-hipError_t launch_permute_stages(const PermPass &P, const float *in, float *out, int64_t S,
-                                 int num_cus, hipStream_t stream);
+hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
+                                 int64_t S, int num_cus, hipStream_t stream);
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
-hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const float *mats,
-                             const float *A, float *C, int64_t S, int ld, int64_t grid,
+// prec: 0 FP32, 1 BF16 (A and matrices stored in BF16), 3 split BF16 (FP32 storage)
+hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
+                             const void *A, float *C, int64_t S, int ld, int64_t grid,
                              hipStream_t stream);
 
 // Register-butterfly engine (uniform hypercube plans).

@@ -351,12 +351,13 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   LargeImage im;
   const int n = p.n;
   im.n = n;
-  // block-contiguous workspace layout, each block's span padded to a multiple of 4
+  // block-contiguous workspace layout, each block's span padded to a multiple of 8 (16-byte
+  // rows of BF16 workspace and matrices)
   std::vector<int32_t> col_node, col_coef;   // per workspace column (or -1 for padding)
   int col = 0;
   size_t mat = 0;
   for (const HostBlock &B : p.blocks) {
-    const int ld = (B.size + 3) & ~3;
+    const int ld = (B.size + 7) & ~7;
     im.blocks.push_back({B.size, col, (int32_t)mat, ld});
     im.block_sizes.push_back(B.size);
     for (int k = 0; k < ld; ++k) {
@@ -378,6 +379,8 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
         im.mats[(size_t)L.mat + (size_t)c * L.ld + k] =
             (float)(B.scale * (direction == 0 ? B.V[(size_t)k * B.size + c] : B.V[(size_t)c * B.size + k]));
   }
+  im.mats16.resize(im.mats.size());
+  for (size_t i = 0; i < im.mats.size(); ++i) im.mats16[i] = to_bf16_bits(im.mats[i]);
   // Workspace column col holds node col_node[col] (coefficient col_coef[col]) of its block,
   // or padding (-1).
   auto inverse_of = [&](const std::vector<int32_t> &cols, int nvals) {
