@@ -311,18 +311,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
 
 // ---------------------------------------------------------------------------- mixed batch
 
-// One tile of T = 16*mt signals of one program: load -> pre stages -> blocks -> post stages
-// -> store.  The program's tables (and fragments, when LDS-resident) are already in LDS.
+// One tile of T = 16*mt signals of one program, its loads already issued into `pre`:
+// commit -> (issue the next tile's loads) -> pre stages -> blocks -> post stages -> store.
+// The program's tables (and fragments, when LDS-resident) are already in LDS.
 template <int MT, int PREC>
 __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t,
                                          const uint32_t *fragbase, const float *gin,
                                          float *gout, int count, float *buf0, float *buf1,
-                                         const floatx4 *spare) {
+                                         floatx4 (&pre)[kPrefetch], const float *next_in,
+                                         int next_count, const floatx4 *spare) {
   constexpr int T = 16 * MT;
-  floatx4 pre[kPrefetch];
-  issue_tile(gin, count, spare, pre);
   commit_tile(gin, count, T, P.n, P.stride, P.magic_n, pre, buf0);
   __syncthreads();
+  issue_tile(next_in, next_count, spare, pre);
   for (int s = 0; s < P.num_pre; ++s) {
     haar_stage(t.stages + 4 * s, t.ops, T, P.stride, buf0);
     __syncthreads();
@@ -394,32 +395,50 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     if (elem[mid] <= e0) lo = mid;
     else hi = mid;
   }
+  // The tiles this workgroup owns (first element in [e0, e1)), in order: (g, t) pairs.
+  // advance() moves (g, t) to the next owned tile at or after it and returns false when
+  // there is none; graphs that are empty or end past total_elems are skipped.
+  auto advance = [&](int &g, int64_t &t) -> bool {
+    while (g < G) {
+      const int64_t gbeg = elem[g], gend = elem[g + 1];
+      if (gend <= gbeg || gend > total_elems) {
+        ++g;
+        t = 0;
+        if (elem[g < G ? g : G] >= e1) return false;
+        continue;
+      }
+      const int64_t tile_elems = (int64_t)16 * progs[g].mt * progs[g].n;
+      if (t < 0) t = (e0 - gbeg + tile_elems - 1) / tile_elems;   // first tile starting >= e0
+      const int64_t start = gbeg + t * tile_elems;
+      if (start >= gend) {   // this graph has no tile left for us: the next one may
+        ++g;
+        t = 0;
+        continue;
+      }
+      return start < e1;
+    }
+    return false;
+  };
+  auto span = [&](int g, int64_t t, int64_t &start) -> int {
+    const int64_t tile_elems = (int64_t)16 * progs[g].mt * progs[g].n;
+    start = elem[g] + t * tile_elems;
+    const int64_t rem = elem[g + 1] - start;
+    return (int)(rem < tile_elems ? rem : tile_elems);
+  };
   int g = lo;
+  int64_t t = -1;
+  if (!advance(g, t)) return;
+  const floatx4 *spare = reinterpret_cast<const floatx4 *>(progs[0].table);
+  floatx4 pre[kPrefetch];
+  int64_t start;
+  int count = span(g, t, start);
+  issue_tile(in + start, count, spare, pre);
   int loaded = -1;
   DevProgram P{};
   LdsTables tabs{};
   const uint32_t *fragbase = nullptr;
   float *buf0 = nullptr, *buf1 = nullptr;
-  int64_t t = -1;
-  while (g < G) {
-    const int64_t gbeg = elem[g], gend = elem[g + 1];
-    if (gend <= gbeg || gend > total_elems) {
-      ++g;
-      t = 0;
-      if (elem[g < G ? g : G] >= e1) break;
-      continue;
-    }
-    const int n = progs[g].n;
-    const int T = 16 * progs[g].mt;
-    const int64_t tile_elems = (int64_t)T * n;
-    if (t < 0) t = (e0 - gbeg + tile_elems - 1) / tile_elems;   // first tile starting >= e0
-    const int64_t start = gbeg + t * tile_elems;
-    if (start >= gend) {   // this graph has no tile left for us: the next one may
-      ++g;
-      t = 0;
-      continue;
-    }
-    if (start >= e1) break;
+  for (;;) {
     if (loaded != g) {
       P = progs[g];
       for (int i = threadIdx.x; i < P.table_words; i += kThreads) area[i] = P.table[i];
@@ -429,20 +448,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int i = threadIdx.x; i < P.frag_words; i += kThreads) lfrag[i] = P.frag[i];
       fragbase = P.frag_lds ? lfrag : P.frag;
       buf0 = reinterpret_cast<float *>(lfrag + (P.frag_lds ? ((P.frag_words + 3) & ~3) : 0));
-      buf1 = buf0 + T * P.stride;
+      buf1 = buf0 + 16 * P.mt * P.stride;
       loaded = g;
       __syncthreads();
     }
-    const int64_t rem = gend - start;
-    const int count = (int)(rem < tile_elems ? rem : tile_elems);
-    const floatx4 *spare = reinterpret_cast<const floatx4 *>(P.table);
+    // the next owned tile, whose loads run while this one is computed (the last tile
+    // re-reads itself rather than branch around the loads)
+    int ng = g;
+    int64_t nt = t + 1;
+    const bool more = advance(ng, nt);
+    int64_t nstart = start;
+    const int ncount = more ? span(ng, nt, nstart) : count;
     switch (P.mt) {
-      case 1: run_tile<1, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
-      case 2: run_tile<2, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
-      case 4: run_tile<4, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
-      default: run_tile<8, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, spare); break;
+      case 1: run_tile<1, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, pre, in + nstart, ncount, spare); break;
+      case 2: run_tile<2, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, pre, in + nstart, ncount, spare); break;
+      case 4: run_tile<4, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, pre, in + nstart, ncount, spare); break;
+      default: run_tile<8, PREC>(P, tabs, fragbase, in + start, out + start, count, buf0, buf1, pre, in + nstart, ncount, spare); break;
     }
-    ++t;
+    if (!more) break;
+    g = ng;
+    t = nt;
+    start = nstart;
+    count = ncount;
   }
 }
 
