@@ -111,7 +111,9 @@ typedef enum {
                               /* the first apply)                                       */
   GFT_ENGINE_LARGE = 3        /* large-signal engine: Haar stages and permutations in    */
                               /* streaming passes, leaf blocks as MFMA GEMM tiles over a */
-                              /* stream-ordered workspace of 2*S*n floats (hipMallocAsync)*/
+                              /* stream-ordered workspace (hipMallocAsync, freed in      */
+                              /* stream order) of 2*S*w floats, w = n plus each leaf     */
+                              /* block padded to a multiple of 8; FP16 is unsupported    */
 } gft_engine;
 
 typedef struct {
@@ -180,8 +182,9 @@ gft_status gft_inverse_batch(gft_plan_t plan, const void *y, void *x,
  * a hipGraph.  Needs a GPU. */
 gft_status gft_plan_prepare(gft_plan_t plan);
 
-/* Engine (gft_engine: GFT_ENGINE_GENERIC or GFT_ENGINE_BUTTERFLY) the plan's image on
- * the current device runs; builds the image like gft_plan_prepare.  Needs a GPU. */
+/* Engine (gft_engine: GFT_ENGINE_GENERIC, GFT_ENGINE_BUTTERFLY or GFT_ENGINE_LARGE) the
+ * plan's image on the current device runs; builds the image like gft_plan_prepare.
+ * Needs a GPU. */
 gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */
