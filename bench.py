@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "split_bf16"])
+    ap.add_argument("--io", default="fp32", choices=["fp32", "bf16"],
+                    help="storage type of signals and coefficients (single-graph workloads)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain device copy of the input size (counter calibration)")
     return ap.parse_args()
@@ -167,17 +169,22 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
 
     dev = torch.device("cuda:0")
     S, n = X_host.shape
+    io16 = getattr(args, "io", "fp32") == "bf16"
+    esz = 2 if io16 else 4
     xa = torch.from_numpy(X_host).to(dev)
+    if io16:
+        xa = xa.to(torch.bfloat16)
     xb = torch.roll(xa, shifts=1, dims=0).contiguous()   # second buffer: defeats the 256 MB cache
     if args.profile_copy:
         out = torch.empty_like(xa)
         for _ in range(max(1, args.steps)):
             out.copy_(xa)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": 2 * xa.numel() * 4}))
+        print(json.dumps({"copy_bytes_per_launch": 2 * xa.numel() * esz}))
         return
 
-    plan = G.Plan.from_graph(graph, engine=args.engine, precision=precision)
+    plan = G.Plan.from_graph(graph, engine=args.engine, precision=precision,
+                             in_dtype=args.io, out_dtype=args.io)
     plan.prepare()
     eng = plan.engine()
     stream = torch.cuda.current_stream()
@@ -202,7 +209,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     ms_step, fwd_ms = run_steps(torch, stream, fwd, inv, args.steps, args.warmup)
     inv_ms = avg_ms(torch, stream, inv, args.steps)
     copy_ms = avg_ms(torch, stream, lambda i: bufs[i & 1][1].copy_(bufs[i & 1][0]), args.steps)
-    bytes_per_launch = 2.0 * S * n * 4
+    bytes_per_launch = 2.0 * S * n * esz
     achieved = bytes_per_launch / (fwd_ms * 1e-3) / 1e9
     copy_gbs = bytes_per_launch / (copy_ms * 1e-3) / 1e9
     kname = (kernel_names or {}).get(eng, f"{eng} engine kernel")
@@ -210,7 +217,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     traffic = None
     try:
         src = open(os.path.join(ROOT, PROFILED_TRAFFIC["source"]), "rb").read()
-        if (args.workload == "grid8x8" and eng == "butterfly" and S == 1 << 20
+        if (args.workload == "grid8x8" and eng == "butterfly" and S == 1 << 20 and not io16
                 and hashlib.sha256(src).hexdigest()[:16] == PROFILED_TRAFFIC["sha256_16"]):
             traffic = PROFILED_TRAFFIC["bytes_per_launch"]
     except OSError:
@@ -232,9 +239,11 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
         "value": 2.0 * S * n / (ms_step * 1e-3), "unit": "coeffs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if precision == "fp32" else f"f32 io, {precision} blocks, f32 acc",
+        "dtype": ("f32" if precision == "fp32" else f"f32 haar, {precision} blocks, f32 acc") +
+                 (", bf16 storage" if io16 else ""),
         "data": "synthetic",
-        "config": dict(workload_cfg, signals=S, n=n, values_per_step=2 * S * n, precision=precision),
+        "config": dict(workload_cfg, signals=S, n=n, values_per_step=2 * S * n, precision=precision,
+                       storage=args.io),
         "roofline": roof,
         "forward_coeffs_per_s": S * n / (fwd_ms * 1e-3),
         "inverse_values_per_s": S * n / (inv_ms * 1e-3), "inverse_avg_launch_ms": inv_ms,
@@ -246,11 +255,13 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     if not args.no_dense:
         # dense GFT as one GEMM on the same GPU, same basis (rows of U = forward(e_i))
         torch.backends.cuda.matmul.allow_tf32 = False
-        Ud = G.gft_forward(plan, torch.eye(n, device=dev))
+        Ud = torch.from_numpy(plan.basis()).float().to(dev)   # y = x @ Ud, the plan's basis
         dense = {}
         for dt_name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
             U1 = Ud.to(dt).contiguous()
             U2 = Ud.t().contiguous().to(dt)
+            if io16 and dt_name == "fp32":
+                continue   # with BF16 storage the comparable dense GEMM is the BF16 one
             xs = [b[0].to(dt) for b in bufs]
             ys = [torch.empty_like(xs[0]) for _ in range(2)]
             xo = torch.empty_like(xs[0])
@@ -268,12 +279,14 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
                                       (", no TF32" if dt_name == "fp32" else "")}
             del xs, ys, xo
         result["dense_gemm"] = dense
-        result["speedup_vs_dense_fp32"] = result["value"] / dense["fp32"]["value"]
+        for k, v in dense.items():
+            result[f"speedup_vs_dense_{k}"] = result["value"] / v["value"]
 
     if not args.no_cpu_baseline:
         rows = slice(0, sample_rows)
         Yg = G.gft_forward(plan, xa[rows]).double().cpu().numpy()
-        result["cpu_baseline"] = cpu_baseline([(graph, X_host[rows], Yg, plan.basis())], sample_desc)
+        Xs = xa[rows].float().cpu().numpy()          # the values the GPU consumed
+        result["cpu_baseline"] = cpu_baseline([(graph, Xs, Yg, plan.basis())], sample_desc)
     print(json.dumps(result), flush=True)
 
 

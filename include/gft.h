@@ -91,6 +91,14 @@ typedef enum {
   GFT_SPLIT_BF16 = 3   /* hi+lo BF16 split, three products, FP32 accumulation         */
 } gft_precision;
 
+/* Storage type of signals or coefficients in device memory.  The arithmetic does not
+ * change: BF16 values are widened to FP32 when loaded and rounded to the nearest BF16
+ * (ties to even) when stored. */
+typedef enum {
+  GFT_DTYPE_FP32 = 0,
+  GFT_DTYPE_BF16 = 1
+} gft_dtype;
+
 typedef enum {
   GFT_ORDER_EIGENVALUE = 0,  /* ascending eigenvalue; ties by leaf-block order, then  */
                              /* local index (any basis of an eigenspace is a GFT)     */
@@ -123,6 +131,12 @@ typedef struct {
   int32_t engine;          /* gft_engine                                              */
   double sym_tol;          /* relative tolerance of the phi-symmetry test on sub-graph*/
                            /* Laplacians; <= 0 selects 1e-12                          */
+  int32_t in_dtype;        /* gft_dtype of signals x: read by the forward, written by */
+                           /* the inverse                                             */
+  int32_t out_dtype;       /* gft_dtype of coefficients y: written by the forward,    */
+                           /* read by the inverse.  BF16 storage runs on the          */
+                           /* butterfly and generic engines of single-graph plans     */
+                           /* (else GFT_ERR_UNSUPPORTED); in place needs equal types  */
 } gft_options;
 
 typedef struct {
@@ -154,8 +168,9 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
                           gft_plan_t *out);
 
 /* y = U^T x for num_signals signals (coefficients; Sec. II-B).
- * x: device, num_signals x n FP32, 16-byte aligned.  y: device, same shape, 16-byte
- * aligned; y == x (in place) is allowed, other overlaps are rejected.
+ * x: device, num_signals x n values of options.in_dtype (FP32 unless set), 16-byte
+ * aligned.  y: device, num_signals x n values of options.out_dtype, 16-byte aligned;
+ * y == x (in place) is allowed when the two types are equal, other overlaps are rejected.
  * num_signals == 0 is a no-op.  Single-graph plans only. */
 gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_signals,
                        void *stream);

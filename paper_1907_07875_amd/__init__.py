@@ -20,6 +20,7 @@ GFT_FP32, GFT_BF16, GFT_FP16, GFT_SPLIT_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": GFT_FP32, "bf16": GFT_BF16, "fp16": GFT_FP16, "split_bf16": GFT_SPLIT_BF16}
 ORDER_EIGENVALUE, ORDER_BLOCK = 0, 1
 ENGINES = {"auto": 0, "generic": 1, "butterfly": 2, "large": 3}
+DTYPES = {"fp32": 0, "bf16": 1}
 
 STATUS = {
     0: "GFT_OK", 1: "GFT_ERR_INVALID_ARG", 2: "GFT_ERR_GRAPH", 3: "GFT_ERR_NOT_INVOLUTION",
@@ -58,7 +59,8 @@ class _Pairing(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("tile_override", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("sym_tol", ctypes.c_double)]
+                ("sym_tol", ctypes.c_double), ("in_dtype", ctypes.c_int32),
+                ("out_dtype", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -155,10 +157,11 @@ def _pairing_struct(n, stages, keep):
     return _Pairing(int(phi.shape[0]), phi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
 
 
-def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto"):
+def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto",
+             in_dtype="fp32", out_dtype="fp32"):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
-    return _Options(prec, int(order), int(tile), eng, float(sym_tol))
+    return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype])
 
 
 def _stream_ptr(stream):
@@ -171,20 +174,23 @@ def _stream_ptr(stream):
 class Plan:
     """A fast-GFT plan: ``gft_plan`` (one graph) or ``gft_plan_batch`` (several graphs)."""
 
-    def __init__(self, handle: int, sizes: List[int], batch: bool, precision: str):
+    def __init__(self, handle: int, sizes: List[int], batch: bool, precision: str,
+                 in_dtype: str = "fp32", out_dtype: str = "fp32"):
         self._h = ctypes.c_void_p(handle)
         self.sizes = sizes
         self.batch = batch
         self.precision = precision
+        self.in_dtype = in_dtype      # storage of signals
+        self.out_dtype = out_dtype    # storage of coefficients
 
     # -- construction ---------------------------------------------------------------
     @classmethod
     def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0,
-                   engine="auto"):
+                   engine="auto", in_dtype="fp32", out_dtype="fp32"):
         """Plan one graph (an object with n, src, dst, weight, self_loop, stages)."""
         return gft_plan(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop,
                         graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol,
-                        engine=engine)
+                        engine=engine, in_dtype=in_dtype, out_dtype=out_dtype)
 
     @property
     def n(self) -> int:
@@ -259,21 +265,23 @@ class Plan:
 
 
 def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
-             order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto") -> Plan:
-    """Plan the fast GFT of one graph (C: ``gft_plan``)."""
+             order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto", in_dtype="fp32",
+             out_dtype="fp32") -> Plan:
+    """Plan the fast GFT of one graph (C: ``gft_plan``).  ``in_dtype`` / ``out_dtype``
+    ("fp32" or "bf16") are the storage types of signals and coefficients."""
     lib = load_library()
     keep = []
     g = _graph_struct(n, src, dst, weight, self_loop, keep)
     p = _pairing_struct(n, stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype)
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
-    return Plan(h.value, [int(n)], False, precision)
+    return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
 
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
-                   sym_tol=0.0, engine="auto") -> Plan:
-    """Plan several graphs for one persistent launch (C: ``gft_plan_batch``)."""
+                   sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32") -> Plan:
+    """Plan several graphs for one persistent launch (C: ``gft_plan_batch``; FP32 storage)."""
     lib = load_library()
     keep = []
     G = (_Graph * len(graphs))()
@@ -281,18 +289,23 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     for i, gr in enumerate(graphs):
         G[i] = _graph_struct(gr.n, gr.src, gr.dst, gr.weight, gr.self_loop, keep)
         Pr[i] = _pairing_struct(gr.n, gr.stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(g.n) for g in graphs], True, precision)
 
 
-def _check_tensor(t, n, what):
+def _torch_dtype(name):
+    import torch
+    return {"fp32": torch.float32, "bf16": torch.bfloat16}[name]
+
+
+def _check_tensor(t, n, what, dtype="fp32"):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{what} must be a CUDA (HIP) tensor")
-    if t.dtype != torch.float32:
-        raise TypeError(f"{what} must be float32")
+    if t.dtype != _torch_dtype(dtype):
+        raise TypeError(f"{what} must be {_torch_dtype(dtype)}")
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     if t.dim() < 1 or t.shape[-1] != n:
@@ -303,11 +316,13 @@ def _apply(fn_name, plan: Plan, x, out, stream):
     import torch
     if plan.batch:
         raise ValueError("batch plans use gft_forward_batch / gft_inverse_batch")
-    _check_tensor(x, plan.n, "input")
+    fwd = fn_name == "gft_forward"
+    din, dout = (plan.in_dtype, plan.out_dtype) if fwd else (plan.out_dtype, plan.in_dtype)
+    _check_tensor(x, plan.n, "input", din)
     if out is None:
-        out = torch.empty_like(x)
+        out = torch.empty(x.shape, dtype=_torch_dtype(dout), device=x.device)
     else:
-        _check_tensor(out, plan.n, "output")
+        _check_tensor(out, plan.n, "output", dout)
         if out.shape != x.shape:
             raise ValueError("output shape must equal input shape")
     S = x.numel() // plan.n

@@ -107,6 +107,9 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
   if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_LARGE)
     return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2 or 3");
+  if ((o.in_dtype != GFT_DTYPE_FP32 && o.in_dtype != GFT_DTYPE_BF16) ||
+      (o.out_dtype != GFT_DTYPE_FP32 && o.out_dtype != GFT_DTYPE_BF16))
+    return set_error(GFT_ERR_INVALID_ARG, "options.in_dtype and options.out_dtype must be gft_dtype values");
   if (o.tile_override != 0 && o.tile_override != 16 && o.tile_override != 32 &&
       o.tile_override != 64 && o.tile_override != 128)
     return set_error(GFT_ERR_INVALID_ARG, "options.tile_override must be 0, 16, 32, 64 or 128");
@@ -144,7 +147,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (plan->opts.engine == GFT_ENGINE_BUTTERFLY && (plan->batch || plan->opts.precision != GFT_FP32))
     return set_error(GFT_ERR_UNSUPPORTED,
                      "the register-butterfly engine runs single-graph FP32 plans only");
-  if (!plan->batch && plan->opts.engine != GFT_ENGINE_GENERIC && plan->opts.precision == GFT_FP32) {
+  if (!plan->batch && (plan->opts.engine == GFT_ENGINE_AUTO || plan->opts.engine == GFT_ENGINE_BUTTERFLY) &&
+      plan->opts.precision == GFT_FP32) {
     use_bf = build_butterfly(plan->graphs[0], 0, ub[0]) && build_butterfly(plan->graphs[0], 1, ub[1]) &&
              butterfly_supported(ub[0].prog.S, ub[0].prog.M);
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
@@ -163,6 +167,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                  (!fits || plan->graphs[0].stats.max_block >= 192));
     if (use_large && plan->opts.precision == GFT_FP16)
       return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine runs FP32, BF16 or split BF16 blocks");
+    if (use_large && (plan->opts.in_dtype != GFT_DTYPE_FP32 || plan->opts.out_dtype != GFT_DTYPE_FP32))
+      return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine reads and writes FP32 storage only");
   }
   if (plan->opts.engine == GFT_ENGINE_LARGE && plan->batch)
     return set_error(GFT_ERR_UNSUPPORTED, "batch plans run the generic engine");
@@ -306,12 +312,15 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   return GFT_OK;
 }
 
-gft_status check_buffers(const void *a, const void *b, int64_t bytes) {
+gft_status check_buffers(const void *a, int64_t abytes, const void *b, int64_t bbytes,
+                         bool same_type) {
   if (!a || !b) return set_error(GFT_ERR_INVALID_ARG, "x and y must be non-NULL device pointers");
   if ((reinterpret_cast<uintptr_t>(a) & 15) || (reinterpret_cast<uintptr_t>(b) & 15))
     return set_error(GFT_ERR_ALIGNMENT, "x and y must be 16-byte aligned");
   const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
-  if (pa != pb && pa < pb + (uintptr_t)bytes && pb < pa + (uintptr_t)bytes)
+  if (pa == pb && !same_type)
+    return set_error(GFT_ERR_ALIGNMENT, "in-place transforms need equal storage types for x and y");
+  if (pa != pb && pa < pb + (uintptr_t)bbytes && pb < pa + (uintptr_t)abytes)
     return set_error(GFT_ERR_ALIGNMENT, "x and y overlap without being equal");
   return GFT_OK;
 }
@@ -323,7 +332,10 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   if (S == 0) return ok();
   const int64_t n = plan->graphs[0].n;
   if (S > (int64_t(1) << 40) / n) return set_error(GFT_ERR_INVALID_ARG, "num_signals too large");
-  gft_status st = check_buffers(in, out, S * n * 4);
+  // forward reads signals (in_dtype) and writes coefficients (out_dtype); inverse the reverse
+  const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
+  const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
+  gft_status st = check_buffers(in, S * n * (in16 ? 2 : 4), out, S * n * (out16 ? 2 : 4), in16 == out16);
   if (st != GFT_OK) return st;
   DeviceImage *img = nullptr;
   st = device_image(plan, &img);
@@ -349,13 +361,12 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
     const hipError_t ef = hipFreeAsync(ws, st);
     if (e == hipSuccess) e = ef;
   } else if (img->butterfly) {
-    e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, static_cast<const float *>(in),
-                         static_cast<float *>(out), S, static_cast<hipStream_t>(stream), img->num_cus);
+    e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, in, out, S,
+                         static_cast<hipStream_t>(stream), img->num_cus, in16, out16);
   } else {
     const DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
     const int cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
-    e = launch_apply(P, static_cast<const float *>(in), static_cast<float *>(out), S,
-                     static_cast<hipStream_t>(stream), cap);
+    e = launch_apply(P, in, out, S, static_cast<hipStream_t>(stream), cap, in16, out16);
   }
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
@@ -404,6 +415,8 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs, const gft
   const gft_options o = default_options(opts);
   gft_status st = check_options(o);
   if (st != GFT_OK) return st;
+  if (o.in_dtype != GFT_DTYPE_FP32 || o.out_dtype != GFT_DTYPE_FP32)
+    return set_error(GFT_ERR_UNSUPPORTED, "batch plans read and write FP32 storage only");
   try {
     auto p = std::make_unique<gft_plan_s>();
     p->opts = o;
@@ -438,7 +451,7 @@ static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *ou
   if (total_elements == 0) return ok();
   if (!signal_offsets) return set_error(GFT_ERR_INVALID_ARG, "signal_offsets is NULL");
   if (total_elements > (int64_t(1) << 40)) return set_error(GFT_ERR_INVALID_ARG, "total_elements too large");
-  gft_status st = check_buffers(in, out, total_elements * 4);
+  gft_status st = check_buffers(in, total_elements * 4, out, total_elements * 4, true);
   if (st != GFT_OK) return st;
   DeviceImage *img = nullptr;
   st = device_image(plan, &img);

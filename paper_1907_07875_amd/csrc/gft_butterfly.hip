@@ -39,18 +39,32 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// FP32 <- BF16 pairs packed in a 32-bit word (element 2i in the low half).
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 }  // namespace
 
-template <int S, int M, int DIR>
-__global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, const float *in,
-                                                                 float *out, int64_t nsig) {
+// IN16 / OUT16: the tile is read / written as BF16 (16-byte accesses of 8 values) instead
+// of FP32 (16-byte accesses of 4 values); everything between runs in FP32.
+template <int S, int M, int DIR, bool IN16, bool OUT16>
+__global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, const void *in,
+                                                                 void *out, int64_t nsig) {
   constexpr int NB = 1 << S;      // leaf blocks = slots per orbit
   constexpr int KC = M / 4;       // K chunks of a block
   constexpr int NT = M / 16;      // 16-row tiles of a block
   constexpr int N = M * NB;       // signal length
   constexpr int Q = N / 4;        // values per lane
   constexpr int STR = N + 4;      // LDS row stride: 16-byte rows, offset banks
-  constexpr int V4 = N / 16;      // float4 per lane per 16-signal tile
   constexpr int NF = NB * NT * KC;
   __shared__ float lds_all[kWaves * 16 * STR];
 
@@ -80,16 +94,21 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
   // Prefetch of a tile into registers.  The loads are unconditional, so that they stay in
   // flight while the previous tile is computed: past the last valid signal a lane
-  // re-reads the tile's last float4 (lim >= N >= 32), whose rows are never stored.
-  floatx4 pre[V4];
+  // re-reads the tile's last 16 bytes (lim >= N >= 32), whose rows are never stored.
+  constexpr int EI = IN16 ? 8 : 4;          // values per 16-byte load
+  constexpr int VI = N / (4 * EI);          // loads per lane per 16-signal tile
+  u32x4 pre[VI];
   auto issue = [&](int64_t t) {
     const int64_t rem = nsig - 16 * t;
     const int lim = (int)(rem < 16 ? rem : 16) * N;
-    const float *src = in + t * 16 * N;
 #pragma unroll
-    for (int k = 0; k < V4; ++k) {
-      const int e = 4 * (lane + 64 * k);
-      pre[k] = *reinterpret_cast<const floatx4 *>(src + (e < lim ? e : lim - 4));
+    for (int k = 0; k < VI; ++k) {
+      const int e = EI * (lane + 64 * k);
+      const int ec = e < lim ? e : lim - EI;
+      if constexpr (IN16)
+        pre[k] = *reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * N + ec);
+      else
+        pre[k] = *reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * N + ec);
     }
   };
   if (wt < ntiles) issue(wt);
@@ -98,9 +117,16 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
     const int64_t rem = nsig - 16 * wt;
     const int lim = (int)(rem < 16 ? rem : 16) * N;
 #pragma unroll
-    for (int k = 0; k < V4; ++k) {
-      const int e = 4 * (lane + 64 * k);
-      *reinterpret_cast<floatx4 *>(T + (e / N) * STR + (e % N)) = pre[k];
+    for (int k = 0; k < VI; ++k) {
+      const int e = EI * (lane + 64 * k);   // a 16-byte group never crosses a row (N % 8 == 0)
+      float *dst = T + (e / N) * STR + (e % N);
+      if constexpr (IN16) {
+        const u32x4 w = pre[k];
+        *reinterpret_cast<floatx4 *>(dst) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
+        *reinterpret_cast<floatx4 *>(dst + 4) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
+      } else {
+        *reinterpret_cast<u32x4 *>(dst) = pre[k];
+      }
     }
     wave_lds_sync();
     // next tile's loads (the last tile re-reads itself rather than branch around the loads)
@@ -172,20 +198,35 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 #pragma unroll
     for (int q = 0; q < Q; ++q) T[sc[q]] = res[q];
     wave_lds_sync();
-    float *dst = out + wt * 16 * N;
-    floatx4 o4[V4];
+    constexpr int EO = OUT16 ? 8 : 4;         // values per 16-byte store
+    constexpr int VO = N / (4 * EO);
+    u32x4 o[VO];
 #pragma unroll
-    for (int k = 0; k < V4; ++k) {
-      const int e = 4 * (lane + 64 * k);
-      o4[k] = *reinterpret_cast<const floatx4 *>(T + (e / N) * STR + (e % N));
+    for (int k = 0; k < VO; ++k) {
+      const int e = EO * (lane + 64 * k);
+      const float *src = T + (e / N) * STR + (e % N);
+      if constexpr (OUT16) {
+        const floatx4 a = *reinterpret_cast<const floatx4 *>(src);
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(src + 4);
+        o[k] = u32x4{bf16_bits(a[0]) | (bf16_bits(a[1]) << 16), bf16_bits(a[2]) | (bf16_bits(a[3]) << 16),
+                     bf16_bits(b[0]) | (bf16_bits(b[1]) << 16), bf16_bits(b[2]) | (bf16_bits(b[3]) << 16)};
+      } else {
+        o[k] = *reinterpret_cast<const u32x4 *>(src);
+      }
     }
+    auto dst_at = [&](int e) -> u32x4 * {
+      if constexpr (OUT16)
+        return reinterpret_cast<u32x4 *>(static_cast<uint16_t *>(out) + wt * 16 * N + e);
+      else
+        return reinterpret_cast<u32x4 *>(static_cast<float *>(out) + wt * 16 * N + e);
+    };
     if (lim == 16 * N) {   // full tile (wave-uniform branch)
 #pragma unroll
-      for (int k = 0; k < V4; ++k) *reinterpret_cast<floatx4 *>(dst + 4 * (lane + 64 * k)) = o4[k];
+      for (int k = 0; k < VO; ++k) *dst_at(EO * (lane + 64 * k)) = o[k];
     } else {
 #pragma unroll
-      for (int k = 0; k < V4; ++k)
-        if (4 * (lane + 64 * k) < lim) *reinterpret_cast<floatx4 *>(dst + 4 * (lane + 64 * k)) = o4[k];
+      for (int k = 0; k < VO; ++k)
+        if (EO * (lane + 64 * k) < lim) *dst_at(EO * (lane + 64 * k)) = o[k];
     }
     wave_lds_sync();
   }
@@ -193,32 +234,42 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
 // ---------------------------------------------------------------------------- launch
 
-template <int S, int M, int DIR>
-static hipError_t launch_bf(const UProgram &P, const float *in, float *out, int64_t nsig,
+template <int S, int M, int DIR, bool IN16, bool OUT16>
+static hipError_t launch_bf(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR, IN16, OUT16>,
                                                    64 * kWaves, 0) != hipSuccess || occ < 1)
     occ = 1;
   const int64_t ntiles = (nsig + 15) / 16;
   const int64_t want = (ntiles + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR>), dim3(grid > 0 ? grid : 1),
+  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR, IN16, OUT16>), dim3(grid > 0 ? grid : 1),
                      dim3(64 * kWaves), 0, stream, P, in, out, nsig);
   return hipGetLastError();
+}
+
+template <int S, int M, int DIR>
+static hipError_t launch_bf_io(const UProgram &P, const void *in, void *out, int64_t nsig,
+                               hipStream_t stream, int num_cus, bool in16, bool out16) {
+  if (in16)
+    return out16 ? launch_bf<S, M, DIR, true, true>(P, in, out, nsig, stream, num_cus)
+                 : launch_bf<S, M, DIR, true, false>(P, in, out, nsig, stream, num_cus);
+  return out16 ? launch_bf<S, M, DIR, false, true>(P, in, out, nsig, stream, num_cus)
+               : launch_bf<S, M, DIR, false, false>(P, in, out, nsig, stream, num_cus);
 }
 
 bool butterfly_supported(int S, int M) {
   return (S == 1 && (M == 16 || M == 32)) || (S == 2 && M == 16) || (S == 3 && M == 16);
 }
 
-hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,
-                            hipStream_t stream, int num_cus) {
-#define GFT_BF_CASE(s, m)                                                                  \
-  if (P.S == s && P.M == m)                                                                \
-    return P.dir == 0 ? launch_bf<s, m, 0>(P, in, out, nsig, stream, num_cus)              \
-                      : launch_bf<s, m, 1>(P, in, out, nsig, stream, num_cus);
+hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
+                            hipStream_t stream, int num_cus, bool in16, bool out16) {
+#define GFT_BF_CASE(s, m)                                                                      \
+  if (P.S == s && P.M == m)                                                                    \
+    return P.dir == 0 ? launch_bf_io<s, m, 0>(P, in, out, nsig, stream, num_cus, in16, out16)  \
+                      : launch_bf_io<s, m, 1>(P, in, out, nsig, stream, num_cus, in16, out16);
   GFT_BF_CASE(1, 16)
   GFT_BF_CASE(1, 32)
   GFT_BF_CASE(2, 16)

@@ -66,19 +66,47 @@ __device__ __forceinline__ LdsTables carve(const DevProgram &P, const int32_t *b
 }
 
 // Tile loads are split in two halves so the next tile's HBM reads overlap the current
-// tile's compute: issue_tile() starts up to kPrefetch float4 loads per thread into
+// tile's compute: issue_tile() starts up to kPrefetch vector loads per thread into
 // registers; commit_tile() writes them to LDS rows of `stride` floats, loads whatever
 // did not fit in registers, and zero-fills rows at and beyond count / n up to `rows`.
+// A vector is 4 consecutive values: a float4 (FP32 storage) or 4 BF16 in 8 bytes (B16).
 constexpr int kPrefetch = 4;
+
+typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+template <bool B16> struct IoVec { typedef floatx4 T; };
+template <> struct IoVec<true> { typedef u32x2v T; };
+
+__device__ __forceinline__ floatx4 widen(const floatx4 &v) { return v; }
+__device__ __forceinline__ floatx4 widen(const u32x2v &w) {
+  return floatx4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                 __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+}
+
+template <bool B16>
+__device__ __forceinline__ float load_one(const void *g, int64_t e) {
+  if constexpr (B16) return __uint_as_float((uint32_t)static_cast<const uint16_t *>(g)[e] << 16);
+  else return static_cast<const float *>(g)[e];
+}
+
+template <bool B16>
+__device__ __forceinline__ const void *advance_ptr(const void *g, int64_t e) {
+  return B16 ? (const void *)(static_cast<const uint16_t *>(g) + e) : (const void *)(static_cast<const float *>(g) + e);
+}
+template <bool B16>
+__device__ __forceinline__ void *advance_ptr(void *g, int64_t e) {
+  return B16 ? (void *)(static_cast<uint16_t *>(g) + e) : (void *)(static_cast<float *>(g) + e);
+}
 
 // The prefetch loads are unconditional so that they stay in flight across the compute of
 // the previous tile (a guarded load is waited for inside its branch): lanes past the
-// tile's last float4 re-read it, and a tile with no whole float4 reads `spare`, 16 bytes
+// tile's last vector re-read it, and a tile with no whole vector reads `spare`, 16 bytes
 // of valid device memory.  commit_tile() only stores the in-range ones.
-__device__ __forceinline__ void issue_tile(const float *g, int count, const floatx4 *spare,
-                                           floatx4 (&pre)[kPrefetch]) {
+template <bool B16>
+__device__ __forceinline__ void issue_tile(const void *g, int count, const floatx4 *spare,
+                                           typename IoVec<B16>::T (&pre)[kPrefetch]) {
+  typedef typename IoVec<B16>::T V;
   const int nvec = count >> 2;
-  const floatx4 *g4 = nvec > 0 ? reinterpret_cast<const floatx4 *>(g) : spare;
+  const V *g4 = nvec > 0 ? static_cast<const V *>(g) : reinterpret_cast<const V *>(spare);
   const int last = nvec > 0 ? nvec - 1 : 0;
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) {
@@ -102,22 +130,25 @@ __device__ __forceinline__ void put4(float *lds, uint32_t e, const floatx4 &val,
   }
 }
 
-__device__ __forceinline__ void commit_tile(const float *g, int count, int rows, int n,
+template <bool B16>
+__device__ __forceinline__ void commit_tile(const void *g, int count, int rows, int n,
                                             int stride, uint32_t magic_n,
-                                            const floatx4 (&pre)[kPrefetch], float *lds) {
+                                            const typename IoVec<B16>::T (&pre)[kPrefetch],
+                                            float *lds) {
+  typedef typename IoVec<B16>::T V;
   const int tid = threadIdx.x;
   const int nvec = count >> 2;
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) {
     const int v = tid + k * kThreads;
-    if (v < nvec) put4(lds, 4u * (uint32_t)v, pre[k], n, stride, magic_n);
+    if (v < nvec) put4(lds, 4u * (uint32_t)v, widen(pre[k]), n, stride, magic_n);
   }
-  const floatx4 *g4 = reinterpret_cast<const floatx4 *>(g);
+  const V *g4 = static_cast<const V *>(g);
   for (int v = tid + kPrefetch * kThreads; v < nvec; v += kThreads)
-    put4(lds, 4u * (uint32_t)v, g4[v], n, stride, magic_n);
+    put4(lds, 4u * (uint32_t)v, widen(g4[v]), n, stride, magic_n);
   for (int e = 4 * nvec + tid; e < count; e += kThreads) {
     const uint32_t r = fdiv((uint32_t)e, magic_n);
-    lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = g[e];
+    lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = load_one<B16>(g, e);
   }
   const int full = rows * n;
   for (int e = count + tid; e < full; e += kThreads) {
@@ -126,11 +157,11 @@ __device__ __forceinline__ void commit_tile(const float *g, int count, int rows,
   }
 }
 
+template <bool B16>
 __device__ __forceinline__ void store_tile(const float *lds, int count, int n, int stride,
-                                           uint32_t magic_n, float *g) {
+                                           uint32_t magic_n, void *g) {
   const int tid = threadIdx.x;
   const int nvec = count >> 2;
-  float4 *g4 = reinterpret_cast<float4 *>(g);
   for (int v = tid; v < nvec; v += kThreads) {
     const uint32_t e = 4u * (uint32_t)v;
     uint32_t r = fdiv(e, magic_n);
@@ -144,11 +175,17 @@ __device__ __forceinline__ void store_tile(const float *lds, int count, int n, i
         ++r;
       }
     }
-    g4[v] = make_float4(q[0], q[1], q[2], q[3]);
+    if constexpr (B16)
+      static_cast<u32x2v *>(g)[v] = u32x2v{bf16_bits(q[0]) | (bf16_bits(q[1]) << 16),
+                                           bf16_bits(q[2]) | (bf16_bits(q[3]) << 16)};
+    else
+      static_cast<float4 *>(g)[v] = make_float4(q[0], q[1], q[2], q[3]);
   }
   for (int e = 4 * nvec + tid; e < count; e += kThreads) {
     const uint32_t r = fdiv((uint32_t)e, magic_n);
-    g[e] = lds[r * stride + ((uint32_t)e - r * (uint32_t)n)];
+    const float x = lds[r * stride + ((uint32_t)e - r * (uint32_t)n)];
+    if constexpr (B16) static_cast<uint16_t *>(g)[e] = (uint16_t)bf16_bits(x);
+    else static_cast<float *>(g)[e] = x;
   }
 }
 
@@ -262,9 +299,9 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
   }
 }
 
-template <int MT, int PREC>
+template <int MT, int PREC, bool IN16, bool OUT16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 8 ? 2 : 4))) void gft_apply(
-    DevProgram P, const float *in, float *out, int64_t S) {
+    DevProgram P, const void *in, void *out, int64_t S) {
   extern __shared__ int32_t smem[];
   constexpr int T = 16 * MT;
   const int n = P.n;
@@ -282,18 +319,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
     const int64_t rem = S - tile * T;
     return (int)(rem < T ? rem : T) * n;
   };
-  floatx4 pre[kPrefetch];
+  typename IoVec<IN16>::T pre[kPrefetch];
   int64_t tile = blockIdx.x;
   const floatx4 *spare = reinterpret_cast<const floatx4 *>(P.table);
-  if (tile < num_tiles) issue_tile(in + tile * T * n, count_of(tile), spare, pre);
+  if (tile < num_tiles) issue_tile<IN16>(advance_ptr<IN16>(in, tile * T * n), count_of(tile), spare, pre);
   __syncthreads();
   for (; tile < num_tiles; tile += gridDim.x) {
     const int count = count_of(tile);
-    commit_tile(in + tile * T * n, count, T, n, stride, P.magic_n, pre, buf0);
+    commit_tile<IN16>(advance_ptr<IN16>(in, tile * T * n), count, T, n, stride, P.magic_n, pre, buf0);
     __syncthreads();
     // next tile's loads (the last tile re-reads itself rather than branch around the loads)
     const int64_t next = tile + gridDim.x < num_tiles ? tile + gridDim.x : num_tiles - 1;
-    issue_tile(in + next * T * n, count_of(next), spare, pre);
+    issue_tile<IN16>(advance_ptr<IN16>(in, next * T * n), count_of(next), spare, pre);
     for (int s = 0; s < P.num_pre; ++s) {
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf0);
       __syncthreads();
@@ -304,7 +341,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 
       haar_stage(t.stages + 4 * s, t.ops, T, stride, buf1);
       __syncthreads();
     }
-    store_tile(buf1, count, n, stride, P.magic_n, out + tile * T * n);
+    store_tile<OUT16>(buf1, count, n, stride, P.magic_n, advance_ptr<OUT16>(out, tile * T * n));
     __syncthreads();
   }
 }
@@ -321,9 +358,9 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
                                          floatx4 (&pre)[kPrefetch], const float *next_in,
                                          int next_count, const floatx4 *spare) {
   constexpr int T = 16 * MT;
-  commit_tile(gin, count, T, P.n, P.stride, P.magic_n, pre, buf0);
+  commit_tile<false>(gin, count, T, P.n, P.stride, P.magic_n, pre, buf0);
   __syncthreads();
-  issue_tile(next_in, next_count, spare, pre);
+  issue_tile<false>(next_in, next_count, spare, pre);
   for (int s = 0; s < P.num_pre; ++s) {
     haar_stage(t.stages + 4 * s, t.ops, T, P.stride, buf0);
     __syncthreads();
@@ -334,7 +371,7 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
     haar_stage(t.stages + 4 * s, t.ops, T, P.stride, buf1);
     __syncthreads();
   }
-  store_tile(buf1, count, P.n, P.stride, P.magic_n, gout);
+  store_tile<false>(buf1, count, P.n, P.stride, P.magic_n, gout);
   __syncthreads();
 }
 
@@ -432,7 +469,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   floatx4 pre[kPrefetch];
   int64_t start;
   int count = span(g, t, start);
-  issue_tile(in + start, count, spare, pre);
+  issue_tile<false>(in + start, count, spare, pre);
   int loaded = -1;
   DevProgram P{};
   LdsTables tabs{};
@@ -475,12 +512,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
 // ---------------------------------------------------------------------------- launch
 
-template <int MT, int PREC>
-static hipError_t launch_mt(const DevProgram &P, const float *in, float *out, int64_t S,
-                            hipStream_t stream, int grid_cap) {
+template <int MT, int PREC, bool IN16, bool OUT16>
+static hipError_t launch_mt_io(const DevProgram &P, const void *in, void *out, int64_t S,
+                               hipStream_t stream, int grid_cap) {
   const size_t lds = program_lds_bytes(P);
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)gft_apply<MT, PREC>,
+    hipError_t e = hipFuncSetAttribute((const void *)gft_apply<MT, PREC, IN16, OUT16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
@@ -488,8 +525,19 @@ static hipError_t launch_mt(const DevProgram &P, const float *in, float *out, in
   const int64_t tiles = (S + T - 1) / T;
   int grid = (int)(tiles < grid_cap ? tiles : grid_cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((gft_apply<MT, PREC>), dim3(grid), dim3(kThreads), lds, stream, P, in, out, S);
+  hipLaunchKernelGGL((gft_apply<MT, PREC, IN16, OUT16>), dim3(grid), dim3(kThreads), lds, stream,
+                     P, in, out, S);
   return hipGetLastError();
+}
+
+template <int MT, int PREC>
+static hipError_t launch_mt(const DevProgram &P, const void *in, void *out, int64_t S,
+                            hipStream_t stream, int grid_cap, bool in16, bool out16) {
+  if (in16)
+    return out16 ? launch_mt_io<MT, PREC, true, true>(P, in, out, S, stream, grid_cap)
+                 : launch_mt_io<MT, PREC, true, false>(P, in, out, S, stream, grid_cap);
+  return out16 ? launch_mt_io<MT, PREC, false, true>(P, in, out, S, stream, grid_cap)
+               : launch_mt_io<MT, PREC, false, false>(P, in, out, S, stream, grid_cap);
 }
 
 template <int PREC>
@@ -498,10 +546,10 @@ static int occupancy_p(const DevProgram &P) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (P.mt) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<1, PREC>, kThreads, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<2, PREC>, kThreads, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<4, PREC>, kThreads, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<8, PREC>, kThreads, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<1, PREC, false, false>, kThreads, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<2, PREC, false, false>, kThreads, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<4, PREC, false, false>, kThreads, lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply<8, PREC, false, false>, kThreads, lds); break;
     default: break;
   }
   if (e != hipSuccess || nb < 1) nb = 1;
@@ -519,24 +567,24 @@ int apply_occupancy(const DevProgram &P) {
 }
 
 template <int PREC>
-static hipError_t launch_p(const DevProgram &P, const float *in, float *out, int64_t S,
-                           hipStream_t stream, int grid_cap) {
+static hipError_t launch_p(const DevProgram &P, const void *in, void *out, int64_t S,
+                           hipStream_t stream, int grid_cap, bool in16, bool out16) {
   switch (P.mt) {
-    case 1: return launch_mt<1, PREC>(P, in, out, S, stream, grid_cap);
-    case 2: return launch_mt<2, PREC>(P, in, out, S, stream, grid_cap);
-    case 4: return launch_mt<4, PREC>(P, in, out, S, stream, grid_cap);
-    case 8: return launch_mt<8, PREC>(P, in, out, S, stream, grid_cap);
+    case 1: return launch_mt<1, PREC>(P, in, out, S, stream, grid_cap, in16, out16);
+    case 2: return launch_mt<2, PREC>(P, in, out, S, stream, grid_cap, in16, out16);
+    case 4: return launch_mt<4, PREC>(P, in, out, S, stream, grid_cap, in16, out16);
+    case 8: return launch_mt<8, PREC>(P, in, out, S, stream, grid_cap, in16, out16);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_t S,
-                        hipStream_t stream, int grid_cap) {
+hipError_t launch_apply(const DevProgram &P, const void *in, void *out, int64_t S,
+                        hipStream_t stream, int grid_cap, bool in16, bool out16) {
   switch (P.prec) {
-    case kFP32: return launch_p<kFP32>(P, in, out, S, stream, grid_cap);
-    case kBF16: return launch_p<kBF16>(P, in, out, S, stream, grid_cap);
-    case kFP16: return launch_p<kFP16>(P, in, out, S, stream, grid_cap);
-    case kSPLIT: return launch_p<kSPLIT>(P, in, out, S, stream, grid_cap);
+    case kFP32: return launch_p<kFP32>(P, in, out, S, stream, grid_cap, in16, out16);
+    case kBF16: return launch_p<kBF16>(P, in, out, S, stream, grid_cap, in16, out16);
+    case kFP16: return launch_p<kFP16>(P, in, out, S, stream, grid_cap, in16, out16);
+    case kSPLIT: return launch_p<kSPLIT>(P, in, out, S, stream, grid_cap, in16, out16);
     default: return hipErrorInvalidValue;
   }
 }

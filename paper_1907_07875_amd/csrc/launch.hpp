@@ -10,8 +10,8 @@
 namespace gft {
 
 // Persistent fused apply of one program to S signals; grid = min(tiles, grid_cap).
-hipError_t launch_apply(const DevProgram &P, const float *in, float *out, int64_t S,
-                        hipStream_t stream, int grid_cap);
+hipError_t launch_apply(const DevProgram &P, const void *in, void *out, int64_t S,
+                        hipStream_t stream, int grid_cap, bool in16, bool out16);
 
 // Resident workgroups per CU of the apply kernel for this program's LDS footprint.
 int apply_occupancy(const DevProgram &P);
@@ -35,7 +35,8 @@ hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const 
 
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(int S, int M);
-hipError_t launch_butterfly(const UProgram &P, const float *in, float *out, int64_t nsig,
-                            hipStream_t stream, int num_cus);
+// in16 / out16: the input / output array holds BF16 values (else FP32).
+hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
+                            hipStream_t stream, int num_cus, bool in16, bool out16);
 
 }  // namespace gft

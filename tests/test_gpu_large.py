@@ -34,6 +34,7 @@ def test_config5b_weighted_path(precision):
 def test_large_engine_small_graphs(g):
     """The large engine forced on graphs the other engines also serve."""
     X = wl.gaussian(777, g.n, wl.rng_for(5, g.n))
+    assert G.Plan.from_graph(g, engine="large").engine() == "large"
     _check_graph(g, X, engine="large")
 
 

@@ -137,6 +137,17 @@ def test_error_bad_options():
     assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, precision=7)) == "GFT_ERR_INVALID_ARG"
     assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, order=3)) == "GFT_ERR_INVALID_ARG"
     assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, tile=24)) == "GFT_ERR_INVALID_ARG"
+    # storage types: only FP32 / BF16 values; batch plans run FP32 storage only
+    o = G._options()
+    o.in_dtype = 2
+    h = ctypes.c_void_p()
+    keep = []
+    gs = G._graph_struct(4, g.src, g.dst, g.weight, None, keep)
+    ps = G._pairing_struct(4, g.stages, keep)
+    assert G.load_library().gft_plan(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(o), ctypes.byref(h)) == 1
+    assert _status(lambda: G.gft_plan_batch([g, wl.path(6)], in_dtype="bf16")) == "GFT_ERR_UNSUPPORTED"
+    p = G.gft_plan(4, g.src, g.dst, g.weight, stages=g.stages, in_dtype="bf16", out_dtype="bf16")
+    assert (p.in_dtype, p.out_dtype) == ("bf16", "bf16")
 
 
 def test_null_arguments_rejected():
