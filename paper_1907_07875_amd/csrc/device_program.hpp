@@ -40,7 +40,7 @@ struct DevBlock {
 
 struct DevProgram {
   int32_t n;          // signal length
-  int32_t stride;     // LDS row stride in floats (odd, >= n)
+  int32_t stride;     // LDS row stride in floats: n (n odd), n + 4 (4 | n), else n + 1
   int32_t mt;         // 16-signal M-tiles per tile; tile = 16*mt signals
   int32_t num_pre;    // stages [0, num_pre) run before the blocks
   int32_t num_post;   // stages [num_pre, num_pre+num_post) run after the blocks

@@ -115,8 +115,22 @@ __device__ __forceinline__ void issue_tile(const void *g, int count, const float
   }
 }
 
+// LDS element of tile element e (row e / n, column e mod n) for a float4 starting at e
+// that is one aligned 16-byte access: stride == n (rows packed) or 4 | n (rows aligned,
+// stride n + 4; a float4 never crosses a row).
+__device__ __forceinline__ bool vec_lds(int n, int stride) { return stride == n || (n & 3) == 0; }
+__device__ __forceinline__ uint32_t vec_index(uint32_t e, int n, int stride, uint32_t magic_n) {
+  if (stride == n) return e;
+  const uint32_t r = fdiv(e, magic_n);
+  return r * (uint32_t)stride + (e - r * (uint32_t)n);
+}
+
 __device__ __forceinline__ void put4(float *lds, uint32_t e, const floatx4 &val, int n,
                                      int stride, uint32_t magic_n) {
+  if (vec_lds(n, stride)) {
+    *reinterpret_cast<floatx4 *>(lds + vec_index(e, n, stride, magic_n)) = val;
+    return;
+  }
   uint32_t r = fdiv(e, magic_n);
   uint32_t c = e - r * (uint32_t)n;
   const float q[4] = {val[0], val[1], val[2], val[3]};
@@ -162,17 +176,26 @@ __device__ __forceinline__ void store_tile(const float *lds, int count, int n, i
                                            uint32_t magic_n, void *g) {
   const int tid = threadIdx.x;
   const int nvec = count >> 2;
+  const bool vec = vec_lds(n, stride);
   for (int v = tid; v < nvec; v += kThreads) {
     const uint32_t e = 4u * (uint32_t)v;
-    uint32_t r = fdiv(e, magic_n);
-    uint32_t c = e - r * (uint32_t)n;
     float q[4];
+    if (vec) {
+      const floatx4 w = *reinterpret_cast<const floatx4 *>(lds + vec_index(e, n, stride, magic_n));
+      q[0] = w[0];
+      q[1] = w[1];
+      q[2] = w[2];
+      q[3] = w[3];
+    } else {
+      uint32_t r = fdiv(e, magic_n);
+      uint32_t c = e - r * (uint32_t)n;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      q[k] = lds[r * stride + c];
-      if (++c == (uint32_t)n) {
-        c = 0;
-        ++r;
+      for (int k = 0; k < 4; ++k) {
+        q[k] = lds[r * stride + c];
+        if (++c == (uint32_t)n) {
+          c = 0;
+          ++r;
+        }
       }
     }
     if constexpr (B16)
@@ -302,7 +325,7 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
 template <int MT, int PREC, bool IN16, bool OUT16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MT >= 8 ? 2 : 4))) void gft_apply(
     DevProgram P, const void *in, void *out, int64_t S) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   constexpr int T = 16 * MT;
   const int n = P.n;
   const int stride = P.stride;
@@ -386,7 +409,7 @@ template <int PREC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void gft_apply_batch(
     const DevProgram *__restrict__ progs, int G, const int64_t *__restrict__ sig_off,
     int64_t total_elems, const float *in, float *out) {
-  extern __shared__ int32_t smem[];
+  extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   int64_t *elem = reinterpret_cast<int64_t *>(smem);          // G + 1 entries
   int32_t *area = smem + 2 * ((G + 2) & ~1);                   // program area
   // per-thread partial sums over contiguous chunks of graphs, then a serial scan of the

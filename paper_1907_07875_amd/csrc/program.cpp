@@ -68,7 +68,10 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   DevProgram &P = out.prog;
   P = DevProgram{};
   P.n = n;
-  P.stride = (n % 2) ? n : n + 1;
+  // Odd n: rows packed (stride n), so the tile is the signals' own contiguous layout.
+  // n a multiple of 4: stride n + 4 keeps every row 16-byte aligned.  Either way a
+  // float4 of the signal array is one aligned 16-byte LDS access.  Otherwise n + 1.
+  P.stride = (n % 2) ? n : ((n % 4 == 0) ? n + 4 : n + 1);
   P.magic_n = magic_for((uint32_t)n);
 
   std::vector<int32_t> stages, ops, blocks, items, gidx, sidx;
