@@ -107,19 +107,61 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   // Blocks.  Forward: K = block nodes (gather node columns), N = eigenvectors (scatter to
   // output positions), M[j][k] = scale * V[j][k].  Inverse: K = output positions, N = nodes,
   // M[k][j] = scale * V[j][k].
-  for (int b = 0; b < (int)p.blocks.size(); ++b) {
-    const HostBlock &B = p.blocks[b];
-    const int sz = B.size;
+  // Leaf blocks of at most 16 nodes are packed, first fit by decreasing size, into device
+  // blocks of at most 16 whose matrix is block diagonal: one 16-column MFMA tile then
+  // serves several small blocks (the zero off-diagonal entries add exact zeros).
+  std::vector<std::vector<int>> groups;
+  {
+    std::vector<int> order(p.blocks.size());
+    for (size_t b = 0; b < order.size(); ++b) order[b] = (int)b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return p.blocks[a].size > p.blocks[c].size; });
+    std::vector<int> fill;
+    for (int b : order) {
+      const int sz = p.blocks[b].size;
+      int dst = -1;
+      if (sz <= 16)
+        for (size_t g = 0; g < groups.size(); ++g)
+          if (fill[g] + sz <= 16 && fill[g] > 0 && p.blocks[groups[g][0]].size <= 16) {
+            dst = (int)g;
+            break;
+          }
+      if (dst < 0) {
+        groups.push_back({});
+        fill.push_back(0);
+        dst = (int)groups.size() - 1;
+      }
+      groups[dst].push_back(b);
+      fill[dst] += sz;
+    }
+  }
+  for (int b = 0; b < (int)groups.size(); ++b) {
+    // concatenated nodes / output positions, and the owning leaf block of each index
+    std::vector<int32_t> knodes, kout;
+    std::vector<const HostBlock *> owner;
+    std::vector<int> local;
+    for (int lb : groups[b]) {
+      const HostBlock &L = p.blocks[lb];
+      for (int k = 0; k < L.size; ++k) {
+        knodes.push_back(L.nodes[k]);
+        kout.push_back(L.out_pos[k]);
+        owner.push_back(&L);
+        local.push_back(k);
+      }
+    }
+    const int sz = (int)knodes.size();
     const int kchunks = (sz + KS - 1) / KS;
     const int ntiles = (sz + 15) / 16;
     const int g_off = (int)gidx.size(), s_off = (int)sidx.size(), f_off = (int)frag.size();
-    const std::vector<int32_t> &kin = direction == 0 ? B.nodes : B.out_pos;
-    const std::vector<int32_t> &nout = direction == 0 ? B.out_pos : B.nodes;
+    const std::vector<int32_t> &kin = direction == 0 ? knodes : kout;
+    const std::vector<int32_t> &nout = direction == 0 ? kout : knodes;
     for (int k = 0; k < KS * kchunks; ++k) gidx.push_back(kin[k < sz ? k : 0]);
     for (int c = 0; c < sz; ++c) sidx.push_back(nout[c]);
     auto mat = [&](int k, int c) -> double {   // M[k][c] of this direction, zero padded
-      if (k >= sz || c >= sz) return 0.0;
-      return B.scale * (direction == 0 ? B.V[(size_t)k * sz + c] : B.V[(size_t)c * sz + k]);
+      if (k >= sz || c >= sz || owner[k] != owner[c]) return 0.0;
+      const HostBlock &B = *owner[k];
+      const int lk = local[k], lc = local[c], bs = B.size;
+      return B.scale * (direction == 0 ? B.V[(size_t)lk * bs + lc] : B.V[(size_t)lc * bs + lk]);
     };
     frag.resize(frag.size() + (size_t)kchunks * ntiles * 64 * WPL, 0u);
     for (int kc = 0; kc < kchunks; ++kc)
@@ -157,7 +199,7 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   std::stable_sort(items.begin(), items.end(), [&](int32_t a, int32_t c) {
     return blocks[8 * (a >> 16) + 1] > blocks[8 * (c >> 16) + 1];
   });
-  P.num_blocks = (int32_t)p.blocks.size();
+  P.num_blocks = (int32_t)groups.size();
   P.num_items = (int32_t)items.size();
   P.gidx_len = (int32_t)gidx.size();
   P.sidx_len = (int32_t)sidx.size();
