@@ -100,6 +100,8 @@ gft_options default_options(const gft_options *o) {
   return d;
 }
 
+constexpr int kBatchRounds = 4;   // batch grid = rounds x resident workgroups
+
 gft_status check_options(const gft_options &o) {
   if (o.precision < GFT_FP32 || o.precision > GFT_SPLIT_BF16)
     return set_error(GFT_ERR_INVALID_ARG, "options.precision is not a gft_precision value");
@@ -135,8 +137,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   size_t budget = std::min<size_t>(kMaxLdsBytes, (size_t)max_lds);
   const int G = (int)plan->graphs.size();
   if (plan->batch) {
-    // the batch kernel keeps G+1 element offsets and 257 partial sums in LDS as well
-    const size_t fixed = batch_lds_bytes(G, 0) + 8 * 257 + 256;
+    // the batch kernel keeps G+1 element offsets and the scan's wave totals in LDS as well
+    const size_t fixed = batch_lds_bytes(G, 0) + 64 + 256;
     if (fixed + 4096 > budget) return set_error(GFT_ERR_UNSUPPORTED, "too many graphs in one batch plan");
     budget -= fixed;
   }
@@ -305,7 +307,9 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     img->dev_fwd = static_cast<const DevProgram *>(parr);
     img->dev_inv = img->dev_fwd + G;
     img->batch_lds = batch_lds_bytes(G, maxlds);
-    img->batch_grid = img->num_cus * batch_occupancy(plan->opts.precision, img->batch_lds);
+    // several rounds of resident workgroups: the hardware then hands the byte-equal shares
+    // to CUs as they free up, which evens out graphs of different cost per byte
+    img->batch_grid = kBatchRounds * img->num_cus * batch_occupancy(plan->opts.precision, img->batch_lds);
   }
   *out = img.get();
   plan->images[dev] = std::move(img);

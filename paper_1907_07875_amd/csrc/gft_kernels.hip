@@ -412,9 +412,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   int64_t *elem = reinterpret_cast<int64_t *>(smem);          // G + 1 entries
   int32_t *area = smem + 2 * ((G + 2) & ~1);                   // program area
-  // per-thread partial sums over contiguous chunks of graphs, then a serial scan of the
-  // kThreads partials by thread 0 and a second pass
-  __shared__ int64_t part[kThreads + 1];
+  // per-thread partial sums over contiguous chunks of graphs, an exclusive scan of the
+  // kThreads partials (inclusive scans inside each wave by shuffles, then the wave totals),
+  // and a second pass writing elem[]
+  __shared__ int64_t wsum[kThreads / 64];
   const int per = (G + kThreads - 1) / kThreads;
   const int g0 = threadIdx.x * per, g1 = g0 + per < G ? g0 + per : G;
   int64_t acc = 0;
@@ -422,25 +423,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int64_t ns = sig_off[g + 1] - sig_off[g];
     acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
   }
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < kThreads; ++i) {
-      const int64_t v = part[i];
-      part[i] = run;
-      run += v;
-    }
-    part[kThreads] = run;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t inc = acc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
   }
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  acc = part[threadIdx.x];
+  int64_t base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  acc = base + inc - acc;                                      // exclusive prefix
   for (int g = g0; g < g1; ++g) {
     elem[g] = acc;
     const int64_t ns = sig_off[g + 1] - sig_off[g];
     acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
   }
-  if (threadIdx.x == 0) elem[G] = part[kThreads];
+  if (threadIdx.x == kThreads - 1) elem[G] = acc;
   __syncthreads();
 
   const int64_t E = elem[G];
@@ -620,7 +620,7 @@ template <int PREC>
 static hipError_t launch_batch_p(const DevProgram *progs, int G, const int64_t *sig_off,
                                  int64_t total_elems, const float *in, float *out,
                                  size_t lds, int grid, hipStream_t stream) {
-  if (lds + 8 * (kThreads + 1) > 64 * 1024) {
+  if (lds + 8 * (kThreads / 64) > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
