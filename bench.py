@@ -187,6 +187,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
                              in_dtype=args.io, out_dtype=args.io)
     plan.prepare()
     eng = plan.engine()
+    tiles = plan.tiles()
     stream = torch.cuda.current_stream()
     ya, yb, xr = torch.empty_like(xa), torch.empty_like(xa), torch.empty_like(xa)
     bufs = [(xa, ya), (xb, yb)]
@@ -226,7 +227,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
-            "kernel": kname + " (forward)", "engine": eng,
+            "kernel": kname + " (forward)", "engine": eng, "signals_per_tile": list(tiles),
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms}
     if flops_per_signal is not None:
         tflops = flops_per_signal * S / (fwd_ms * 1e-3) / 1e12

@@ -127,7 +127,8 @@ typedef enum {
 typedef struct {
   int32_t precision;       /* gft_precision                                           */
   int32_t order;           /* gft_order                                               */
-  int32_t tile_override;   /* 0 = tuned choice; else signals per tile (multiple of 16)*/
+  int32_t tile_override;   /* 0 = autotuned at plan preparation (generic engine);     */
+                           /* else signals per tile: 16, 32, 64 or 128                */
   int32_t engine;          /* gft_engine                                              */
   double sym_tol;          /* relative tolerance of the phi-symmetry test on sub-graph*/
                            /* Laplacians; <= 0 selects 1e-12                          */
@@ -201,6 +202,13 @@ gft_status gft_plan_prepare(gft_plan_t plan);
  * plan's image on the current device runs; builds the image like gft_plan_prepare.
  * Needs a GPU. */
 gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
+
+/* Signals per tile of the forward and inverse kernels on the current device (single-graph
+ * plans; builds the image like gft_plan_prepare): the generic engine's tile height, which
+ * options.tile_override fixes or, when it is 0, the plan-time autotuner picks by timing
+ * every height that fits in LDS on a synthetic batch (same results for every height);
+ * 16 for the butterfly engine (per wave); 0 for the large-signal engine.  Needs a GPU. */
+gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */
 gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out);

@@ -32,7 +32,7 @@ STATUS = {
 # Every symbol include/gft.h declares.
 EXPORTS = [
     "gft_plan", "gft_plan_batch", "gft_forward", "gft_inverse", "gft_forward_batch",
-    "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_info", "gft_plan_num_graphs",
+    "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_tiles", "gft_plan_info", "gft_plan_num_graphs",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version",
 ]
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_inverse_batch": ([P, P, P, P, i64, P], i32),
         "gft_plan_prepare": ([P], i32),
         "gft_plan_engine": ([P, ctypes.POINTER(i32)], i32),
+        "gft_plan_tiles": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "gft_plan_info": ([P, i32, ctypes.POINTER(PlanStats)], i32),
         "gft_plan_num_graphs": ([P, ctypes.POINTER(i32)], i32),
         "gft_plan_size": ([P, i32, ctypes.POINTER(i32)], i32),
@@ -255,6 +256,12 @@ class Plan:
         e = ctypes.c_int32()
         _check(load_library().gft_plan_engine(self._h, ctypes.byref(e)))
         return {1: "generic", 2: "butterfly", 3: "large"}[e.value]
+
+    def tiles(self):
+        """(forward, inverse) signals per tile on the current device (0 = large engine)."""
+        f, i = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().gft_plan_tiles(self._h, ctypes.byref(f), ctypes.byref(i)))
+        return f.value, i.value
 
     # -- device apply ----------------------------------------------------------------
     def forward(self, x, out=None, stream=None):

@@ -118,6 +118,66 @@ gft_status check_options(const gft_options &o) {
   return GFT_OK;
 }
 
+// Tile autotuning of the generic engine, a plan-time step: every tile height 16*mt whose
+// LDS footprint fits `budget` is timed on a zero-filled synthetic batch (16M values) on this
+// device, on a stream of its own: after a warm-up, the candidates take turns over several
+// rounds and each keeps its best time (clock ramps and noise then hit all alike); another
+// height replaces the built-in choice only when it is at least 3% faster.  The transform's
+// arithmetic does not depend on mt (the same products in the same order), so the choice
+// changes speed only.  On any HIP error the built-in choice stays.
+void autotune_generic(DeviceImage *img, int dir, size_t budget, bool in16, bool out16) {
+  DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
+  int &cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
+  const int64_t n = P.n;
+  const int64_t S = std::max<int64_t>((int64_t)(16 << 20) / n, 16 * 8 * (int64_t)img->num_cus);
+  void *buf = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipMalloc(&buf, 2 * (size_t)S * n * 4) != hipSuccess) return;
+  bool okay = hipMemset(buf, 0, 2 * (size_t)S * n * 4) == hipSuccess &&
+              hipStreamCreate(&st) == hipSuccess && hipEventCreate(&ev[0]) == hipSuccess &&
+              hipEventCreate(&ev[1]) == hipSuccess;
+  const float *in = static_cast<const float *>(buf);
+  float *outp = static_cast<float *>(buf) + (size_t)S * n;
+  std::vector<DevProgram> cand;
+  std::vector<int> caps;
+  for (int mt : {8, 4, 2, 1}) {
+    DevProgram C = P;
+    C.mt = mt;
+    if (program_lds_bytes(C) > budget) continue;
+    cand.push_back(C);
+    caps.push_back(img->num_cus * apply_occupancy(C));
+  }
+  std::vector<float> best(cand.size(), 0.0f);
+  int base = -1;
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (cand[c].mt == P.mt) base = (int)c;
+  for (int w = 0; w < 6 && okay && base >= 0; ++w)      // warm-up: clocks, code, caches
+    okay = launch_apply(cand[base], in, outp, S, st, caps[base], in16, out16) == hipSuccess;
+  for (int round = 0; round < 4 && okay; ++round)
+    for (size_t c = 0; c < cand.size() && okay; ++c) {
+      okay = hipEventRecord(ev[0], st) == hipSuccess;
+      for (int r = 0; r < 2 && okay; ++r)
+        okay = launch_apply(cand[c], in, outp, S, st, caps[c], in16, out16) == hipSuccess;
+      float ms = 0.0f;
+      okay = okay && hipEventRecord(ev[1], st) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+             hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess;
+      if (okay && (best[c] == 0.0f || ms < best[c])) best[c] = ms;
+    }
+  if (okay && base >= 0) {
+    int pick = base;
+    for (size_t c = 0; c < cand.size(); ++c)
+      if (best[c] < 0.97f * best[pick]) pick = (int)c;
+    P.mt = cand[pick].mt;
+    cap = caps[pick];
+  }
+  (void)hipGetLastError();
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipFree(buf);
+}
+
 // Get (building on first use) the image of `plan` on the current device.
 gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   int dev = -1;
@@ -311,6 +371,12 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     // to CUs as they free up, which evens out graphs of different cost per byte
     img->batch_grid = kBatchRounds * img->num_cus * batch_occupancy(plan->opts.precision, img->batch_lds);
   }
+  if (!plan->batch && !img->butterfly && !img->large && plan->opts.tile_override == 0)
+    for (int d = 0; d < 2; ++d) {
+      const bool i16 = (d == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
+      const bool o16 = (d == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
+      autotune_generic(img.get(), d, budget, i16, o16);
+    }
   *out = img.get();
   plan->images[dev] = std::move(img);
   return GFT_OK;
@@ -491,6 +557,23 @@ gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out) {
   gft_status st = device_image(plan, &img);
   if (st != GFT_OK) return st;
   *engine_out = img->butterfly ? GFT_ENGINE_BUTTERFLY : (img->large ? GFT_ENGINE_LARGE : GFT_ENGINE_GENERIC);
+  return ok();
+}
+
+gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile) {
+  if (!plan || !fwd_tile || !inv_tile) return set_error(GFT_ERR_INVALID_ARG, "plan and outputs must be non-NULL");
+  if (plan->batch) return set_error(GFT_ERR_INVALID_ARG, "batch plans keep one tile per graph");
+  DeviceImage *img = nullptr;
+  gft_status st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  if (img->butterfly) {
+    *fwd_tile = *inv_tile = 16;
+  } else if (img->large) {
+    *fwd_tile = *inv_tile = 0;
+  } else {
+    *fwd_tile = 16 * img->fwd[0].mt;
+    *inv_tile = 16 * img->inv[0].mt;
+  }
   return ok();
 }
 
