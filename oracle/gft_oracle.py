@@ -61,6 +61,33 @@ def laplacian_of(graph):
     return laplacian(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop)
 
 
+def degrees(n, src, dst, weight):
+    """d_i = sum_{j != i} w_ij (the degree of eq. l_from_sw: self-loops excluded)."""
+    d = np.zeros(n, dtype=np.float64)
+    for i, j, w in zip(np.asarray(src), np.asarray(dst), np.asarray(weight, dtype=np.float64)):
+        d[int(i)] += w
+        d[int(j)] += w
+    return d
+
+
+def normalized_laplacian(n, src, dst, weight, self_loop=None):
+    """Symmetric normalized Laplacian D^{-1/2} L D^{-1/2} (Sec. II-B), written entry by entry:
+    l_ij / sqrt(d_i d_j) with L = D - W + S and d the degrees.  Every node needs d_i > 0."""
+    L = laplacian(n, src, dst, weight, self_loop)
+    d = degrees(n, src, dst, weight)
+    if np.any(d <= 0):
+        raise ValueError("the normalized Laplacian needs every node to have a positive degree")
+    Ln = np.empty_like(L)
+    for i in range(n):
+        for j in range(n):
+            Ln[i, j] = L[i, j] / np.sqrt(d[i] * d[j])
+    return Ln
+
+
+def normalized_laplacian_of(graph):
+    return normalized_laplacian(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop)
+
+
 def weights_from_laplacian(L):
     """Inverse map of eq. sw_from_l: s_i = sum_j l_ij and w_ij = -l_ij (i != j)."""
     L = np.asarray(L, dtype=np.float64)

@@ -376,6 +376,48 @@ def test_k_regular_bipartite_eigen_pairing():
         np.testing.assert_allclose(L @ u, (4 - lam[k]) * u, atol=1e-12)
 
 
+def test_normalized_laplacian_closed_forms():
+    """Symmetric normalized Laplacian (Sec. II-B) pinned without its own formula:
+    k-regular graphs give L / k (cycle: 1 - cos(2 pi k / n)); the unweighted path has
+    eigenvalues 1 - cos(pi k / (n - 1)); D^{1/2} 1 spans the null space; the spectrum equals
+    that of the random-walk Laplacian D^{-1} L (a similar matrix, computed separately)."""
+    n = 10
+    lam = np.linalg.eigvalsh(O.normalized_laplacian_of(wl.cycle(n)))
+    np.testing.assert_allclose(lam, np.sort(1 - np.cos(2 * np.pi * np.arange(n) / n)), atol=1e-13)
+    for n in (2, 3, 7, 16):
+        lam = np.linalg.eigvalsh(O.normalized_laplacian_of(wl.path(n)))
+        np.testing.assert_allclose(lam, np.sort(1 - np.cos(np.pi * np.arange(n) / (n - 1))), atol=1e-13)
+    g = wl._graph(12, [(i, i + 1) for i in range(11)] + [(0, 5), (3, 9)],
+                  wl.rng_for(9, 1).uniform(0.1, 1.0, 13))
+    d = O.degrees(g.n, g.src, g.dst, g.weight)
+    Ln = O.normalized_laplacian_of(g)
+    np.testing.assert_allclose(Ln @ np.sqrt(d), 0, atol=1e-13)
+    rw = np.sort(np.linalg.eigvals(np.diag(1 / d) @ O.laplacian_of(g)).real)
+    np.testing.assert_allclose(np.linalg.eigvalsh(Ln), rw, atol=1e-12)
+    with pytest.raises(ValueError):
+        O.normalized_laplacian(3, [0], [1], [1.0])        # node 2 has no edge
+
+
+def test_normalized_bipartite_spectrum_is_symmetric_about_one():
+    """Normalized-Laplacian analogue of Lemma k-rbg: for any bipartite graph, (u1; -u2) is an
+    eigenvector with eigenvalue 2 - lambda (parts listed first / second)."""
+    rng = wl.rng_for(9, 2)
+    p, q = 5, 8
+    edges, wts = [], []
+    for i in range(p):
+        for j in range(q):
+            if rng.random() < 0.5 or j == i:
+                edges.append((i, p + j))
+                wts.append(rng.uniform(0.5, 1.5))
+    g = wl._graph(p + q, edges, wts)
+    Ln = O.normalized_laplacian_of(g)
+    lam, U = O.gft(Ln)
+    for k in range(p + q):
+        u = U[:, k].copy()
+        u[p:] *= -1
+        np.testing.assert_allclose(Ln @ u, (2 - lam[k]) * u, atol=1e-12)
+
+
 def test_connected_components():
     g = wl._graph(7, [(0, 1), (1, 2), (3, 4), (5, 6)])
     comps = O.connected_components(O.laplacian_of(g))
