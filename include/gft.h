@@ -99,6 +99,14 @@ typedef enum {
   GFT_DTYPE_BF16 = 1
 } gft_dtype;
 
+/* Which Laplacian the GFT diagonalises (Sec. II-B). */
+typedef enum {
+  GFT_LAPLACIAN_COMBINATORIAL = 0,  /* L = D - W + S (eq. l_from_sw)                        */
+  GFT_LAPLACIAN_NORMALIZED = 1      /* D^{-1/2} L D^{-1/2}, d_i = sum_{j != i} w_ij; every  */
+                                    /* node needs d_i > 0 (else GFT_ERR_GRAPH).  The left   */
+                                    /* Haar decomposition holds for it as well (Sec. IV-B) */
+} gft_laplacian;
+
 typedef enum {
   GFT_ORDER_EIGENVALUE = 0,  /* ascending eigenvalue; ties by leaf-block order, then  */
                              /* local index (any basis of an eigenspace is a GFT)     */
@@ -138,6 +146,7 @@ typedef struct {
                            /* read by the inverse.  BF16 storage runs on the          */
                            /* butterfly and generic engines of single-graph plans     */
                            /* (else GFT_ERR_UNSUPPORTED); in place needs equal types  */
+  int32_t laplacian;       /* gft_laplacian                                           */
 } gft_options;
 
 typedef struct {

@@ -21,6 +21,7 @@ PRECISIONS = {"fp32": GFT_FP32, "bf16": GFT_BF16, "fp16": GFT_FP16, "split_bf16"
 ORDER_EIGENVALUE, ORDER_BLOCK = 0, 1
 ENGINES = {"auto": 0, "generic": 1, "butterfly": 2, "large": 3}
 DTYPES = {"fp32": 0, "bf16": 1}
+LAPLACIANS = {"combinatorial": 0, "normalized": 1}
 
 STATUS = {
     0: "GFT_OK", 1: "GFT_ERR_INVALID_ARG", 2: "GFT_ERR_GRAPH", 3: "GFT_ERR_NOT_INVOLUTION",
@@ -60,7 +61,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("tile_override", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("sym_tol", ctypes.c_double), ("in_dtype", ctypes.c_int32),
-                ("out_dtype", ctypes.c_int32)]
+                ("out_dtype", ctypes.c_int32), ("laplacian", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -159,10 +160,11 @@ def _pairing_struct(n, stages, keep):
 
 
 def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto",
-             in_dtype="fp32", out_dtype="fp32"):
+             in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial"):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
-    return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype])
+    lap = LAPLACIANS[laplacian] if isinstance(laplacian, str) else int(laplacian)
+    return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype], lap)
 
 
 def _stream_ptr(stream):
@@ -187,11 +189,11 @@ class Plan:
     # -- construction ---------------------------------------------------------------
     @classmethod
     def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0,
-                   engine="auto", in_dtype="fp32", out_dtype="fp32"):
+                   engine="auto", in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial"):
         """Plan one graph (an object with n, src, dst, weight, self_loop, stages)."""
         return gft_plan(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop,
                         graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol,
-                        engine=engine, in_dtype=in_dtype, out_dtype=out_dtype)
+                        engine=engine, in_dtype=in_dtype, out_dtype=out_dtype, laplacian=laplacian)
 
     @property
     def n(self) -> int:
@@ -273,21 +275,22 @@ class Plan:
 
 def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
              order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto", in_dtype="fp32",
-             out_dtype="fp32") -> Plan:
+             out_dtype="fp32", laplacian="combinatorial") -> Plan:
     """Plan the fast GFT of one graph (C: ``gft_plan``).  ``in_dtype`` / ``out_dtype``
     ("fp32" or "bf16") are the storage types of signals and coefficients."""
     lib = load_library()
     keep = []
     g = _graph_struct(n, src, dst, weight, self_loop, keep)
     p = _pairing_struct(n, stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian)
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
 
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
-                   sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32") -> Plan:
+                   sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32",
+                   laplacian="combinatorial") -> Plan:
     """Plan several graphs for one persistent launch (C: ``gft_plan_batch``; FP32 storage)."""
     lib = load_library()
     keep = []
@@ -296,7 +299,7 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     for i, gr in enumerate(graphs):
         G[i] = _graph_struct(gr.n, gr.src, gr.dst, gr.weight, gr.self_loop, keep)
         Pr[i] = _pairing_struct(gr.n, gr.stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(g.n) for g in graphs], True, precision)

@@ -109,6 +109,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
   if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_LARGE)
     return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2 or 3");
+  if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL && o.laplacian != GFT_LAPLACIAN_NORMALIZED)
+    return set_error(GFT_ERR_INVALID_ARG, "options.laplacian must be a gft_laplacian value");
   if ((o.in_dtype != GFT_DTYPE_FP32 && o.in_dtype != GFT_DTYPE_BF16) ||
       (o.out_dtype != GFT_DTYPE_FP32 && o.out_dtype != GFT_DTYPE_BF16))
     return set_error(GFT_ERR_INVALID_ARG, "options.in_dtype and options.out_dtype must be gft_dtype values");

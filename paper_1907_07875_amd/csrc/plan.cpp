@@ -184,6 +184,23 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
   subs[0].nodes.resize(n);
   std::iota(subs[0].nodes.begin(), subs[0].nodes.end(), 0);
   subs[0].L = dense_laplacian(g);
+  if (opts.laplacian == GFT_LAPLACIAN_NORMALIZED) {
+    // D^{-1/2} L D^{-1/2} with the degrees of eq. l_from_sw (self-loops excluded)
+    std::vector<double> d(n, 0.0);
+    for (int32_t e = 0; e < g.num_edges; ++e) {
+      d[g.src[e]] += g.weight[e];
+      d[g.dst[e]] += g.weight[e];
+    }
+    for (int32_t i = 0; i < n; ++i)
+      if (!(d[i] > 0.0)) {
+        std::ostringstream os;
+        os << "the normalized Laplacian needs a positive degree at every node; node " << i
+           << " has degree " << d[i];
+        fail(GFT_ERR_GRAPH, os.str());
+      }
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t j = 0; j < n; ++j) subs[0].L[(size_t)i * n + j] /= std::sqrt(d[i] * d[j]);
+  }
   const double scale_L = std::max(max_abs(subs[0].L), 1e-300);
 
   std::vector<int32_t> owner(n, 0), local(n, 0);

@@ -19,10 +19,10 @@ def gpu_basis(plan, dev):
     return plan.forward(eye).double().cpu().numpy()
 
 
-def aligned_oracle_basis(graph, Uhat, sv_tol=1e-5):
+def aligned_oracle_basis(graph, Uhat, sv_tol=1e-5, laplacian="combinatorial"):
     """Oracle eigenbasis rotated onto Uhat inside each eigenvalue cluster (sign / rotation
     are free in a GFT); asserts Uhat spans the oracle's eigenspaces."""
-    L = O.laplacian_of(graph)
+    L = O.laplacian_of(graph) if laplacian == "combinatorial" else O.normalized_laplacian_of(graph)
     lam, U = O.gft(L)
     Ua, min_sv = O.align(U, Uhat, lam)
     assert min_sv > 1 - sv_tol, f"GPU basis leaves the oracle eigenspaces: min singular value {min_sv}"

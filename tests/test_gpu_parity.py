@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 TOL_FP32 = 1e-5
 
 
-def _check_graph(g, X, tol=TOL_FP32, engine="auto", precision="fp32", basis_tol=2e-6):
+def _check_graph(g, X, tol=TOL_FP32, engine="auto", precision="fp32", basis_tol=2e-6,
+                 laplacian="combinatorial"):
     """Forward, inverse and round trip of plan(g) on X against the oracle.
 
     The oracle basis is rotated, inside each eigenvalue cluster, onto the plan's FP64 basis
@@ -25,9 +26,9 @@ def _check_graph(g, X, tol=TOL_FP32, engine="auto", precision="fp32", basis_tol=
     eigenspaces; the basis the GPU applies must equal the plan's to `basis_tol`.
     """
     dev = device()
-    plan = G.Plan.from_graph(g, engine=engine, precision=precision)
+    plan = G.Plan.from_graph(g, engine=engine, precision=precision, laplacian=laplacian)
     Uplan = plan.basis()
-    lam, Ua = aligned_oracle_basis(g, Uplan, sv_tol=1e-9)
+    lam, Ua = aligned_oracle_basis(g, Uplan, sv_tol=1e-9, laplacian=laplacian)
     Uhat = gpu_basis(plan, dev)
     assert np.abs(Uhat - Uplan).max() <= basis_tol, np.abs(Uhat - Uplan).max()
     Xd = X.astype(np.float64)
@@ -198,3 +199,13 @@ def test_autograd_backward_is_inverse_kernel():
         fp = (plan.forward(xd + e) * w).double().sum().item()
         fm = (plan.forward(xd - e) * w).double().sum().item()
         assert abs((fp - fm) / 2 - x.grad[s, i].item()) <= 1e-3
+
+
+@pytest.mark.parametrize("engine", ["auto", "generic", "large"])
+@pytest.mark.parametrize("g", [wl.config2_graph(), wl.config3_graph(), wl.cycle_two_stage(16),
+                               wl.weighted_symmetric_path(64, wl.rng_for(9, 64))],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_normalized_laplacian_parity(g, engine):
+    """GFT of the symmetric normalized Laplacian D^{-1/2} L D^{-1/2} on every engine."""
+    X = wl.gaussian(1500, g.n, wl.rng_for(9, g.n, 3))
+    _check_graph(g, X, engine=engine, laplacian="normalized")

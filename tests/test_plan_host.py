@@ -52,6 +52,32 @@ def test_plan_basis_is_an_oracle_eigenbasis(g):
     assert st["max_orth_error"] < 1e-12 and st["max_residual"] < 1e-12
 
 
+@pytest.mark.parametrize("g", [wl.path(8), wl.cycle(12), wl.config2_graph(), wl.config3_graph(),
+                               wl.weighted_symmetric_path(16, wl.rng_for(9, 16)),
+                               wl.symmetric_bipartite(40, wl.rng_for(4, 40)), wl.cycle_two_stage(16)],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_normalized_laplacian_plan_is_an_oracle_eigenbasis(g):
+    """Same stages on D^{-1/2} L D^{-1/2}: symmetric graphs have d_i = d_phi(i), so the
+    normalized Laplacian keeps every phi-symmetry and the left Haar decomposition applies."""
+    if np.any(O.degrees(g.n, g.src, g.dst, g.weight) <= 0):
+        pytest.skip("graph has an isolated node")
+    plan = G.Plan.from_graph(g, laplacian="normalized")
+    lam, U = O.gft(O.normalized_laplacian_of(g))
+    np.testing.assert_allclose(plan.eigenvalues(), lam, atol=1e-10 * max(1.0, np.abs(lam).max()))
+    Uh = plan.basis()
+    np.testing.assert_allclose(Uh.T @ Uh, np.eye(g.n), atol=1e-12)
+    Ua, min_sv = O.align(U, Uh, lam)
+    assert min_sv > 1 - 1e-9
+    X = wl.gaussian(9, g.n, wl.rng_for(9, g.n, 1), dtype=np.float64)
+    np.testing.assert_allclose(plan.apply_host(X, 0), O.forward(X, Ua), atol=1e-10)
+    assert plan.info()["num_stages"] == len(g.stages)
+
+
+def test_normalized_laplacian_rejects_isolated_nodes():
+    g = wl._graph(4, [(0, 1), (1, 2)])
+    assert _status(lambda: G.gft_plan(4, g.src, g.dst, g.weight, laplacian="normalized")) == "GFT_ERR_GRAPH"
+
+
 def test_config_op_counts():
     """Fast op counts (Table tab:runtime convention) of the benchmark graphs."""
     want = {"path8": (1, 4, 2, 32, 32), "grid8x8": (2, 64, 4, 1088, 1024),
