@@ -107,6 +107,18 @@ typedef enum {
                                     /* Haar decomposition holds for it as well (Sec. IV-B) */
 } gft_laplacian;
 
+/* Right (bipartite) Haar stages (Sec. III, eq. right_gft, Thm. right_haar): a leaf
+ * sub-graph (connected component) whose Laplacian has a constant diagonal c and whose
+ * edges join two parts S1, S2 (a k-regular bipartite graph, or any bipartite graph under
+ * the normalized Laplacian) is applied as two blocks E (on S1) and F (on S2) followed by
+ * right Haar units: eigenvectors (u1; u2) at c - s and (u1; -u2) at c + s (Lemma k-rbg)
+ * share E's column sqrt2 u1 and F's column sqrt2 u2.  Cost |S1|^2 + |S2|^2 instead of
+ * (|S1| + |S2|)^2 multiplications. */
+typedef enum {
+  GFT_RIGHT_HAAR_AUTO = 0,   /* use them on every leaf that qualifies                  */
+  GFT_RIGHT_HAAR_OFF = 1     /* dense leaf blocks only                                 */
+} gft_right_haar;
+
 typedef enum {
   GFT_ORDER_EIGENVALUE = 0,  /* ascending eigenvalue; ties by leaf-block order, then  */
                              /* local index (any basis of an eigenspace is a GFT)     */
@@ -147,12 +159,13 @@ typedef struct {
                            /* butterfly and generic engines of single-graph plans     */
                            /* (else GFT_ERR_UNSUPPORTED); in place needs equal types  */
   int32_t laplacian;       /* gft_laplacian                                           */
+  int32_t right_haar;      /* gft_right_haar                                          */
 } gft_options;
 
 typedef struct {
   int32_t n;
   int32_t num_stages;      /* stages given                                            */
-  int32_t num_units;       /* Haar units over all stages                              */
+  int32_t num_units;       /* Haar units over all stages, left and right              */
   int32_t num_blocks;      /* dense leaf blocks                                       */
   int32_t max_block;       /* largest leaf block                                      */
   int32_t num_z_scalings;  /* sum over stages of |V_Z| in the sub-graphs split        */
@@ -160,6 +173,8 @@ typedef struct {
   int64_t mults;           /* sum_b b^2 + num_z_scalings          (Table tab:runtime)  */
   double max_residual;     /* max over blocks of ||L_b V_b - V_b Lambda_b||_F/||L_b||_F*/
   double max_orth_error;   /* max over blocks of ||V_b^T V_b - I||_max                */
+  int32_t num_right_units; /* right Haar units (included in num_units and adds)       */
+  int32_t num_right_leaves;/* leaf components applied with right Haar units           */
 } gft_plan_stats;
 
 /* Build a plan for one graph.  Validates the graph and every stage, forms the sub-graph

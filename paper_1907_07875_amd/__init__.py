@@ -61,7 +61,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("tile_override", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("sym_tol", ctypes.c_double), ("in_dtype", ctypes.c_int32),
-                ("out_dtype", ctypes.c_int32), ("laplacian", ctypes.c_int32)]
+                ("out_dtype", ctypes.c_int32), ("laplacian", ctypes.c_int32),
+                ("right_haar", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -69,7 +70,8 @@ class PlanStats(ctypes.Structure):
                 ("num_units", ctypes.c_int32), ("num_blocks", ctypes.c_int32),
                 ("max_block", ctypes.c_int32), ("num_z_scalings", ctypes.c_int32),
                 ("adds", ctypes.c_int64), ("mults", ctypes.c_int64),
-                ("max_residual", ctypes.c_double), ("max_orth_error", ctypes.c_double)]
+                ("max_residual", ctypes.c_double), ("max_orth_error", ctypes.c_double),
+                ("num_right_units", ctypes.c_int32), ("num_right_leaves", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -160,11 +162,12 @@ def _pairing_struct(n, stages, keep):
 
 
 def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto",
-             in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial"):
+             in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial", right_haar=True):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
     lap = LAPLACIANS[laplacian] if isinstance(laplacian, str) else int(laplacian)
-    return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype], lap)
+    return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype], lap,
+                    0 if right_haar else 1)
 
 
 def _stream_ptr(stream):
@@ -189,11 +192,13 @@ class Plan:
     # -- construction ---------------------------------------------------------------
     @classmethod
     def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0,
-                   engine="auto", in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial"):
+                   engine="auto", in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial",
+                   right_haar=True):
         """Plan one graph (an object with n, src, dst, weight, self_loop, stages)."""
         return gft_plan(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop,
                         graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol,
-                        engine=engine, in_dtype=in_dtype, out_dtype=out_dtype, laplacian=laplacian)
+                        engine=engine, in_dtype=in_dtype, out_dtype=out_dtype, laplacian=laplacian,
+                        right_haar=right_haar)
 
     @property
     def n(self) -> int:
@@ -275,14 +280,14 @@ class Plan:
 
 def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
              order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto", in_dtype="fp32",
-             out_dtype="fp32", laplacian="combinatorial") -> Plan:
+             out_dtype="fp32", laplacian="combinatorial", right_haar=True) -> Plan:
     """Plan the fast GFT of one graph (C: ``gft_plan``).  ``in_dtype`` / ``out_dtype``
     ("fp32" or "bf16") are the storage types of signals and coefficients."""
     lib = load_library()
     keep = []
     g = _graph_struct(n, src, dst, weight, self_loop, keep)
     p = _pairing_struct(n, stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar)
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
@@ -290,7 +295,7 @@ def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
                    sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32",
-                   laplacian="combinatorial") -> Plan:
+                   laplacian="combinatorial", right_haar=True) -> Plan:
     """Plan several graphs for one persistent launch (C: ``gft_plan_batch``; FP32 storage)."""
     lib = load_library()
     keep = []
@@ -299,7 +304,7 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     for i, gr in enumerate(graphs):
         G[i] = _graph_struct(gr.n, gr.src, gr.dst, gr.weight, gr.self_loop, keep)
         Pr[i] = _pairing_struct(gr.n, gr.stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(g.n) for g in graphs], True, precision)

@@ -109,6 +109,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
   if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_LARGE)
     return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2 or 3");
+  if (o.right_haar != GFT_RIGHT_HAAR_AUTO && o.right_haar != GFT_RIGHT_HAAR_OFF)
+    return set_error(GFT_ERR_INVALID_ARG, "options.right_haar must be a gft_right_haar value");
   if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL && o.laplacian != GFT_LAPLACIAN_NORMALIZED)
     return set_error(GFT_ERR_INVALID_ARG, "options.laplacian must be a gft_laplacian value");
   if ((o.in_dtype != GFT_DTYPE_FP32 && o.in_dtype != GFT_DTYPE_BF16) ||
@@ -271,11 +273,11 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       if (!build_large(plan->graphs[0], d, lgi[d]))
         return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine takes at most " +
                                                   std::to_string(kLargeMaxCols) + " workspace columns");
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < 2; ++k) {
+        loff[d][2 * k] = blob.add(lgi[d].stages[k].data(), lgi[d].stages[k].size() * 4);
         loff[d][2 * k + 1] = blob.add(lgi[d].gather[k].data(), lgi[d].gather[k].size() * 4);
-      const int sp = d == 0 ? 0 : 1;   // pass holding the stages
-      loff[d][4] = blob.add(lgi[d].stages[sp].data(), lgi[d].stages[sp].size() * 4);
-      loff[d][5] = blob.add(lgi[d].ops[sp].data(), lgi[d].ops[sp].size() * 4);
+        loff[d][4 + k] = blob.add(lgi[d].ops[k].data(), lgi[d].ops[k].size() * 4);
+      }
       loff[d][6] = blob.add(lgi[d].blocks.data(), lgi[d].blocks.size() * sizeof(LBlock));
       lgi[d].block_sizes.shrink_to_fit();
       // matrices last (largest)
@@ -330,8 +332,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       for (int k = 0; k < 2; ++k) {
         PermPass &P = L.pass[k];
         P.gather = L.gather[k].empty() ? nullptr : reinterpret_cast<const int32_t *>(base + loff[d][2 * k + 1]);
-        P.stages = reinterpret_cast<const int32_t *>(base + loff[d][4]);
-        P.ops = reinterpret_cast<const uint32_t *>(base + loff[d][5]);
+        P.stages = reinterpret_cast<const int32_t *>(base + loff[d][2 * k]);
+        P.ops = reinterpret_cast<const uint32_t *>(base + loff[d][4 + k]);
       }
       L.dev_blocks = reinterpret_cast<const LBlock *>(base + loff[d][6]);
       L.dev_mats = mats16 ? nullptr : reinterpret_cast<const float *>(base + lmat[d]);

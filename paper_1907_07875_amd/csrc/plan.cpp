@@ -140,6 +140,130 @@ void split(const Sub &H, const std::vector<int32_t> &lp, Sub &plus, Sub &minus,
 }
 
 // Connected components of a sub-graph (couplings with |l_ab| > tol), each ascending.
+// Right Haar split of a connected leaf (Sec. III, eq. right_gft, Thm. right_haar; Lemma
+// k-rbg for the eigenvector pairing).  Lb is the leaf's b x b Laplacian.  It qualifies when
+// its diagonal is a constant c and its off-diagonal pattern is bipartite (parts part1,
+// part2).  From an FP64 eigendecomposition of Lb: every eigenvector (u1; u2) with eigenvalue
+// c - s < c gives E's column sqrt2 u1 and F's column sqrt2 u2 (its mirror (u1; -u2) at c + s
+// is the difference of the same two columns); the eigenspace of c splits into an
+// orthonormal basis of its part-1 halves (E's remaining columns) and of its part-2 halves
+// (F's).  Returns false when the leaf does not qualify or the counts do not come out.
+struct RightSplit {
+  std::vector<int> part1, part2;
+  std::vector<double> E, F;          // p x p and q x q, column k of E at E[j * p + k]
+  std::vector<double> lamE, lamF;    // eigenvalue carried by each column
+  int pairs = 0;                     // leading paired columns
+  std::vector<double> U, lamU;       // the b x b eigenbasis they imply (for the checks)
+};
+
+// Modified Gram-Schmidt (twice) of candidate vectors of length m; keeps those whose
+// remaining norm exceeds keep_tol, appended to `basis` (k vectors of length m, column-major).
+void orthonormal_extend(int m, const std::vector<std::vector<double>> &cands, double keep_tol,
+                        std::vector<std::vector<double>> &basis) {
+  for (std::vector<double> v : cands) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (const std::vector<double> &w : basis) {
+        double d = 0.0;
+        for (int i = 0; i < m; ++i) d += w[i] * v[i];
+        for (int i = 0; i < m; ++i) v[i] -= d * w[i];
+      }
+    double nr = 0.0;
+    for (int i = 0; i < m; ++i) nr += v[i] * v[i];
+    nr = std::sqrt(nr);
+    if (nr <= keep_tol) continue;
+    for (int i = 0; i < m; ++i) v[i] /= nr;
+    basis.push_back(std::move(v));
+  }
+}
+
+bool right_split(int b, const std::vector<double> &Lb, double tol, RightSplit &rs) {
+  if (b < 2) return false;
+  const double c = Lb[0];
+  for (int i = 0; i < b; ++i)
+    if (std::fabs(Lb[(size_t)i * b + i] - c) > tol) return false;
+  std::vector<int> side(b, -1), queue{0};
+  side[0] = 0;
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int i = queue[h];
+    for (int j = 0; j < b; ++j) {
+      if (j == i || std::fabs(Lb[(size_t)i * b + j]) <= tol) continue;
+      if (side[j] < 0) {
+        side[j] = 1 - side[i];
+        queue.push_back(j);
+      } else if (side[j] == side[i]) {
+        return false;   // odd cycle: not bipartite
+      }
+    }
+  }
+  for (int i = 0; i < b; ++i) {
+    if (side[i] < 0) return false;   // not connected (components are, so this is defensive)
+    (side[i] == 0 ? rs.part1 : rs.part2).push_back(i);
+  }
+  const int p = (int)rs.part1.size(), q = (int)rs.part2.size();
+  std::vector<double> lam, V;
+  if (!symmetric_eigen(b, Lb, lam, V)) return false;
+  double lmax = 1.0;
+  for (double l : lam) lmax = std::max(lmax, std::fabs(l));
+  const double thr = 1e-8 * lmax;
+  std::vector<std::vector<double>> e_cols, f_cols, e_null, f_null;
+  std::vector<double> pair_lam;
+  int above = 0;
+  std::vector<std::vector<double>> h1, h2;
+  for (int k = 0; k < b; ++k) {
+    std::vector<double> u1(p), u2(q);
+    for (int a = 0; a < p; ++a) u1[a] = V[(size_t)rs.part1[a] * b + k];
+    for (int a = 0; a < q; ++a) u2[a] = V[(size_t)rs.part2[a] * b + k];
+    if (lam[k] < c - thr) {
+      for (double &x : u1) x *= std::sqrt(2.0);
+      for (double &x : u2) x *= std::sqrt(2.0);
+      e_cols.push_back(std::move(u1));
+      f_cols.push_back(std::move(u2));
+      pair_lam.push_back(lam[k]);
+    } else if (lam[k] > c + thr) {
+      ++above;
+    } else {
+      h1.push_back(std::move(u1));
+      h2.push_back(std::move(u2));
+    }
+  }
+  const int m = (int)e_cols.size();
+  if (above != m) return false;
+  orthonormal_extend(p, h1, 1e-6, e_null);
+  orthonormal_extend(q, h2, 1e-6, f_null);
+  if (m + (int)e_null.size() != p || m + (int)f_null.size() != q) return false;
+  rs.pairs = m;
+  rs.E.assign((size_t)p * p, 0.0);
+  rs.F.assign((size_t)q * q, 0.0);
+  for (int k = 0; k < p; ++k) {
+    const std::vector<double> &col = k < m ? e_cols[k] : e_null[k - m];
+    for (int j = 0; j < p; ++j) rs.E[(size_t)j * p + k] = col[j];
+    rs.lamE.push_back(k < m ? pair_lam[k] : c);
+  }
+  for (int k = 0; k < q; ++k) {
+    const std::vector<double> &col = k < m ? f_cols[k] : f_null[k - m];
+    for (int j = 0; j < q; ++j) rs.F[(size_t)j * q + k] = col[j];
+    rs.lamF.push_back(k < m ? 2 * c - pair_lam[k] : c);
+  }
+  // the implied eigenbasis of Lb: (e; f)/sqrt2 and (e; -f)/sqrt2 per pair, (e0; 0), (0; f0)
+  rs.U.assign((size_t)b * b, 0.0);
+  int col = 0;
+  auto put = [&](const std::vector<double> *e, const std::vector<double> *f, double fs, double sc,
+                 double l) {
+    for (int a = 0; a < p && e; ++a) rs.U[(size_t)rs.part1[a] * b + col] = sc * (*e)[a];
+    for (int a = 0; a < q && f; ++a) rs.U[(size_t)rs.part2[a] * b + col] = sc * fs * (*f)[a];
+    rs.lamU.push_back(l);
+    ++col;
+  };
+  const double r2 = 1.0 / std::sqrt(2.0);
+  for (int k = 0; k < m; ++k) {
+    put(&e_cols[k], &f_cols[k], 1.0, r2, pair_lam[k]);
+    put(&e_cols[k], &f_cols[k], -1.0, r2, 2 * c - pair_lam[k]);
+  }
+  for (const auto &v : e_null) put(&v, nullptr, 1.0, 1.0, c);
+  for (const auto &v : f_null) put(nullptr, &v, 1.0, 1.0, c);
+  return col == b;
+}
+
 std::vector<std::vector<int>> components(const Sub &H, double tol) {
   const int m = (int)H.nodes.size();
   std::vector<int> comp(m, -1);
@@ -264,8 +388,13 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
     if (!stage.pair_x.empty()) plan.stages.push_back(std::move(stage));
   }
 
-  // Leaves -> connected components -> dense blocks with FP64 eigensolves.
+  // Leaves -> connected components -> dense blocks with FP64 eigensolves, or block pairs
+  // (E, F) with right Haar units for leaves that qualify.
   double max_res = 0.0, max_orth = 0.0;
+  struct RightPair {
+    int32_t e, f, pairs;
+  };
+  std::vector<RightPair> right_pairs;
   for (const Sub &H : subs) {
     const int m = (int)H.nodes.size();
     const double tol = sym_tol * std::max(max_abs(H.L), 1e-300 * scale_L);
@@ -280,7 +409,12 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
         B.nodes.push_back(H.nodes[comp[p]]);
         for (int q = 0; q < b; ++q) Lb[(size_t)p * b + q] = H.L[(size_t)comp[p] * m + comp[q]];
       }
-      if (!symmetric_eigen(b, Lb, B.lambda, B.V)) {
+      RightSplit rs;
+      const bool right = opts.right_haar == GFT_RIGHT_HAAR_AUTO && right_split(b, Lb, tol, rs);
+      if (right) {
+        B.lambda = rs.lamU;
+        B.V = rs.U;            // checked below as any leaf basis
+      } else if (!symmetric_eigen(b, Lb, B.lambda, B.V)) {
         std::ostringstream os;
         os << "eigensolver did not converge on a leaf block of size " << b;
         fail(GFT_ERR_EIGENSOLVE, os.str());
@@ -307,6 +441,29 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
         os << "leaf block of size " << b << " failed the plan-time check (orthogonality "
            << orth << ", residual " << res << ")";
         fail(GFT_ERR_ORTHOGONALITY, os.str());
+      }
+      if (right) {
+        // E on part 1, F on part 2; the paired columns carry the 1/sqrt2 of their Haar unit
+        HostBlock E, F;
+        E.depth = F.depth = B.depth;
+        E.scale = F.scale = B.scale;
+        E.size = (int32_t)rs.part1.size();
+        F.size = (int32_t)rs.part2.size();
+        for (int a : rs.part1) E.nodes.push_back(B.nodes[a]);
+        for (int a : rs.part2) F.nodes.push_back(B.nodes[a]);
+        E.V = rs.E;
+        F.V = rs.F;
+        E.lambda = rs.lamE;
+        F.lambda = rs.lamF;
+        const double r2 = 1.0 / std::sqrt(2.0);
+        for (int k = 0; k < rs.pairs; ++k) {
+          for (int j = 0; j < E.size; ++j) E.V[(size_t)j * E.size + k] *= r2;
+          for (int j = 0; j < F.size; ++j) F.V[(size_t)j * F.size + k] *= r2;
+        }
+        right_pairs.push_back({(int32_t)plan.blocks.size(), (int32_t)plan.blocks.size() + 1, rs.pairs});
+        plan.blocks.push_back(std::move(E));
+        plan.blocks.push_back(std::move(F));
+        continue;
       }
       plan.blocks.push_back(std::move(B));
     }
@@ -348,6 +505,12 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
     plan.lambda_out[p] = ents[p].lam;
   }
 
+  for (const RightPair &rp : right_pairs)
+    for (int k = 0; k < rp.pairs; ++k) {
+      plan.right.pair_x.push_back(plan.blocks[rp.e].out_pos[k]);   // c - s: the sum
+      plan.right.pair_y.push_back(plan.blocks[rp.f].out_pos[k]);   // c + s: the difference
+    }
+
   gft_plan_stats &st = plan.stats;
   st.n = n;
   st.num_stages = num_stages;
@@ -357,6 +520,9 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
     st.num_units += (int32_t)S.pair_x.size();
     st.num_z_scalings += (int32_t)S.znodes.size();
   }
+  st.num_right_units = (int32_t)plan.right.pair_x.size();
+  st.num_right_leaves = (int32_t)right_pairs.size();
+  st.num_units += st.num_right_units;
   st.num_blocks = (int32_t)plan.blocks.size();
   st.max_block = 0;
   int64_t sum_b2 = 0, sum_bb1 = 0;
@@ -394,11 +560,22 @@ void apply_host(const GraphPlan &p, int direction, const double *x, double *y, i
           for (int j = 0; j < B.size; ++j) acc += B.V[(size_t)j * B.size + k] * z[B.nodes[j]];
           ys[B.out_pos[k]] = B.scale * acc;
         }
+      for (size_t u = 0; u < p.right.pair_x.size(); ++u) {   // right Haar units
+        const double a = ys[p.right.pair_x[u]], b = ys[p.right.pair_y[u]];
+        ys[p.right.pair_x[u]] = a + b;
+        ys[p.right.pair_y[u]] = a - b;
+      }
     } else {
+      std::copy(xs, xs + n, z.begin());
+      for (size_t u = 0; u < p.right.pair_x.size(); ++u) {   // right Haar units (own inverse)
+        const double a = z[p.right.pair_x[u]], b = z[p.right.pair_y[u]];
+        z[p.right.pair_x[u]] = a + b;
+        z[p.right.pair_y[u]] = a - b;
+      }
       for (const HostBlock &B : p.blocks)
         for (int j = 0; j < B.size; ++j) {
           double acc = 0.0;
-          for (int k = 0; k < B.size; ++k) acc += B.V[(size_t)j * B.size + k] * xs[B.out_pos[k]];
+          for (int k = 0; k < B.size; ++k) acc += B.V[(size_t)j * B.size + k] * z[B.out_pos[k]];
           w[B.nodes[j]] = B.scale * acc;
         }
       for (auto it = p.stages.rbegin(); it != p.stages.rend(); ++it) {

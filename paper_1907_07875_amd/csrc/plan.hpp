@@ -36,7 +36,7 @@ struct HostBlock {
   int32_t depth = 0;
   double scale = 1.0;               // 2^(-depth/2)
   std::vector<int32_t> nodes;       // node labels, ascending
-  std::vector<double> lambda;       // ascending
+  std::vector<double> lambda;       // eigenvalue of column k (ascending for dense blocks)
   std::vector<double> V;            // size*size, V[j*size + k]
   std::vector<int32_t> out_pos;     // output position of eigenvector k
 };
@@ -45,6 +45,10 @@ struct GraphPlan {
   int32_t n = 0;
   int32_t num_stages_given = 0;
   std::vector<HostStage> stages;    // stages that split something (others dropped)
+  // Right Haar units (Sec. III, eq. right_gft) after the blocks, on output positions:
+  // forward y[pair_x] = a + b, y[pair_y] = a - b with a, b the two blocks' outputs there
+  // (the 1/sqrt 2 is folded into those block columns).  znodes unused.
+  HostStage right;
   std::vector<HostBlock> blocks;
   std::vector<double> lambda_out;   // eigenvalues in output order
   gft_plan_stats stats{};

@@ -81,10 +81,10 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
   const int KS = precision == GFT_FP32 ? 4 : 16;                  // K per MFMA
   const int WPL = precision == GFT_FP32 ? 1 : (precision == GFT_SPLIT_BF16 ? 4 : 2);
 
-  // Haar stages: forward in plan order before the blocks; inverse in reverse after them.
-  const int ns = (int)p.stages.size();
-  for (int q = 0; q < ns; ++q) {
-    const HostStage &st = p.stages[direction == 0 ? q : ns - 1 - q];
+  // Haar stages.  Forward: left stages in plan order before the blocks (node positions),
+  // the right stage after them (output positions).  Inverse: the right stage before the
+  // blocks, the left stages in reverse order after them.
+  auto emit = [&](const HostStage &st) {
     const int off = (int)(ops.size() / 2);
     for (size_t u = 0; u < st.pair_x.size(); ++u) {
       ops.push_back(st.pair_x[u]);
@@ -97,11 +97,22 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
     const int cnt = (int)(ops.size() / 2) - off;
     stages.push_back(off);
     stages.push_back(cnt);
-    stages.push_back((int32_t)magic_for((uint32_t)cnt));
+    stages.push_back((int32_t)magic_for((uint32_t)std::max(cnt, 1)));
     stages.push_back(0);
+  };
+  const int ns = (int)p.stages.size();
+  const int nr = p.right.pair_x.empty() ? 0 : 1;
+  if (direction == 0) {
+    for (int q = 0; q < ns; ++q) emit(p.stages[q]);
+    if (nr) emit(p.right);
+    P.num_pre = ns;
+    P.num_post = nr;
+  } else {
+    if (nr) emit(p.right);
+    for (int q = ns - 1; q >= 0; --q) emit(p.stages[q]);
+    P.num_pre = nr;
+    P.num_post = ns;
   }
-  P.num_pre = direction == 0 ? ns : 0;
-  P.num_post = direction == 0 ? 0 : ns;
   P.total_ops = (int32_t)(ops.size() / 2);
 
   // Blocks.  Forward: K = block nodes (gather node columns), N = eigenvectors (scatter to
@@ -240,7 +251,7 @@ namespace gft {
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
   const int n = p.n;
   const int S = (int)p.stages.size();
-  if (S < 1 || S > 3) return false;
+  if (S < 1 || S > 3 || !p.right.pair_x.empty()) return false;
   const int NB = 1 << S;
   if ((int)p.blocks.size() != NB || n % NB) return false;
   const int M = n / NB;
@@ -435,26 +446,32 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
     return inv;
   };
   const std::vector<int32_t> wcol_node = inverse_of(col_node, n);
-  // stage program (forward order for the forward, reversed for the inverse); the forward
-  // runs it on x (tile columns = nodes), the inverse on W2 (tile columns = workspace)
-  const int stages_pass = direction == 0 ? 0 : 1;
-  auto tcol = [&](int32_t v) { return (uint32_t)(direction == 0 ? v : wcol_node[v]); };
-  std::vector<int32_t> st;
-  std::vector<uint32_t> ops;
+  const std::vector<int32_t> wcol_coef = inverse_of(col_coef, n);
+  // Stage programs of the two passes.  Pass 1 works on the input row (tile columns = node
+  // positions forward, coefficient positions inverse); pass 3 on the workspace row (tile
+  // columns = workspace columns).  Forward: left stages in pass 1, the right stage in pass
+  // 3; inverse: the right stage in pass 1, the left stages (reversed) in pass 3.
+  auto emit = [&](int k, const HostStage &S, const std::vector<int32_t> *map) {
+    auto tcol = [&](int32_t v) { return (uint32_t)(map ? (*map)[v] : v); };
+    const int off = (int)im.ops[k].size();
+    for (size_t u = 0; u < S.pair_x.size(); ++u)
+      im.ops[k].push_back(tcol(S.pair_x[u]) | (tcol(S.pair_y[u]) << 16));
+    for (int32_t c : S.znodes) im.ops[k].push_back(tcol(c) | (0xffffu << 16));
+    im.stages[k].push_back(off);
+    im.stages[k].push_back((int)im.ops[k].size() - off);
+  };
   const int ns = (int)p.stages.size();
-  for (int q = 0; q < ns; ++q) {
-    const HostStage &S = p.stages[direction == 0 ? q : ns - 1 - q];
-    const int off = (int)ops.size();
-    for (size_t u = 0; u < S.pair_x.size(); ++u) ops.push_back(tcol(S.pair_x[u]) | (tcol(S.pair_y[u]) << 16));
-    for (int32_t c : S.znodes) ops.push_back(tcol(c) | (0xffffu << 16));
-    st.push_back(off);
-    st.push_back((int)ops.size() - off);
+  const bool has_right = !p.right.pair_x.empty();
+  if (direction == 0) {
+    for (int q = 0; q < ns; ++q) emit(0, p.stages[q], nullptr);
+    if (has_right) emit(1, p.right, &wcol_coef);
+  } else {
+    if (has_right) emit(0, p.right, nullptr);
+    for (int q = ns - 1; q >= 0; --q) emit(1, p.stages[q], &wcol_node);
   }
-  im.stages[stages_pass] = st;
-  im.ops[stages_pass] = ops;
   for (int k = 0; k < 2; ++k) {
     PermPass &P = im.pass[k];
-    P.num_stages = k == stages_pass ? ns : 0;
+    P.num_stages = (int32_t)im.stages[k].size() / 2;
     const std::vector<int32_t> &map = (direction == 0) == (k == 0) ? col_node : col_coef;
     if (k == 0) {          // n-wide input -> workspace layout
       P.in_cols = n;

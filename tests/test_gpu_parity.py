@@ -209,3 +209,46 @@ def test_normalized_laplacian_parity(g, engine):
     """GFT of the symmetric normalized Laplacian D^{-1/2} L D^{-1/2} on every engine."""
     X = wl.gaussian(1500, g.n, wl.rng_for(9, g.n, 3))
     _check_graph(g, X, engine=engine, laplacian="normalized")
+
+
+def _c4_with_stage():
+    g = wl.cycle(4)
+    g.stages = [np.array([3, 2, 1, 0], dtype=np.int32)]
+    return g
+
+
+def _cycle_no_stage(n):
+    g = wl.cycle(n)
+    g.stages = []
+    return g
+
+
+def _k_regular_bipartite(m, weights):
+    edges, w = [], []
+    for r, wr in enumerate(weights):
+        for i in range(m):
+            edges.append((i, m + (i + r) % m))
+            w.append(wr)
+    return wl._graph(2 * m, edges, w, name=f"krbg{len(weights)}_")
+
+
+@pytest.mark.parametrize("engine", ["auto", "generic", "large"])
+@pytest.mark.parametrize("g", [_c4_with_stage(), _cycle_no_stage(12), _cycle_no_stage(30),
+                               _k_regular_bipartite(16, [0.3, 1.7, 0.9])],
+                         ids=lambda g: f"{g.name}{g.n}s{len(g.stages)}")
+def test_right_haar_parity(g, engine):
+    """Plans with right Haar units (forward: after the blocks; inverse: before them)."""
+    plan = G.Plan.from_graph(g, engine=engine)
+    assert plan.info()["num_right_leaves"] >= 1
+    X = wl.gaussian(2500, g.n, wl.rng_for(9, g.n, 4))
+    _check_graph(g, X, engine=engine)
+
+
+def test_right_haar_large_k_regular_bipartite():
+    """n = 600 3-regular weighted bipartite graph: blocks E, F of 300 on the large engine."""
+    g = _k_regular_bipartite(300, [0.4, 1.1, 0.8])
+    plan = G.Plan.from_graph(g)
+    assert plan.engine() == "large" and plan.info()["max_block"] == 300
+    X = wl.gaussian(700, g.n, wl.rng_for(9, 600))
+    _check_graph(g, X)
+    _check_graph(g, X, precision="split_bf16", tol=1e-5, basis_tol=5e-6)

@@ -212,3 +212,111 @@ def test_two_sparse_transposition_stage():
     lam, U = O.gft(O.laplacian_of(g))
     Ua, sv = O.align(U, plan.basis(), lam)
     assert sv > 1 - 1e-10
+
+
+# ------------------------------------------------------------------ right Haar units
+
+def _golden_c4():
+    rows, scale = [], 1.0
+    for line in open(os.path.join(ROOT, "tests", "golden", "c4_cycle.txt")):
+        line = line.split("#")[0].strip()
+        if not line or line.startswith("eigenvalues"):
+            continue
+        if line.startswith("scale"):
+            scale = float(line.split()[1])
+        else:
+            rows.append([float(v) for v in line.split()])
+    return scale * np.array(rows)
+
+
+def _assert_oracle_basis(plan, g, laplacian="combinatorial"):
+    L = O.laplacian_of(g) if laplacian == "combinatorial" else O.normalized_laplacian_of(g)
+    lam, U = O.gft(L)
+    np.testing.assert_allclose(plan.eigenvalues(), lam, atol=1e-10 * max(1.0, np.abs(lam).max()))
+    Uh = plan.basis()
+    np.testing.assert_allclose(Uh.T @ Uh, np.eye(g.n), atol=1e-12)
+    Ua, min_sv = O.align(U, Uh, lam)
+    assert min_sv > 1 - 1e-9
+    X = wl.gaussian(7, g.n, wl.rng_for(9, g.n, 2), dtype=np.float64)
+    np.testing.assert_allclose(plan.apply_host(X, 0), O.forward(X, Ua), atol=1e-10)
+    np.testing.assert_allclose(plan.apply_host(O.forward(X, Ua), 1), X, atol=1e-10)
+
+
+def test_c4_left_and_right_haar_reproduce_the_printed_gft():
+    """Sec. III: the 4-cycle GFT factors into a left and a right butterfly stage.  With the
+    reversal pairing, both leaves (L+ = [[1,-1],[-1,1]], L- = [[3,-1],[-1,3]]) have a
+    constant diagonal and one edge, so each becomes two 1 x 1 blocks and a right Haar unit;
+    the basis is the printed C4 matrix up to column signs."""
+    g = wl.cycle(4)
+    g.stages = [np.array([3, 2, 1, 0], dtype=np.int32)]
+    plan = G.Plan.from_graph(g)
+    st = plan.info()
+    assert (st["num_right_leaves"], st["num_right_units"], st["num_blocks"], st["max_block"]) == (2, 2, 4, 1)
+    assert (st["num_units"], st["mults"], st["adds"]) == (4, 4, 8)
+    Uc4 = _golden_c4()
+    np.testing.assert_allclose(np.abs(plan.basis().T @ Uc4), np.eye(4), atol=1e-14)
+    _assert_oracle_basis(plan, g)
+    dense = G.Plan.from_graph(g, right_haar=False).info()
+    assert (dense["num_right_leaves"], dense["num_blocks"], dense["mults"]) == (0, 2, 8)
+
+
+@pytest.mark.parametrize("n", [8, 12, 30])
+def test_even_cycle_is_two_regular_bipartite(n):
+    """Without left stages an even cycle is one 2-regular bipartite leaf: blocks n/2 + n/2
+    and n/2 right Haar units (Thm. right_haar), (n/2)^2 * 2 multiplications instead of n^2."""
+    g = wl.cycle(n)
+    g.stages = []
+    plan = G.Plan.from_graph(g)
+    st = plan.info()
+    assert (st["num_right_leaves"], st["num_blocks"], st["max_block"], st["mults"]) == (1, 2, n // 2, n * n // 2)
+    # eigenvalue c = 2 (singular value 0, cos(2 pi k / n) = 0) occurs twice exactly when 4 | n;
+    # those two columns pass through unpaired
+    assert st["num_right_units"] == n // 2 - (1 if n % 4 == 0 else 0)
+    _assert_oracle_basis(plan, g)
+
+
+def _k_regular_bipartite(m, weights, loop=0.0):
+    """Parts {0..m-1}, {m..2m-1}; node i joins m + (i + r) mod m with weight weights[r]:
+    every node has weighted degree sum(weights) (a weighted k-regular bipartite graph)."""
+    edges, w = [], []
+    for r, wr in enumerate(weights):
+        for i in range(m):
+            edges.append((i, m + (i + r) % m))
+            w.append(wr)
+    return wl._graph(2 * m, edges, w, loops=np.full(2 * m, loop) if loop else None)
+
+
+@pytest.mark.parametrize("m,weights,loop", [(5, [1.0, 1.0, 1.0], 0.0), (7, [0.3, 1.7, 0.9], 0.25),
+                                            (16, [1.0, 0.5], 0.0)])
+def test_weighted_k_regular_bipartite(m, weights, loop):
+    g = _k_regular_bipartite(m, weights, loop)
+    plan = G.Plan.from_graph(g)
+    st = plan.info()
+    assert (st["num_right_leaves"], st["num_blocks"], st["max_block"]) == (1, 2, m)
+    _assert_oracle_basis(plan, g)
+
+
+def test_normalized_laplacian_of_any_bipartite_graph():
+    """Normalized Laplacian of a bipartite graph with parts of 5 and 9 nodes: diagonal 1, so
+    the leaf takes right Haar units with p != n - p; the 4 extra part-2 columns are null
+    vectors of the cross block (eigenvalue 1) and pass through."""
+    rng = wl.rng_for(9, 3)
+    p, q = 5, 9
+    edges, w = [], []
+    for j in range(q):
+        for i in range(p):
+            if rng.random() < 0.45 or i == j % p:
+                edges.append((i, p + j))
+                w.append(rng.uniform(0.5, 1.5))
+    g = wl._graph(p + q, edges, w)
+    plan = G.Plan.from_graph(g, laplacian="normalized")
+    st = plan.info()
+    assert (st["num_right_leaves"], st["num_blocks"], st["max_block"], st["num_right_units"]) == (1, 2, q, p)
+    _assert_oracle_basis(plan, g, laplacian="normalized")
+    assert G.Plan.from_graph(g).info()["num_right_leaves"] == 0     # combinatorial: degrees differ
+
+
+def test_right_haar_leaves_benchmark_plans_alone():
+    """Leaves of the benchmark graphs have varying diagonals: no right Haar units there."""
+    for g in (wl.config1_graph(), wl.config2_graph(), wl.config3_graph(), wl.config5b_graph()):
+        assert G.Plan.from_graph(g).info()["num_right_leaves"] == 0
