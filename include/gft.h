@@ -186,6 +186,21 @@ typedef struct {
 gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing,
                     const gft_options *opts, gft_plan_t *out);
 
+/* Search node pairings for the left Haar stages (Sec. V-F, pruning based on the degree
+ * list), stage by stage: stage s is an involution that acts inside each sub-graph produced
+ * by the stages before it (as gft_plan splits them) and keeps each such sub-graph
+ * phi-symmetric (Definition 2), chosen to have the most node pairs (fewest multiplications,
+ * p^2 + (n - p)^2).  A node is only paired with nodes of equal diagonal and equal sorted
+ * list of edge weights; a depth-first search, most constrained nodes first, checks
+ * l_ij = l_phi(i)phi(j) as it assigns and stops at a perfect pairing or after max_steps
+ * steps per sub-graph (<= 0: 200000), keeping the best found.  The search stops when no
+ * sub-graph has a non-trivial symmetry or max_stages is reached.
+ * graph: host, as for gft_plan; opts: its laplacian and sym_tol are used (NULL = defaults).
+ * phi: host array of max_stages * n int32 written with the stages found (phi[s*n + i]),
+ * the gft_pairing input of gft_plan.  *num_stages receives their number (0: none). */
+gft_status gft_find_pairing(const gft_graph *graph, const gft_options *opts, int32_t max_stages,
+                            int64_t max_steps, int32_t *phi, int32_t *num_stages);
+
 /* Build one plan covering num_graphs graphs (arrays of num_graphs graphs and pairings)
  * for gft_forward_batch / gft_inverse_batch.  Each graph is planned as by gft_plan. */
 gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,

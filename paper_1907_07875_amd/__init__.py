@@ -34,6 +34,7 @@ STATUS = {
 EXPORTS = [
     "gft_plan", "gft_plan_batch", "gft_forward", "gft_inverse", "gft_forward_batch",
     "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_tiles", "gft_plan_info", "gft_plan_num_graphs",
+    "gft_find_pairing",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version",
 ]
@@ -108,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_plan_prepare": ([P], i32),
         "gft_plan_engine": ([P, ctypes.POINTER(i32)], i32),
         "gft_plan_tiles": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "gft_find_pairing": ([ctypes.POINTER(_Graph), ctypes.POINTER(_Options), i32, i64, P,
+                              ctypes.POINTER(i32)], i32),
         "gft_plan_info": ([P, i32, ctypes.POINTER(PlanStats)], i32),
         "gft_plan_num_graphs": ([P, ctypes.POINTER(i32)], i32),
         "gft_plan_size": ([P, i32, ctypes.POINTER(i32)], i32),
@@ -291,6 +294,21 @@ def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
+
+
+def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_steps=0,
+                     laplacian="combinatorial", sym_tol=0.0):
+    """Search left Haar pairings stage by stage (C: ``gft_find_pairing``); returns a list of
+    int32 arrays, one involution per stage, usable as ``stages`` of :func:`gft_plan`."""
+    lib = load_library()
+    keep = []
+    g = _graph_struct(n, src, dst, weight, self_loop, keep)
+    o = _options(laplacian=laplacian, sym_tol=sym_tol)
+    phi = np.empty(max(1, max_stages) * int(n), dtype=np.int32)
+    k = ctypes.c_int32()
+    _check(lib.gft_find_pairing(ctypes.byref(g), ctypes.byref(o), int(max_stages), int(max_steps),
+                                phi.ctypes.data, ctypes.byref(k)))
+    return [phi[s * n:(s + 1) * n].copy() for s in range(k.value)]
 
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,

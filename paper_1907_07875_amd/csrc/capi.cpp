@@ -481,6 +481,28 @@ gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing, const gf
   return ok();
 }
 
+gft_status gft_find_pairing(const gft_graph *graph, const gft_options *opts, int32_t max_stages,
+                            int64_t max_steps, int32_t *phi, int32_t *num_stages) {
+  if (!graph || !phi || !num_stages)
+    return set_error(GFT_ERR_INVALID_ARG, "graph, phi and num_stages must be non-NULL");
+  if (max_stages < 0) return set_error(GFT_ERR_INVALID_ARG, "max_stages must be >= 0");
+  *num_stages = 0;
+  const gft_options o = default_options(opts);
+  gft_status st = check_options(o);
+  if (st != GFT_OK) return st;
+  try {
+    std::vector<int32_t> found;
+    const int k = find_pairing(*graph, o, max_stages, max_steps > 0 ? max_steps : 200000, found);
+    std::copy(found.begin(), found.end(), phi);
+    *num_stages = k;
+  } catch (const PlanError &err) {
+    return set_error(err.status, err.message);
+  } catch (const std::bad_alloc &) {
+    return set_error(GFT_ERR_OOM, "host allocation failed while searching");
+  }
+  return ok();
+}
+
 gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs, const gft_pairing *pairings,
                           const gft_options *opts, gft_plan_t *out) {
   if (!out) return set_error(GFT_ERR_INVALID_ARG, "out is NULL");

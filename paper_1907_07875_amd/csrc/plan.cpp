@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <numeric>
 #include <set>
 #include <sstream>
@@ -137,6 +138,85 @@ void split(const Sub &H, const std::vector<int32_t> &lp, Sub &plus, Sub &minus,
       minus.L[(size_t)q * mm + p] = v;
     }
   }
+}
+
+// Involution search on one sub-graph (Sec. V-F, pruning based on the degree list): a node
+// can only be paired with a node of equal invariant (its diagonal entry and the sorted list
+// of its off-diagonal entries, the weighted-degree-list generalisation), and a depth-first
+// search assigns nodes, most constrained first, either a partner or a fixed point, keeping
+// l_ab = l_phi(a)phi(b) against every node already assigned (Definition 2).  It maximises
+// the number of pairs (minimising p^2 + (n - p)^2, Sec. V-G), stops at a perfect pairing, and
+// gives up after `budget` search steps with the best involution found so far.
+std::vector<int32_t> search_involution(const Sub &H, double tol, int64_t budget) {
+  const int m = (int)H.nodes.size();
+  auto L = [&](int a, int b) { return H.L[(size_t)a * m + b]; };
+  std::vector<std::vector<double>> inv(m);
+  for (int a = 0; a < m; ++a) {
+    for (int b = 0; b < m; ++b)
+      if (b != a && std::fabs(L(a, b)) > tol) inv[a].push_back(L(a, b));
+    std::sort(inv[a].begin(), inv[a].end());
+    inv[a].insert(inv[a].begin(), L(a, a));
+  }
+  auto same = [&](int a, int b) {
+    if (inv[a].size() != inv[b].size()) return false;
+    for (size_t i = 0; i < inv[a].size(); ++i)
+      if (std::fabs(inv[a][i] - inv[b][i]) > tol) return false;
+    return true;
+  };
+  std::vector<std::vector<int>> cand(m);
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      if (b != a && same(a, b)) cand[a].push_back(b);
+  std::vector<int> order(m);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return cand[a].size() < cand[b].size(); });
+  std::vector<int32_t> phi(m, -1), best(m);
+  std::iota(best.begin(), best.end(), 0);
+  std::vector<int> assigned;
+  int best_pairs = 0;
+  int64_t steps = 0;
+  auto consistent = [&](int a, int b) {
+    for (int k : assigned) {
+      if (std::fabs(L(a, k) - L(b, phi[k])) > tol) return false;
+      if (b != a && std::fabs(L(b, k) - L(a, phi[k])) > tol) return false;
+    }
+    return true;
+  };
+  std::function<void(int, int, int)> dfs = [&](int pos, int pairs, int open) {
+    if (++steps > budget || best_pairs * 2 >= m - 1) return;
+    while (pos < m && phi[order[pos]] >= 0) ++pos;
+    if (pos == m) {
+      if (pairs > best_pairs) {
+        best_pairs = pairs;
+        best = phi;
+      }
+      return;
+    }
+    if (pairs + open / 2 <= best_pairs) return;   // cannot beat the best found
+    const int a = order[pos];
+    for (int b : cand[a]) {
+      if (phi[b] >= 0 || !consistent(a, b)) continue;
+      phi[a] = b;
+      phi[b] = a;
+      assigned.push_back(a);
+      assigned.push_back(b);
+      dfs(pos + 1, pairs + 1, open - 2);
+      assigned.pop_back();
+      assigned.pop_back();
+      phi[a] = phi[b] = -1;
+      if (steps > budget || best_pairs * 2 >= m - 1) return;
+    }
+    if (consistent(a, a)) {
+      phi[a] = a;
+      assigned.push_back(a);
+      dfs(pos + 1, pairs, open - 1);
+      assigned.pop_back();
+      phi[a] = -1;
+    }
+  };
+  dfs(0, 0, m);
+  return best;
 }
 
 // Connected components of a sub-graph (couplings with |l_ab| > tol), each ascending.
@@ -536,6 +616,60 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
   st.max_residual = max_res;
   st.max_orth_error = max_orth;
   return plan;
+}
+
+int find_pairing(const gft_graph &g, const gft_options &opts, int max_stages, int64_t budget,
+                 std::vector<int32_t> &phi_out) {
+  validate_graph(g);
+  const int32_t n = g.n;
+  const double sym_tol = opts.sym_tol > 0 ? opts.sym_tol : 1e-12;
+  std::vector<Sub> subs(1);
+  subs[0].nodes.resize(n);
+  std::iota(subs[0].nodes.begin(), subs[0].nodes.end(), 0);
+  subs[0].L = dense_laplacian(g);
+  if (opts.laplacian == GFT_LAPLACIAN_NORMALIZED) {
+    std::vector<double> d(n, 0.0);
+    for (int32_t e = 0; e < g.num_edges; ++e) {
+      d[g.src[e]] += g.weight[e];
+      d[g.dst[e]] += g.weight[e];
+    }
+    for (int32_t i = 0; i < n; ++i)
+      if (!(d[i] > 0.0)) fail(GFT_ERR_GRAPH, "the normalized Laplacian needs a positive degree at every node");
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t j = 0; j < n; ++j) subs[0].L[(size_t)i * n + j] /= std::sqrt(d[i] * d[j]);
+  }
+  const double scale_L = std::max(max_abs(subs[0].L), 1e-300);
+  phi_out.clear();
+  int stages = 0;
+  for (; stages < max_stages; ++stages) {
+    std::vector<int32_t> phi(n);
+    std::iota(phi.begin(), phi.end(), 0);
+    std::vector<Sub> next;
+    bool any = false;
+    HostStage unused;
+    for (Sub &H : subs) {
+      const double tol = sym_tol * std::max(max_abs(H.L), 1e-300 * scale_L);
+      const std::vector<int32_t> lp = search_involution(H, tol, budget);
+      bool moves = false;
+      for (size_t a = 0; a < lp.size(); ++a) {
+        phi[H.nodes[a]] = H.nodes[lp[a]];
+        moves |= lp[a] != (int32_t)a;
+      }
+      if (!moves) {
+        next.push_back(std::move(H));
+        continue;
+      }
+      any = true;
+      Sub plus, minus;
+      split(H, lp, plus, minus, unused);
+      next.push_back(std::move(plus));
+      if (!minus.nodes.empty()) next.push_back(std::move(minus));
+    }
+    if (!any) break;
+    phi_out.insert(phi_out.end(), phi.begin(), phi.end());
+    subs = std::move(next);
+  }
+  return stages;
 }
 
 void apply_host(const GraphPlan &p, int direction, const double *x, double *y, int64_t S) {

@@ -54,6 +54,12 @@ struct GraphPlan {
   gft_plan_stats stats{};
 };
 
+// Search up to max_stages pairings stage by stage (each stage searched inside every current
+// sub-graph, as the plan splits them); returns the number found, phi_out = stages * n.
+// `budget` caps the search steps per sub-graph.  Throws PlanError on a bad graph.
+int find_pairing(const gft_graph &g, const gft_options &opts, int max_stages, int64_t budget,
+                 std::vector<int32_t> &phi_out);
+
 // Build the plan of one graph.  Throws PlanError.
 GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
                            const gft_options &opts);

@@ -252,3 +252,12 @@ def test_right_haar_large_k_regular_bipartite():
     X = wl.gaussian(700, g.n, wl.rng_for(9, 600))
     _check_graph(g, X)
     _check_graph(g, X, precision="split_bf16", tol=1e-5, basis_tol=5e-6)
+
+
+@pytest.mark.parametrize("g", [wl.grid(8, 8), wl.path(16), wl.config3_graph()], ids=lambda g: f"{g.name}{g.n}")
+def test_searched_pairings_parity(g):
+    """Stages from gft_find_pairing (6 for the 8x8 grid) run on the GPU like given ones."""
+    st = G.gft_find_pairing(g.n, g.src, g.dst, g.weight, g.self_loop, max_stages=8)
+    h = wl._graph(g.n, np.stack([g.src, g.dst], 1), g.weight, loops=g.self_loop, stages=st, name=g.name)
+    X = wl.gaussian(2000, g.n, wl.rng_for(9, g.n, 5))
+    _check_graph(h, X)

@@ -320,3 +320,77 @@ def test_right_haar_leaves_benchmark_plans_alone():
     """Leaves of the benchmark graphs have varying diagonals: no right Haar units there."""
     for g in (wl.config1_graph(), wl.config2_graph(), wl.config3_graph(), wl.config5b_graph()):
         assert G.Plan.from_graph(g).info()["num_right_leaves"] == 0
+
+
+# ------------------------------------------------------------------ pairing search
+
+def _sym_graph(phi, rng, p=0.6):
+    """Random phi-symmetric weighted graph with self-loops (Definition 2)."""
+    n = len(phi)
+    W = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if W[i, j] == 0 and rng.random() < p:
+                w = rng.uniform(0.1, 2.0)
+                for a, b in ((i, j), (phi[i], phi[j])):
+                    if a != b:
+                        W[a, b] = W[b, a] = w
+    s = rng.uniform(0.0, 1.0, n)
+    return W, 0.5 * (s + s[phi])
+
+
+def _graph_from_weights(W, s):
+    n = len(W)
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if W[i, j] != 0]
+    return wl._graph(n, edges, [W[i, j] for i, j in edges], loops=s)
+
+
+def _find(g, **kw):
+    return G.gft_find_pairing(g.n, g.src, g.dst, g.weight, g.self_loop, **kw)
+
+
+def test_find_pairing_matches_brute_force_optimum():
+    """Sec. V-F: the search returns a valid involution (Definition 2, checked by the oracle)
+    with as many pairs as the best of all T(n) involutions, found by brute force."""
+    rng = np.random.default_rng(21)
+    for n in (3, 4, 5, 6, 7, 8):
+        invs = O.involutions(n)
+        for trial in range(5):
+            phi0 = invs[rng.integers(len(invs))]
+            W, s = _sym_graph(phi0, rng, p=0.6)
+            g = _graph_from_weights(W, s)
+            best = max(O.p_phi(phi) for phi in invs if O.is_phi_symmetric(W, s, phi, tol=1e-12))
+            st = _find(g, max_stages=1)
+            assert (O.p_phi(st[0]) if st else 0) == best, (n, phi0)
+            if st:
+                assert O.is_phi_symmetric(W, s, st[0], tol=1e-12)
+
+
+@pytest.mark.parametrize("g", [wl.path(16), wl.cycle(12), wl.grid(8, 8), wl.config3_graph(),
+                               wl.weighted_symmetric_path(24, wl.rng_for(9, 24))],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_found_stages_plan_an_exact_gft(g):
+    """Stages found stage by stage inside the current sub-graphs: gft_plan accepts them (it
+    checks Definition 2 on every sub-graph), the plan is an oracle eigenbasis, and it needs
+    no more multiplications than the dense GFT."""
+    st = _find(g, max_stages=8)
+    assert len(st) >= 1
+    assert O.p_phi(st[0]) == {"path": 8, "cycle": 6, "grid": 32, "skeleton25": 10, "wpath": 12}[g.name]
+    plan = G.gft_plan(g.n, g.src, g.dst, g.weight, g.self_loop, stages=st)
+    assert plan.info()["mults"] <= g.n * g.n
+    _assert_oracle_basis(plan, g)
+
+
+def test_find_pairing_on_paths_is_the_reversal_then_recursion():
+    """A path's only non-trivial symmetry is the reversal; G+ is again a path with both end
+    diagonals 1, so the next stage reverses it, and so on (the recursion of Sec. V)."""
+    st = _find(wl.path(16), max_stages=8)
+    np.testing.assert_array_equal(st[0], np.arange(15, -1, -1))
+    assert [O.p_phi(p) for p in st] == [8, 4, 2, 1]
+
+
+def test_find_pairing_no_symmetry():
+    g = wl._graph(5, [(0, 1), (1, 2), (2, 3), (3, 4), (0, 2)], [1.0, 2.0, 3.0, 4.0, 5.0])
+    assert _find(g) == []
+    st = _find(wl.path(6), laplacian="normalized", max_stages=1)
+    np.testing.assert_array_equal(st[0], np.arange(5, -1, -1))
