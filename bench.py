@@ -41,7 +41,7 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 # (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for the kernel source it was measured
 # on: reported as null once that file changes.
 PROFILED_TRAFFIC = {"source": "paper_1907_07875_amd/csrc/gft_butterfly.hip",
-                    "sha256_16": "80803b11fea3051c",
+                    "sha256_16": "cc01dbb6cc13f3c8",
                     "bytes_per_launch": 2.0 * 131134 * 1024 + 262144 * 1024}
 
 
