@@ -106,9 +106,9 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
       const int e = EI * (lane + 64 * k);
       const int ec = e < lim ? e : lim - EI;
       if constexpr (IN16)
-        pre[k] = *reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * N + ec);
+        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * N + ec));
       else
-        pre[k] = *reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * N + ec);
+        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * N + ec));
     }
   };
   if (wt < ntiles) issue(wt);
@@ -222,11 +222,11 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
     };
     if (lim == 16 * N) {   // full tile (wave-uniform branch)
 #pragma unroll
-      for (int k = 0; k < VO; ++k) *dst_at(EO * (lane + 64 * k)) = o[k];
+      for (int k = 0; k < VO; ++k) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
     } else {
 #pragma unroll
       for (int k = 0; k < VO; ++k)
-        if (EO * (lane + 64 * k) < lim) *dst_at(EO * (lane + 64 * k)) = o[k];
+        if (EO * (lane + 64 * k) < lim) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
     }
     wave_lds_sync();
   }

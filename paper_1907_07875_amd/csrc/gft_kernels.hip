@@ -111,7 +111,7 @@ __device__ __forceinline__ void issue_tile(const void *g, int count, const float
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) {
     const int v = threadIdx.x + k * kThreads;
-    pre[k] = g4[v < last ? v : last];
+    pre[k] = __builtin_nontemporal_load(g4 + (v < last ? v : last));   // streamed once
   }
 }
 
@@ -159,7 +159,7 @@ __device__ __forceinline__ void commit_tile(const void *g, int count, int rows, 
   }
   const V *g4 = static_cast<const V *>(g);
   for (int v = tid + kPrefetch * kThreads; v < nvec; v += kThreads)
-    put4(lds, 4u * (uint32_t)v, widen(g4[v]), n, stride, magic_n);
+    put4(lds, 4u * (uint32_t)v, widen(__builtin_nontemporal_load(g4 + v)), n, stride, magic_n);
   for (int e = 4 * nvec + tid; e < count; e += kThreads) {
     const uint32_t r = fdiv((uint32_t)e, magic_n);
     lds[r * stride + ((uint32_t)e - r * (uint32_t)n)] = load_one<B16>(g, e);
@@ -199,10 +199,11 @@ __device__ __forceinline__ void store_tile(const float *lds, int count, int n, i
       }
     }
     if constexpr (B16)
-      static_cast<u32x2v *>(g)[v] = u32x2v{bf16_bits(q[0]) | (bf16_bits(q[1]) << 16),
-                                           bf16_bits(q[2]) | (bf16_bits(q[3]) << 16)};
+      __builtin_nontemporal_store(u32x2v{bf16_bits(q[0]) | (bf16_bits(q[1]) << 16),
+                                         bf16_bits(q[2]) | (bf16_bits(q[3]) << 16)},
+                                  static_cast<u32x2v *>(g) + v);
     else
-      static_cast<float4 *>(g)[v] = make_float4(q[0], q[1], q[2], q[3]);
+      __builtin_nontemporal_store(floatx4{q[0], q[1], q[2], q[3]}, static_cast<floatx4 *>(g) + v);
   }
   for (int e = 4 * nvec + tid; e < count; e += kThreads) {
     const uint32_t r = fdiv((uint32_t)e, magic_n);

@@ -71,11 +71,11 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
       for (; e + 3 * kThreads < tot; e += 4 * kThreads) {
         floatx4 v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = s4[e + q * kThreads];
+        for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(s4 + e + q * kThreads);
 #pragma unroll
         for (int q = 0; q < 4; ++q) t4[e + q * kThreads] = v[q];
       }
-      for (; e < tot; e += kThreads) t4[e] = s4[e];
+      for (; e < tot; e += kThreads) t4[e] = __builtin_nontemporal_load(s4 + e);
     } else {
       const int tot = nr * ic;
       for (int e = tid; e < tot; e += kThreads) tile[e] = src[e];
@@ -117,10 +117,11 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
             v[q] = g[q] >= 0 ? x : 0.0f;
           }
           if constexpr (OUT16)
-            *reinterpret_cast<u32x2 *>(dst16 + (int64_t)r * oc + c) =
-                u32x2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)};
+            __builtin_nontemporal_store(
+                u32x2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)},
+                reinterpret_cast<u32x2 *>(dst16 + (int64_t)r * oc + c));
           else
-            *reinterpret_cast<floatx4 *>(dst + (int64_t)r * oc + c) = v;
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(dst + (int64_t)r * oc + c));
         }
       }
     } else {
