@@ -41,8 +41,8 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 # (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for the kernel source it was measured
 # on: reported as null once that file changes.
 PROFILED_TRAFFIC = {"source": "paper_1907_07875_amd/csrc/gft_butterfly.hip",
-                    "sha256_16": "cc01dbb6cc13f3c8",
-                    "bytes_per_launch": 2.0 * 131134 * 1024 + 262144 * 1024}
+                    "sha256_16": "ad60527b97c1d5a2",
+                    "bytes_per_launch": 2.0 * 131160.84 * 1024 + 262145.75 * 1024}
 
 
 def parse():
