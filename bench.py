@@ -230,11 +230,19 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
             "kernel": kname + " (forward)", "engine": eng, "signals_per_tile": list(tiles),
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms}
     if flops_per_signal is not None:
+        # the binding roofline: MFMA when the leaf products' arithmetic intensity (flop per
+        # algorithmic byte) is above the ridge point of their precision, else HBM
         tflops = flops_per_signal * S / (fwd_ms * 1e-3) / 1e12
         peak = MFMA_PEAK_TFLOPS[precision]
-        roof.update({"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": tflops / peak, "algorithmic_flops_per_launch": flops_per_signal * S,
-                     "hbm_GB_per_s": achieved, "hbm_frac": achieved / HBM_PEAK_GBS})
+        intensity = flops_per_signal / (bytes_per_launch / S)
+        ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+        roof.update({"intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                     "algorithmic_flops_per_launch": flops_per_signal * S,
+                     "mfma_TFLOP_per_s": tflops, "mfma_peak": peak, "mfma_frac": tflops / peak})
+        if intensity >= ridge:
+            roof.update({"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                         "frac": tflops / peak, "hbm_GB_per_s": achieved,
+                         "hbm_frac": achieved / HBM_PEAK_GBS})
     result = {
         "metric": METRIC,
         "value": 2.0 * S * n / (ms_step * 1e-3), "unit": "coeffs/s", "n_gpus": 1,

@@ -140,8 +140,10 @@ typedef enum {
   GFT_ENGINE_LARGE = 3        /* large-signal engine: Haar stages and permutations in    */
                               /* streaming passes, leaf blocks as MFMA GEMM tiles over a */
                               /* stream-ordered workspace (hipMallocAsync, freed in      */
-                              /* stream order) of 2*S*w floats, w = n plus each leaf     */
-                              /* block padded to a multiple of 8; FP16 is unsupported    */
+                              /* stream order) of S*w floats (2*S*w when the last pass   */
+                              /* has Haar stages or there are more than 8 leaf blocks),  */
+                              /* w = n plus each leaf block padded to                    */
+                              /* a multiple of 8; FP16 is unsupported                    */
 } gft_engine;
 
 typedef struct {

@@ -101,6 +101,7 @@ gft_options default_options(const gft_options *o) {
 }
 
 constexpr int kBatchRounds = 4;   // batch grid = rounds x resident workgroups
+constexpr size_t kFuseMaxBlocks = 8;   // large engine: fused output permutation up to here
 
 gft_status check_options(const gft_options &o) {
   if (o.precision < GFT_FP32 || o.precision > GFT_SPLIT_BF16)
@@ -267,7 +268,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       uoff[d][3] = blob.add(ub[d].flips.data(), ub[d].flips.size() * 4);
     }
   LargeImage lgi[2];
-  size_t loff[2][7] = {};
+  size_t loff[2][8] = {};
   if (use_large)
     for (int d = 0; d < 2; ++d) {
       if (!build_large(plan->graphs[0], d, lgi[d]))
@@ -279,6 +280,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
         loff[d][4 + k] = blob.add(lgi[d].ops[k].data(), lgi[d].ops[k].size() * 4);
       }
       loff[d][6] = blob.add(lgi[d].blocks.data(), lgi[d].blocks.size() * sizeof(LBlock));
+      loff[d][7] = blob.add(lgi[d].omap.data(), lgi[d].omap.size() * 4);
       lgi[d].block_sizes.shrink_to_fit();
       // matrices last (largest)
     }
@@ -336,6 +338,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
         P.ops = reinterpret_cast<const uint32_t *>(base + loff[d][4 + k]);
       }
       L.dev_blocks = reinterpret_cast<const LBlock *>(base + loff[d][6]);
+      L.dev_omap = reinterpret_cast<const int32_t *>(base + loff[d][7]);
       L.dev_mats = mats16 ? nullptr : reinterpret_cast<const float *>(base + lmat[d]);
       L.dev_mats16 = mats16 ? reinterpret_cast<const uint16_t *>(base + lmat[d]) : nullptr;
       L.mats.clear();
@@ -418,19 +421,26 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   if (img->large) {
     const LargeImage &L = img->lg[dir];
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t ws_bytes = 2 * (size_t)S * (size_t)L.ldw * 4;
+    // With no Haar stage in pass 3 and few leaf blocks the GEMM writes the final positions
+    // itself (no W2, no pass 3).  With many blocks whose outputs interleave in the output
+    // order, each output line collects partial writes from many workgroups and the m-panel
+    // tile order spoils the reuse of the block matrices in L2: measured slower on the 64x64
+    // grid (49 blocks), faster on the 1024-node path (2 blocks).
+    const bool fused = L.pass[1].num_stages == 0 && L.blocks.size() <= kFuseMaxBlocks;
+    const size_t ws_bytes = (fused ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
     void *ws = nullptr;
     e = hipMallocAsync(&ws, ws_bytes, st);
     if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
-    float *W1 = static_cast<float *>(ws), *W2 = W1 + (size_t)S * L.ldw;
+    float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
     const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
     e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st);
     if (e == hipSuccess)
       e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
                             (int)L.blocks.size(), ws16 ? (const void *)L.dev_mats16 : (const void *)L.dev_mats,
-                            W1, W2, S, L.ldw,
-                            block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S), st);
-    if (e == hipSuccess)
+                            W1, fused ? static_cast<float *>(out) : W2, S, L.ldw,
+                            block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S),
+                            fused ? L.dev_omap : nullptr, (int)n, st);
+    if (e == hipSuccess && !fused)
       e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st);
     const hipError_t ef = hipFreeAsync(ws, st);
     if (e == hipSuccess) e = ef;

@@ -115,6 +115,7 @@ struct LBlock {
   int32_t col;      // column offset in the workspace (multiple of 8)
   int32_t mat;      // offset of M_b^T in the matrix array (elements, multiple of 8)
   int32_t ld;       // row stride of M_b^T (multiple of 8, >= b)
+  int32_t omap;     // offset of the block's output positions in the output map (forward)
 };
 
 }  // namespace gft

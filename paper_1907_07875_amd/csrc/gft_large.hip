@@ -173,7 +173,7 @@ template <int PREC, int BK>
 __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restrict__ blocks,
                                                            int nblocks, const void *mats_raw,
                                                            const void *A_raw, float *C, int64_t S,
-                                                           int ld) {
+                                                           int ld, const int32_t *omap, int ldy) {
   using Cfg = GemmCfg<PREC, BK>;
   constexpr int kRowBytes = Cfg::row_bytes;
   constexpr int KS = PREC == 0 ? 4 : 8;                     // k per lane per fragment load
@@ -186,16 +186,34 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
   if (id < (int64_t)(gridDim.x & ~63u)) id = (id & ~63ll) + ((id & 7) << 3) + ((id >> 3) & 7);
   const int64_t mtiles = (S + kBM - 1) / kBM;
   int b = 0;
-  for (; b < nblocks; ++b) {
-    const int64_t nt = (blocks[b].size + kBN - 1) / kBN;
-    if (id < mtiles * nt) break;
-    id -= mtiles * nt;
+  int64_t row0;
+  int col0;
+  if (omap) {
+    // output scattered to its final positions: the tiles of one m panel (every block, every
+    // n tile) are consecutive, so the partial lines of its output rows meet in one L2
+    int64_t per_m = 0;
+    for (int q = 0; q < nblocks; ++q) per_m += (blocks[q].size + kBN - 1) / kBN;
+    row0 = (id / per_m) * kBM;
+    int64_t t = id % per_m;
+    for (; b < nblocks; ++b) {
+      const int64_t nt = (blocks[b].size + kBN - 1) / kBN;
+      if (t < nt) break;
+      t -= nt;
+    }
+    if (b >= nblocks || row0 >= S) return;
+    col0 = (int)t * kBN;
+  } else {
+    for (; b < nblocks; ++b) {
+      const int64_t nt = (blocks[b].size + kBN - 1) / kBN;
+      if (id < mtiles * nt) break;
+      id -= mtiles * nt;
+    }
+    if (b >= nblocks) return;
+    const int ntb = (blocks[b].size + kBN - 1) / kBN;
+    row0 = (id / ntb) * kBM;
+    col0 = (int)(id % ntb) * kBN;
   }
-  if (b >= nblocks) return;
   const LBlock blk = blocks[b];
-  const int ntb = (blk.size + kBN - 1) / kBN;
-  const int64_t row0 = (id / ntb) * kBM;
-  const int col0 = (int)(id % ntb) * kBN;
   const int K = blk.size;
 
   // global -> registers.  FP32 storage (PREC 0, 3): NLD float4 of A (row m, k quad kq) and
@@ -332,19 +350,23 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
     store((kt + 1) & 1);     // the other buffer: last read before the previous barrier
     __syncthreads();
   }
-  // epilogue: lane (g, r) holds rows 4g + v, column r of each 16x16 tile
+  // epilogue: lane (g, r) holds rows 4g + v, column r of each 16x16 tile; column c goes to
+  // the workspace (C, row stride ld) or, with omap, to output position omap[blk.omap + c]
+  // of the final array (C, row stride ldy)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j) {
+    const int c = col0 + wn * 64 + 16 * j + r;
+    if (c >= K) continue;
+    const int64_t dcol = omap ? (int64_t)omap[blk.omap + c] : (int64_t)blk.col + c;
+    const int64_t dld = omap ? ldy : ld;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = col0 + wn * 64 + 16 * j + r;
-      if (c >= K) continue;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + wm * 64 + 16 * i + 4 * g + v;
-        if (row < S) C[row * ld + blk.col + c] = acc[i][j][v];
+        if (row < S) C[row * dld + dcol] = acc[i][j][v];
       }
-    }
+  }
 }
 
 // ---------------------------------------------------------------------------- launch
@@ -386,7 +408,7 @@ int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S) {
 template <int PREC, int BK>
 static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const void *mats,
                                    const void *A, float *C, int64_t S, int ld, int64_t grid,
-                                   hipStream_t stream) {
+                                   const int32_t *omap, int ldy, hipStream_t stream) {
   const int lds = GemmCfg<PREC, BK>::lds_bytes;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_block_gemm<PREC, BK>,
@@ -394,19 +416,19 @@ static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const void
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((gft_block_gemm<PREC, BK>), dim3((unsigned)grid), dim3(kThreads), lds, stream,
-                     blocks, nblocks, mats, A, C, S, ld);
+                     blocks, nblocks, mats, A, C, S, ld, omap, ldy);
   return hipGetLastError();
 }
 
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
                              const void *A, float *C, int64_t S, int ld, int64_t grid,
-                             hipStream_t stream) {
+                             const int32_t *omap, int ldy, hipStream_t stream) {
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   switch (prec) {
-    case 0: return launch_gemm_prec<0, 16>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
-    case 1: return launch_gemm_prec<1, 32>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
-    case 3: return launch_gemm_prec<3, 32>(blocks, nblocks, mats, A, C, S, ld, grid, stream);
+    case 0: return launch_gemm_prec<0, 16>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+    case 1: return launch_gemm_prec<1, 32>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+    case 3: return launch_gemm_prec<3, 32>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
     default: return hipErrorInvalidValue;
   }
 }

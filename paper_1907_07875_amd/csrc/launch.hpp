@@ -29,9 +29,11 @@ hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, 
                                  int64_t S, int num_cus, hipStream_t stream);
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
 // prec: 0 FP32, 1 BF16 (A and matrices stored in BF16), 3 split BF16 (FP32 storage)
+// omap non-null: column c of block b is written to column omap[b.omap + c] of C (row
+// stride ldy) instead of the workspace (the output permutation fused into the epilogue).
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
                              const void *A, float *C, int64_t S, int ld, int64_t grid,
-                             hipStream_t stream);
+                             const int32_t *omap, int ldy, hipStream_t stream);
 
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(int S, int M);

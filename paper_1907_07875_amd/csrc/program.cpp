@@ -414,7 +414,10 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   size_t mat = 0;
   for (const HostBlock &B : p.blocks) {
     const int ld = (B.size + 7) & ~7;
-    im.blocks.push_back({B.size, col, (int32_t)mat, ld});
+    im.blocks.push_back({B.size, col, (int32_t)mat, ld, (int32_t)im.omap.size()});
+    // final position of each block output: coefficients (forward) or nodes (inverse)
+    const std::vector<int32_t> &dst = direction == 0 ? B.out_pos : B.nodes;
+    im.omap.insert(im.omap.end(), dst.begin(), dst.end());
     im.block_sizes.push_back(B.size);
     for (int k = 0; k < ld; ++k) {
       col_node.push_back(k < B.size ? B.nodes[k] : -1);

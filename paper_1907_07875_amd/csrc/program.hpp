@@ -58,9 +58,11 @@ struct LargeImage {
   std::vector<int32_t> block_sizes;
   std::vector<float> mats;
   std::vector<uint16_t> mats16;         // the same matrices rounded to BF16 (RNE)
+  std::vector<int32_t> omap;            // final position of every block output
   const LBlock *dev_blocks = nullptr;   // device copies, set at upload
   const float *dev_mats = nullptr;
   const uint16_t *dev_mats16 = nullptr;
+  const int32_t *dev_omap = nullptr;
 };
 
 // Largest tile row (workspace columns) of the large-signal engine: op indices are 16-bit.
