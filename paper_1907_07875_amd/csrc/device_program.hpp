@@ -61,8 +61,9 @@ struct DevProgram {
   const uint32_t *frag;
 };
 
-// Register-butterfly program (uniform hypercube plans): S stages, 2^S leaf blocks of M
-// nodes, n = M * 2^S; orbit o (o < M) holds node node(o, b) of every block b at block
+// Register-butterfly program (uniform hypercube plans, and one-stage plans with n odd
+// padded to 2M slots, where gcol / scol entries of -1 read a zero / write nowhere): S stages,
+// 2^S leaf blocks of M nodes, n = M * 2^S; orbit o (o < M) holds node node(o, b) of every block b at block
 // position o, and stage t pairs slots b and b ^ 2^(S-1-t).  Lane l of a wave works on
 // signal l % 16 of a 16-signal tile and on lane group g = l / 16.
 //   gcol[g * Q + q] (Q = n/4): LDS column the lane gathers into data register q;

@@ -56,31 +56,41 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // IN16 / OUT16: the tile is read / written as BF16 (16-byte accesses of 8 values) instead
 // of FP32 (16-byte accesses of 4 values); everything between runs in FP32.
-template <int S, int M, int DIR, bool IN16, bool OUT16>
+// GEN: a one-stage program with n = P.n < N signal values (odd, >= 16), padded slots: the
+// LDS tile is then the 16 signals' own contiguous layout (row stride n), a gather column
+// of -1 reads a zero word and a scatter column of -1 writes a scratch word.
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN>
 __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, const void *in,
                                                                  void *out, int64_t nsig) {
   constexpr int NB = 1 << S;      // leaf blocks = slots per orbit
   constexpr int KC = M / 4;       // K chunks of a block
   constexpr int NT = M / 16;      // 16-row tiles of a block
-  constexpr int N = M * NB;       // signal length
+  constexpr int N = M * NB;       // slots per signal (= n unless GEN)
   constexpr int Q = N / 4;        // values per lane
   constexpr int STR = N + 4;      // LDS row stride: 16-byte rows, offset banks
   constexpr int NF = NB * NT * KC;
-  __shared__ float lds_all[kWaves * 16 * STR];
+  __shared__ __attribute__((aligned(16))) float lds_all[kWaves * 16 * STR];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int r = lane & 15;
   float *T = lds_all + wave * 16 * STR;
+  const int n = GEN ? P.n : N;           // values per signal in memory
+  const int rstride = GEN ? n : STR;     // LDS row stride
+  constexpr int kZero = 16 * N, kScratch = 16 * N + 1;   // past any tile word (GEN)
 
   // LDS offsets of this lane's gathers and scatters
   int gc[Q], sc[Q];
   float af[NF];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    gc[q] = r * STR + P.gcol[g * Q + q];
-    sc[q] = r * STR + P.scol[g * Q + q];
+    const int gq = P.gcol[g * Q + q], sq = P.scol[g * Q + q];
+    gc[q] = gq >= 0 ? r * rstride + gq : kZero;
+    sc[q] = sq >= 0 ? r * rstride + sq : kScratch;
+  }
+  if constexpr (GEN) {
+    if (lane == 0) T[kZero] = 0.0f;
   }
 #pragma unroll
   for (int f = 0; f < NF; ++f) af[f] = P.afrag[f * 64 + lane];
@@ -94,38 +104,50 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
   // Prefetch of a tile into registers.  The loads are unconditional, so that they stay in
   // flight while the previous tile is computed: past the last valid signal a lane
-  // re-reads the tile's last 16 bytes (lim >= N >= 32), whose rows are never stored.
+  // re-reads the tile's last 16 bytes (lim >= n >= 16), whose rows are never stored.
   constexpr int EI = IN16 ? 8 : 4;          // values per 16-byte load
-  constexpr int VI = N / (4 * EI);          // loads per lane per 16-signal tile
+  constexpr int VI = N / (4 * EI);          // loads per lane per 16-signal tile (16n <= 16N)
   u32x4 pre[VI];
+  // Whole 16-byte groups only: a tile's last lim mod EI values (GEN partial tiles) are read
+  // by scalar loads in the loop below.
   auto issue = [&](int64_t t) {
     const int64_t rem = nsig - 16 * t;
-    const int lim = (int)(rem < 16 ? rem : 16) * N;
+    const int limv = ((int)(rem < 16 ? rem : 16) * n) & ~(EI - 1);
 #pragma unroll
     for (int k = 0; k < VI; ++k) {
       const int e = EI * (lane + 64 * k);
-      const int ec = e < lim ? e : lim - EI;
+      const int ec = e < limv ? e : limv - EI;
       if constexpr (IN16)
-        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * N + ec));
+        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * n + ec));
       else
-        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * N + ec));
+        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * n + ec));
     }
   };
   if (wt < ntiles) issue(wt);
 
   for (; wt < ntiles; wt += step) {
     const int64_t rem = nsig - 16 * wt;
-    const int lim = (int)(rem < 16 ? rem : 16) * N;
+    const int lim = (int)(rem < 16 ? rem : 16) * n;
 #pragma unroll
     for (int k = 0; k < VI; ++k) {
-      const int e = EI * (lane + 64 * k);   // a 16-byte group never crosses a row (N % 8 == 0)
-      float *dst = T + (e / N) * STR + (e % N);
+      // a 16-byte group never crosses a row (N % 8 == 0); GEN: the tile is contiguous and
+      // the words past 16n it receives are never gathered
+      const int e = EI * (lane + 64 * k);
+      float *dst = GEN ? T + e : T + (e / N) * STR + (e % N);
       if constexpr (IN16) {
         const u32x4 w = pre[k];
         *reinterpret_cast<floatx4 *>(dst) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
         *reinterpret_cast<floatx4 *>(dst + 4) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
       } else {
         *reinterpret_cast<u32x4 *>(dst) = pre[k];
+      }
+    }
+    if constexpr (GEN) {
+      for (int e = (lim & ~(EI - 1)) + lane; e < lim; e += 64) {   // partial tile's tail
+        if constexpr (IN16)
+          T[e] = __uint_as_float((uint32_t)static_cast<const uint16_t *>(in)[wt * 16 * n + e] << 16);
+        else
+          T[e] = static_cast<const float *>(in)[wt * 16 * n + e];
       }
     }
     wave_lds_sync();
@@ -204,7 +226,7 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 #pragma unroll
     for (int k = 0; k < VO; ++k) {
       const int e = EO * (lane + 64 * k);
-      const float *src = T + (e / N) * STR + (e % N);
+      const float *src = GEN ? T + e : T + (e / N) * STR + (e % N);
       if constexpr (OUT16) {
         const floatx4 a = *reinterpret_cast<const floatx4 *>(src);
         const floatx4 b = *reinterpret_cast<const floatx4 *>(src + 4);
@@ -216,17 +238,26 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
     }
     auto dst_at = [&](int e) -> u32x4 * {
       if constexpr (OUT16)
-        return reinterpret_cast<u32x4 *>(static_cast<uint16_t *>(out) + wt * 16 * N + e);
+        return reinterpret_cast<u32x4 *>(static_cast<uint16_t *>(out) + wt * 16 * n + e);
       else
-        return reinterpret_cast<u32x4 *>(static_cast<float *>(out) + wt * 16 * N + e);
+        return reinterpret_cast<u32x4 *>(static_cast<float *>(out) + wt * 16 * n + e);
     };
-    if (lim == 16 * N) {   // full tile (wave-uniform branch)
+    if (!GEN && lim == 16 * N) {   // full tile (wave-uniform branch)
 #pragma unroll
       for (int k = 0; k < VO; ++k) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
     } else {
+      const int limv = lim & ~(EO - 1);   // whole groups; GEN tail values stored one by one
 #pragma unroll
       for (int k = 0; k < VO; ++k)
-        if (EO * (lane + 64 * k) < lim) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
+        if (EO * (lane + 64 * k) < limv) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
+      if constexpr (GEN) {
+        for (int e = limv + lane; e < lim; e += 64) {
+          if constexpr (OUT16)
+            static_cast<uint16_t *>(out)[wt * 16 * n + e] = (uint16_t)bf16_bits(T[e]);
+          else
+            static_cast<float *>(out)[wt * 16 * n + e] = T[e];
+        }
+      }
     }
     wave_lds_sync();
   }
@@ -234,30 +265,30 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
 // ---------------------------------------------------------------------------- launch
 
-template <int S, int M, int DIR, bool IN16, bool OUT16>
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN>
 static hipError_t launch_bf(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR, IN16, OUT16>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN>,
                                                    64 * kWaves, 0) != hipSuccess || occ < 1)
     occ = 1;
   const int64_t ntiles = (nsig + 15) / 16;
   const int64_t want = (ntiles + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR, IN16, OUT16>), dim3(grid > 0 ? grid : 1),
+  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN>), dim3(grid > 0 ? grid : 1),
                      dim3(64 * kWaves), 0, stream, P, in, out, nsig);
   return hipGetLastError();
 }
 
-template <int S, int M, int DIR>
+template <int S, int M, int DIR, bool GEN>
 static hipError_t launch_bf_io(const UProgram &P, const void *in, void *out, int64_t nsig,
                                hipStream_t stream, int num_cus, bool in16, bool out16) {
   if (in16)
-    return out16 ? launch_bf<S, M, DIR, true, true>(P, in, out, nsig, stream, num_cus)
-                 : launch_bf<S, M, DIR, true, false>(P, in, out, nsig, stream, num_cus);
-  return out16 ? launch_bf<S, M, DIR, false, true>(P, in, out, nsig, stream, num_cus)
-               : launch_bf<S, M, DIR, false, false>(P, in, out, nsig, stream, num_cus);
+    return out16 ? launch_bf<S, M, DIR, true, true, GEN>(P, in, out, nsig, stream, num_cus)
+                 : launch_bf<S, M, DIR, true, false, GEN>(P, in, out, nsig, stream, num_cus);
+  return out16 ? launch_bf<S, M, DIR, false, true, GEN>(P, in, out, nsig, stream, num_cus)
+               : launch_bf<S, M, DIR, false, false, GEN>(P, in, out, nsig, stream, num_cus);
 }
 
 bool butterfly_supported(int S, int M) {
@@ -266,14 +297,16 @@ bool butterfly_supported(int S, int M) {
 
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16) {
-#define GFT_BF_CASE(s, m)                                                                      \
-  if (P.S == s && P.M == m)                                                                    \
-    return P.dir == 0 ? launch_bf_io<s, m, 0>(P, in, out, nsig, stream, num_cus, in16, out16)  \
-                      : launch_bf_io<s, m, 1>(P, in, out, nsig, stream, num_cus, in16, out16);
-  GFT_BF_CASE(1, 16)
-  GFT_BF_CASE(1, 32)
-  GFT_BF_CASE(2, 16)
-  GFT_BF_CASE(3, 16)
+#define GFT_BF_CASE(s, m, gen)                                                                   \
+  if (P.S == s && P.M == m && (P.n != (m << s)) == gen)                                          \
+    return P.dir == 0 ? launch_bf_io<s, m, 0, gen>(P, in, out, nsig, stream, num_cus, in16, out16) \
+                      : launch_bf_io<s, m, 1, gen>(P, in, out, nsig, stream, num_cus, in16, out16);
+  GFT_BF_CASE(1, 16, false)
+  GFT_BF_CASE(1, 32, false)
+  GFT_BF_CASE(2, 16, false)
+  GFT_BF_CASE(3, 16, false)
+  GFT_BF_CASE(1, 16, true)
+  GFT_BF_CASE(1, 32, true)
 #undef GFT_BF_CASE
   return hipErrorInvalidValue;
 }

@@ -248,7 +248,99 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
 
 namespace gft {
 
+// One-stage plans that are not uniform hypercubes (fixed nodes V_Z, blocks of unequal size
+// or split into components, n odd, 16 <= n <= 63): orbit o holds the o-th V_X node (or, past
+// the pairs, the V_Z nodes) in slot 0 and its partner in slot 1 (a zero word for V_Z and
+// padding), so the register Haar gives the G+ input (x + x') and the G- input (x - x').  G+
+// (V_X then V_Z positions) and G- (V_Y positions) are each one zero-padded block of M = 16 or
+// 32 rows holding their leaf blocks on the diagonal; the sqrt 2 of a V_Z node is folded into
+// its G+ row (the kernel's Haar adds a zero to it).  Slot 0 always holds the V_X node, so no
+// sign flips.
+static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgramImage &out) {
+  const int n = p.n;
+  if (p.stages.size() != 1 || !p.right.pair_x.empty() || n % 2 == 0 || n < 16) return false;
+  const HostStage &st = p.stages[0];
+  const int P = (int)st.pair_x.size(), Z = (int)st.znodes.size();
+  const int pp = P + Z;                        // |G+|
+  const int M = std::max(pp, P) <= 16 ? 16 : (std::max(pp, P) <= 32 ? 32 : 0);
+  if (M == 0 || 2 * P + Z != n) return false;
+  std::vector<int> plus_node(pp), minus_node(P), side(n, -1), ppos(n, -1);
+  for (int u = 0; u < P; ++u) {
+    plus_node[u] = st.pair_x[u];
+    minus_node[u] = st.pair_y[u];
+  }
+  for (int z = 0; z < Z; ++z) plus_node[P + z] = st.znodes[z];
+  for (int o = 0; o < pp; ++o) {
+    side[plus_node[o]] = 0;
+    ppos[plus_node[o]] = o;
+  }
+  for (int o = 0; o < P; ++o) {
+    side[minus_node[o]] = 1;
+    ppos[minus_node[o]] = o;
+  }
+  for (int i = 0; i < n; ++i)
+    if (side[i] < 0) return false;
+  // super-block matrices Vs[b][o][c] (row = position o, column = output column c) and the
+  // output position of each column
+  std::vector<std::vector<double>> Vs(2, std::vector<double>((size_t)M * M, 0.0));
+  std::vector<std::vector<int>> outp(2, std::vector<int>(M, -1));
+  int ncol[2] = {0, 0};
+  for (const HostBlock &B : p.blocks) {
+    const int b = side[B.nodes[0]];
+    for (int k = 0; k < B.size; ++k)
+      if (side[B.nodes[k]] != b || B.depth != 1) return false;
+    if (ncol[b] + B.size > M) return false;
+    for (int k = 0; k < B.size; ++k) {
+      const int o = ppos[B.nodes[k]];
+      const double zs = (b == 0 && o >= P) ? std::sqrt(2.0) : 1.0;   // V_Z row
+      for (int c = 0; c < B.size; ++c) Vs[b][(size_t)o * M + ncol[b] + c] = zs * B.scale * B.V[(size_t)k * B.size + c];
+    }
+    for (int c = 0; c < B.size; ++c) outp[b][ncol[b] + c] = B.out_pos[c];
+    ncol[b] += B.size;
+  }
+  if (ncol[0] != pp || ncol[1] != P) return false;
+  const int NB = 2, KC = M / 4, NT = M / 16, Q = NB * M / 4;
+  auto node_at = [&](int b, int o) { return b == 0 ? (o < pp ? plus_node[o] : -1) : (o < P ? minus_node[o] : -1); };
+  UProgramImage im;
+  im.prog.S = 1;
+  im.prog.M = M;
+  im.prog.n = n;
+  im.prog.dir = direction;
+  im.gcol.assign((size_t)4 * Q, -1);
+  im.scol.assign((size_t)4 * Q, -1);
+  im.flips.assign(8, 0);
+  for (int g = 0; g < 4; ++g) {
+    for (int kc = 0; kc < KC; ++kc)
+      for (int b = 0; b < NB; ++b)
+        im.gcol[(size_t)g * Q + kc * NB + b] = direction == 0 ? node_at(b, 4 * kc + g) : outp[b][4 * kc + g];
+    for (int nt = 0; nt < NT; ++nt)
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * nt + 4 * g + v;
+        for (int b = 0; b < NB; ++b) {
+          if (direction == 0)
+            im.scol[(size_t)g * Q + (b * NT + nt) * 4 + v] = outp[b][c];
+          else
+            im.scol[(size_t)g * Q + (nt * 4 + v) * NB + b] = node_at(b, c);
+        }
+      }
+  }
+  im.afrag.assign((size_t)NB * NT * KC * 64, 0.0f);
+  for (int b = 0; b < NB; ++b)
+    for (int nt = 0; nt < NT; ++nt)
+      for (int kc = 0; kc < KC; ++kc)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = 16 * nt + lane % 16, k = 4 * kc + lane / 16;
+          // forward: A[c][o] = Vs[o][c]; inverse: A[o][k] = Vs[o][k]
+          const int o = direction == 0 ? k : row;
+          const int c = direction == 0 ? row : k;
+          im.afrag[((size_t)(b * NT + nt) * KC + kc) * 64 + lane] = (float)Vs[b][(size_t)o * M + c];
+        }
+  out = std::move(im);
+  return true;
+}
+
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
+  if (build_butterfly_one_stage(p, direction, out)) return true;
   const int n = p.n;
   const int S = (int)p.stages.size();
   if (S < 1 || S > 3 || !p.right.pair_x.empty()) return false;

@@ -84,13 +84,14 @@ def test_butterfly_engine_shapes(g):
 def test_auto_engine_choice():
     device()
     assert G.Plan.from_graph(wl.config2_graph()).engine() == "butterfly"
-    assert G.Plan.from_graph(wl.config3_graph()).engine() == "generic"
+    assert G.Plan.from_graph(wl.config3_graph()).engine() == "butterfly"          # one stage, n odd
+    assert G.Plan.from_graph(wl.config3_graph(), precision="bf16").engine() == "generic"
     assert G.Plan.from_graph(wl.config2_graph(), engine="generic").engine() == "generic"
 
 
 def test_butterfly_engine_rejects_non_uniform_plan():
     dev = device()
-    plan = G.Plan.from_graph(wl.config3_graph(), engine="butterfly")
+    plan = G.Plan.from_graph(wl.grid(5, 5), engine="butterfly")       # two stages, n odd
     with pytest.raises(G.GFTError) as e:
         plan.forward(torch.zeros((16, 25), device=dev))
     assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
@@ -261,3 +262,29 @@ def test_searched_pairings_parity(g):
     h = wl._graph(g.n, np.stack([g.src, g.dst], 1), g.weight, loops=g.self_loop, stages=st, name=g.name)
     X = wl.gaussian(2000, g.n, wl.rng_for(9, g.n, 5))
     _check_graph(h, X)
+
+
+@pytest.mark.parametrize("S", [1, 15, 17, 1003])
+@pytest.mark.parametrize("g", [wl.config3_graph(), wl.path(17), wl.cycle(31), wl.path(63),
+                               wl.weighted_symmetric_path(33, wl.rng_for(9, 33))],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_one_stage_butterfly_general(g, S):
+    """One-stage plans with odd n (V_Z nodes, unequal or split blocks) on the register
+    butterfly engine: padded slots, the signals' own LDS layout and exact tile tails."""
+    assert G.Plan.from_graph(g).engine() == "butterfly"
+    X = wl.gaussian(S, g.n, wl.rng_for(9, g.n, S))
+    _check_graph(g, X, engine="butterfly")
+
+
+@pytest.mark.parametrize("io", [("bf16", "bf16"), ("fp32", "bf16"), ("bf16", "fp32")])
+def test_one_stage_butterfly_storage(io):
+    dev = device()
+    g = wl.config3_graph()
+    X = wl.gaussian(1003, 25, wl.rng_for(9, 25, 8))
+    plan = G.Plan.from_graph(g, in_dtype=io[0], out_dtype=io[1])
+    ref = G.Plan.from_graph(g, engine="butterfly")
+    assert plan.engine() == "butterfly"
+    x = torch.from_numpy(X).to(dev).to({"fp32": torch.float32, "bf16": torch.bfloat16}[io[0]])
+    y = plan.forward(x)
+    assert torch.equal(y, ref.forward(x.float()).to(y.dtype))
+    assert torch.equal(plan.inverse(y), ref.inverse(y.float()).to(x.dtype))
