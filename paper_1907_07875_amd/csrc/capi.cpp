@@ -211,17 +211,20 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   // Register-butterfly engine for single-graph uniform hypercube plans.
   UProgramImage ub[2];
   bool use_bf = false;
-  if (plan->opts.engine == GFT_ENGINE_BUTTERFLY && (plan->batch || plan->opts.precision != GFT_FP32))
+  const int prec = plan->opts.precision;
+  if (plan->opts.engine == GFT_ENGINE_BUTTERFLY &&
+      (plan->batch || (prec != GFT_FP32 && prec != GFT_BF16)))
     return set_error(GFT_ERR_UNSUPPORTED,
-                     "the register-butterfly engine runs single-graph FP32 plans only");
+                     "the register-butterfly engine runs single-graph FP32 or BF16 plans only");
   if (!plan->batch && (plan->opts.engine == GFT_ENGINE_AUTO || plan->opts.engine == GFT_ENGINE_BUTTERFLY) &&
-      plan->opts.precision == GFT_FP32) {
-    use_bf = build_butterfly(plan->graphs[0], 0, ub[0]) && build_butterfly(plan->graphs[0], 1, ub[1]) &&
+      (prec == GFT_FP32 || prec == GFT_BF16)) {
+    use_bf = build_butterfly(plan->graphs[0], 0, ub[0], prec) && build_butterfly(plan->graphs[0], 1, ub[1], prec) &&
              butterfly_supported(ub[0].prog.S, ub[0].prog.M);
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
       return set_error(GFT_ERR_UNSUPPORTED,
                        "the register-butterfly engine does not cover this plan (needs a uniform "
-                       "hypercube with a compiled shape)");
+                       "hypercube with a compiled shape, or one stage with n odd, 16 <= n <= 63; "
+                       "BF16 blocks: the one-stage form only)");
   }
 
   // Large-signal engine: signals whose 16-signal tile does not fit LDS, or big leaf blocks.

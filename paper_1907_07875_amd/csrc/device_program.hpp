@@ -75,6 +75,9 @@ struct DevProgram {
 // (lo + hi, +-(lo - hi)); the sign is flipped where the V_X node started in slot hi.
 // Flip bit of orbit register set j, stage t, lo-slot rank k: j * S * 2^(S-1) + t * 2^(S-1) + k,
 // where j = kc (forward) or nt * 4 + v (inverse).
+// BF16 programs (16x16x16 MFMA, 4 k values per lane) put orbit 16(kc/4) + 4g + kc%4 in data
+// register set kc instead, and their afrag holds 2 words (4 BF16) per lane per fragment
+// f = (b * M/16 + nt) * M/16 + kc/4.
 // Register order (forward): data q = kc * 2^S + b (orbit 4kc+g, slot b); results
 // q = (b * M/16 + nt) * 4 + v (coefficient 16nt+4g+v of block b).  Inverse: data
 // q = kc * 2^S + b (coefficient 4kc+g of block b); results q = (nt * 4 + v) * 2^S + b
@@ -84,6 +87,7 @@ struct UProgram {
   int32_t M;
   int32_t n;
   int32_t dir;
+  int32_t prec;             // gft_precision of the blocks: FP32, or BF16 (one-stage programs)
   const int32_t *gcol;
   const int32_t *scol;
   const uint32_t *flips;

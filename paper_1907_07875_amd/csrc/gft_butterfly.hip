@@ -51,6 +51,8 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 }  // namespace
 
@@ -59,7 +61,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // GEN: a one-stage program with n = P.n < N signal values (odd, >= 16), padded slots: the
 // LDS tile is then the 16 signals' own contiguous layout (row stride n), a gather column
 // of -1 reads a zero word and a scatter column of -1 writes a scratch word.
-template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN>
+// BF: BF16 leaf blocks (one-stage programs): the block inputs are rounded to BF16 after the
+// FP32 Haar stage and multiplied on 16x16x16 BF16 MFMA with FP32 accumulation.
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF>
 __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, const void *in,
                                                                  void *out, int64_t nsig) {
   constexpr int NB = 1 << S;      // leaf blocks = slots per orbit
@@ -82,7 +86,8 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
   // LDS offsets of this lane's gathers and scatters
   int gc[Q], sc[Q];
-  float af[NF];
+  constexpr int NAF = BF ? NF / 2 : NF;   // BF16: 2 words per 4-k fragment
+  float af[NAF];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int gq = P.gcol[g * Q + q], sq = P.scol[g * Q + q];
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
     if (lane == 0) T[kZero] = 0.0f;
   }
 #pragma unroll
-  for (int f = 0; f < NF; ++f) af[f] = P.afrag[f * 64 + lane];
+  for (int f = 0; f < NAF; ++f) af[f] = BF ? P.afrag[((f >> 1) * 64 + lane) * 2 + (f & 1)] : P.afrag[f * 64 + lane];
   constexpr int PPS = NB / 2;
   constexpr int FB = S * PPS;
   const uint64_t flips = ((uint64_t)P.flips[2 * g + 1] << 32) | P.flips[2 * g];
@@ -185,10 +190,22 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (BF) {
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[(b * NT + nt) * KC + kc], d[kc * NB + b],
-                                                     acc, 0, 0, 0);
+          for (int k4 = 0; k4 < KC / 4; ++k4) {
+            const int f = (b * NT + nt) * (KC / 4) + k4;
+            const u32x2 aw = {__float_as_uint(af[2 * f]), __float_as_uint(af[2 * f + 1])};
+            const u32x2 bw = {bf16_bits(d[(4 * k4) * NB + b]) | (bf16_bits(d[(4 * k4 + 1) * NB + b]) << 16),
+                              bf16_bits(d[(4 * k4 + 2) * NB + b]) | (bf16_bits(d[(4 * k4 + 3) * NB + b]) << 16)};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, aw),
+                                                            __builtin_bit_cast(bf16x4, bw), acc, 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[(b * NT + nt) * KC + kc], d[kc * NB + b],
+                                                       acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if (DIR == 0) res[(b * NT + nt) * 4 + v] = acc[v];
@@ -265,30 +282,30 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
 // ---------------------------------------------------------------------------- launch
 
-template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN>
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF>
 static hipError_t launch_bf(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN, BF>,
                                                    64 * kWaves, 0) != hipSuccess || occ < 1)
     occ = 1;
   const int64_t ntiles = (nsig + 15) / 16;
   const int64_t want = (ntiles + kWaves - 1) / kWaves;
   const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN>), dim3(grid > 0 ? grid : 1),
+  hipLaunchKernelGGL((gft_butterfly_f32<S, M, DIR, IN16, OUT16, GEN, BF>), dim3(grid > 0 ? grid : 1),
                      dim3(64 * kWaves), 0, stream, P, in, out, nsig);
   return hipGetLastError();
 }
 
-template <int S, int M, int DIR, bool GEN>
+template <int S, int M, int DIR, bool GEN, bool BF>
 static hipError_t launch_bf_io(const UProgram &P, const void *in, void *out, int64_t nsig,
                                hipStream_t stream, int num_cus, bool in16, bool out16) {
   if (in16)
-    return out16 ? launch_bf<S, M, DIR, true, true, GEN>(P, in, out, nsig, stream, num_cus)
-                 : launch_bf<S, M, DIR, true, false, GEN>(P, in, out, nsig, stream, num_cus);
-  return out16 ? launch_bf<S, M, DIR, false, true, GEN>(P, in, out, nsig, stream, num_cus)
-               : launch_bf<S, M, DIR, false, false, GEN>(P, in, out, nsig, stream, num_cus);
+    return out16 ? launch_bf<S, M, DIR, true, true, GEN, BF>(P, in, out, nsig, stream, num_cus)
+                 : launch_bf<S, M, DIR, true, false, GEN, BF>(P, in, out, nsig, stream, num_cus);
+  return out16 ? launch_bf<S, M, DIR, false, true, GEN, BF>(P, in, out, nsig, stream, num_cus)
+               : launch_bf<S, M, DIR, false, false, GEN, BF>(P, in, out, nsig, stream, num_cus);
 }
 
 bool butterfly_supported(int S, int M) {
@@ -297,16 +314,18 @@ bool butterfly_supported(int S, int M) {
 
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16) {
-#define GFT_BF_CASE(s, m, gen)                                                                   \
-  if (P.S == s && P.M == m && (P.n != (m << s)) == gen)                                          \
-    return P.dir == 0 ? launch_bf_io<s, m, 0, gen>(P, in, out, nsig, stream, num_cus, in16, out16) \
-                      : launch_bf_io<s, m, 1, gen>(P, in, out, nsig, stream, num_cus, in16, out16);
-  GFT_BF_CASE(1, 16, false)
-  GFT_BF_CASE(1, 32, false)
-  GFT_BF_CASE(2, 16, false)
-  GFT_BF_CASE(3, 16, false)
-  GFT_BF_CASE(1, 16, true)
-  GFT_BF_CASE(1, 32, true)
+#define GFT_BF_CASE(s, m, gen, bf)                                                                   \
+  if (P.S == s && P.M == m && (P.n != (m << s)) == gen && (P.prec != 0) == bf)                      \
+    return P.dir == 0 ? launch_bf_io<s, m, 0, gen, bf>(P, in, out, nsig, stream, num_cus, in16, out16) \
+                      : launch_bf_io<s, m, 1, gen, bf>(P, in, out, nsig, stream, num_cus, in16, out16);
+  GFT_BF_CASE(1, 16, false, false)
+  GFT_BF_CASE(1, 32, false, false)
+  GFT_BF_CASE(2, 16, false, false)
+  GFT_BF_CASE(3, 16, false, false)
+  GFT_BF_CASE(1, 16, true, false)
+  GFT_BF_CASE(1, 32, true, false)
+  GFT_BF_CASE(1, 16, true, true)
+  GFT_BF_CASE(1, 32, true, true)
 #undef GFT_BF_CASE
   return hipErrorInvalidValue;
 }

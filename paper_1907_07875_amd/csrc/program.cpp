@@ -256,7 +256,8 @@ namespace gft {
 // 32 rows holding their leaf blocks on the diagonal; the sqrt 2 of a V_Z node is folded into
 // its G+ row (the kernel's Haar adds a zero to it).  Slot 0 always holds the V_X node, so no
 // sign flips.
-static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgramImage &out) {
+static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgramImage &out,
+                                      int precision) {
   const int n = p.n;
   if (p.stages.size() != 1 || !p.right.pair_x.empty() || n % 2 == 0 || n < 16) return false;
   const HostStage &st = p.stages[0];
@@ -299,20 +300,25 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
     ncol[b] += B.size;
   }
   if (ncol[0] != pp || ncol[1] != P) return false;
+  if (precision != GFT_FP32 && precision != GFT_BF16) return false;
+  const bool bf = precision == GFT_BF16;
   const int NB = 2, KC = M / 4, NT = M / 16, Q = NB * M / 4;
   auto node_at = [&](int b, int o) { return b == 0 ? (o < pp ? plus_node[o] : -1) : (o < P ? minus_node[o] : -1); };
+  // orbit in data register set kc of lane group g (BF16: 4 consecutive k per 16x16x16 MFMA)
+  auto orbit = [&](int g, int kc) { return bf ? 16 * (kc / 4) + 4 * g + kc % 4 : 4 * kc + g; };
   UProgramImage im;
   im.prog.S = 1;
   im.prog.M = M;
   im.prog.n = n;
   im.prog.dir = direction;
+  im.prog.prec = precision;
   im.gcol.assign((size_t)4 * Q, -1);
   im.scol.assign((size_t)4 * Q, -1);
   im.flips.assign(8, 0);
   for (int g = 0; g < 4; ++g) {
     for (int kc = 0; kc < KC; ++kc)
       for (int b = 0; b < NB; ++b)
-        im.gcol[(size_t)g * Q + kc * NB + b] = direction == 0 ? node_at(b, 4 * kc + g) : outp[b][4 * kc + g];
+        im.gcol[(size_t)g * Q + kc * NB + b] = direction == 0 ? node_at(b, orbit(g, kc)) : outp[b][orbit(g, kc)];
     for (int nt = 0; nt < NT; ++nt)
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * nt + 4 * g + v;
@@ -324,23 +330,41 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
         }
       }
   }
-  im.afrag.assign((size_t)NB * NT * KC * 64, 0.0f);
-  for (int b = 0; b < NB; ++b)
-    for (int nt = 0; nt < NT; ++nt)
-      for (int kc = 0; kc < KC; ++kc)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int row = 16 * nt + lane % 16, k = 4 * kc + lane / 16;
-          // forward: A[c][o] = Vs[o][c]; inverse: A[o][k] = Vs[o][k]
-          const int o = direction == 0 ? k : row;
-          const int c = direction == 0 ? row : k;
-          im.afrag[((size_t)(b * NT + nt) * KC + kc) * 64 + lane] = (float)Vs[b][(size_t)o * M + c];
-        }
+  // forward: A[c][o] = Vs[o][c]; inverse: A[o][k] = Vs[o][k]
+  auto aval = [&](int b, int row, int k) {
+    const int o = direction == 0 ? k : row;
+    const int c = direction == 0 ? row : k;
+    return Vs[b][(size_t)o * M + c];
+  };
+  if (bf) {
+    im.afrag.assign((size_t)NB * NT * (KC / 4) * 64 * 2, 0.0f);
+    for (int b = 0; b < NB; ++b)
+      for (int nt = 0; nt < NT; ++nt)
+        for (int k4 = 0; k4 < KC / 4; ++k4)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int row = 16 * nt + lane % 16, k0 = 16 * k4 + 4 * (lane / 16);
+            uint32_t w[2];
+            for (int h = 0; h < 2; ++h)
+              w[h] = (uint32_t)to_bf16_bits((float)aval(b, row, k0 + 2 * h)) |
+                     ((uint32_t)to_bf16_bits((float)aval(b, row, k0 + 2 * h + 1)) << 16);
+            std::memcpy(&im.afrag[(((size_t)(b * NT + nt) * (KC / 4) + k4) * 64 + lane) * 2], w, 8);
+          }
+  } else {
+    im.afrag.assign((size_t)NB * NT * KC * 64, 0.0f);
+    for (int b = 0; b < NB; ++b)
+      for (int nt = 0; nt < NT; ++nt)
+        for (int kc = 0; kc < KC; ++kc)
+          for (int lane = 0; lane < 64; ++lane)
+            im.afrag[((size_t)(b * NT + nt) * KC + kc) * 64 + lane] =
+                (float)aval(b, 16 * nt + lane % 16, 4 * kc + lane / 16);
+  }
   out = std::move(im);
   return true;
 }
 
-bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
-  if (build_butterfly_one_stage(p, direction, out)) return true;
+bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int precision) {
+  if (build_butterfly_one_stage(p, direction, out, precision)) return true;
+  if (precision != GFT_FP32) return false;
   const int n = p.n;
   const int S = (int)p.stages.size();
   if (S < 1 || S > 3 || !p.right.pair_x.empty()) return false;
@@ -446,6 +470,7 @@ bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out) {
   im.prog.M = M;
   im.prog.n = n;
   im.prog.dir = direction;
+  im.prog.prec = GFT_FP32;
   im.gcol.assign((size_t)4 * Q, 0);
   im.scol.assign((size_t)4 * Q, 0);
   im.flips.assign(8, 0);

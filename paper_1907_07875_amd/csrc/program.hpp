@@ -46,7 +46,8 @@ struct UProgramImage {
 // differs only in slot bit S-1-t (a 2-colouring per stage; orientation is fixed by a
 // per-orbit sign flip).  The leaf block of a node is its slot after the last stage.
 // Returns false (out untouched) otherwise.
-bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out);
+// `precision`: GFT_FP32 (every shape above) or GFT_BF16 (one-stage programs only).
+bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int precision = 0);
 
 // Host image of the large-signal engine for one direction (see PermPass, LBlock).
 struct LargeImage {

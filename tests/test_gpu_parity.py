@@ -85,7 +85,8 @@ def test_auto_engine_choice():
     device()
     assert G.Plan.from_graph(wl.config2_graph()).engine() == "butterfly"
     assert G.Plan.from_graph(wl.config3_graph()).engine() == "butterfly"          # one stage, n odd
-    assert G.Plan.from_graph(wl.config3_graph(), precision="bf16").engine() == "generic"
+    assert G.Plan.from_graph(wl.config3_graph(), precision="bf16").engine() == "butterfly"
+    assert G.Plan.from_graph(wl.config3_graph(), precision="fp16").engine() == "generic"
     assert G.Plan.from_graph(wl.config2_graph(), engine="generic").engine() == "generic"
 
 
@@ -270,10 +271,14 @@ def test_searched_pairings_parity(g):
                          ids=lambda g: f"{g.name}{g.n}")
 def test_one_stage_butterfly_general(g, S):
     """One-stage plans with odd n (V_Z nodes, unequal or split blocks) on the register
-    butterfly engine: padded slots, the signals' own LDS layout and exact tile tails."""
+    butterfly engine: padded slots, the signals' own LDS layout and exact tile tails; FP32
+    blocks and BF16 blocks (16x16x16 MFMA on inputs rounded after the FP32 Haar stage)."""
     assert G.Plan.from_graph(g).engine() == "butterfly"
     X = wl.gaussian(S, g.n, wl.rng_for(9, g.n, S))
     _check_graph(g, X, engine="butterfly")
+    assert G.Plan.from_graph(g, precision="bf16").engine() == "butterfly"
+    _, _, _, err = _check_graph(g, X, engine="butterfly", precision="bf16", tol=2e-2, basis_tol=1e-2)
+    assert err > 1e-5, "BF16 error suspiciously small: blocks may not run in BF16"
 
 
 @pytest.mark.parametrize("io", [("bf16", "bf16"), ("fp32", "bf16"), ("bf16", "fp32")])
