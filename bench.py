@@ -41,8 +41,8 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 # (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for the kernel source it was measured
 # on: reported as null once that file changes.
 PROFILED_TRAFFIC = {"source": "paper_1907_07875_amd/csrc/gft_butterfly.hip",
-                    "sha256_16": "ad60527b97c1d5a2",
-                    "bytes_per_launch": 2.0 * 131160.84 * 1024 + 262145.75 * 1024}
+                    "sha256_16": "510cb789a49487f4",
+                    "bytes_per_launch": 2.0 * 131165.33 * 1024 + 262148.06 * 1024}
 
 
 def parse():
@@ -320,7 +320,8 @@ def bench_skeleton(args):
                   "stages": "left/right limb swap (10 Haar units), leaf blocks 15 + 5 + 5",
                   "shape": f"[{seqs}, 3, 300, 25]"},
                  8 * 900, "first 8 sequences (7200 signals) of the same skeleton workload",
-                 kernel_names={"generic": f"gft_apply<8,{args.precision or 'bf16'}>"})
+                 kernel_names={"butterfly": "gft_butterfly_f32<1,16,0> (one-stage layout)",
+                               "generic": f"gft_apply<8,{args.precision or 'bf16'}>"})
 
 
 def _large_workload(args, graph, S, name, desc):
@@ -337,7 +338,8 @@ def _large_workload(args, graph, S, name, desc):
                   "leaf_blocks": st["num_blocks"], "max_block": st["max_block"],
                   "dense_flops_per_signal": 2.0 * graph.n * graph.n, "fast_flops_per_signal": flops},
                  256, "first 256 signals of the same workload",
-                 kernel_names={"large": "large engine: permute_stages + block_gemm + permute_stages"},
+                 kernel_names={"large": "large engine: permute_stages + block_gemm (+ permute_stages "
+                                          "unless the output order is fused)"},
                  flops_per_signal=flops)
 
 
