@@ -223,7 +223,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
       return set_error(GFT_ERR_UNSUPPORTED,
                        "the register-butterfly engine does not cover this plan (needs a uniform "
-                       "hypercube with a compiled shape, or one stage with n odd, 16 <= n <= 63; "
+                       "hypercube with a compiled shape, or one stage with 8 <= n <= 64 and sides of at "
+                       "most 32 nodes; "
                        "BF16 blocks: the one-stage form only)");
   }
 

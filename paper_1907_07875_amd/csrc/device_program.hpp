@@ -61,8 +61,8 @@ struct DevProgram {
   const uint32_t *frag;
 };
 
-// Register-butterfly program (uniform hypercube plans, and one-stage plans with n odd
-// padded to 2M slots, where gcol / scol entries of -1 read a zero / write nowhere): S stages,
+// Register-butterfly program (uniform hypercube plans, and one-stage plans with n >= 8
+// padded to 2M slots, gen = 1, where gcol / scol entries of -1 read a zero / write nowhere): S stages,
 // 2^S leaf blocks of M nodes, n = M * 2^S; orbit o (o < M) holds node node(o, b) of every block b at block
 // position o, and stage t pairs slots b and b ^ 2^(S-1-t).  Lane l of a wave works on
 // signal l % 16 of a 16-signal tile and on lane group g = l / 16.
@@ -88,6 +88,7 @@ struct UProgram {
   int32_t n;
   int32_t dir;
   int32_t prec;             // gft_precision of the blocks: FP32, or BF16 (one-stage programs)
+  int32_t gen;              // 1: the padded one-stage layout (n <= 2M), 0: uniform (n = M 2^S)
   const int32_t *gcol;
   const int32_t *scol;
   const uint32_t *flips;

@@ -58,9 +58,11 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // IN16 / OUT16: the tile is read / written as BF16 (16-byte accesses of 8 values) instead
 // of FP32 (16-byte accesses of 4 values); everything between runs in FP32.
-// GEN: a one-stage program with n = P.n < N signal values (odd, >= 16), padded slots: the
-// LDS tile is then the 16 signals' own contiguous layout (row stride n), a gather column
-// of -1 reads a zero word and a scatter column of -1 writes a scratch word.
+// GEN: a one-stage program with n = P.n <= N signal values (n >= 8), padded slots: a
+// gather column of -1 reads a zero word and a scatter column of -1 writes a scratch word.
+// The LDS tile keeps the 16 signals' own contiguous layout (row stride n) when n is odd or
+// n = 2 mod 4, where 16 rows at stride n fall in distinct banks; for 4 | n rows are padded
+// to a stride = 4 mod 8 (n + 4 or n + 8), which keeps 16-byte groups inside a row.
 // BF: BF16 leaf blocks (one-stage programs): the block inputs are rounded to BF16 after the
 // FP32 Haar stage and multiplied on 16x16x16 BF16 MFMA with FP32 accumulation.
 template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF>
@@ -73,16 +75,21 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
   constexpr int Q = N / 4;        // values per lane
   constexpr int STR = N + 4;      // LDS row stride: 16-byte rows, offset banks
   constexpr int NF = NB * NT * KC;
-  __shared__ __attribute__((aligned(16))) float lds_all[kWaves * 16 * STR];
+  constexpr int TW = 16 * STR + 4;  // words per wave: the tile, then the zero and scratch words
+  __shared__ __attribute__((aligned(16))) float lds_all[kWaves * TW];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int r = lane & 15;
-  float *T = lds_all + wave * 16 * STR;
+  float *T = lds_all + wave * TW;
   const int n = GEN ? P.n : N;           // values per signal in memory
-  const int rstride = GEN ? n : STR;     // LDS row stride
-  constexpr int kZero = 16 * N, kScratch = 16 * N + 1;   // past any tile word (GEN)
+  // LDS row stride (GEN: n + 8 <= N + 4 when n = 4 mod 8, since then n <= N - 4)
+  const int rstride = !GEN ? STR : ((n & 3) ? n : ((n & 7) ? n + 8 : n + 4));
+  const bool packed = GEN && rstride == n;   // tile word e of the signals is LDS word e
+  constexpr int kZero = 16 * STR, kScratch = 16 * STR + 1;   // past any tile word (GEN)
+  // LDS word of tile element e < 16 n (a row-padded tile: row e / n, column e % n)
+  auto tw = [&](int e) -> int { return packed ? e : (GEN ? (e / n) * rstride + e % n : (e / N) * STR + (e % N)); };
 
   // LDS offsets of this lane's gathers and scatters
   int gc[Q], sc[Q];
@@ -109,10 +116,20 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 
   // Prefetch of a tile into registers.  The loads are unconditional, so that they stay in
   // flight while the previous tile is computed: past the last valid signal a lane
-  // re-reads the tile's last 16 bytes (lim >= n >= 16), whose rows are never stored.
+  // re-reads the tile's last 16 bytes (lim >= n >= 8), whose rows are never stored.
   constexpr int EI = IN16 ? 8 : 4;          // values per 16-byte load
   constexpr int VI = N / (4 * EI);          // loads per lane per 16-signal tile (16n <= 16N)
+  constexpr int H = EI / 4;                 // LDS groups of 4 values per load
   u32x4 pre[VI];
+  // LDS words of this lane's load groups (-1: past the tile's 16 rows, never written)
+  int ld_at[VI * H];
+#pragma unroll
+  for (int k = 0; k < VI; ++k)
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int e = EI * (lane + 64 * k) + 4 * h;
+      ld_at[k * H + h] = packed || e < 16 * n ? tw(e) : -1;
+    }
   // Whole 16-byte groups only: a tile's last lim mod EI values (GEN partial tiles) are read
   // by scalar loads in the loop below.
   auto issue = [&](int64_t t) {
@@ -130,29 +147,43 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
   };
   if (wt < ntiles) issue(wt);
 
+  constexpr int EO = OUT16 ? 8 : 4;         // values per 16-byte store
+  constexpr int VO = N / (4 * EO);
+  constexpr int HO = EO / 4;
+  // LDS words of this lane's store groups (past the tile's 16 rows: word 0, never stored)
+  int st_at[VO * HO];
+#pragma unroll
+  for (int k = 0; k < VO; ++k)
+#pragma unroll
+    for (int h = 0; h < HO; ++h) {
+      const int e = EO * (lane + 64 * k) + 4 * h;
+      st_at[k * HO + h] = packed || e < 16 * n ? tw(e) : 0;
+    }
+
   for (; wt < ntiles; wt += step) {
     const int64_t rem = nsig - 16 * wt;
     const int lim = (int)(rem < 16 ? rem : 16) * n;
 #pragma unroll
     for (int k = 0; k < VI; ++k) {
-      // a 16-byte group never crosses a row (N % 8 == 0); GEN: the tile is contiguous and
-      // the words past 16n it receives are never gathered
-      const int e = EI * (lane + 64 * k);
-      float *dst = GEN ? T + e : T + (e / N) * STR + (e % N);
+      // a group of 4 values never crosses a row (4 | N, and 4 | n where GEN rows are
+      // padded); a packed GEN tile is contiguous and the words past 16n it receives are
+      // never gathered
       if constexpr (IN16) {
         const u32x4 w = pre[k];
-        *reinterpret_cast<floatx4 *>(dst) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
-        *reinterpret_cast<floatx4 *>(dst + 4) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
+        if (ld_at[2 * k] >= 0)
+          *reinterpret_cast<floatx4 *>(T + ld_at[2 * k]) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
+        if (ld_at[2 * k + 1] >= 0)
+          *reinterpret_cast<floatx4 *>(T + ld_at[2 * k + 1]) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
       } else {
-        *reinterpret_cast<u32x4 *>(dst) = pre[k];
+        if (ld_at[k] >= 0) *reinterpret_cast<u32x4 *>(T + ld_at[k]) = pre[k];
       }
     }
     if constexpr (GEN) {
       for (int e = (lim & ~(EI - 1)) + lane; e < lim; e += 64) {   // partial tile's tail
         if constexpr (IN16)
-          T[e] = __uint_as_float((uint32_t)static_cast<const uint16_t *>(in)[wt * 16 * n + e] << 16);
+          T[tw(e)] = __uint_as_float((uint32_t)static_cast<const uint16_t *>(in)[wt * 16 * n + e] << 16);
         else
-          T[e] = static_cast<const float *>(in)[wt * 16 * n + e];
+          T[tw(e)] = static_cast<const float *>(in)[wt * 16 * n + e];
       }
     }
     wave_lds_sync();
@@ -237,16 +268,13 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
 #pragma unroll
     for (int q = 0; q < Q; ++q) T[sc[q]] = res[q];
     wave_lds_sync();
-    constexpr int EO = OUT16 ? 8 : 4;         // values per 16-byte store
-    constexpr int VO = N / (4 * EO);
     u32x4 o[VO];
 #pragma unroll
     for (int k = 0; k < VO; ++k) {
-      const int e = EO * (lane + 64 * k);
-      const float *src = GEN ? T + e : T + (e / N) * STR + (e % N);
+      const float *src = T + st_at[k * HO];
       if constexpr (OUT16) {
         const floatx4 a = *reinterpret_cast<const floatx4 *>(src);
-        const floatx4 b = *reinterpret_cast<const floatx4 *>(src + 4);
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(T + st_at[k * HO + 1]);
         o[k] = u32x4{bf16_bits(a[0]) | (bf16_bits(a[1]) << 16), bf16_bits(a[2]) | (bf16_bits(a[3]) << 16),
                      bf16_bits(b[0]) | (bf16_bits(b[1]) << 16), bf16_bits(b[2]) | (bf16_bits(b[3]) << 16)};
       } else {
@@ -270,9 +298,9 @@ __global__ __launch_bounds__(64 * kWaves) void gft_butterfly_f32(UProgram P, con
       if constexpr (GEN) {
         for (int e = limv + lane; e < lim; e += 64) {
           if constexpr (OUT16)
-            static_cast<uint16_t *>(out)[wt * 16 * n + e] = (uint16_t)bf16_bits(T[e]);
+            static_cast<uint16_t *>(out)[wt * 16 * n + e] = (uint16_t)bf16_bits(T[tw(e)]);
           else
-            static_cast<float *>(out)[wt * 16 * n + e] = T[e];
+            static_cast<float *>(out)[wt * 16 * n + e] = T[tw(e)];
         }
       }
     }
@@ -314,10 +342,10 @@ bool butterfly_supported(int S, int M) {
 
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16) {
-#define GFT_BF_CASE(s, m, gen, bf)                                                                   \
-  if (P.S == s && P.M == m && (P.n != (m << s)) == gen && (P.prec != 0) == bf)                      \
-    return P.dir == 0 ? launch_bf_io<s, m, 0, gen, bf>(P, in, out, nsig, stream, num_cus, in16, out16) \
-                      : launch_bf_io<s, m, 1, gen, bf>(P, in, out, nsig, stream, num_cus, in16, out16);
+#define GFT_BF_CASE(s, m, pad, bf)                                                                   \
+  if (P.S == s && P.M == m && (P.gen != 0) == pad && (P.prec != 0) == bf)                           \
+    return P.dir == 0 ? launch_bf_io<s, m, 0, pad, bf>(P, in, out, nsig, stream, num_cus, in16, out16) \
+                      : launch_bf_io<s, m, 1, pad, bf>(P, in, out, nsig, stream, num_cus, in16, out16);
   GFT_BF_CASE(1, 16, false, false)
   GFT_BF_CASE(1, 32, false, false)
   GFT_BF_CASE(2, 16, false, false)

@@ -249,7 +249,7 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
 namespace gft {
 
 // One-stage plans that are not uniform hypercubes (fixed nodes V_Z, blocks of unequal size
-// or split into components, n odd, 16 <= n <= 63): orbit o holds the o-th V_X node (or, past
+// or split into components, 8 <= n <= 64): orbit o holds the o-th V_X node (or, past
 // the pairs, the V_Z nodes) in slot 0 and its partner in slot 1 (a zero word for V_Z and
 // padding), so the register Haar gives the G+ input (x + x') and the G- input (x - x').  G+
 // (V_X then V_Z positions) and G- (V_Y positions) are each one zero-padded block of M = 16 or
@@ -259,7 +259,7 @@ namespace gft {
 static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgramImage &out,
                                       int precision) {
   const int n = p.n;
-  if (p.stages.size() != 1 || !p.right.pair_x.empty() || n % 2 == 0 || n < 16) return false;
+  if (p.stages.size() != 1 || !p.right.pair_x.empty() || n < 8) return false;
   const HostStage &st = p.stages[0];
   const int P = (int)st.pair_x.size(), Z = (int)st.znodes.size();
   const int pp = P + Z;                        // |G+|
@@ -312,6 +312,7 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
   im.prog.n = n;
   im.prog.dir = direction;
   im.prog.prec = precision;
+  im.prog.gen = 1;
   im.gcol.assign((size_t)4 * Q, -1);
   im.scol.assign((size_t)4 * Q, -1);
   im.flips.assign(8, 0);
@@ -362,9 +363,14 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
   return true;
 }
 
+static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramImage &out);
+
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int precision) {
-  if (build_butterfly_one_stage(p, direction, out, precision)) return true;
-  if (precision != GFT_FP32) return false;
+  if (precision == GFT_FP32 && build_butterfly_uniform(p, direction, out)) return true;
+  return build_butterfly_one_stage(p, direction, out, precision);
+}
+
+static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramImage &out) {
   const int n = p.n;
   const int S = (int)p.stages.size();
   if (S < 1 || S > 3 || !p.right.pair_x.empty()) return false;
@@ -471,6 +477,7 @@ bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int 
   im.prog.n = n;
   im.prog.dir = direction;
   im.prog.prec = GFT_FP32;
+  im.prog.gen = 0;
   im.gcol.assign((size_t)4 * Q, 0);
   im.scol.assign((size_t)4 * Q, 0);
   im.flips.assign(8, 0);

@@ -40,7 +40,9 @@ struct UProgramImage {
   std::vector<float> afrag;
 };
 
-// Build the register-butterfly program of `p` if the plan is a uniform hypercube: every
+// Build the register-butterfly program of `p` if the plan is a uniform hypercube (or, failing
+// that, a one-stage plan with 8 <= n <= 64 whose sides have at most 32 nodes, laid out on
+// padded slots: UProgram::gen): every
 // stage pairs every node (no V_Z), 2^S leaf blocks of equal size M (a multiple of 16),
 // and each Haar orbit can be laid out on 2^S register slots so that every stage-t pair
 // differs only in slot bit S-1-t (a 2-colouring per stage; orientation is fixed by a

@@ -265,14 +265,22 @@ def test_searched_pairings_parity(g):
     _check_graph(h, X)
 
 
+# n odd and n = 2 mod 4 keep the signals' own LDS layout; n = 0 mod 8 and n = 4 mod 8 pad the
+# rows (to n + 4 and n + 8; n = 60 reaches the largest padded tile of 32-slot sides)
+ONE_STAGE_GRAPHS = [wl.config3_graph(), wl.path(17), wl.cycle(31), wl.path(63),
+                    wl.weighted_symmetric_path(33, wl.rng_for(9, 33)), wl.path(8), wl.path(12),
+                    wl.cycle(22), wl.path(40), wl.path(44), wl.cycle(48), wl.cycle(60),
+                    wl.symmetric_bipartite(40, wl.rng_for(4, 40)),
+                    wl.weighted_symmetric_path(36, wl.rng_for(9, 36))]
+
+
 @pytest.mark.parametrize("S", [1, 15, 17, 1003])
-@pytest.mark.parametrize("g", [wl.config3_graph(), wl.path(17), wl.cycle(31), wl.path(63),
-                               wl.weighted_symmetric_path(33, wl.rng_for(9, 33))],
-                         ids=lambda g: f"{g.name}{g.n}")
+@pytest.mark.parametrize("g", ONE_STAGE_GRAPHS, ids=lambda g: f"{g.name}{g.n}")
 def test_one_stage_butterfly_general(g, S):
-    """One-stage plans with odd n (V_Z nodes, unequal or split blocks) on the register
-    butterfly engine: padded slots, the signals' own LDS layout and exact tile tails; FP32
-    blocks and BF16 blocks (16x16x16 MFMA on inputs rounded after the FP32 Haar stage)."""
+    """One-stage plans that are not uniform hypercubes (V_Z nodes, unequal or split blocks,
+    8 <= n <= 64) on the register butterfly engine: padded slots, the LDS row layouts and
+    exact tile tails; FP32 blocks and BF16 blocks (16x16x16 MFMA on inputs rounded after the
+    FP32 Haar stage)."""
     assert G.Plan.from_graph(g).engine() == "butterfly"
     X = wl.gaussian(S, g.n, wl.rng_for(9, g.n, S))
     _check_graph(g, X, engine="butterfly")
@@ -282,10 +290,13 @@ def test_one_stage_butterfly_general(g, S):
 
 
 @pytest.mark.parametrize("io", [("bf16", "bf16"), ("fp32", "bf16"), ("bf16", "fp32")])
-def test_one_stage_butterfly_storage(io):
+@pytest.mark.parametrize("g", [wl.config3_graph(), wl.path(12), wl.cycle(22), wl.path(44), wl.cycle(48)],
+                         ids=lambda g: f"{g.name}{g.n}")
+def test_one_stage_butterfly_storage(io, g):
+    """BF16 storage on the one-stage layouts (16-byte groups of 8 values split across padded
+    rows when n = 4 mod 8) equals FP32 storage rounded."""
     dev = device()
-    g = wl.config3_graph()
-    X = wl.gaussian(1003, 25, wl.rng_for(9, 25, 8))
+    X = wl.gaussian(1003, g.n, wl.rng_for(9, g.n, 8))
     plan = G.Plan.from_graph(g, in_dtype=io[0], out_dtype=io[1])
     ref = G.Plan.from_graph(g, engine="butterfly")
     assert plan.engine() == "butterfly"
