@@ -1,6 +1,7 @@
 // C ABI of libgft (include/gft.h): argument checking, plan ownership, per-device images.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -46,10 +47,13 @@ struct DeviceImage {
   // large-signal engine (single-graph plans)
   bool large = false;
   LargeImage lg[2];
-  // batch plans: device arrays of the G forward and G inverse programs
+  // batch plans: device arrays of the G forward and G inverse programs, and of their
+  // register-butterfly programs (S = 0 where a graph runs its LDS program; null if none)
   const DevProgram *dev_fwd = nullptr, *dev_inv = nullptr;
+  const UProgram *dev_ufwd = nullptr, *dev_uinv = nullptr;
   size_t batch_lds = 0;
   int batch_grid = 1;
+  int reg_groups = 0;
 };
 
 // Byte blob assembled on the host and uploaded in one copy; offsets are 256-aligned.
@@ -203,7 +207,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   const int G = (int)plan->graphs.size();
   if (plan->batch) {
     // the batch kernel keeps G+1 element offsets and the scan's wave totals in LDS as well
-    const size_t fixed = batch_lds_bytes(G, 0) + 64 + 256;
+    const size_t fixed = batch_lds_bytes(G, 0, false) + 64 + 256;
     if (fixed + 4096 > budget) return set_error(GFT_ERR_UNSUPPORTED, "too many graphs in one batch plan");
     budget -= fixed;
   }
@@ -226,6 +230,23 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                        "hypercube with a compiled shape, or one stage with 8 <= n <= 64 and sides of at "
                        "most 32 nodes; "
                        "BF16 blocks: the one-stage form only)");
+  }
+
+  // Batch plans: every graph whose plan the batch kernel's register-butterfly forms cover
+  // runs there (unless the generic engine is forced); the others run their LDS programs.
+  std::vector<UProgramImage> bub;            // 2 per graph (forward, inverse); empty: LDS program
+  std::vector<char> breg(G, 0);
+  if (plan->batch && plan->opts.engine == GFT_ENGINE_AUTO) {
+    bub.resize((size_t)2 * G);
+    for (int g = 0; g < G; ++g) {
+      UProgramImage f, i;
+      if (build_butterfly(plan->graphs[g], 0, f, prec) && build_butterfly(plan->graphs[g], 1, i, prec) &&
+          batch_butterfly_supported(prec, f.prog) && batch_butterfly_supported(prec, i.prog)) {
+        bub[2 * g] = std::move(f);
+        bub[2 * g + 1] = std::move(i);
+        breg[g] = 1;
+      }
+    }
   }
 
   // Large-signal engine: signals whose 16-signal tile does not fit LDS, or big leaf blocks.
@@ -270,6 +291,14 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       uoff[d][1] = blob.add(ub[d].scol.data(), ub[d].scol.size() * 4);
       uoff[d][2] = blob.add(ub[d].afrag.data(), ub[d].afrag.size() * 4);
       uoff[d][3] = blob.add(ub[d].flips.data(), ub[d].flips.size() * 4);
+    }
+  std::vector<size_t> boff(bub.size() * 4, 0);
+  for (size_t k = 0; k < bub.size(); ++k)
+    if (breg[k / 2]) {
+      boff[4 * k + 0] = blob.add(bub[k].gcol.data(), bub[k].gcol.size() * 4);
+      boff[4 * k + 1] = blob.add(bub[k].scol.data(), bub[k].scol.size() * 4);
+      boff[4 * k + 2] = blob.add(bub[k].afrag.data(), bub[k].afrag.size() * 4);
+      boff[4 * k + 3] = blob.add(bub[k].flips.data(), bub[k].flips.size() * 4);
     }
   LargeImage lgi[2];
   size_t loff[2][8] = {};
@@ -354,21 +383,39 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (plan->batch) {
     std::vector<DevProgram> arr;
     size_t maxlds = 0;
-    for (int g = 0; g < G; ++g) {
-      arr.push_back(img->fwd[g]);
-      maxlds = std::max(maxlds, program_lds_bytes(img->fwd[g]));
-    }
-    for (int g = 0; g < G; ++g) {
-      arr.push_back(img->inv[g]);
-      maxlds = std::max(maxlds, program_lds_bytes(img->inv[g]));
-    }
+    for (int d = 0; d < 2; ++d)
+      for (int g = 0; g < G; ++g) {
+        const DevProgram &P = d == 0 ? img->fwd[g] : img->inv[g];
+        arr.push_back(P);
+        if (!breg[g]) maxlds = std::max(maxlds, program_lds_bytes(P));
+      }
+    const bool any_reg = std::find(breg.begin(), breg.end(), 1) != breg.end();
+    std::vector<UProgram> uarr;
+    if (any_reg)
+      for (int d = 0; d < 2; ++d)
+        for (int g = 0; g < G; ++g) {
+          UProgram U{};   // S = 0: the graph runs its LDS program
+          if (breg[g]) {
+            const size_t k = (size_t)2 * g + d;
+            U = bub[k].prog;
+            U.gcol = reinterpret_cast<const int32_t *>(base + boff[4 * k + 0]);
+            U.scol = reinterpret_cast<const int32_t *>(base + boff[4 * k + 1]);
+            U.afrag = reinterpret_cast<const float *>(base + boff[4 * k + 2]);
+            U.flips = reinterpret_cast<const uint32_t *>(base + boff[4 * k + 3]);
+          }
+          uarr.push_back(U);
+        }
+    const size_t pbytes = arr.size() * sizeof(DevProgram);
+    const size_t ubytes = uarr.size() * sizeof(UProgram);
     void *parr = nullptr;
-    e = hipMalloc(&parr, arr.size() * sizeof(DevProgram));
+    e = hipMalloc(&parr, pbytes + ubytes);
     if (e != hipSuccess) {
       (void)hipFree(img->mem);
       return set_error(GFT_ERR_OOM, "hipMalloc of the batch program array failed");
     }
-    e = hipMemcpy(parr, arr.data(), arr.size() * sizeof(DevProgram), hipMemcpyHostToDevice);
+    e = hipMemcpy(parr, arr.data(), pbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ubytes)
+      e = hipMemcpy(static_cast<char *>(parr) + pbytes, uarr.data(), ubytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(parr);
       (void)hipFree(img->mem);
@@ -377,10 +424,18 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     img->mem2 = parr;
     img->dev_fwd = static_cast<const DevProgram *>(parr);
     img->dev_inv = img->dev_fwd + G;
-    img->batch_lds = batch_lds_bytes(G, maxlds);
+    if (any_reg) {
+      img->dev_ufwd = reinterpret_cast<const UProgram *>(static_cast<char *>(parr) + pbytes);
+      img->dev_uinv = img->dev_ufwd + G;
+    }
+    img->batch_lds = batch_lds_bytes(G, maxlds, any_reg);
+    const int occ = batch_occupancy(plan->opts.precision, img->batch_lds);
     // several rounds of resident workgroups: the hardware then hands the byte-equal shares
-    // to CUs as they free up, which evens out graphs of different cost per byte
-    img->batch_grid = kBatchRounds * img->num_cus * batch_occupancy(plan->opts.precision, img->batch_lds);
+    // of the LDS-program graphs to CUs as they free up, which evens out graphs of different
+    // cost per byte; the register phase runs on the first round, whose waves take longer
+    // shares (fewer per-graph start-ups)
+    img->batch_grid = kBatchRounds * img->num_cus * occ;
+    img->reg_groups = any_reg ? img->num_cus * occ : 0;
   }
   if (!plan->batch && !img->butterfly && !img->large && plan->opts.tile_override == 0)
     for (int d = 0; d < 2; ++d) {
@@ -566,10 +621,12 @@ static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *ou
   DeviceImage *img = nullptr;
   st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  hipError_t e = launch_apply_batch(plan->opts.precision, dir == 0 ? img->dev_fwd : img->dev_inv,
+  hipError_t e = launch_apply_batch(plan->opts.precision, dir, dir == 0 ? img->dev_fwd : img->dev_inv,
+                                    dir == 0 ? img->dev_ufwd : img->dev_uinv,
                                     (int)plan->graphs.size(), signal_offsets, total_elements,
                                     static_cast<const float *>(in), static_cast<float *>(out),
-                                    img->batch_lds, img->batch_grid, static_cast<hipStream_t>(stream));
+                                    img->batch_lds, img->batch_grid, img->reg_groups,
+                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
 }

@@ -12,6 +12,7 @@
 
 #include <cstdint>
 
+#include "butterfly_core.hpp"
 #include "device_program.hpp"
 #include "program.hpp"
 
@@ -399,73 +400,162 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
   __syncthreads();
 }
 
+// Register-butterfly programs the batch kernel runs (FP32 blocks; BF16 blocks on the
+// padded one-stage layout): S = 1 with M = 16 or 32, S = 2 with M = 16.
+template <int PREC, int DIR>
+__device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *in, float *out,
+                                                int64_t nsig, int64_t t0, int64_t t1, float *T) {
+  if constexpr (PREC == kFP32) {
+    if (U.S == 1 && U.M == 16) {
+      if (U.gen) bfly::butterfly_tiles<1, 16, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<1, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+    } else if (U.S == 1 && U.M == 32) {
+      if (U.gen) bfly::butterfly_tiles<1, 32, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<1, 32, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+    } else if (U.S == 2 && U.M == 16 && !U.gen) {
+      bfly::butterfly_tiles<2, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+    }
+  } else if constexpr (PREC == kBF16) {
+    if (U.gen && U.S == 1 && U.M == 16)
+      bfly::butterfly_tiles<1, 16, DIR, false, false, true, true>(U, in, out, nsig, t0, t1, 1, T);
+    else if (U.gen && U.S == 1 && U.M == 32)
+      bfly::butterfly_tiles<1, 32, DIR, false, false, true, true>(U, in, out, nsig, t0, t1, 1, T);
+  }
+}
+
 // Many graphs in one persistent launch.  Graph g owns signals [off[g], off[g+1]) and its
 // data starts at element elem[g] = sum_{h<g} (off[h+1]-off[h]) * n_h of in/out; each
 // workgroup first rebuilds elem[] in LDS from the device offsets (no host sync, no
-// workspace), then takes the tiles whose first element falls in its 1/gridDim share of
-// [0, elem[G]): a byte-balanced, contiguous partition.  Graphs whose data would end past
-// total_elems are skipped.  A workgroup reloads a program's tables into LDS only when it
-// moves to another graph.
-template <int PREC>
+// workspace), together with the prefix sums of the graphs each engine serves: those with a
+// register-butterfly program (uprogs[g].S > 0, or none when uprogs is null) and the rest.
+//   Register phase: the waves of the first reg_groups workgroups split the first class's
+//   elements into contiguous, byte-equal shares; a wave runs the 16-signal tiles whose
+//   first element lies in its share, graph by graph, through the butterfly tile loop.
+//   LDS-program phase: every workgroup takes the tiles (16 * mt signals) of the other
+//   graphs whose first element lies in its 1/gridDim share of their elements, and reloads
+//   a program's tables into LDS only when it moves to another graph.
+// Graphs whose data would end past total_elems are skipped.
+template <int PREC, int DIR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void gft_apply_batch(
-    const DevProgram *__restrict__ progs, int G, const int64_t *__restrict__ sig_off,
-    int64_t total_elems, const float *in, float *out) {
+    const DevProgram *__restrict__ progs, const UProgram *__restrict__ uprogs, int G,
+    const int64_t *__restrict__ sig_off, int64_t total_elems, const float *in, float *out,
+    int reg_groups) {
   extern __shared__ __attribute__((aligned(16))) int32_t smem[];
-  int64_t *elem = reinterpret_cast<int64_t *>(smem);          // G + 1 entries
-  int32_t *area = smem + 2 * ((G + 2) & ~1);                   // program area
+  const int GP = (G + 2) & ~1;                                 // G + 1 rounded to even
+  int64_t *elem = reinterpret_cast<int64_t *>(smem);           // all graphs
+  int64_t *elemR = elem + GP;                                  // register-program graphs
+  int64_t *elemL = elemR + GP;                                 // LDS-program graphs
+  int32_t *area = smem + 6 * GP;                               // program area / tiles
   // per-thread partial sums over contiguous chunks of graphs, an exclusive scan of the
   // kThreads partials (inclusive scans inside each wave by shuffles, then the wave totals),
-  // and a second pass writing elem[]
-  __shared__ int64_t wsum[kThreads / 64];
+  // and a second pass writing the prefix arrays
+  __shared__ int64_t wsum[2][kThreads / 64];
   const int per = (G + kThreads - 1) / kThreads;
   const int g0 = threadIdx.x * per, g1 = g0 + per < G ? g0 + per : G;
-  int64_t acc = 0;
-  for (int g = g0; g < g1; ++g) {
+  auto elems = [&](int g, bool &reg) -> int64_t {
     const int64_t ns = sig_off[g + 1] - sig_off[g];
-    acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+    reg = uprogs != nullptr && uprogs[g].S > 0;
+    return (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+  };
+  int64_t accA = 0, accR = 0;
+  for (int g = g0; g < g1; ++g) {
+    bool reg;
+    const int64_t e = elems(g, reg);
+    accA += e;
+    if (reg) accR += e;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t inc = acc;
+  int64_t incA = accA, incR = accR;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const int64_t o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
+    const int64_t oA = __shfl_up(incA, d, 64), oR = __shfl_up(incR, d, 64);
+    if (lane >= d) {
+      incA += oA;
+      incR += oR;
+    }
   }
-  if (lane == 63) wsum[wave] = inc;
+  if (lane == 63) {
+    wsum[0][wave] = incA;
+    wsum[1][wave] = incR;
+  }
   __syncthreads();
-  int64_t base = 0;
-  for (int w = 0; w < wave; ++w) base += wsum[w];
-  acc = base + inc - acc;                                      // exclusive prefix
-  for (int g = g0; g < g1; ++g) {
-    elem[g] = acc;
-    const int64_t ns = sig_off[g + 1] - sig_off[g];
-    acc += (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+  int64_t baseA = 0, baseR = 0;
+  for (int w = 0; w < wave; ++w) {
+    baseA += wsum[0][w];
+    baseR += wsum[1][w];
   }
-  if (threadIdx.x == kThreads - 1) elem[G] = acc;
+  accA = baseA + incA - accA;                                  // exclusive prefixes
+  accR = baseR + incR - accR;
+  for (int g = g0; g < g1; ++g) {
+    elem[g] = accA;
+    elemR[g] = accR;
+    elemL[g] = accA - accR;
+    bool reg;
+    const int64_t e = elems(g, reg);
+    accA += e;
+    if (reg) accR += e;
+  }
+  if (threadIdx.x == kThreads - 1) {
+    elem[G] = accA;
+    elemR[G] = accR;
+    elemL[G] = accA - accR;
+  }
   __syncthreads();
 
-  const int64_t E = elem[G];
+  // ---- register phase
+  if (uprogs != nullptr && (int)blockIdx.x < reg_groups) {
+    const int64_t ER = elemR[G];
+    const int64_t W = (int64_t)reg_groups * 4;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t e0 = (int64_t)(((__int128)ER * w) / W);
+    const int64_t e1 = (int64_t)(((__int128)ER * (w + 1)) / W);
+    if (e0 < e1) {
+      // graph holding element e0 of the class: last g with elemR[g] <= e0
+      int lo = 0, hi = G;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (elemR[mid] <= e0) lo = mid;
+        else hi = mid;
+      }
+      float *T = reinterpret_cast<float *>(area) + wave * bfly::tile_words<1, 32>();
+      for (int g = lo; g < G && elemR[g] < e1; ++g) {
+        const int64_t gb = elemR[g], ge = elemR[g + 1];
+        if (ge <= gb || elem[g + 1] > total_elems) continue;
+        const UProgram U = uprogs[g];
+        const int64_t te = 16 * (int64_t)U.n;                  // elements per tile
+        const int64_t t0 = e0 > gb ? (e0 - gb + te - 1) / te : 0;
+        const int64_t t1 = ((e1 < ge ? e1 : ge) - gb + te - 1) / te;
+        if (t0 < t1)
+          batch_butterfly<PREC, DIR>(U, in + elem[g], out + elem[g], (ge - gb) / U.n, t0, t1, T);
+      }
+    }
+  }
+  __syncthreads();   // the LDS-program phase reuses the tile regions
+
+  // ---- LDS-program phase
+  const int64_t E = elemL[G];
   const int64_t W = gridDim.x;
   const int64_t e0 = (int64_t)(((__int128)E * blockIdx.x) / W);
   const int64_t e1 = (int64_t)(((__int128)E * (blockIdx.x + 1)) / W);
   if (e0 >= e1) return;
-  // graph holding element e0: last g with elem[g] <= e0
+  // graph holding element e0 of the class: last g with elemL[g] <= e0
   int lo = 0, hi = G;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (elem[mid] <= e0) lo = mid;
+    if (elemL[mid] <= e0) lo = mid;
     else hi = mid;
   }
-  // The tiles this workgroup owns (first element in [e0, e1)), in order: (g, t) pairs.
-  // advance() moves (g, t) to the next owned tile at or after it and returns false when
-  // there is none; graphs that are empty or end past total_elems are skipped.
+  // The tiles this workgroup owns (first element in [e0, e1) of the class), in order:
+  // (g, t) pairs.  advance() moves (g, t) to the next owned tile at or after it and returns
+  // false when there is none; graphs that are empty, of the other class, or end past
+  // total_elems are skipped.
   auto advance = [&](int &g, int64_t &t) -> bool {
     while (g < G) {
-      const int64_t gbeg = elem[g], gend = elem[g + 1];
-      if (gend <= gbeg || gend > total_elems) {
+      const int64_t gbeg = elemL[g], gend = elemL[g + 1];
+      if (gend <= gbeg || elem[g + 1] > total_elems) {
         ++g;
         t = 0;
-        if (elem[g < G ? g : G] >= e1) return false;
+        if (elemL[g < G ? g : G] >= e1) return false;
         continue;
       }
       const int64_t tile_elems = (int64_t)16 * progs[g].mt * progs[g].n;
@@ -480,6 +570,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
     return false;
   };
+  // element offset in in/out and element count of tile t of graph g
   auto span = [&](int g, int64_t t, int64_t &start) -> int {
     const int64_t tile_elems = (int64_t)16 * progs[g].mt * progs[g].n;
     start = elem[g] + t * tile_elems;
@@ -613,46 +704,66 @@ hipError_t launch_apply(const DevProgram &P, const void *in, void *out, int64_t 
   }
 }
 
-size_t batch_lds_bytes(int G, size_t max_program_lds) {
-  return 8 * (size_t)((G + 2) & ~1) + max_program_lds;
+size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase) {
+  // three int64 prefix arrays of G + 1 entries (rounded to even), then the program area,
+  // which the register phase uses as four wave tile regions
+  const size_t reg = reg_phase ? 4 * sizeof(float) * (size_t)bfly::tile_words<1, 32>() : 0;
+  return 3 * 8 * (size_t)((G + 2) & ~1) + (max_program_lds > reg ? max_program_lds : reg);
 }
 
-template <int PREC>
-static hipError_t launch_batch_p(const DevProgram *progs, int G, const int64_t *sig_off,
-                                 int64_t total_elems, const float *in, float *out,
-                                 size_t lds, int grid, hipStream_t stream) {
-  if (lds + 8 * (kThreads / 64) > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC>,
+template <int PREC, int DIR>
+static hipError_t launch_batch_pd(const DevProgram *progs, const UProgram *uprogs, int G,
+                                  const int64_t *sig_off, int64_t total_elems, const float *in,
+                                  float *out, size_t lds, int grid, int reg_groups,
+                                  hipStream_t stream) {
+  if (lds + 16 * (kThreads / 64) > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC, DIR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((gft_apply_batch<PREC>), dim3(grid), dim3(kThreads), lds, stream, progs, G,
-                     sig_off, total_elems, in, out);
+  hipLaunchKernelGGL((gft_apply_batch<PREC, DIR>), dim3(grid), dim3(kThreads), lds, stream, progs,
+                     uprogs, G, sig_off, total_elems, in, out, reg_groups);
   return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_batch_p(int dir, const DevProgram *progs, const UProgram *uprogs, int G,
+                                 const int64_t *sig_off, int64_t total_elems, const float *in,
+                                 float *out, size_t lds, int grid, int reg_groups,
+                                 hipStream_t stream) {
+  return dir == 0 ? launch_batch_pd<PREC, 0>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream)
+                  : launch_batch_pd<PREC, 1>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
 }
 
 int batch_occupancy(int prec, size_t lds) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (prec) {
-    case kFP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP32>, kThreads, lds); break;
-    case kBF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kBF16>, kThreads, lds); break;
-    case kFP16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP16>, kThreads, lds); break;
-    case kSPLIT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kSPLIT>, kThreads, lds); break;
+    case kFP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP32, 0>, kThreads, lds); break;
+    case kBF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kBF16, 0>, kThreads, lds); break;
+    case kFP16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kFP16, 0>, kThreads, lds); break;
+    case kSPLIT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gft_apply_batch<kSPLIT, 0>, kThreads, lds); break;
     default: break;
   }
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 
-hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const int64_t *sig_off,
-                              int64_t total_elems, const float *in, float *out, size_t lds,
-                              int grid, hipStream_t stream) {
+bool batch_butterfly_supported(int prec, const UProgram &U) {
+  if (prec == kFP32)
+    return (U.S == 1 && (U.M == 16 || U.M == 32)) || (U.S == 2 && U.M == 16 && !U.gen);
+  if (prec == kBF16) return U.gen && U.S == 1 && (U.M == 16 || U.M == 32);
+  return false;
+}
+
+hipError_t launch_apply_batch(int prec, int dir, const DevProgram *progs, const UProgram *uprogs,
+                              int G, const int64_t *sig_off, int64_t total_elems, const float *in,
+                              float *out, size_t lds, int grid, int reg_groups, hipStream_t stream) {
   switch (prec) {
-    case kFP32: return launch_batch_p<kFP32>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
-    case kBF16: return launch_batch_p<kBF16>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
-    case kFP16: return launch_batch_p<kFP16>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
-    case kSPLIT: return launch_batch_p<kSPLIT>(progs, G, sig_off, total_elems, in, out, lds, grid, stream);
+    case kFP32: return launch_batch_p<kFP32>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
+    case kBF16: return launch_batch_p<kBF16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
+    case kFP16: return launch_batch_p<kFP16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
+    case kSPLIT: return launch_batch_p<kSPLIT>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
     default: return hipErrorInvalidValue;
   }
 }

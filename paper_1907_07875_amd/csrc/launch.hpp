@@ -16,12 +16,15 @@ hipError_t launch_apply(const DevProgram &P, const void *in, void *out, int64_t 
 // Resident workgroups per CU of the apply kernel for this program's LDS footprint.
 int apply_occupancy(const DevProgram &P);
 
-// Mixed batch: G programs (device array `progs`) in one persistent launch.
-size_t batch_lds_bytes(int G, size_t max_program_lds);
+// Mixed batch: G programs (device array `progs`) in one persistent launch; graphs with a
+// register-butterfly program (device array `uprogs`, entry S = 0 for the others; or null)
+// run on the first reg_groups workgroups' waves, the rest on the LDS programs.
+size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase);
 int batch_occupancy(int prec, size_t lds);
-hipError_t launch_apply_batch(int prec, const DevProgram *progs, int G, const int64_t *sig_off,
-                              int64_t total_elems, const float *in, float *out, size_t lds,
-                              int grid, hipStream_t stream);
+bool batch_butterfly_supported(int prec, const UProgram &U);
+hipError_t launch_apply_batch(int prec, int dir, const DevProgram *progs, const UProgram *uprogs,
+                              int G, const int64_t *sig_off, int64_t total_elems, const float *in,
+                              float *out, size_t lds, int grid, int reg_groups, hipStream_t stream);
 
 // Large-signal engine.
 int permute_rows(const PermPass &P);   // signal rows per LDS tile of a stage/gather pass

@@ -60,19 +60,46 @@ def test_config4_mixed_batch_forward_inverse():
     assert O.relative_error(xr, flat.astype(np.float64)) <= 2e-5
 
 
-def test_batch_matches_single_graph_generic_plans():
+def _batch_engine(g):
+    """The engine a batch plan runs graph g on: the register-butterfly forms the batch kernel
+    compiles (one stage with 16- or 32-slot sides, or the 2-stage 16-node hypercube), else
+    the LDS program."""
+    try:
+        p = G.Plan.from_graph(g, engine="butterfly")
+        p.prepare()
+    except G.GFTError:
+        return "generic"
+    return "generic" if len(g.stages) > 2 else "butterfly"
+
+
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_batch_matches_single_graph_plans(direction):
+    """Each graph's slice of a mixed batch equals its single-graph plan: bit for bit on the
+    register-butterfly engine (the same tile loop), to rounding on the LDS-program engine;
+    with the generic engine forced the whole batch runs LDS programs and matches too."""
     dev = device()
     rng = wl.rng_for(4, 2)
-    graphs = [wl.path(7), wl.grid(8, 8), wl.config3_graph(), wl.cycle(13), wl.path(64),
-              wl.symmetric_bipartite(72, wl.rng_for(4, 72)), wl.grid(5, 5)]
-    counts = np.array([1, 300, 47, 16, 1000, 33, 5])
-    plan = G.gft_plan_batch(graphs)
+    graphs = [wl.path(7), wl.path(8), wl.grid(8, 8), wl.config3_graph(), wl.cycle(13), wl.path(64),
+              wl.symmetric_bipartite(72, wl.rng_for(4, 72)), wl.grid(5, 5), wl.cycle(48), wl.path(44),
+              wl.symmetric_bipartite(40, wl.rng_for(4, 40)), wl.cycle(22)]
+    counts = np.array([1, 17, 300, 47, 16, 1000, 33, 5, 129, 77, 250, 3])
+    engines = [_batch_engine(g) for g in graphs]
+    assert engines.count("butterfly") >= 8 and engines.count("generic") >= 3, engines
     xs, flat, off = _pack(graphs, counts, rng)
-    y = to_np(G.gft_forward_batch(plan, torch.from_numpy(flat).to(dev), torch.from_numpy(off).to(dev)))
-    for (a, b), g, xg in zip(_slices(graphs, counts), graphs, xs):
-        single = G.Plan.from_graph(g, engine="generic")
-        ys = to_np(single.forward(torch.from_numpy(xg).to(dev))).reshape(-1)
-        np.testing.assert_allclose(y[a:b], ys, rtol=0, atol=1e-6 * max(1.0, np.abs(ys).max()))
+    offs = torch.from_numpy(off).to(dev)
+    apply = G.gft_forward_batch if direction == "forward" else G.gft_inverse_batch
+    for forced in ("auto", "generic"):
+        plan = G.gft_plan_batch(graphs, engine=forced)
+        y = to_np(apply(plan, torch.from_numpy(flat).to(dev), offs))
+        for (a, b), g, xg, eng in zip(_slices(graphs, counts), graphs, xs, engines):
+            eng = "generic" if forced == "generic" else eng
+            single = G.Plan.from_graph(g, engine=eng)
+            xt = torch.from_numpy(xg).to(dev)
+            ys = to_np(single.forward(xt) if direction == "forward" else single.inverse(xt)).reshape(-1)
+            if eng == "butterfly":
+                assert np.array_equal(y[a:b], ys), f"{g.name}{g.n}: batch register phase differs"
+            else:
+                np.testing.assert_allclose(y[a:b], ys, rtol=0, atol=1e-6 * max(1.0, np.abs(ys).max()))
 
 
 def test_batch_respects_total_elements_and_empty():
