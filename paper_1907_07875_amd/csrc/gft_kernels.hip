@@ -401,7 +401,9 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
 }
 
 // Register-butterfly programs the batch kernel runs (FP32 blocks; BF16 blocks on the
-// padded one-stage layout): S = 1 with M = 16 or 32, S = 2 with M = 16.
+// padded one-stage layout): S = 1 with M = 16 or 32, S = 2 with M = 16.  (48-slot sides
+// would raise the whole kernel's register count past the point where it spills.)
+constexpr int kBatchTileWords = bfly::tile_words<1, 32>();   // the largest of these
 template <int PREC, int DIR>
 __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *in, float *out,
                                                 int64_t nsig, int64_t t0, int64_t t1, float *T) {
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         if (elemR[mid] <= e0) lo = mid;
         else hi = mid;
       }
-      float *T = reinterpret_cast<float *>(area) + wave * bfly::tile_words<1, 32>();
+      float *T = reinterpret_cast<float *>(area) + wave * kBatchTileWords;
       for (int g = lo; g < G && elemR[g] < e1; ++g) {
         const int64_t gb = elemR[g], ge = elemR[g + 1];
         if (ge <= gb || elem[g + 1] > total_elems) continue;
@@ -707,7 +709,7 @@ hipError_t launch_apply(const DevProgram &P, const void *in, void *out, int64_t 
 size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase) {
   // three int64 prefix arrays of G + 1 entries (rounded to even), then the program area,
   // which the register phase uses as four wave tile regions
-  const size_t reg = reg_phase ? 4 * sizeof(float) * (size_t)bfly::tile_words<1, 32>() : 0;
+  const size_t reg = reg_phase ? 4 * sizeof(float) * (size_t)kBatchTileWords : 0;
   return 3 * 8 * (size_t)((G + 2) & ~1) + (max_program_lds > reg ? max_program_lds : reg);
 }
 

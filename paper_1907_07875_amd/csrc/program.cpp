@@ -249,12 +249,12 @@ bool build_program(const GraphPlan &p, int direction, int tile_override, size_t 
 namespace gft {
 
 // One-stage plans that are not uniform hypercubes (fixed nodes V_Z, blocks of unequal size
-// or split into components, 8 <= n <= 64): orbit o holds the o-th V_X node (or, past
+// or split into components, 8 <= n <= 96): orbit o holds the o-th V_X node (or, past
 // the pairs, the V_Z nodes) in slot 0 and its partner in slot 1 (a zero word for V_Z and
 // padding), so the register Haar gives the G+ input (x + x') and the G- input (x - x').  G+
-// (V_X then V_Z positions) and G- (V_Y positions) are each one zero-padded block of M = 16 or
-// 32 rows holding their leaf blocks on the diagonal; the sqrt 2 of a V_Z node is folded into
-// its G+ row (the kernel's Haar adds a zero to it).  Slot 0 always holds the V_X node, so no
+// (V_X then V_Z positions) and G- (V_Y positions) are each one zero-padded block of M = 16, 32
+// or 48 rows holding their leaf blocks on the diagonal; the sqrt 2 of a V_Z node is folded
+// into its G+ row (the kernel's Haar adds a zero to it).  Slot 0 always holds the V_X node, so no
 // sign flips.
 static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgramImage &out,
                                       int precision) {
@@ -263,7 +263,8 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
   const HostStage &st = p.stages[0];
   const int P = (int)st.pair_x.size(), Z = (int)st.znodes.size();
   const int pp = P + Z;                        // |G+|
-  const int M = std::max(pp, P) <= 16 ? 16 : (std::max(pp, P) <= 32 ? 32 : 0);
+  const int wide = std::max(pp, P);
+  const int M = wide <= 16 ? 16 : (wide <= 32 ? 32 : (wide <= 48 ? 48 : 0));
   if (M == 0 || 2 * P + Z != n) return false;
   std::vector<int> plus_node(pp), minus_node(P), side(n, -1), ppos(n, -1);
   for (int u = 0; u < P; ++u) {

@@ -266,12 +266,16 @@ def test_searched_pairings_parity(g):
 
 
 # n odd and n = 2 mod 4 keep the signals' own LDS layout; n = 0 mod 8 and n = 4 mod 8 pad the
-# rows (to n + 4 and n + 8; n = 60 reaches the largest padded tile of 32-slot sides)
+# rows (to n + 4 and n + 8; n = 60 and 92 reach the largest padded tiles of 32- and 48-slot
+# sides)
 ONE_STAGE_GRAPHS = [wl.config3_graph(), wl.path(17), wl.cycle(31), wl.path(63),
                     wl.weighted_symmetric_path(33, wl.rng_for(9, 33)), wl.path(8), wl.path(12),
                     wl.cycle(22), wl.path(40), wl.path(44), wl.cycle(48), wl.cycle(60),
                     wl.symmetric_bipartite(40, wl.rng_for(4, 40)),
-                    wl.weighted_symmetric_path(36, wl.rng_for(9, 36))]
+                    wl.weighted_symmetric_path(36, wl.rng_for(9, 36)),
+                    # 48-slot sides
+                    wl.path(72), wl.cycle(84), wl.cycle(92), wl.symmetric_bipartite(72, wl.rng_for(4, 72)),
+                    wl.weighted_symmetric_path(90, wl.rng_for(9, 90))]
 
 
 @pytest.mark.parametrize("S", [1, 15, 17, 1003])
