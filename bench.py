@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--signals", type=int, default=None, help="override the signal count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly", "product"],
+                    help="product: the 64x64 grid as a product plan of two 64-node paths")
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "split_bf16"])
     ap.add_argument("--io", default="fp32", choices=["fp32", "bf16"],
                     help="storage type of signals and coefficients (single-graph workloads)")
@@ -161,8 +162,9 @@ def _c(ptr):
 
 
 def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, sample_desc,
-                 kernel_names=None, flops_per_signal=None):
-    """Shared body of the single-graph workloads."""
+                 kernel_names=None, flops_per_signal=None, make_plan=None):
+    """Shared body of the single-graph workloads (make_plan: builds the plan instead of
+    planning `graph`, which then only serves the oracle)."""
     import torch
 
     import paper_1907_07875_amd as G
@@ -183,8 +185,8 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
         print(json.dumps({"copy_bytes_per_launch": 2 * xa.numel() * esz}))
         return
 
-    plan = G.Plan.from_graph(graph, engine=args.engine, precision=precision,
-                             in_dtype=args.io, out_dtype=args.io)
+    plan = make_plan() if make_plan else G.Plan.from_graph(graph, engine=args.engine, precision=precision,
+                                                           in_dtype=args.io, out_dtype=args.io)
     plan.prepare()
     eng = plan.engine()
     tiles = plan.tiles()
@@ -345,8 +347,33 @@ def _large_workload(args, graph, S, name, desc):
 
 def bench_grid64(args):
     import workloads as wl
+    if args.engine == "product":
+        return bench_grid64_product(args)
     _large_workload(args, wl.config5a_graph(), args.signals or 65536, "grid64x64_fwd_inv",
                     "64x64 grid, LR/UD reversals recursed on the + branch (12 stages)")
+
+
+def bench_grid64_product(args):
+    """The same 64x64 grid planned as the Cartesian product path64 x path64 (each axis with
+    its 6 halving reversal stages): separable factor GFTs, y = U_a^T X U_b per signal."""
+    import paper_1907_07875_amd as G
+    import workloads as wl
+    if (args.precision or "fp32") != "fp32" or args.io != "fp32":
+        sys.exit("product plans run FP32 (precision and storage)")
+    S = args.signals or 65536
+    axis = wl.path_recursive(64)
+    graph = wl.cartesian_product(axis, axis, name="grid64x64")
+    X = wl.gaussian(S, graph.n, wl.rng_for(5, 7))
+    bench_single(args, graph, X, "fp32",
+                 {"workload": "grid64x64_product_fwd_inv",
+                  "graph": "64x64 grid as path64 x path64, halving reversal stages per axis (6 + 6)",
+                  "factor_gfts": "two dense 64x64 FP32 factor GFTs per signal (separable)",
+                  "dense_flops_per_signal": 2.0 * graph.n * graph.n,
+                  "fast_flops_per_signal": 2.0 * graph.n * (64 + 64)},
+                 256, "first 256 signals of the same workload",
+                 kernel_names={"product": "gft_product<64,64,0>"},
+                 flops_per_signal=2.0 * graph.n * (64 + 64),
+                 make_plan=lambda: G.Plan.from_product(axis, axis))
 
 
 def bench_wpath(args):

@@ -137,13 +137,15 @@ typedef enum {
   GFT_ENGINE_GENERIC = 1,     /* LDS-program engine (one fused kernel)                  */
   GFT_ENGINE_BUTTERFLY = 2,   /* register-butterfly engine (else GFT_ERR_UNSUPPORTED at  */
                               /* the first apply)                                       */
-  GFT_ENGINE_LARGE = 3        /* large-signal engine: Haar stages and permutations in    */
+  GFT_ENGINE_LARGE = 3,       /* large-signal engine: Haar stages and permutations in    */
                               /* streaming passes, leaf blocks as MFMA GEMM tiles over a */
                               /* stream-ordered workspace (hipMallocAsync, freed in      */
                               /* stream order) of S*w floats (2*S*w when the last pass   */
                               /* has Haar stages or there are more than 8 leaf blocks),  */
                               /* w = n plus each leaf block padded to                    */
                               /* a multiple of 8; FP16 is unsupported                    */
+  GFT_ENGINE_PRODUCT = 4      /* reported for product-graph plans (gft_plan_product);    */
+                              /* not an options.engine value                             */
 } gft_engine;
 
 typedef struct {
@@ -209,6 +211,23 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
                           const gft_pairing *pairings, const gft_options *opts,
                           gft_plan_t *out);
 
+/* Build a plan for the Cartesian product G_a x G_b of two graphs (node (i, j) has label
+ * i * n_b + j; edges (i, j)-(i', j) of weight w_a(i, i') and (i, j)-(i, j') of weight
+ * w_b(j, j'); self-loop s_a(i) + s_b(j)).  Its Laplacian is L_a (x) I + I (x) L_b, so the
+ * Kronecker product U_a (x) U_b of the factor GFTs is a GFT of the product (eigenvalue
+ * lambda_p + mu_q for basis vector (p, q)): the separable form of the grid GFTs of
+ * Sec. V-D, whose axis-wise stages leave leaf blocks that are Kronecker products of the
+ * axes' leaves.  Each factor is planned as by gft_plan (its stages, if any, shape its
+ * basis); the transform runs as y = U_a^T X U_b per signal X (n_a x n_b, row-major), the
+ * factors applied as dense FP32 matrices on MFMA, then the coefficients in output order
+ * (ascending lambda_p + mu_q, ties by p then q; GFT_ORDER_BLOCK: p * n_b + q).
+ * Requires n_a, n_b <= 64, FP32 precision and storage, the combinatorial Laplacian and
+ * options.engine 0 (else GFT_ERR_UNSUPPORTED).  gft_plan_info reports the two factor GFTs
+ * as num_blocks = 2 with their dense costs; gft_plan_blocks is unsupported.  Host-only. */
+gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing_a,
+                            const gft_graph *graph_b, const gft_pairing *pairing_b,
+                            const gft_options *opts, gft_plan_t *out);
+
 /* y = U^T x for num_signals signals (coefficients; Sec. II-B).
  * x: device, num_signals x n values of options.in_dtype (FP32 unless set), 16-byte
  * aligned.  y: device, num_signals x n values of options.out_dtype, 16-byte aligned;
@@ -239,7 +258,8 @@ gft_status gft_inverse_batch(gft_plan_t plan, const void *y, void *x,
  * a hipGraph.  Needs a GPU. */
 gft_status gft_plan_prepare(gft_plan_t plan);
 
-/* Engine (gft_engine: GFT_ENGINE_GENERIC, GFT_ENGINE_BUTTERFLY or GFT_ENGINE_LARGE) the
+/* Engine (gft_engine: GFT_ENGINE_GENERIC, GFT_ENGINE_BUTTERFLY, GFT_ENGINE_LARGE or
+ * GFT_ENGINE_PRODUCT) the
  * plan's image on the current device runs; builds the image like gft_plan_prepare.
  * Needs a GPU. */
 gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
@@ -248,7 +268,8 @@ gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
  * plans; builds the image like gft_plan_prepare): the generic engine's tile height, which
  * options.tile_override fixes or, when it is 0, the plan-time autotuner picks by timing
  * every height that fits in LDS on a synthetic batch (same results for every height);
- * 16 for the butterfly engine (per wave); 0 for the large-signal engine.  Needs a GPU. */
+ * 16 for the butterfly engine (per wave); 0 for the large-signal engine; 1 for product
+ * plans (one signal per wave).  Needs a GPU. */
 gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */

@@ -34,7 +34,7 @@ STATUS = {
 EXPORTS = [
     "gft_plan", "gft_plan_batch", "gft_forward", "gft_inverse", "gft_forward_batch",
     "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_tiles", "gft_plan_info", "gft_plan_num_graphs",
-    "gft_find_pairing",
+    "gft_find_pairing", "gft_plan_product",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version",
 ]
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "gft_plan": ([ctypes.POINTER(_Graph), ctypes.POINTER(_Pairing), ctypes.POINTER(_Options), pp], i32),
         "gft_plan_batch": ([i32, ctypes.POINTER(_Graph), ctypes.POINTER(_Pairing), ctypes.POINTER(_Options), pp], i32),
+        "gft_plan_product": ([ctypes.POINTER(_Graph), ctypes.POINTER(_Pairing), ctypes.POINTER(_Graph),
+                              ctypes.POINTER(_Pairing), ctypes.POINTER(_Options), pp], i32),
         "gft_forward": ([P, P, P, i64, P], i32),
         "gft_inverse": ([P, P, P, i64, P], i32),
         "gft_forward_batch": ([P, P, P, P, i64, P], i32),
@@ -203,6 +205,11 @@ class Plan:
                         engine=engine, in_dtype=in_dtype, out_dtype=out_dtype, laplacian=laplacian,
                         right_haar=right_haar)
 
+    @classmethod
+    def from_product(cls, graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, right_haar=True):
+        """Plan the Cartesian product of two graphs (node (i, j) = i * graph_b.n + j)."""
+        return gft_plan_product(graph_a, graph_b, order=order, sym_tol=sym_tol, right_haar=right_haar)
+
     @property
     def n(self) -> int:
         return self.sizes[0]
@@ -262,10 +269,10 @@ class Plan:
         _check(load_library().gft_plan_prepare(self._h))
 
     def engine(self) -> str:
-        """Kernel family the plan runs on the current device ("generic" or "butterfly")."""
+        """Kernel family the plan runs on the current device."""
         e = ctypes.c_int32()
         _check(load_library().gft_plan_engine(self._h, ctypes.byref(e)))
-        return {1: "generic", 2: "butterfly", 3: "large"}[e.value]
+        return {1: "generic", 2: "butterfly", 3: "large", 4: "product"}[e.value]
 
     def tiles(self):
         """(forward, inverse) signals per tile on the current device (0 = large engine)."""
@@ -294,6 +301,24 @@ def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
+
+
+def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, right_haar=True,
+                     precision="fp32", laplacian="combinatorial", engine="auto") -> Plan:
+    """Plan the GFT of the Cartesian product of two graphs (C: ``gft_plan_product``): each
+    argument is an object with n, src, dst, weight, self_loop, stages."""
+    lib = load_library()
+    keep = []
+    ga = _graph_struct(graph_a.n, graph_a.src, graph_a.dst, graph_a.weight, graph_a.self_loop, keep)
+    pa = _pairing_struct(graph_a.n, graph_a.stages, keep)
+    gb = _graph_struct(graph_b.n, graph_b.src, graph_b.dst, graph_b.weight, graph_b.self_loop, keep)
+    pb = _pairing_struct(graph_b.n, graph_b.stages, keep)
+    o = _options(precision=precision, order=order, sym_tol=sym_tol, engine=engine,
+                 laplacian=laplacian, right_haar=right_haar)
+    h = ctypes.c_void_p()
+    _check(lib.gft_plan_product(ctypes.byref(ga), ctypes.byref(pa), ctypes.byref(gb), ctypes.byref(pb),
+                                ctypes.byref(o), ctypes.byref(h)))
+    return Plan(h.value, [int(graph_a.n) * int(graph_b.n)], False, "fp32", "fp32", "fp32")
 
 
 def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_steps=0,

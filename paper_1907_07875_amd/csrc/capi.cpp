@@ -47,6 +47,9 @@ struct DeviceImage {
   // large-signal engine (single-graph plans)
   bool large = false;
   LargeImage lg[2];
+  // product-graph plans: the two factor matrices and the output permutation per direction
+  bool product = false;
+  PProgram pfwd{}, pinv{};
   // batch plans: device arrays of the G forward and G inverse programs, and of their
   // register-butterfly programs (S = 0 where a graph runs its LDS program; null if none)
   const DevProgram *dev_fwd = nullptr, *dev_inv = nullptr;
@@ -73,6 +76,13 @@ struct gft_plan_s {
   std::vector<GraphPlan> graphs;
   gft_options opts{};
   bool batch = false;
+  // Product-graph plans: graphs[0] describes the product (n, eigenvalues, statistics); the
+  // factor plans and factor bases (node i of basis vector k at [i * n + k], FP64) act along
+  // the two axes; order[k] = p * nb + q gives the factor indices of output coefficient k.
+  bool product = false;
+  GraphPlan fa, fb;
+  std::vector<double> ua, ub;
+  std::vector<int32_t> order;
   std::mutex mu;
   std::map<int, std::unique_ptr<DeviceImage>> images;
 
@@ -187,6 +197,68 @@ void autotune_generic(DeviceImage *img, int dir, size_t budget, bool in16, bool 
   (void)hipFree(buf);
 }
 
+// Device image of a product-graph plan on device `dev` (caller holds plan->mu): per
+// direction the zero-padded factor matrices (forward B = U_b, A = U_a^T; inverse B = U_b^T,
+// A = U_a) and the LDS word of every output-order coefficient.
+gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(CU count)");
+  const int na = plan->fa.n, nb = plan->fb.n, n = na * nb;
+  const int NA = product_pad(na), NB = product_pad(nb), stride = NB + 1;
+  Blob blob;
+  size_t off[2][3];
+  for (int d = 0; d < 2; ++d) {
+    std::vector<float> A((size_t)NA * NA, 0.0f), B((size_t)NB * NB, 0.0f);
+    for (int i = 0; i < na; ++i)
+      for (int k = 0; k < na; ++k) {
+        const float u = (float)plan->ua[(size_t)i * na + k];   // node i of vector k
+        if (d == 0) A[(size_t)k * NA + i] = u;
+        else A[(size_t)i * NA + k] = u;
+      }
+    for (int j = 0; j < nb; ++j)
+      for (int q = 0; q < nb; ++q) {
+        const float u = (float)plan->ub[(size_t)j * nb + q];
+        if (d == 0) B[(size_t)j * NB + q] = u;
+        else B[(size_t)q * NB + j] = u;
+      }
+    std::vector<uint16_t> perm(n);
+    for (int k = 0; k < n; ++k) {
+      const int p = plan->order[k] / nb, q = plan->order[k] % nb;
+      perm[k] = (uint16_t)(p * stride + q);
+    }
+    off[d][0] = blob.add(A.data(), A.size() * 4);
+    off[d][1] = blob.add(B.data(), B.size() * 4);
+    off[d][2] = blob.add(perm.data(), perm.size() * 2);
+  }
+  auto img = std::make_unique<DeviceImage>();
+  img->device = dev;
+  img->num_cus = std::max(1, cus);
+  e = hipMalloc(&img->mem, blob.bytes.size());
+  if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMalloc of the plan image failed");
+  e = hipMemcpy(img->mem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(img->mem);
+    return set_error(GFT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  const char *base = static_cast<const char *>(img->mem);
+  PProgram *dst[2] = {&img->pfwd, &img->pinv};
+  for (int d = 0; d < 2; ++d) {
+    PProgram &P = *dst[d];
+    P.na = na;
+    P.nb = nb;
+    P.dir = d;
+    P.stride = stride;
+    P.amat = reinterpret_cast<const float *>(base + off[d][0]);
+    P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
+    P.perm = reinterpret_cast<const uint16_t *>(base + off[d][2]);
+  }
+  img->product = true;
+  *out = img.get();
+  plan->images[dev] = std::move(img);
+  return GFT_OK;
+}
+
 // Get (building on first use) the image of `plan` on the current device.
 gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   int dev = -1;
@@ -198,6 +270,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     *out = it->second.get();
     return GFT_OK;
   }
+  if (plan->product) return product_image(plan, dev, out);
   int max_lds = 0, cus = 0;
   e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(shared memory)");
@@ -477,7 +550,10 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   st = device_image(plan, &img);
   if (st != GFT_OK) return st;
   hipError_t e;
-  if (img->large) {
+  if (img->product) {
+    e = launch_product(dir == 0 ? img->pfwd : img->pinv, static_cast<const float *>(in),
+                       static_cast<float *>(out), S, static_cast<hipStream_t>(stream), img->num_cus);
+  } else if (img->large) {
     const LargeImage &L = img->lg[dir];
     const hipStream_t st = static_cast<hipStream_t>(stream);
     // With no Haar stage in pass 3 and few leaf blocks the GEMM writes the final positions
@@ -513,6 +589,60 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   }
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
+}
+
+// FP64 fast basis of a graph plan: U[i * n + k] is node i of basis vector k (column k is the
+// inverse transform of the unit coefficient vector e_k, run block-locally).
+std::vector<double> plan_basis(const GraphPlan &g) {
+  const int n = g.n;
+  std::vector<double> U((size_t)n * n, 0.0), e(n, 0.0), col(n);
+  for (int k = 0; k < n; ++k) {
+    e[k] = 1.0;
+    apply_host(g, 1, e.data(), col.data(), 1);
+    e[k] = 0.0;
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + k] = col[i];
+  }
+  return U;
+}
+
+// FP64 separable application of a product plan: forward y_k = (U_a^T X U_b)[p][q] with
+// (p, q) = order[k]; inverse X = U_a Y U_b^T.
+void product_apply_host(const gft_plan_s &P, int direction, const double *x, double *y, int64_t S) {
+  const int na = P.fa.n, nb = P.fb.n, n = na * nb;
+  std::vector<double> Z((size_t)n), T((size_t)n);
+  for (int64_t s = 0; s < S; ++s) {
+    const double *in = x + s * n;
+    double *out = y + s * n;
+    if (direction == 0) {
+      for (int p = 0; p < na; ++p)                       // T = U_a^T X
+        for (int j = 0; j < nb; ++j) {
+          double acc = 0.0;
+          for (int i = 0; i < na; ++i) acc += P.ua[(size_t)i * na + p] * in[(size_t)i * nb + j];
+          T[(size_t)p * nb + j] = acc;
+        }
+      for (int p = 0; p < na; ++p)                       // Z = T U_b
+        for (int q = 0; q < nb; ++q) {
+          double acc = 0.0;
+          for (int j = 0; j < nb; ++j) acc += T[(size_t)p * nb + j] * P.ub[(size_t)j * nb + q];
+          Z[(size_t)p * nb + q] = acc;
+        }
+      for (int k = 0; k < n; ++k) out[k] = Z[P.order[k]];
+    } else {
+      for (int k = 0; k < n; ++k) Z[P.order[k]] = in[k];
+      for (int i = 0; i < na; ++i)                       // T = U_a Y
+        for (int q = 0; q < nb; ++q) {
+          double acc = 0.0;
+          for (int p = 0; p < na; ++p) acc += P.ua[(size_t)i * na + p] * Z[(size_t)p * nb + q];
+          T[(size_t)i * nb + q] = acc;
+        }
+      for (int i = 0; i < na; ++i)                       // X = T U_b^T
+        for (int j = 0; j < nb; ++j) {
+          double acc = 0.0;
+          for (int q = 0; q < nb; ++q) acc += T[(size_t)i * nb + q] * P.ub[(size_t)j * nb + q];
+          out[(size_t)i * nb + j] = acc;
+        }
+    }
+  }
 }
 
 gft_status get_graph(gft_plan_t plan, int32_t index, const GraphPlan **g) {
@@ -600,6 +730,72 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs, const gft
   return ok();
 }
 
+gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing_a,
+                            const gft_graph *graph_b, const gft_pairing *pairing_b,
+                            const gft_options *opts, gft_plan_t *out) {
+  if (!out) return set_error(GFT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!graph_a || !graph_b) return set_error(GFT_ERR_INVALID_ARG, "graph_a and graph_b must be non-NULL");
+  const gft_options o = default_options(opts);
+  gft_status st = check_options(o);
+  if (st != GFT_OK) return st;
+  if (o.precision != GFT_FP32)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans run FP32 factor products");
+  if (o.in_dtype != GFT_DTYPE_FP32 || o.out_dtype != GFT_DTYPE_FP32)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans read and write FP32 storage");
+  if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL)
+    return set_error(GFT_ERR_UNSUPPORTED,
+                     "the normalized Laplacian of a product graph is not a Kronecker sum");
+  if (o.engine != GFT_ENGINE_AUTO)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans run their own engine (options.engine must be 0)");
+  try {
+    auto p = std::make_unique<gft_plan_s>();
+    p->opts = o;
+    p->product = true;
+    try {
+      p->fa = build_graph_plan(*graph_a, pairing_a, o);
+    } catch (const PlanError &err) {
+      return set_error(err.status, "graph_a: " + err.message);
+    }
+    try {
+      p->fb = build_graph_plan(*graph_b, pairing_b, o);
+    } catch (const PlanError &err) {
+      return set_error(err.status, "graph_b: " + err.message);
+    }
+    const int na = p->fa.n, nb = p->fb.n, n = na * nb;
+    if (na > 64 || nb > 64)
+      return set_error(GFT_ERR_UNSUPPORTED, "product plans take factors of at most 64 nodes");
+    p->ua = plan_basis(p->fa);
+    p->ub = plan_basis(p->fb);
+    // eigenvalue of basis vector (p, q): lambda_p + mu_q; output order ascending (ties by p,
+    // then q) or, with GFT_ORDER_BLOCK, (p, q) in row-major order
+    std::vector<double> lam((size_t)n);
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < nb; ++b) lam[(size_t)a * nb + b] = p->fa.lambda_out[a] + p->fb.lambda_out[b];
+    p->order.resize(n);
+    for (int k = 0; k < n; ++k) p->order[k] = k;
+    if (o.order == GFT_ORDER_EIGENVALUE)
+      std::stable_sort(p->order.begin(), p->order.end(),
+                       [&](int32_t u, int32_t v) { return lam[u] < lam[v]; });
+    GraphPlan g;
+    g.n = n;
+    g.lambda_out.resize(n);
+    for (int k = 0; k < n; ++k) g.lambda_out[k] = lam[p->order[k]];
+    g.stats.n = n;
+    g.stats.num_blocks = 2;                 // the two factor GFTs, applied as dense matrices
+    g.stats.max_block = std::max(na, nb);
+    g.stats.mults = (int64_t)n * (na + nb);
+    g.stats.adds = (int64_t)n * (na - 1 + nb - 1);
+    g.stats.max_residual = std::max(p->fa.stats.max_residual, p->fb.stats.max_residual);
+    g.stats.max_orth_error = std::max(p->fa.stats.max_orth_error, p->fb.stats.max_orth_error);
+    p->graphs.push_back(std::move(g));
+    *out = p.release();
+  } catch (const std::bad_alloc &) {
+    return set_error(GFT_ERR_OOM, "host allocation failed while planning");
+  }
+  return ok();
+}
+
 gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_signals, void *stream) {
   return apply(plan, 0, x, y, num_signals, stream);
 }
@@ -653,7 +849,8 @@ gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out) {
   DeviceImage *img = nullptr;
   gft_status st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  *engine_out = img->butterfly ? GFT_ENGINE_BUTTERFLY : (img->large ? GFT_ENGINE_LARGE : GFT_ENGINE_GENERIC);
+  *engine_out = img->product ? GFT_ENGINE_PRODUCT
+                : img->butterfly ? GFT_ENGINE_BUTTERFLY : (img->large ? GFT_ENGINE_LARGE : GFT_ENGINE_GENERIC);
   return ok();
 }
 
@@ -663,7 +860,9 @@ gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile)
   DeviceImage *img = nullptr;
   gft_status st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  if (img->butterfly) {
+  if (img->product) {
+    *fwd_tile = *inv_tile = 1;
+  } else if (img->butterfly) {
     *fwd_tile = *inv_tile = 16;
   } else if (img->large) {
     *fwd_tile = *inv_tile = 0;
@@ -713,15 +912,19 @@ gft_status gft_plan_basis(gft_plan_t plan, int32_t index, double *U) {
   if (st != GFT_OK) return st;
   if (!U) return set_error(GFT_ERR_INVALID_ARG, "U is NULL");
   const int n = g->n;
-  // column k = inverse transform of the unit coefficient vector e_k, run block-locally
-  std::vector<double> e(n, 0.0), col(n);
-  for (size_t i = 0; i < (size_t)n * n; ++i) U[i] = 0.0;
-  for (int k = 0; k < n; ++k) {
-    e[k] = 1.0;
-    apply_host(*g, 1, e.data(), col.data(), 1);
-    e[k] = 0.0;
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + k] = col[i];
+  if (plan->product) {
+    // node (i, j) of basis vector k = (p, q): U_a[i][p] U_b[j][q]
+    const int na = plan->fa.n, nb = plan->fb.n;
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < nb; ++j)
+        for (int k = 0; k < n; ++k) {
+          const int p = plan->order[k] / nb, q = plan->order[k] % nb;
+          U[((size_t)i * nb + j) * n + k] = plan->ua[(size_t)i * na + p] * plan->ub[(size_t)j * nb + q];
+        }
+    return ok();
   }
+  const std::vector<double> B = plan_basis(*g);
+  std::memcpy(U, B.data(), sizeof(double) * B.size());
   return ok();
 }
 
@@ -733,7 +936,8 @@ gft_status gft_plan_apply_host(gft_plan_t plan, int32_t index, int32_t direction
   if (direction != 0 && direction != 1) return set_error(GFT_ERR_INVALID_ARG, "direction must be 0 or 1");
   if (num_signals < 0) return set_error(GFT_ERR_INVALID_ARG, "num_signals must be >= 0");
   if (num_signals > 0 && (!x || !y)) return set_error(GFT_ERR_INVALID_ARG, "x and y must be non-NULL");
-  apply_host(*g, direction, x, y, num_signals);
+  if (plan->product) product_apply_host(*plan, direction, x, y, num_signals);
+  else apply_host(*g, direction, x, y, num_signals);
   return ok();
 }
 
@@ -742,6 +946,8 @@ gft_status gft_plan_blocks(gft_plan_t plan, int32_t index, int32_t *sizes, int32
   gft_status st = get_graph(plan, index, &g);
   if (st != GFT_OK) return st;
   if (!sizes) return set_error(GFT_ERR_INVALID_ARG, "sizes is NULL");
+  if (plan->product)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans have no leaf blocks (two factor GFTs)");
   size_t pos = 0;
   for (size_t b = 0; b < g->blocks.size(); ++b) {
     sizes[b] = g->blocks[b].size;

@@ -124,4 +124,20 @@ struct LBlock {
   int32_t omap;     // offset of the block's output positions in the output map (forward)
 };
 
+// Product-graph program (one direction): the GFT of a Cartesian product G_a x G_b (node
+// (i, j) = i * nb + j) is U_a (x) U_b, so a signal X (na x nb, row-major) maps to
+// U_a^T X U_b.  The kernel computes Y1 = Z * B then Y2 = A * Y1 on zero-padded NA x NA and
+// NB x NB matrices, Z the signal (forward) or the coefficients placed by perm (inverse).
+//   forward: B = U_b, A = U_a^T, the coefficients leave in output order through perm;
+//   inverse: B = U_b^T, A = U_a, the signal leaves in node order.
+struct PProgram {
+  int32_t na, nb;           // factor sizes (<= the kernel's NA, NB)
+  int32_t dir;
+  int32_t stride;           // LDS row stride of the wave's tile (NB + 1)
+  const float *amat;        // NA x NA row-major, zero beyond na
+  const float *bmat;        // NB x NB row-major, zero beyond nb
+  const uint16_t *perm;     // na * nb entries: LDS word p * stride + q of output-order
+                            // coefficient k (its factor indices p, q)
+};
+
 }  // namespace gft

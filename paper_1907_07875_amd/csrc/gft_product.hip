@@ -1,0 +1,223 @@
+// Separable GFT of Cartesian product graphs (gfx950).
+//
+// The Laplacian of G_a x G_b is L_a (x) I + I (x) L_b, so U_a (x) U_b is a GFT of the product
+// graph (eigenvalue lambda_p + mu_q for basis vector (p, q)): the fast GFT of a grid whose
+// stages act along one axis at a time (Sec. V-D) has leaf blocks that are Kronecker
+// products of the axes' leaf blocks, and applying it axis by axis replaces the 2-D leaf
+// products by two 1-D transforms.  Per signal X (na x nb, row-major) the kernel computes
+// U_a^T X U_b as two MFMA products on a wave-private LDS tile:
+//   HBM --16B loads, prefetched one signal ahead--> registers --> LDS tile (row stride
+//   NB + 1: odd, so the 16 rows an MFMA operand spans fall in distinct banks)
+//   --> Y1 = Z * B, one 16-row block at a time, written back over that block
+//   --> Y2 = A * Y1, one 16-column block at a time, written back over that block
+//   --> LDS words in output order (perm) --> 16B stores.
+// Both matrices stay in registers as MFMA fragments (v_mfma_f32_16x16x4_f32: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the result D[4 (l / 16) + v][l % 16]).  Padding
+// rows and columns of the tile and of the matrices are zero, so they stay zero.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_program.hpp"
+
+namespace gft {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPWaves = 4;
+
+// Orders this wave's LDS accesses: every lane's earlier LDS operations complete before any
+// later one.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NA, int NB>
+constexpr size_t product_lds_bytes(int n) {
+  return (size_t)kPWaves * NA * (NB + 1) * sizeof(float) + (((size_t)n * 2 + 15) & ~(size_t)15);
+}
+
+}  // namespace
+
+template <int NA, int NB, int DIR>
+__global__ __launch_bounds__(64 * kPWaves) void gft_product(PProgram P, const float *in, float *out,
+                                                            int64_t nsig) {
+  constexpr int STR = NB + 1;
+  constexpr int TW = NA * STR;
+  constexpr int MAXV = NA * NB / 256;   // 16-byte groups per lane of a full NA x NB signal
+  extern __shared__ __attribute__((aligned(16))) float psmem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
+  float *T = psmem + wave * TW;
+  uint16_t *perm = reinterpret_cast<uint16_t *>(psmem + kPWaves * TW);
+  const int na = P.na, nb = P.nb, n = na * nb;
+  for (int i = threadIdx.x; i < n; i += 64 * kPWaves) perm[i] = P.perm[i];
+  for (int i = lane; i < TW; i += 64) T[i] = 0.0f;
+  __syncthreads();
+
+  float bf[NB / 4][NB / 16];   // B[4 kc + g4][16 nt + r16]
+  float af[NA / 16][NA / 4];   // A[16 mt + r16][4 kc + g4]
+#pragma unroll
+  for (int kc = 0; kc < NB / 4; ++kc)
+#pragma unroll
+    for (int nt = 0; nt < NB / 16; ++nt) bf[kc][nt] = P.bmat[(4 * kc + g4) * NB + 16 * nt + r16];
+#pragma unroll
+  for (int mt = 0; mt < NA / 16; ++mt)
+#pragma unroll
+    for (int kc = 0; kc < NA / 4; ++kc) af[mt][kc] = P.amat[(16 * mt + r16) * NA + 4 * kc + g4];
+
+  // LDS word of signal element e in node order (row e / nb, column e mod nb)
+  const bool full = nb == NB;
+  auto natural = [&](int e) -> int {
+    const int i = full ? e / NB : e / nb;
+    return i * STR + (e - i * nb);
+  };
+  auto lds_in = [&](int e) -> int { return DIR == 0 ? natural(e) : (int)perm[e]; };
+  auto lds_out = [&](int e) -> int { return DIR == 0 ? (int)perm[e] : natural(e); };
+
+  const int64_t W = (int64_t)gridDim.x * kPWaves;
+  int64_t s = (int64_t)blockIdx.x * kPWaves + wave;
+  // Whole signals move as 16-byte groups when n % 4 == 0 (every signal then starts 16-byte
+  // aligned); the loads are unconditional and clamped, so that they stay in flight while
+  // the previous signal is computed (the last signal re-reads itself).
+  const bool vec = (n & 3) == 0;
+  const int nv = n >> 2;
+  floatx4 pre[MAXV];
+  auto issue = [&](int64_t sig) {
+    const floatx4 *src = reinterpret_cast<const floatx4 *>(in + sig * n);
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const int v = lane + 64 * k;
+      pre[k] = __builtin_nontemporal_load(src + (v < nv ? v : nv - 1));
+    }
+  };
+  if (vec && s < nsig) issue(s);
+
+  for (; s < nsig; s += W) {
+    if (vec) {
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) {
+        const int v = lane + 64 * k;
+        if (v < nv) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) T[lds_in(4 * v + j)] = pre[k][j];
+        }
+      }
+      const int64_t nx = s + W;
+      issue(nx < nsig ? nx : s);
+    } else {
+      for (int e = lane; e < n; e += 64) T[lds_in(e)] = in[s * n + e];
+    }
+    wave_sync();
+
+    // Y1 = Z * B, 16 rows at a time (a row block of Y1 needs only that row block of Z)
+#pragma unroll
+    for (int mt = 0; mt < NA / 16; ++mt) {
+      floatx4 acc[NB / 16];
+#pragma unroll
+      for (int nt = 0; nt < NB / 16; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < NB / 4; ++kc) {
+        const float a = T[(16 * mt + r16) * STR + 4 * kc + g4];
+#pragma unroll
+        for (int nt = 0; nt < NB / 16; ++nt)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[kc][nt], acc[nt], 0, 0, 0);
+      }
+      wave_sync();
+#pragma unroll
+      for (int nt = 0; nt < NB / 16; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[(16 * mt + 4 * g4 + v) * STR + 16 * nt + r16] = acc[nt][v];
+      wave_sync();
+    }
+    // Y2 = A * Y1, 16 columns at a time (a column block of Y2 needs only that of Y1)
+#pragma unroll
+    for (int nt = 0; nt < NB / 16; ++nt) {
+      floatx4 acc[NA / 16];
+#pragma unroll
+      for (int mt = 0; mt < NA / 16; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < NA / 4; ++kc) {
+        const float b = T[(4 * kc + g4) * STR + 16 * nt + r16];
+#pragma unroll
+        for (int mt = 0; mt < NA / 16; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][kc], b, acc[mt], 0, 0, 0);
+      }
+      wave_sync();
+#pragma unroll
+      for (int mt = 0; mt < NA / 16; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[(16 * mt + 4 * g4 + v) * STR + 16 * nt + r16] = acc[mt][v];
+      wave_sync();
+    }
+
+    if (vec) {
+      floatx4 *dst = reinterpret_cast<floatx4 *>(out + s * n);
+      for (int v = lane; v < nv; v += 64) {
+        const int e = 4 * v;
+        const floatx4 o = {T[lds_out(e)], T[lds_out(e + 1)], T[lds_out(e + 2)], T[lds_out(e + 3)]};
+        __builtin_nontemporal_store(o, dst + v);
+      }
+    } else {
+      for (int e = lane; e < n; e += 64) out[s * n + e] = T[lds_out(e)];
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------- launch
+
+template <int NA, int NB, int DIR>
+static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus) {
+  const size_t lds = product_lds_bytes<NA, NB>(P.na * P.nb);
+  const void *k = (const void *)gft_product<NA, NB, DIR>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR>, 64 * kPWaves, lds) !=
+          hipSuccess || occ < 1)
+    occ = 1;
+  const int64_t want = (nsig + kPWaves - 1) / kPWaves;
+  const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
+  const int grid = (int)(want < cap ? want : cap);
+  hipLaunchKernelGGL((gft_product<NA, NB, DIR>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
+                     stream, P, in, out, nsig);
+  return hipGetLastError();
+}
+
+template <int NA, int NB>
+static hipError_t launch_pab(const PProgram &P, const float *in, float *out, int64_t nsig,
+                             hipStream_t stream, int num_cus) {
+  return P.dir == 0 ? launch_pd<NA, NB, 0>(P, in, out, nsig, stream, num_cus)
+                    : launch_pd<NA, NB, 1>(P, in, out, nsig, stream, num_cus);
+}
+
+int product_pad(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0)); }
+
+hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
+                          hipStream_t stream, int num_cus) {
+  const int NA = product_pad(P.na), NB = product_pad(P.nb);
+  if (P.stride != NB + 1) return hipErrorInvalidValue;
+#define GFT_PROD_CASE(a, b) \
+  if (NA == a && NB == b) return launch_pab<a, b>(P, in, out, nsig, stream, num_cus);
+  GFT_PROD_CASE(16, 16)
+  GFT_PROD_CASE(16, 32)
+  GFT_PROD_CASE(16, 64)
+  GFT_PROD_CASE(32, 16)
+  GFT_PROD_CASE(32, 32)
+  GFT_PROD_CASE(32, 64)
+  GFT_PROD_CASE(64, 16)
+  GFT_PROD_CASE(64, 32)
+  GFT_PROD_CASE(64, 64)
+#undef GFT_PROD_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gft

@@ -44,4 +44,9 @@ bool butterfly_supported(int S, int M);
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16);
 
+// Product-graph engine: factor sizes padded to 16, 32 or 64 (0 above 64).
+int product_pad(int n);
+hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
+                          hipStream_t stream, int num_cus);
+
 }  // namespace gft

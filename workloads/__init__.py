@@ -242,6 +242,37 @@ def grid_recursive(N: int, name="grid_recursive") -> Graph:
     return _graph(N * N, grid_edges(N, N), None, None, stages, name)
 
 
+def path_recursive(N: int, name="path_recursive") -> Graph:
+    """Path of N nodes (N a power of two) with the reversal recursed on the + branch:
+    stage t reverses the first N / 2^t nodes among themselves (log2 N stages); one axis
+    of :func:`grid_recursive`."""
+    g = path(N, name=name)
+    g.stages = [reversal_on(N, r) for r in _halving_chain(N)]
+    return g
+
+
+def cartesian_product(ga: Graph, gb: Graph, name="product") -> Graph:
+    """Cartesian product of two graphs: node (i, j) has label i * gb.n + j; edges
+    (i, j)-(i', j) carry ga's weights, (i, j)-(i, j') gb's; self-loop s_a(i) + s_b(j).
+    No stages (the product is planned from its factors)."""
+    na, nb = ga.n, gb.n
+    edges, w = [], []
+    for e in range(ga.num_edges):
+        for j in range(nb):
+            edges.append((int(ga.src[e]) * nb + j, int(ga.dst[e]) * nb + j))
+            w.append(float(ga.weight[e]))
+    for e in range(gb.num_edges):
+        for i in range(na):
+            edges.append((i * nb + int(gb.src[e]), i * nb + int(gb.dst[e])))
+            w.append(float(gb.weight[e]))
+    loops = None
+    if ga.self_loop is not None or gb.self_loop is not None:
+        sa = np.zeros(na) if ga.self_loop is None else np.asarray(ga.self_loop, dtype=np.float64)
+        sb = np.zeros(nb) if gb.self_loop is None else np.asarray(gb.self_loop, dtype=np.float64)
+        loops = (sa[:, None] + sb[None, :]).reshape(-1)
+    return _graph(na * nb, edges, w, loops, None, name)
+
+
 def skeleton25(name="skeleton25") -> Graph:
     """25-node skeleton tree: 5-node spine plus mirror-symmetric arms and legs of 5 nodes.
 
