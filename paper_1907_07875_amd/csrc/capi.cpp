@@ -249,6 +249,7 @@ gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
     P.nb = nb;
     P.dir = d;
     P.stride = stride;
+    P.same = na == nb && plan->ua == plan->ub;
     P.amat = reinterpret_cast<const float *>(base + off[d][0]);
     P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
     P.perm = reinterpret_cast<const uint16_t *>(base + off[d][2]);

@@ -134,6 +134,7 @@ struct PProgram {
   int32_t na, nb;           // factor sizes (<= the kernel's NA, NB)
   int32_t dir;
   int32_t stride;           // LDS row stride of the wave's tile (NB + 1)
+  int32_t same;             // 1: U_a = U_b (one graph squared), one set of fragments
   const float *amat;        // NA x NA row-major, zero beyond na
   const float *bmat;        // NB x NB row-major, zero beyond nb
   const uint16_t *perm;     // na * nb entries: LDS word p * stride + q of output-order

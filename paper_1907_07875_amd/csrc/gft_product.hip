@@ -6,10 +6,11 @@
 // products of the axes' leaf blocks, and applying it axis by axis replaces the 2-D leaf
 // products by two 1-D transforms.  Per signal X (na x nb, row-major) the kernel computes
 // U_a^T X U_b as two MFMA products on a wave-private LDS tile:
-//   HBM --16B loads, prefetched one signal ahead--> registers --> LDS tile (row stride
-//   NB + 1: odd, so the 16 rows an MFMA operand spans fall in distinct banks)
-//   --> Y1 = Z * B, one 16-row block at a time, written back over that block
-//   --> Y2 = A * Y1, one 16-column block at a time, written back over that block
+//   HBM --16B loads--> registers --> LDS tile (row stride NB + 1: odd, so the 16 rows an
+//   MFMA operand spans fall in distinct banks)
+//   --> Y1 = Z * B into MFMA result registers
+//   --> Y2 = A * Y1 straight from those registers (the contraction order over k follows
+//   the result layout), one 16-column block at a time, written into the tile
 //   --> LDS words in output order (perm) --> 16B stores.
 // Both matrices stay in registers as MFMA fragments (v_mfma_f32_16x16x4_f32: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the result D[4 (l / 16) + v][l % 16]).  Padding
@@ -43,12 +44,16 @@ constexpr size_t product_lds_bytes(int n) {
 
 }  // namespace
 
-template <int NA, int NB, int DIR>
-__global__ __launch_bounds__(64 * kPWaves) void gft_product(PProgram P, const float *in, float *out,
-                                                            int64_t nsig) {
+// SAME: the two factors are one matrix (U_a = U_b, square products of one graph), whose
+// fragments then serve both products.
+template <int NA, int NB, int DIR, bool SAME>
+__global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2))) void gft_product(
+    PProgram P, const float *in, float *out, int64_t nsig) {
+  static_assert(!SAME || NA == NB, "one matrix needs equal factor sizes");
   constexpr int STR = NB + 1;
   constexpr int TW = NA * STR;
   constexpr int MAXV = NA * NB / 256;   // 16-byte groups per lane of a full NA x NB signal
+  constexpr int MA = NA / 16, MB = NB / 16;
   extern __shared__ __attribute__((aligned(16))) float psmem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
@@ -59,16 +64,29 @@ __global__ __launch_bounds__(64 * kPWaves) void gft_product(PProgram P, const fl
   for (int i = lane; i < TW; i += 64) T[i] = 0.0f;
   __syncthreads();
 
-  float bf[NB / 4][NB / 16];   // B[4 kc + g4][16 nt + r16]
-  float af[NA / 16][NA / 4];   // A[16 mt + r16][4 kc + g4]
+  // Y1 stays in the MFMA result registers: lane (g4, r16) holds Y1[16 mt + 4 g4 + v]
+  // [16 nt + r16] in y1[mt][nt][v], so Y2 = A * Y1 sums over k in the order (mt, v, g4): MFMA
+  // step (mt, v) takes row 16 mt + 4 g4 + v of Y1 from lane group g4, and the A fragment of
+  // that step holds A[16 mo + r16][16 mt + 4 g4 + v].  Y1 = Z * B sums over k in the same
+  // order, so its B fragment for step (mk, v) holds B[16 mk + 4 g4 + v][16 nt + r16]; with
+  // one matrix for both factors that is af[nt][mk][v] (both are U[16 mk + 4 g4 + v]
+  // [16 nt + r16], forward and inverse alike).
+  float bf[SAME ? 1 : MB][4][SAME ? 1 : MB];
+  float af[MA][MA][4];
+  if constexpr (!SAME) {
 #pragma unroll
-  for (int kc = 0; kc < NB / 4; ++kc)
+    for (int mk = 0; mk < MB; ++mk)
 #pragma unroll
-    for (int nt = 0; nt < NB / 16; ++nt) bf[kc][nt] = P.bmat[(4 * kc + g4) * NB + 16 * nt + r16];
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-  for (int mt = 0; mt < NA / 16; ++mt)
+        for (int nt = 0; nt < MB; ++nt) bf[mk][v][nt] = P.bmat[(16 * mk + 4 * g4 + v) * NB + 16 * nt + r16];
+  }
 #pragma unroll
-    for (int kc = 0; kc < NA / 4; ++kc) af[mt][kc] = P.amat[(16 * mt + r16) * NA + 4 * kc + g4];
+  for (int mo = 0; mo < MA; ++mo)
+#pragma unroll
+    for (int mt = 0; mt < MA; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) af[mo][mt][v] = P.amat[(16 * mo + r16) * NA + 16 * mt + 4 * g4 + v];
 
   // LDS word of signal element e in node order (row e / nb, column e mod nb)
   const bool full = nb == NB;
@@ -80,83 +98,84 @@ __global__ __launch_bounds__(64 * kPWaves) void gft_product(PProgram P, const fl
   auto lds_out = [&](int e) -> int { return DIR == 0 ? (int)perm[e] : natural(e); };
 
   const int64_t W = (int64_t)gridDim.x * kPWaves;
-  int64_t s = (int64_t)blockIdx.x * kPWaves + wave;
   // Whole signals move as 16-byte groups when n % 4 == 0 (every signal then starts 16-byte
-  // aligned); the loads are unconditional and clamped, so that they stay in flight while
-  // the previous signal is computed (the last signal re-reads itself).
+  // aligned).  Load latency is covered by the other wave of the SIMD, not by a prefetch
+  // (whose registers would cost that second wave).
   const bool vec = (n & 3) == 0;
   const int nv = n >> 2;
-  floatx4 pre[MAXV];
-  auto issue = [&](int64_t sig) {
-    const floatx4 *src = reinterpret_cast<const floatx4 *>(in + sig * n);
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) {
-      const int v = lane + 64 * k;
-      pre[k] = __builtin_nontemporal_load(src + (v < nv ? v : nv - 1));
-    }
-  };
-  if (vec && s < nsig) issue(s);
-
-  for (; s < nsig; s += W) {
+  for (int64_t s = (int64_t)blockIdx.x * kPWaves + wave; s < nsig; s += W) {
     if (vec) {
+      const floatx4 *src = reinterpret_cast<const floatx4 *>(in + s * n);
+      floatx4 ld[MAXV];
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) {
+        const int v = lane + 64 * k;
+        ld[k] = __builtin_nontemporal_load(src + (v < nv ? v : nv - 1));
+      }
 #pragma unroll
       for (int k = 0; k < MAXV; ++k) {
         const int v = lane + 64 * k;
         if (v < nv) {
+          if (DIR == 0 && (nb & 3) == 0) {   // a group of 4 stays inside one row
+            float *row = T + natural(4 * v);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) T[lds_in(4 * v + j)] = pre[k][j];
+            for (int j = 0; j < 4; ++j) row[j] = ld[k][j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) T[lds_in(4 * v + j)] = ld[k][j];
+          }
         }
       }
-      const int64_t nx = s + W;
-      issue(nx < nsig ? nx : s);
     } else {
       for (int e = lane; e < n; e += 64) T[lds_in(e)] = in[s * n + e];
     }
     wave_sync();
 
-    // Y1 = Z * B, 16 rows at a time (a row block of Y1 needs only that row block of Z)
+    // Y1 = Z * B
+    floatx4 y1[MA][MB];
 #pragma unroll
-    for (int mt = 0; mt < NA / 16; ++mt) {
-      floatx4 acc[NB / 16];
+    for (int mt = 0; mt < MA; ++mt) {
 #pragma unroll
-      for (int nt = 0; nt < NB / 16; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int nt = 0; nt < MB; ++nt) y1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kc = 0; kc < NB / 4; ++kc) {
-        const float a = T[(16 * mt + r16) * STR + 4 * kc + g4];
+      for (int mk = 0; mk < MB; ++mk)
 #pragma unroll
-        for (int nt = 0; nt < NB / 16; ++nt)
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[kc][nt], acc[nt], 0, 0, 0);
-      }
-      wave_sync();
+        for (int v = 0; v < 4; ++v) {
+          const float a = T[(16 * mt + r16) * STR + 16 * mk + 4 * g4 + v];
 #pragma unroll
-      for (int nt = 0; nt < NB / 16; ++nt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[(16 * mt + 4 * g4 + v) * STR + 16 * nt + r16] = acc[nt][v];
-      wave_sync();
+          for (int nt = 0; nt < MB; ++nt) {
+            float b;
+            if constexpr (SAME) b = af[nt][mk][v];
+            else b = bf[mk][v][nt];
+            y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, y1[mt][nt], 0, 0, 0);
+          }
+        }
     }
-    // Y2 = A * Y1, 16 columns at a time (a column block of Y2 needs only that of Y1)
+    wave_sync();   // every read of Z is done before Y2 overwrites the tile
+
+    // Y2 = A * Y1, one 16-column block at a time, into the tile
 #pragma unroll
-    for (int nt = 0; nt < NB / 16; ++nt) {
-      floatx4 acc[NA / 16];
+    for (int nt = 0; nt < MB; ++nt) {
+      floatx4 acc[MA];
 #pragma unroll
-      for (int mt = 0; mt < NA / 16; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int mo = 0; mo < MA; ++mo) acc[mo] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kc = 0; kc < NA / 4; ++kc) {
-        const float b = T[(4 * kc + g4) * STR + 16 * nt + r16];
+      for (int mt = 0; mt < MA; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < NA / 16; ++mt)
-          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][kc], b, acc[mt], 0, 0, 0);
-      }
-      wave_sync();
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int mt = 0; mt < NA / 16; ++mt)
+          for (int mo = 0; mo < MA; ++mo)
+            acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mo][mt][v], y1[mt][nt][v], acc[mo], 0, 0, 0);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[(16 * mt + 4 * g4 + v) * STR + 16 * nt + r16] = acc[mt][v];
-      wave_sync();
+      for (int mo = 0; mo < MA; ++mo)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[(16 * mo + 4 * g4 + v) * STR + 16 * nt + r16] = acc[mo][v];
     }
+    wave_sync();
 
     if (vec) {
       floatx4 *dst = reinterpret_cast<floatx4 *>(out + s * n);
+#pragma unroll 2
       for (int v = lane; v < nv; v += 64) {
         const int e = 4 * v;
         const floatx4 o = {T[lds_out(e)], T[lds_out(e + 1)], T[lds_out(e + 2)], T[lds_out(e + 3)]};
@@ -171,23 +190,23 @@ __global__ __launch_bounds__(64 * kPWaves) void gft_product(PProgram P, const fl
 
 // ---------------------------------------------------------------------------- launch
 
-template <int NA, int NB, int DIR>
+template <int NA, int NB, int DIR, bool SAME>
 static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
                             hipStream_t stream, int num_cus) {
   const size_t lds = product_lds_bytes<NA, NB>(P.na * P.nb);
-  const void *k = (const void *)gft_product<NA, NB, DIR>;
+  const void *k = (const void *)gft_product<NA, NB, DIR, SAME>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR>, 64 * kPWaves, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR, SAME>, 64 * kPWaves, lds) !=
           hipSuccess || occ < 1)
     occ = 1;
   const int64_t want = (nsig + kPWaves - 1) / kPWaves;
   const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_product<NA, NB, DIR>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
+  hipLaunchKernelGGL((gft_product<NA, NB, DIR, SAME>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
                      stream, P, in, out, nsig);
   return hipGetLastError();
 }
@@ -195,8 +214,13 @@ static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int6
 template <int NA, int NB>
 static hipError_t launch_pab(const PProgram &P, const float *in, float *out, int64_t nsig,
                              hipStream_t stream, int num_cus) {
-  return P.dir == 0 ? launch_pd<NA, NB, 0>(P, in, out, nsig, stream, num_cus)
-                    : launch_pd<NA, NB, 1>(P, in, out, nsig, stream, num_cus);
+  if constexpr (NA == NB) {
+    if (P.same)
+      return P.dir == 0 ? launch_pd<NA, NB, 0, true>(P, in, out, nsig, stream, num_cus)
+                        : launch_pd<NA, NB, 1, true>(P, in, out, nsig, stream, num_cus);
+  }
+  return P.dir == 0 ? launch_pd<NA, NB, 0, false>(P, in, out, nsig, stream, num_cus)
+                    : launch_pd<NA, NB, 1, false>(P, in, out, nsig, stream, num_cus);
 }
 
 int product_pad(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0)); }
