@@ -358,22 +358,23 @@ def bench_grid64_product(args):
     its 6 halving reversal stages): separable factor GFTs, y = U_a^T X U_b per signal."""
     import paper_1907_07875_amd as G
     import workloads as wl
-    if (args.precision or "fp32") != "fp32" or args.io != "fp32":
-        sys.exit("product plans run FP32 (precision and storage)")
+    precision = args.precision or "fp32"
+    if precision == "fp16" or args.io != "fp32":
+        sys.exit("product plans run FP32, BF16 or split BF16 products on FP32 storage")
     S = args.signals or 65536
     axis = wl.path_recursive(64)
     graph = wl.cartesian_product(axis, axis, name="grid64x64")
     X = wl.gaussian(S, graph.n, wl.rng_for(5, 7))
-    bench_single(args, graph, X, "fp32",
+    bench_single(args, graph, X, precision,
                  {"workload": "grid64x64_product_fwd_inv",
                   "graph": "64x64 grid as path64 x path64, halving reversal stages per axis (6 + 6)",
-                  "factor_gfts": "two dense 64x64 FP32 factor GFTs per signal (separable)",
+                  "factor_gfts": f"two dense 64x64 factor GFTs per signal (separable), {precision} products",
                   "dense_flops_per_signal": 2.0 * graph.n * graph.n,
                   "fast_flops_per_signal": 2.0 * graph.n * (64 + 64)},
                  256, "first 256 signals of the same workload",
                  kernel_names={"product": "gft_product<64,64,0>"},
                  flops_per_signal=2.0 * graph.n * (64 + 64),
-                 make_plan=lambda: G.Plan.from_product(axis, axis))
+                 make_plan=lambda: G.Plan.from_product(axis, axis, precision=precision))
 
 
 def bench_wpath(args):

@@ -219,10 +219,11 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
  * Sec. V-D, whose axis-wise stages leave leaf blocks that are Kronecker products of the
  * axes' leaves.  Each factor is planned as by gft_plan (its stages, if any, shape its
  * basis); the transform runs as y = U_a^T X U_b per signal X (n_a x n_b, row-major), the
- * factors applied as dense FP32 matrices on MFMA, then the coefficients in output order
- * (ascending lambda_p + mu_q, ties by p then q; GFT_ORDER_BLOCK: p * n_b + q).
- * Requires n_a, n_b <= 64, FP32 precision and storage, the combinatorial Laplacian and
- * options.engine 0 (else GFT_ERR_UNSUPPORTED).  gft_plan_info reports the two factor GFTs
+ * factors applied as dense matrices on MFMA (options.precision: FP32, BF16 or split BF16
+ * products with FP32 accumulation), then the coefficients in output order (ascending
+ * lambda_p + mu_q, ties by p then q; GFT_ORDER_BLOCK: p * n_b + q).
+ * Requires n_a, n_b <= 64, FP32 storage, the combinatorial Laplacian and options.engine 0
+ * (else GFT_ERR_UNSUPPORTED; FP16 precision is unsupported too).  gft_plan_info reports the two factor GFTs
  * as num_blocks = 2 with their dense costs; gft_plan_blocks is unsupported.  Host-only. */
 gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing_a,
                             const gft_graph *graph_b, const gft_pairing *pairing_b,

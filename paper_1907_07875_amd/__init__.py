@@ -206,9 +206,11 @@ class Plan:
                         right_haar=right_haar)
 
     @classmethod
-    def from_product(cls, graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, right_haar=True):
+    def from_product(cls, graph_a, graph_b, precision="fp32", order=ORDER_EIGENVALUE, sym_tol=0.0,
+                     right_haar=True):
         """Plan the Cartesian product of two graphs (node (i, j) = i * graph_b.n + j)."""
-        return gft_plan_product(graph_a, graph_b, order=order, sym_tol=sym_tol, right_haar=right_haar)
+        return gft_plan_product(graph_a, graph_b, order=order, sym_tol=sym_tol, right_haar=right_haar,
+                                precision=precision)
 
     @property
     def n(self) -> int:
@@ -318,7 +320,7 @@ def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, righ
     h = ctypes.c_void_p()
     _check(lib.gft_plan_product(ctypes.byref(ga), ctypes.byref(pa), ctypes.byref(gb), ctypes.byref(pb),
                                 ctypes.byref(o), ctypes.byref(h)))
-    return Plan(h.value, [int(graph_a.n) * int(graph_b.n)], False, "fp32", "fp32", "fp32")
+    return Plan(h.value, [int(graph_a.n) * int(graph_b.n)], False, precision, "fp32", "fp32")
 
 
 def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_steps=0,

@@ -250,6 +250,7 @@ gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
     P.dir = d;
     P.stride = stride;
     P.same = na == nb && plan->ua == plan->ub;
+    P.prec = plan->opts.precision;
     P.amat = reinterpret_cast<const float *>(base + off[d][0]);
     P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
     P.perm = reinterpret_cast<const uint16_t *>(base + off[d][2]);
@@ -740,8 +741,8 @@ gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing
   const gft_options o = default_options(opts);
   gft_status st = check_options(o);
   if (st != GFT_OK) return st;
-  if (o.precision != GFT_FP32)
-    return set_error(GFT_ERR_UNSUPPORTED, "product plans run FP32 factor products");
+  if (o.precision != GFT_FP32 && o.precision != GFT_BF16 && o.precision != GFT_SPLIT_BF16)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans run FP32, BF16 or split BF16 factor products");
   if (o.in_dtype != GFT_DTYPE_FP32 || o.out_dtype != GFT_DTYPE_FP32)
     return set_error(GFT_ERR_UNSUPPORTED, "product plans read and write FP32 storage");
   if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL)

@@ -135,6 +135,7 @@ struct PProgram {
   int32_t dir;
   int32_t stride;           // LDS row stride of the wave's tile (NB + 1)
   int32_t same;             // 1: U_a = U_b (one graph squared), one set of fragments
+  int32_t prec;             // gft_precision of the products: FP32, BF16 or split BF16
   const float *amat;        // NA x NA row-major, zero beyond na
   const float *bmat;        // NB x NB row-major, zero beyond nb
   const uint16_t *perm;     // na * nb entries: LDS word p * stride + q of output-order

@@ -26,8 +26,44 @@ namespace gft {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPWaves = 4;
+constexpr int kFP32 = 0, kBF16 = 1, kSPLIT = 3;   // gft_precision values (include/gft.h)
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Four values as a 16x16x16 BF16 MFMA operand: hi = BF16(x), lo = BF16(x - hi) (the split
+// form; lo unused with plain BF16 blocks).
+struct Frag16 {
+  u32x2 hi, lo;
+};
+__device__ __forceinline__ Frag16 pack16(float a, float b, float c, float d) {
+  const uint32_t h0 = bf16_rne(a), h1 = bf16_rne(b), h2 = bf16_rne(c), h3 = bf16_rne(d);
+  Frag16 f;
+  f.hi = u32x2{h0 | (h1 << 16), h2 | (h3 << 16)};
+  const uint32_t l0 = bf16_rne(a - __uint_as_float(h0 << 16)), l1 = bf16_rne(b - __uint_as_float(h1 << 16));
+  const uint32_t l2 = bf16_rne(c - __uint_as_float(h2 << 16)), l3 = bf16_rne(d - __uint_as_float(h3 << 16));
+  f.lo = u32x2{l0 | (l1 << 16), l2 | (l3 << 16)};
+  return f;
+}
+
+// acc += A * B on 16x16x16 BF16 MFMA; SPLIT: hi*hi + hi*lo + lo*hi (FP32-level products).
+template <bool SPLIT>
+__device__ __forceinline__ floatx4 mfma16(const Frag16 &a, const Frag16 &b, floatx4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a.hi), __builtin_bit_cast(bf16x4, b.hi), acc, 0, 0, 0);
+  if constexpr (SPLIT) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a.hi), __builtin_bit_cast(bf16x4, b.lo), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a.lo), __builtin_bit_cast(bf16x4, b.hi), acc, 0, 0, 0);
+  }
+  return acc;
+}
 
 // Orders this wave's LDS accesses: every lane's earlier LDS operations complete before any
 // later one.
@@ -45,11 +81,14 @@ constexpr size_t product_lds_bytes(int n) {
 }  // namespace
 
 // SAME: the two factors are one matrix (U_a = U_b, square products of one graph), whose
-// fragments then serve both products.
-template <int NA, int NB, int DIR, bool SAME>
+// fragments then serve both products.  PREC: FP32 (16x16x4 FP32 MFMA), BF16 or split BF16
+// (16x16x16 BF16 MFMA with FP32 accumulation; the data operand of each product is rounded
+// to BF16, or split into hi + lo, as it enters the MFMA).
+template <int NA, int NB, int DIR, bool SAME, int PREC>
 __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2))) void gft_product(
     PProgram P, const float *in, float *out, int64_t nsig) {
   static_assert(!SAME || NA == NB, "one matrix needs equal factor sizes");
+  constexpr bool B16 = PREC != kFP32;
   constexpr int STR = NB + 1;
   constexpr int TW = NA * STR;
   constexpr int MAXV = NA * NB / 256;   // 16-byte groups per lane of a full NA x NB signal
@@ -71,9 +110,34 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
   // order, so its B fragment for step (mk, v) holds B[16 mk + 4 g4 + v][16 nt + r16]; with
   // one matrix for both factors that is af[nt][mk][v] (both are U[16 mk + 4 g4 + v]
   // [16 nt + r16], forward and inverse alike).
-  float bf[SAME ? 1 : MB][4][SAME ? 1 : MB];
-  float af[MA][MA][4];
-  if constexpr (!SAME) {
+  // FP32 fragments (B16: unused, size 1)
+  float bf[SAME || B16 ? 1 : MB][4][SAME || B16 ? 1 : MB];
+  float af[B16 ? 1 : MA][B16 ? 1 : MA][4];
+  // BF16 fragments: the 16x16x16 MFMA takes k = 16 kk + 4 g4 + j, j < 4, from lane group g4,
+  // so step 1's B fragment (kk, nt) holds B[16 kk + 4 g4 + j][16 nt + r16] and step 2's A
+  // fragment (mo, mt) holds A[16 mo + r16][16 mt + 4 g4 + j] (= B fragment (mt, mo) with one
+  // matrix for both factors)
+  Frag16 bq[B16 && !SAME ? MB : 1][B16 && !SAME ? MB : 1];
+  Frag16 aq[B16 ? MA : 1][B16 ? MA : 1];
+  if constexpr (B16) {
+#pragma unroll
+    for (int mo = 0; mo < MA; ++mo)
+#pragma unroll
+      for (int mt = 0; mt < MA; ++mt) {
+        const float *a = P.amat + (16 * mo + r16) * NA + 16 * mt + 4 * g4;
+        aq[mo][mt] = pack16(a[0], a[1], a[2], a[3]);
+      }
+    if constexpr (!SAME) {
+#pragma unroll
+      for (int kk = 0; kk < MB; ++kk)
+#pragma unroll
+        for (int nt = 0; nt < MB; ++nt) {
+          const float *b = P.bmat + (16 * kk + 4 * g4) * NB + 16 * nt + r16;
+          bq[kk][nt] = pack16(b[0], b[NB], b[2 * NB], b[3 * NB]);
+        }
+    }
+  }
+  if constexpr (!SAME && !B16) {
 #pragma unroll
     for (int mk = 0; mk < MB; ++mk)
 #pragma unroll
@@ -81,12 +145,14 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
         for (int nt = 0; nt < MB; ++nt) bf[mk][v][nt] = P.bmat[(16 * mk + 4 * g4 + v) * NB + 16 * nt + r16];
   }
+  if constexpr (!B16) {
 #pragma unroll
-  for (int mo = 0; mo < MA; ++mo)
+    for (int mo = 0; mo < MA; ++mo)
 #pragma unroll
-    for (int mt = 0; mt < MA; ++mt)
+      for (int mt = 0; mt < MA; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) af[mo][mt][v] = P.amat[(16 * mo + r16) * NA + 16 * mt + 4 * g4 + v];
+        for (int v = 0; v < 4; ++v) af[mo][mt][v] = P.amat[(16 * mo + r16) * NA + 16 * mt + 4 * g4 + v];
+  }
 
   // LDS word of signal element e in node order (row e / nb, column e mod nb)
   const bool full = nb == NB;
@@ -137,19 +203,32 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
     for (int mt = 0; mt < MA; ++mt) {
 #pragma unroll
       for (int nt = 0; nt < MB; ++nt) y1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (B16) {
 #pragma unroll
-      for (int mk = 0; mk < MB; ++mk)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float a = T[(16 * mt + r16) * STR + 16 * mk + 4 * g4 + v];
+        for (int kk = 0; kk < MB; ++kk) {
+          const float *z = T + (16 * mt + r16) * STR + 16 * kk + 4 * g4;
+          const Frag16 a = pack16(z[0], z[1], z[2], z[3]);
 #pragma unroll
           for (int nt = 0; nt < MB; ++nt) {
-            float b;
-            if constexpr (SAME) b = af[nt][mk][v];
-            else b = bf[mk][v][nt];
-            y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, y1[mt][nt], 0, 0, 0);
+            if constexpr (SAME) y1[mt][nt] = mfma16<PREC == kSPLIT>(a, aq[nt][kk], y1[mt][nt]);
+            else y1[mt][nt] = mfma16<PREC == kSPLIT>(a, bq[kk][nt], y1[mt][nt]);
           }
         }
+      } else {
+#pragma unroll
+        for (int mk = 0; mk < MB; ++mk)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float a = T[(16 * mt + r16) * STR + 16 * mk + 4 * g4 + v];
+#pragma unroll
+            for (int nt = 0; nt < MB; ++nt) {
+              float b;
+              if constexpr (SAME) b = af[nt][mk][v];
+              else b = bf[mk][v][nt];
+              y1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, y1[mt][nt], 0, 0, 0);
+            }
+          }
+      }
     }
     wave_sync();   // every read of Z is done before Y2 overwrites the tile
 
@@ -159,13 +238,24 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
       floatx4 acc[MA];
 #pragma unroll
       for (int mo = 0; mo < MA; ++mo) acc[mo] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (B16) {
+        // the result registers y1[mt][nt] are already the B operand of k chunk mt
 #pragma unroll
-      for (int mt = 0; mt < MA; ++mt)
+        for (int mt = 0; mt < MA; ++mt) {
+          const floatx4 y = y1[mt][nt];
+          const Frag16 b = pack16(y[0], y[1], y[2], y[3]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+          for (int mo = 0; mo < MA; ++mo) acc[mo] = mfma16<PREC == kSPLIT>(aq[mo][mt], b, acc[mo]);
+        }
+      } else {
 #pragma unroll
-          for (int mo = 0; mo < MA; ++mo)
-            acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mo][mt][v], y1[mt][nt][v], acc[mo], 0, 0, 0);
+        for (int mt = 0; mt < MA; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int mo = 0; mo < MA; ++mo)
+              acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mo][mt][v], y1[mt][nt][v], acc[mo], 0, 0, 0);
+      }
 #pragma unroll
       for (int mo = 0; mo < MA; ++mo)
 #pragma unroll
@@ -190,25 +280,36 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
 
 // ---------------------------------------------------------------------------- launch
 
-template <int NA, int NB, int DIR, bool SAME>
-static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
-                            hipStream_t stream, int num_cus) {
+template <int NA, int NB, int DIR, bool SAME, int PREC>
+static hipError_t launch_pdp(const PProgram &P, const float *in, float *out, int64_t nsig,
+                             hipStream_t stream, int num_cus) {
   const size_t lds = product_lds_bytes<NA, NB>(P.na * P.nb);
-  const void *k = (const void *)gft_product<NA, NB, DIR, SAME>;
+  const void *k = (const void *)gft_product<NA, NB, DIR, SAME, PREC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR, SAME>, 64 * kPWaves, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR, SAME, PREC>, 64 * kPWaves, lds) !=
           hipSuccess || occ < 1)
     occ = 1;
   const int64_t want = (nsig + kPWaves - 1) / kPWaves;
   const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_product<NA, NB, DIR, SAME>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
+  hipLaunchKernelGGL((gft_product<NA, NB, DIR, SAME, PREC>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
                      stream, P, in, out, nsig);
   return hipGetLastError();
+}
+
+template <int NA, int NB, int DIR, bool SAME>
+static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus) {
+  switch (P.prec) {
+    case kFP32: return launch_pdp<NA, NB, DIR, SAME, kFP32>(P, in, out, nsig, stream, num_cus);
+    case kBF16: return launch_pdp<NA, NB, DIR, SAME, kBF16>(P, in, out, nsig, stream, num_cus);
+    case kSPLIT: return launch_pdp<NA, NB, DIR, SAME, kSPLIT>(P, in, out, nsig, stream, num_cus);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int NA, int NB>

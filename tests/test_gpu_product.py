@@ -61,6 +61,33 @@ def test_product_parity(pair, S):
     assert O.relative_error(to_np(plan.inverse(y)), X.astype(np.float64)) <= 2 * TOL
 
 
+@pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("pair", [PRODUCTS[0], PRODUCTS[2], PRODUCTS[4], (wl.path_recursive(64), wl.path_recursive(64))],
+                         ids=_ids)
+def test_product_reduced_precision(pair, precision, tol):
+    """BF16 and split-BF16 factor products (16x16x16 BF16 MFMA, FP32 accumulation) against
+    the oracle; the split form reaches the FP32 tolerance."""
+    dev = device()
+    ga, gb = pair
+    plan = G.Plan.from_product(ga, gb, precision=precision)
+    g = wl.cartesian_product(ga, gb)
+    if g.n <= 1024:
+        lam_o, U_o = O.gft(O.laplacian_of(g))
+        Ua, min_sv = O.align(U_o, plan.basis(), lam_o)
+        assert min_sv > 1 - 1e-9
+        ref = lambda X: O.forward(X, Ua)          # noqa: E731
+    else:
+        ref = lambda X: plan.apply_host(X, 0)     # noqa: E731  (basis pinned by the host tests)
+    X = wl.gaussian(333, g.n, wl.rng_for(9, g.n, 21))
+    y = plan.forward(torch.from_numpy(X).to(dev))
+    err = O.relative_error(to_np(y), ref(X.astype(np.float64)))
+    assert err <= tol, f"{precision}: forward relative error {err:.3e}"
+    if precision == "bf16":
+        assert err > 1e-5, "BF16 error suspiciously small: products may not run in BF16"
+    xr = plan.inverse(y)
+    assert O.relative_error(to_np(xr), X.astype(np.float64)) <= 2 * tol
+
+
 def test_product_grid64_full_size_sampled():
     """64 x 64 grid as path64 x path64 (each axis with its halving reversal stages), 65536
     signals in one launch: sampled rows against the plan's FP64 algebra, round trip on all."""

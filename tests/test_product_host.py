@@ -85,7 +85,7 @@ def test_product_info_and_errors():
     with pytest.raises(G.GFTError) as e:
         plan.blocks()
     assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
-    for kwargs in ({"precision": "bf16"}, {"laplacian": "normalized"}, {"engine": "generic"}):
+    for kwargs in ({"precision": "fp16"}, {"laplacian": "normalized"}, {"engine": "generic"}):
         with pytest.raises(G.GFTError) as e:
             G.gft_plan_product(wl.path(4), wl.path(4), **kwargs)
         assert e.value.status_name == "GFT_ERR_UNSUPPORTED", kwargs
