@@ -40,9 +40,11 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 # WRITE_SIZE, scaled by the same counters on a 256 MiB device copy
 # (profiles/gft_grid8x8_hbm_traffic.md).  Valid only for the kernel source it was measured
 # on: reported as null once that file changes.
-PROFILED_TRAFFIC = {"source": "paper_1907_07875_amd/csrc/gft_butterfly.hip",
-                    "sha256_16": "510cb789a49487f4",
-                    "bytes_per_launch": 2.0 * 131165.33 * 1024 + 262148.06 * 1024}
+PROFILED_TRAFFIC = {"sources": ["paper_1907_07875_amd/csrc/gft_butterfly.hip",
+                                "paper_1907_07875_amd/csrc/butterfly_core.hpp",
+                                "paper_1907_07875_amd/csrc/device_program.hpp"],
+                    "sha256_16": "c3005ee97cb46c20",
+                    "bytes_per_launch": 2.0 * 131161.98 * 1024 + 262146.81 * 1024}
 
 
 def parse():
@@ -219,7 +221,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
 
     traffic = None
     try:
-        src = open(os.path.join(ROOT, PROFILED_TRAFFIC["source"]), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in PROFILED_TRAFFIC["sources"])
         if (args.workload == "grid8x8" and eng == "butterfly" and S == 1 << 20 and not io16
                 and hashlib.sha256(src).hexdigest()[:16] == PROFILED_TRAFFIC["sha256_16"]):
             traffic = PROFILED_TRAFFIC["bytes_per_launch"]
