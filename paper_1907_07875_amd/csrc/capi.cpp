@@ -282,7 +282,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   const int G = (int)plan->graphs.size();
   if (plan->batch) {
     // the batch kernel keeps G+1 element offsets and the scan's wave totals in LDS as well
-    const size_t fixed = batch_lds_bytes(G, 0, false) + 64 + 256;
+    const size_t fixed = batch_lds_bytes(G, 0, false) + 96 + 256;
     if (fixed + 4096 > budget) return set_error(GFT_ERR_UNSUPPORTED, "too many graphs in one batch plan");
     budget -= fixed;
   }

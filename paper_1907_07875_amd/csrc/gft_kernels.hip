@@ -425,14 +425,24 @@ __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *
   }
 }
 
+// Cost of one signal in the register phase, in element-equivalents: a 16-signal tile takes
+// about the longer of its HBM traffic (n values) and a fixed part that grows with the
+// padded slot count N = M 2^S (measured per graph shape on this kernel: the fixed part
+// equals about 11 N / 16 values' worth of traffic).
+__device__ __forceinline__ int64_t reg_cost(const UProgram &U) {
+  const int fixed = (11 * (U.M << U.S)) / 16;
+  return U.n > fixed ? U.n : fixed;
+}
+
 // Many graphs in one persistent launch.  Graph g owns signals [off[g], off[g+1]) and its
 // data starts at element elem[g] = sum_{h<g} (off[h+1]-off[h]) * n_h of in/out; each
 // workgroup first rebuilds elem[] in LDS from the device offsets (no host sync, no
-// workspace), together with the prefix sums of the graphs each engine serves: those with a
-// register-butterfly program (uprogs[g].S > 0, or none when uprogs is null) and the rest.
+// workspace), together with prefix sums over the graphs each engine serves: the cost
+// (reg_cost per signal) of those with a register-butterfly program (uprogs[g].S > 0, or none
+// when uprogs is null) and the elements of the rest.
 //   Register phase: the waves of the first reg_groups workgroups split the first class's
-//   elements into contiguous, byte-equal shares; a wave runs the 16-signal tiles whose
-//   first element lies in its share, graph by graph, through the butterfly tile loop.
+//   cost into contiguous, equal shares; a wave runs the 16-signal tiles whose first signal's
+//   cost offset lies in its share, graph by graph, through the butterfly tile loop.
 //   LDS-program phase: every workgroup takes the tiles (16 * mt signals) of the other
 //   graphs whose first element lies in its 1/gridDim share of their elements, and reloads
 //   a program's tables into LDS only when it moves to another graph.
@@ -445,62 +455,70 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   const int GP = (G + 2) & ~1;                                 // G + 1 rounded to even
   int64_t *elem = reinterpret_cast<int64_t *>(smem);           // all graphs
-  int64_t *elemR = elem + GP;                                  // register-program graphs
+  int64_t *elemR = elem + GP;                                  // register-program graphs (cost)
   int64_t *elemL = elemR + GP;                                 // LDS-program graphs
   int32_t *area = smem + 6 * GP;                               // program area / tiles
   // per-thread partial sums over contiguous chunks of graphs, an exclusive scan of the
   // kThreads partials (inclusive scans inside each wave by shuffles, then the wave totals),
   // and a second pass writing the prefix arrays
-  __shared__ int64_t wsum[2][kThreads / 64];
+  __shared__ int64_t wsum[3][kThreads / 64];
   const int per = (G + kThreads - 1) / kThreads;
   const int g0 = threadIdx.x * per, g1 = g0 + per < G ? g0 + per : G;
-  auto elems = [&](int g, bool &reg) -> int64_t {
+  // elements of graph g, and its register-phase cost (0 for the LDS-program class)
+  auto elems = [&](int g, int64_t &cost) -> int64_t {
     const int64_t ns = sig_off[g + 1] - sig_off[g];
-    reg = uprogs != nullptr && uprogs[g].S > 0;
-    return (ns > 0 ? ns : 0) * (int64_t)progs[g].n;
+    const int64_t s = ns > 0 ? ns : 0;
+    cost = (uprogs != nullptr && uprogs[g].S > 0) ? s * reg_cost(uprogs[g]) : 0;
+    return s * (int64_t)progs[g].n;
   };
-  int64_t accA = 0, accR = 0;
+  int64_t accA = 0, accR = 0, accL = 0;
   for (int g = g0; g < g1; ++g) {
-    bool reg;
-    const int64_t e = elems(g, reg);
+    int64_t c;
+    const int64_t e = elems(g, c);
     accA += e;
-    if (reg) accR += e;
+    accR += c;
+    if (c == 0) accL += e;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t incA = accA, incR = accR;
+  int64_t incA = accA, incR = accR, incL = accL;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const int64_t oA = __shfl_up(incA, d, 64), oR = __shfl_up(incR, d, 64);
+    const int64_t oA = __shfl_up(incA, d, 64), oR = __shfl_up(incR, d, 64), oL = __shfl_up(incL, d, 64);
     if (lane >= d) {
       incA += oA;
       incR += oR;
+      incL += oL;
     }
   }
   if (lane == 63) {
     wsum[0][wave] = incA;
     wsum[1][wave] = incR;
+    wsum[2][wave] = incL;
   }
   __syncthreads();
-  int64_t baseA = 0, baseR = 0;
+  int64_t baseA = 0, baseR = 0, baseL = 0;
   for (int w = 0; w < wave; ++w) {
     baseA += wsum[0][w];
     baseR += wsum[1][w];
+    baseL += wsum[2][w];
   }
   accA = baseA + incA - accA;                                  // exclusive prefixes
   accR = baseR + incR - accR;
+  accL = baseL + incL - accL;
   for (int g = g0; g < g1; ++g) {
     elem[g] = accA;
     elemR[g] = accR;
-    elemL[g] = accA - accR;
-    bool reg;
-    const int64_t e = elems(g, reg);
+    elemL[g] = accL;
+    int64_t c;
+    const int64_t e = elems(g, c);
     accA += e;
-    if (reg) accR += e;
+    accR += c;
+    if (c == 0) accL += e;
   }
   if (threadIdx.x == kThreads - 1) {
     elem[G] = accA;
     elemR[G] = accR;
-    elemL[G] = accA - accR;
+    elemL[G] = accL;
   }
   __syncthreads();
 
@@ -512,7 +530,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int64_t e0 = (int64_t)(((__int128)ER * w) / W);
     const int64_t e1 = (int64_t)(((__int128)ER * (w + 1)) / W);
     if (e0 < e1) {
-      // graph holding element e0 of the class: last g with elemR[g] <= e0
+      // graph holding cost offset e0 of the class: last g with elemR[g] <= e0
       int lo = 0, hi = G;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -524,11 +542,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         const int64_t gb = elemR[g], ge = elemR[g + 1];
         if (ge <= gb || elem[g + 1] > total_elems) continue;
         const UProgram U = uprogs[g];
-        const int64_t te = 16 * (int64_t)U.n;                  // elements per tile
+        const int64_t cs = reg_cost(U), te = 16 * cs;          // cost per signal, per tile
         const int64_t t0 = e0 > gb ? (e0 - gb + te - 1) / te : 0;
         const int64_t t1 = ((e1 < ge ? e1 : ge) - gb + te - 1) / te;
         if (t0 < t1)
-          batch_butterfly<PREC, DIR>(U, in + elem[g], out + elem[g], (ge - gb) / U.n, t0, t1, T);
+          batch_butterfly<PREC, DIR>(U, in + elem[g], out + elem[g], (ge - gb) / cs, t0, t1, T);
       }
     }
   }
@@ -718,7 +736,7 @@ static hipError_t launch_batch_pd(const DevProgram *progs, const UProgram *uprog
                                   const int64_t *sig_off, int64_t total_elems, const float *in,
                                   float *out, size_t lds, int grid, int reg_groups,
                                   hipStream_t stream) {
-  if (lds + 16 * (kThreads / 64) > 64 * 1024) {
+  if (lds + 24 * (kThreads / 64) > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC, DIR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
