@@ -71,7 +71,10 @@ constexpr int tile_words() { return 16 * ((M << S) + 4) + 4; }
 // FP32 Haar stage and multiplied on 16x16x16 BF16 MFMA with FP32 accumulation.
 // Tiles wt, wt + step, ... (< wend) of the nsig signals at in / out, by this wave, with T
 // its private LDS region of tile_words<S, M>() words.
-template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF>
+// LEAN: fewer live registers, for kernels that hold several forms at once: the LDS offsets
+// are kept as 16-bit pairs and a tile's loads are issued when the tile starts (no prefetch
+// of the next tile; other waves cover the latency).
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF, bool LEAN = false>
 __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *in, void *out,
                                                 int64_t nsig, int64_t wt, int64_t wend,
                                                 int64_t step, float *T) {
@@ -95,15 +98,30 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
   auto tw = [&](int e) -> int { return packed ? e : (GEN ? (e / n) * rstride + e % n : (e / N) * STR + (e % N)); };
 
   // LDS offsets of this lane's gathers and scatters
-  int gc[Q], sc[Q];
+  constexpr int QO = LEAN ? (Q + 1) / 2 : Q;   // offset registers (LEAN: two per register)
+  int gc[QO], sc[QO];
   constexpr int NAF = BF ? NF / 2 : NF;   // BF16: 2 words per 4-k fragment
   float af[NAF];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int gq = P.gcol[g * Q + q], sq = P.scol[g * Q + q];
-    gc[q] = gq >= 0 ? r * rstride + gq : kZero;
-    sc[q] = sq >= 0 ? r * rstride + sq : kScratch;
+    const int go = gq >= 0 ? r * rstride + gq : kZero;
+    const int so = sq >= 0 ? r * rstride + sq : kScratch;
+    if constexpr (LEAN) {   // words < 2^16: the tile region has at most 16 * 100 + 4 words
+      if (q & 1) {
+        gc[q / 2] |= go << 16;
+        sc[q / 2] |= so << 16;
+      } else {
+        gc[q / 2] = go;
+        sc[q / 2] = so;
+      }
+    } else {
+      gc[q] = go;
+      sc[q] = so;
+    }
   }
+  auto gat = [&](int q) -> int { return LEAN ? (gc[q / 2] >> (16 * (q & 1))) & 0xffff : gc[q]; };
+  auto sat = [&](int q) -> int { return LEAN ? (sc[q / 2] >> (16 * (q & 1))) & 0xffff : sc[q]; };
   if constexpr (GEN) {
     if (lane == 0) T[kZero] = 0.0f;
   }
@@ -145,7 +163,7 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
         pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * n + ec));
     }
   };
-  if (wt < wend) issue(wt);
+  if (!LEAN && wt < wend) issue(wt);
 
   constexpr int EO = OUT16 ? 8 : 4;         // values per 16-byte store
   constexpr int VO = N / (4 * EO);
@@ -163,6 +181,7 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
   for (; wt < wend; wt += step) {
     const int64_t rem = nsig - 16 * wt;
     const int lim = (int)(rem < 16 ? rem : 16) * n;
+    if constexpr (LEAN) issue(wt);
 #pragma unroll
     for (int k = 0; k < VI; ++k) {
       // a group of 4 values never crosses a row (4 | N, and 4 | n where GEN rows are
@@ -188,12 +207,14 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
     }
     wave_lds_sync();
     // next tile's loads (the last tile re-reads itself rather than branch around the loads)
-    const int64_t nxt = wt + step;
-    issue(nxt < wend ? nxt : wend - 1);
+    if constexpr (!LEAN) {
+      const int64_t nxt = wt + step;
+      issue(nxt < wend ? nxt : wend - 1);
+    }
 
     float d[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) d[q] = T[gc[q]];
+    for (int q = 0; q < Q; ++q) d[q] = T[gat(q)];
 
     if (DIR == 0) {
       // forward Haar stages, in stage order: slots lo and lo | bit, bit = 2^(S-1-t)
@@ -266,7 +287,7 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
 
     wave_lds_sync();
 #pragma unroll
-    for (int q = 0; q < Q; ++q) T[sc[q]] = res[q];
+    for (int q = 0; q < Q; ++q) T[sat(q)] = res[q];
     wave_lds_sync();
     u32x4 o[VO];
 #pragma unroll
