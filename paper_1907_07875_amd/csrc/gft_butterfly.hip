@@ -53,7 +53,7 @@ static hipError_t launch_bf_io(const UProgram &P, const void *in, void *out, int
 }
 
 bool butterfly_supported(int S, int M) {
-  return (S == 1 && (M == 16 || M == 32 || M == 48)) || (S == 2 && M == 16) || (S == 3 && M == 16);
+  return (S == 1 && (M == 16 || M == 32 || M == 48)) || (S == 2 && (M == 16 || M == 32)) || (S == 3 && M == 16);
 }
 
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
@@ -71,6 +71,8 @@ hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_
   GFT_BF_CASE(1, 16, true, true)
   GFT_BF_CASE(1, 32, true, true)
   GFT_BF_CASE(1, 48, true, false)
+  GFT_BF_CASE(2, 16, true, false)
+  GFT_BF_CASE(2, 32, true, false)
   GFT_BF_CASE(1, 48, true, true)
 #undef GFT_BF_CASE
   return hipErrorInvalidValue;

@@ -403,7 +403,7 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
 // Register-butterfly programs the batch kernel runs (FP32 blocks; BF16 blocks on the
 // padded one-stage layout): S = 1 with M = 16, 32 or 48 (48: padded layout, in the lean
 // form that keeps the whole kernel's register count below the point where it spills),
-// S = 2 with M = 16.
+// S = 2 with M = 16 (uniform or padded).
 constexpr int kBatchTileWords = bfly::tile_words<1, 48>();   // the largest of these
 template <int PREC, int DIR>
 __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *in, float *out,
@@ -417,8 +417,9 @@ __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *
       else bfly::butterfly_tiles<1, 32, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 1 && U.M == 48 && U.gen) {
       bfly::butterfly_tiles<1, 48, DIR, false, false, true, false, true>(U, in, out, nsig, t0, t1, 1, T);
-    } else if (U.S == 2 && U.M == 16 && !U.gen) {
-      bfly::butterfly_tiles<2, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+    } else if (U.S == 2 && U.M == 16) {
+      if (U.gen) bfly::butterfly_tiles<2, 16, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<2, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
     }
   } else if constexpr (PREC == kBF16) {
     if (U.gen && U.S == 1 && U.M == 16)
@@ -774,7 +775,7 @@ int batch_occupancy(int prec, size_t lds) {
 
 bool batch_butterfly_supported(int prec, const UProgram &U) {
   if (prec == kFP32)
-    return (U.S == 1 && (U.M == 16 || U.M == 32 || (U.M == 48 && U.gen))) || (U.S == 2 && U.M == 16 && !U.gen);
+    return (U.S == 1 && (U.M == 16 || U.M == 32 || (U.M == 48 && U.gen))) || (U.S == 2 && U.M == 16);
   if (prec == kBF16) return U.gen && U.S == 1 && (U.M == 16 || U.M == 32);
   return false;
 }

@@ -2,6 +2,7 @@
 #include "program.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -364,11 +365,180 @@ static bool build_butterfly_one_stage(const GraphPlan &p, int direction, UProgra
   return true;
 }
 
+// Two-stage plans that are not uniform hypercubes (odd or unequal grids under LR then UD,
+// fixed nodes at either stage, leaves split into components), FP32 blocks.  An orbit is led
+// by a node a of the first stage's sum side G+ (V_X1 or V_Z1) that is the V_X node or a
+// fixed node of the second stage there: slot 0 = a, slot 1 = its second-stage partner a'
+// in G+, slot 2 = phi1(a), slot 3 = phi1(a') (the first-stage partners, in G-), with empty
+// slots where a node is fixed or absent (a zero word).  The kernel's stage 1 combines slots
+// (0, 2) and (1, 3), stage 2 slots (0, 1) and (2, 3), so G-'s second-stage pairs must be
+// exactly (phi1(a), phi1(a')), a sign flip orienting them (the difference belongs at
+// G-'s V_X2 node).  A slot left empty before a stage receives a copy of its partner's
+// value; the layout is accepted only where such copies meet other copies or empty slots,
+// never a real value (checked per orbit).  The final slot b of an orbit is leaf block class
+// b (++, +-, -+, --); every missing partner along a value's way (a fixed node) leaves out
+// a factor sqrt 2, folded into that value's block row.
+static bool build_butterfly_two_stage(const GraphPlan &p, int direction, UProgramImage &out) {
+  const int n = p.n;
+  if (p.stages.size() != 2 || !p.right.pair_x.empty() || n < 8) return false;
+  const HostStage &s1 = p.stages[0], &s2 = p.stages[1];
+  if ((int)(s2.pair_x.size() * 2 + s2.znodes.size()) != n) return false;   // both sides split
+  if ((int)(s1.pair_x.size() * 2 + s1.znodes.size()) != n) return false;
+  std::vector<int> phi1(n, -1), phi2(n, -1), is_x2(n, 0), side(n, -1), z1(n, 0), z2(n, 0);
+  for (size_t u = 0; u < s1.pair_x.size(); ++u) {
+    phi1[s1.pair_x[u]] = s1.pair_y[u];
+    phi1[s1.pair_y[u]] = s1.pair_x[u];
+    side[s1.pair_x[u]] = 0;
+    side[s1.pair_y[u]] = 1;
+  }
+  for (int z : s1.znodes) {
+    side[z] = 0;
+    z1[z] = 1;
+  }
+  for (size_t u = 0; u < s2.pair_x.size(); ++u) {
+    phi2[s2.pair_x[u]] = s2.pair_y[u];
+    phi2[s2.pair_y[u]] = s2.pair_x[u];
+    is_x2[s2.pair_x[u]] = 1;
+  }
+  for (int z : s2.znodes) z2[z] = 1;
+  for (int i = 0; i < n; ++i)
+    if (side[i] < 0 || (phi2[i] < 0 && !z2[i]) || (phi2[i] >= 0 && side[phi2[i]] != side[i])) return false;
+  // orbits: slots {a, a', phi1(a), phi1(a')}, -1 empty
+  std::vector<std::array<int, 4>> orb;
+  std::vector<int> seen(n, 0);
+  for (int a = 0; a < n; ++a) {
+    if (side[a] != 0 || !(is_x2[a] || z2[a])) continue;
+    std::array<int, 4> o{a, z2[a] ? -1 : phi2[a], -1, -1};
+    if (!z1[a]) o[2] = phi1[a];
+    if (o[1] >= 0 && !z1[o[1]]) o[3] = phi1[o[1]];
+    // G-'s second-stage structure must match: a pair (phi1 a, phi1 a') or fixed nodes
+    if (o[2] >= 0 && o[3] >= 0 && phi2[o[2]] != o[3]) return false;
+    if (o[2] >= 0 && o[3] < 0 && !z2[o[2]]) return false;
+    if (o[2] < 0 && o[3] >= 0) return false;
+    // copies made by stage 1 (slot j empty-partner) must not meet real values at stage 2
+    const bool e0 = o[0] < 0, e1 = o[1] < 0, e2 = o[2] < 0, e3 = o[3] < 0;
+    if (e2 && !e0 && !e3) return false;
+    if (e3 && !e1 && !e2) return false;
+    for (int v : o)
+      if (v >= 0) {
+        if (seen[v]) return false;
+        seen[v] = 1;
+      }
+    orb.push_back(o);
+  }
+  for (int i = 0; i < n; ++i)
+    if (!seen[i]) return false;
+  const int O = (int)orb.size();
+  // final slot (leaf class) and orbit of every node's value after the two stages: slot 0
+  // holds a's label, slot 1 a', slot 2 G-'s V_X2 (or fixed) node, slot 3 its V_Y2 node
+  std::vector<int> fslot(n, -1), forb(n, -1), flip(O, 0);
+  for (int o = 0; o < O; ++o) {
+    const auto &v = orb[o];
+    fslot[v[0]] = 0;
+    forb[v[0]] = o;
+    if (v[1] >= 0) {
+      fslot[v[1]] = 1;
+      forb[v[1]] = o;
+    }
+    if (v[2] >= 0) {
+      const bool sw = v[3] >= 0 && !is_x2[v[2]];   // G-'s V_X2 node sits in slot 3
+      flip[o] = sw;
+      const int lx = sw ? v[3] : v[2], ly = sw ? v[2] : v[3];
+      fslot[lx] = 2;
+      forb[lx] = o;
+      if (ly >= 0) {
+        fslot[ly] = 3;
+        forb[ly] = o;
+      }
+    }
+  }
+  // super-blocks: leaf blocks of class b packed by columns, rows = orbit positions
+  int maxcol[4] = {0, 0, 0, 0};
+  for (const HostBlock &B : p.blocks) {
+    const int b = fslot[B.nodes[0]];
+    for (int k = 0; k < B.size; ++k)
+      if (fslot[B.nodes[k]] != b || B.depth != 2) return false;
+    maxcol[b] += B.size;
+  }
+  const int wide = std::max(O, std::max(std::max(maxcol[0], maxcol[1]), std::max(maxcol[2], maxcol[3])));
+  const int M = wide <= 16 ? 16 : (wide <= 32 ? 32 : 0);
+  if (M == 0) return false;
+  const int NB = 4, KC = M / 4, NT = M / 16, Q = NB * M / 4;
+  std::vector<std::vector<double>> Vs(4, std::vector<double>((size_t)M * M, 0.0));
+  std::vector<std::vector<int>> outp(4, std::vector<int>(M, -1));
+  int ncol[4] = {0, 0, 0, 0};
+  for (const HostBlock &B : p.blocks) {
+    const int b = fslot[B.nodes[0]];
+    for (int k = 0; k < B.size; ++k) {
+      const int v = B.nodes[k];
+      const double zs = (z1[v] && side[v] == 0 ? std::sqrt(2.0) : 1.0) * (z2[v] ? std::sqrt(2.0) : 1.0);
+      for (int c = 0; c < B.size; ++c)
+        Vs[b][(size_t)forb[v] * M + ncol[b] + c] = zs * B.scale * B.V[(size_t)k * B.size + c];
+    }
+    for (int c = 0; c < B.size; ++c) outp[b][ncol[b] + c] = B.out_pos[c];
+    ncol[b] += B.size;
+  }
+  auto node_at = [&](int o, int b) { return o < O ? orb[o][b] : -1; };
+  UProgramImage im;
+  im.prog.S = 2;
+  im.prog.M = M;
+  im.prog.n = n;
+  im.prog.dir = direction;
+  im.prog.prec = GFT_FP32;
+  im.prog.gen = 1;
+  im.gcol.assign((size_t)4 * Q, -1);
+  im.scol.assign((size_t)4 * Q, -1);
+  im.flips.assign(8, 0);
+  for (int g = 0; g < 4; ++g) {
+    uint64_t fw = 0;
+    for (int kc = 0; kc < KC; ++kc)
+      for (int b = 0; b < NB; ++b)
+        im.gcol[(size_t)g * Q + kc * NB + b] = direction == 0 ? node_at(4 * kc + g, b) : outp[b][4 * kc + g];
+    for (int nt = 0; nt < NT; ++nt)
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * nt + 4 * g + v;
+        for (int b = 0; b < NB; ++b) {
+          if (direction == 0)
+            im.scol[(size_t)g * Q + (b * NT + nt) * 4 + v] = outp[b][c];
+          else
+            im.scol[(size_t)g * Q + (nt * 4 + v) * NB + b] = node_at(c, b);
+        }
+      }
+    // flip bit of register set j, stage t = 1, lo-slot rank k = 1 (slots 2, 3): 4 j + 3;
+    // j = kc (forward, orbit 4 kc + g) or nt * 4 + v (inverse, orbit 16 nt + 4 g + v)
+    if (direction == 0) {
+      for (int kc = 0; kc < KC; ++kc)
+        if (4 * kc + g < O && flip[4 * kc + g]) fw |= 1ull << (4 * kc + 3);
+    } else {
+      for (int j = 0; j < NT * 4; ++j) {
+        const int o = 16 * (j / 4) + 4 * g + j % 4;
+        if (o < O && flip[o]) fw |= 1ull << (4 * j + 3);
+      }
+    }
+    im.flips[2 * g] = (uint32_t)fw;
+    im.flips[2 * g + 1] = (uint32_t)(fw >> 32);
+  }
+  auto aval = [&](int b, int row, int k) {
+    const int o = direction == 0 ? k : row;
+    const int c = direction == 0 ? row : k;
+    return Vs[b][(size_t)o * M + c];
+  };
+  im.afrag.assign((size_t)NB * NT * KC * 64, 0.0f);
+  for (int b = 0; b < NB; ++b)
+    for (int nt = 0; nt < NT; ++nt)
+      for (int kc = 0; kc < KC; ++kc)
+        for (int lane = 0; lane < 64; ++lane)
+          im.afrag[((size_t)(b * NT + nt) * KC + kc) * 64 + lane] = (float)aval(b, 16 * nt + lane % 16, 4 * kc + lane / 16);
+  out = std::move(im);
+  return true;
+}
+
 static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramImage &out);
 
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int precision) {
   if (precision == GFT_FP32 && build_butterfly_uniform(p, direction, out)) return true;
-  return build_butterfly_one_stage(p, direction, out, precision);
+  if (build_butterfly_one_stage(p, direction, out, precision)) return true;
+  return precision == GFT_FP32 && build_butterfly_two_stage(p, direction, out);
 }
 
 static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramImage &out) {

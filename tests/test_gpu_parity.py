@@ -92,9 +92,9 @@ def test_auto_engine_choice():
 
 def test_butterfly_engine_rejects_non_uniform_plan():
     dev = device()
-    plan = G.Plan.from_graph(wl.grid(5, 5), engine="butterfly")       # two stages, n odd
+    plan = G.Plan.from_graph(wl.grid(11, 11), engine="butterfly")     # two stages, 36-node leaf
     with pytest.raises(G.GFTError) as e:
-        plan.forward(torch.zeros((16, 25), device=dev))
+        plan.forward(torch.zeros((16, 121), device=dev))
     assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
 
 
@@ -291,6 +291,22 @@ def test_one_stage_butterfly_general(g, S):
     assert G.Plan.from_graph(g, precision="bf16").engine() == "butterfly"
     _, _, _, err = _check_graph(g, X, engine="butterfly", precision="bf16", tol=2e-2, basis_tol=1e-2)
     assert err > 1e-5, "BF16 error suspiciously small: blocks may not run in BF16"
+
+
+TWO_STAGE_GRAPHS = [wl.grid(5, 5), wl.grid(6, 6), wl.grid(7, 7), wl.grid(3, 3), wl.grid(5, 7),
+                    wl.grid(8, 5), wl.grid(9, 9), wl.grid(10, 10), wl.cycle_two_stage(20),
+                    wl.cycle_two_stage(44)]
+
+
+@pytest.mark.parametrize("S", [1, 17, 1003])
+@pytest.mark.parametrize("g", TWO_STAGE_GRAPHS, ids=lambda g: f"{g.name}{g.n}")
+def test_two_stage_butterfly_general(g, S):
+    """Two-stage plans that are not uniform hypercubes (odd and unequal grids under LR then
+    UD, fixed nodes at either stage, components) on the register butterfly's padded
+    two-stage layout: 16- and 32-slot sides, sign flips on the difference side, ragged S."""
+    assert G.Plan.from_graph(g).engine() == "butterfly"
+    X = wl.gaussian(S, g.n, wl.rng_for(9, g.n, S, 5))
+    _check_graph(g, X, engine="butterfly")
 
 
 @pytest.mark.parametrize("io", [("bf16", "bf16"), ("fp32", "bf16"), ("bf16", "fp32")])
