@@ -401,10 +401,12 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
 }
 
 // Register-butterfly programs the batch kernel runs (FP32 blocks; BF16 blocks on the
-// padded one-stage layout): S = 1 with M = 16, 32 or 48 (48: padded layout, in the lean
-// form that keeps the whole kernel's register count below the point where it spills),
-// S = 2 with M = 16 (uniform or padded).
-constexpr int kBatchTileWords = bfly::tile_words<1, 48>();   // the largest of these
+// padded one-stage layout): S = 1 with M = 16, 32 or 48 (48: padded layout), S = 2 with
+// M = 16 (uniform or padded) or 32 (padded).  The 48- and 32-slot padded forms run the lean
+// tile loop (packed offsets, no next-tile prefetch), which keeps the kernel at 256 VGPRs;
+// the two-stage 32-slot form still spills a little in its own path (measured: the batch
+// is faster with it than with those grids on their LDS programs).
+constexpr int kBatchTileWords = bfly::tile_words<2, 32>();   // the largest of these
 template <int PREC, int DIR>
 __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *in, float *out,
                                                 int64_t nsig, int64_t t0, int64_t t1, float *T) {
@@ -417,6 +419,8 @@ __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *
       else bfly::butterfly_tiles<1, 32, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 1 && U.M == 48 && U.gen) {
       bfly::butterfly_tiles<1, 48, DIR, false, false, true, false, true>(U, in, out, nsig, t0, t1, 1, T);
+    } else if (U.S == 2 && U.M == 32 && U.gen) {
+      bfly::butterfly_tiles<2, 32, DIR, false, false, true, false, true>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 2 && U.M == 16) {
       if (U.gen) bfly::butterfly_tiles<2, 16, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
       else bfly::butterfly_tiles<2, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
@@ -775,7 +779,7 @@ int batch_occupancy(int prec, size_t lds) {
 
 bool batch_butterfly_supported(int prec, const UProgram &U) {
   if (prec == kFP32)
-    return (U.S == 1 && (U.M == 16 || U.M == 32 || (U.M == 48 && U.gen))) || (U.S == 2 && U.M == 16);
+    return (U.S == 1 && (U.M == 16 || U.M == 32 || (U.M == 48 && U.gen))) || (U.S == 2 && (U.M == 16 || (U.M == 32 && U.gen)));
   if (prec == kBF16) return U.gen && U.S == 1 && (U.M == 16 || U.M == 32);
   return false;
 }

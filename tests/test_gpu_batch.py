@@ -62,8 +62,8 @@ def test_config4_mixed_batch_forward_inverse():
 
 def _batch_engine(g):
     """The engine a batch plan runs graph g on: the register-butterfly forms the batch kernel
-    compiles (one stage with sides of at most 48 nodes, or two stages on 16-slot sides: the
-    test's two-stage graphs have n <= 64 exactly then), else the LDS program."""
+    compiles (one stage with sides of at most 48 nodes, or two stages on 16- or 32-slot
+    sides: the test's two-stage graphs have n <= 100 exactly then), else the LDS program."""
     try:
         p = G.Plan.from_graph(g, engine="butterfly")
         p.prepare()
@@ -74,7 +74,7 @@ def _batch_engine(g):
         fixed = int(np.sum(phi == np.arange(g.n)))
         pairs = (g.n - fixed) // 2
         return "butterfly" if pairs + fixed <= 48 else "generic"
-    return "butterfly" if len(g.stages) == 2 and g.n <= 64 else "generic"   # 16-slot sides
+    return "butterfly" if len(g.stages) == 2 and g.n <= 100 else "generic"   # <= 32-slot sides
 
 
 @pytest.mark.parametrize("direction", ["forward", "inverse"])
@@ -90,7 +90,7 @@ def test_batch_matches_single_graph_plans(direction):
               wl.symmetric_bipartite(120, wl.rng_for(4, 120)), wl.grid(7, 7), wl.grid(9, 9)]
     counts = np.array([1, 17, 300, 47, 16, 1000, 33, 5, 129, 77, 250, 3, 61, 40, 45, 70])
     engines = [_batch_engine(g) for g in graphs]
-    assert engines.count("butterfly") >= 10 and engines.count("generic") >= 3, engines
+    assert engines.count("butterfly") >= 12 and engines.count("generic") >= 2, engines
     xs, flat, off = _pack(graphs, counts, rng)
     offs = torch.from_numpy(off).to(dev)
     apply = G.gft_forward_batch if direction == "forward" else G.gft_inverse_batch
