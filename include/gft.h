@@ -126,12 +126,17 @@ typedef enum {
                              /* ascending eigenvalue inside each block                */
 } gft_order;
 
-/* Kernel family.  AUTO picks, for single-graph plans: the register-butterfly engine when
- * the plan is a uniform hypercube (every stage pairs every node, 2^S equal connected leaf
- * blocks, each Haar orbit holding one node of every block), its shape is compiled in and
- * the blocks are FP32; else the large-signal engine when a tile of 16 signals does not fit
- * a workgroup's LDS or a leaf block has 192 nodes or more; else the generic engine.  Batch
- * plans always run the generic engine. */
+/* Kernel family.  AUTO picks, for single-graph plans without right Haar units: the
+ * register-butterfly engine when the plan is a uniform hypercube (every stage pairs every
+ * node, 2^S equal connected leaf blocks, each Haar orbit holding one node of every block)
+ * of a compiled shape with FP32 blocks, or a one-stage plan with 8 <= n <= 96 and sides of
+ * at most 48 nodes (FP32 or BF16 blocks), or a two-stage plan whose orbits and leaf blocks
+ * fit 16 or 32 slots per side (FP32 blocks); else the large-signal engine when a tile of 16
+ * signals does not fit a workgroup's LDS or a leaf block has 192 nodes or more; else the
+ * generic engine.  Batch plans run each graph that a register-butterfly form of the batch
+ * kernel covers (one stage with sides of at most 48 nodes, two stages on 16- or 32-slot
+ * sides, FP32 blocks; BF16 blocks: one stage) in its register phase and the others on their
+ * generic-engine programs; GFT_ENGINE_GENERIC puts every graph on the latter. */
 typedef enum {
   GFT_ENGINE_AUTO = 0,
   GFT_ENGINE_GENERIC = 1,     /* LDS-program engine (one fused kernel)                  */

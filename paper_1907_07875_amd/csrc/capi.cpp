@@ -287,7 +287,8 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     budget -= fixed;
   }
 
-  // Register-butterfly engine for single-graph uniform hypercube plans.
+  // Register-butterfly engine for single-graph plans of the shapes it covers (uniform
+  // hypercubes, padded one- and two-stage layouts).
   UProgramImage ub[2];
   bool use_bf = false;
   const int prec = plan->opts.precision;
@@ -302,9 +303,9 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
       return set_error(GFT_ERR_UNSUPPORTED,
                        "the register-butterfly engine does not cover this plan (needs a uniform "
-                       "hypercube with a compiled shape, or one stage with 8 <= n <= 64 and sides of at "
-                       "most 32 nodes; "
-                       "BF16 blocks: the one-stage form only)");
+                       "hypercube with a compiled shape, one stage with 8 <= n <= 96 and sides of at "
+                       "most 48 nodes, or two stages on sides of at most 32 slots, and no right Haar "
+                       "units; BF16 blocks: the one-stage form only)");
   }
 
   // Batch plans: every graph whose plan the batch kernel's register-butterfly forms cover

@@ -310,11 +310,12 @@ def test_two_stage_butterfly_general(g, S):
 
 
 @pytest.mark.parametrize("io", [("bf16", "bf16"), ("fp32", "bf16"), ("bf16", "fp32")])
-@pytest.mark.parametrize("g", [wl.config3_graph(), wl.path(12), wl.cycle(22), wl.path(44), wl.cycle(48)],
+@pytest.mark.parametrize("g", [wl.config3_graph(), wl.path(12), wl.cycle(22), wl.path(44), wl.cycle(48),
+                               wl.grid(5, 5), wl.grid(10, 10)],
                          ids=lambda g: f"{g.name}{g.n}")
 def test_one_stage_butterfly_storage(io, g):
-    """BF16 storage on the one-stage layouts (16-byte groups of 8 values split across padded
-    rows when n = 4 mod 8) equals FP32 storage rounded."""
+    """BF16 storage on the padded layouts, one and two stages (16-byte groups of 8 values
+    split across padded rows when n = 4 mod 8) equals FP32 storage rounded."""
     dev = device()
     X = wl.gaussian(1003, g.n, wl.rng_for(9, g.n, 8))
     plan = G.Plan.from_graph(g, in_dtype=io[0], out_dtype=io[1])
