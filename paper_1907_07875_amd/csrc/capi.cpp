@@ -299,7 +299,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (!plan->batch && (plan->opts.engine == GFT_ENGINE_AUTO || plan->opts.engine == GFT_ENGINE_BUTTERFLY) &&
       (prec == GFT_FP32 || prec == GFT_BF16)) {
     use_bf = build_butterfly(plan->graphs[0], 0, ub[0], prec) && build_butterfly(plan->graphs[0], 1, ub[1], prec) &&
-             butterfly_supported(ub[0].prog.S, ub[0].prog.M);
+             butterfly_supported(ub[0].prog) && butterfly_supported(ub[1].prog);
     if (!use_bf && plan->opts.engine == GFT_ENGINE_BUTTERFLY)
       return set_error(GFT_ERR_UNSUPPORTED,
                        "the register-butterfly engine does not cover this plan (needs a uniform "

@@ -95,6 +95,14 @@ struct UProgram {
   const float *afrag;
 };
 
+// Register-butterfly shapes with a compiled single-graph kernel: uniform (gen = 0) S = 1
+// with M = 16 or 32, S = 2 or 3 with M = 16; padded (gen = 1) S = 1 with M = 16, 32 or 48,
+// S = 2 with M = 16 or 32.
+inline bool butterfly_shape_compiled(int S, int M, bool gen) {
+  if (gen) return (S == 1 && (M == 16 || M == 32 || M == 48)) || (S == 2 && (M == 16 || M == 32));
+  return (S == 1 && (M == 16 || M == 32)) || ((S == 2 || S == 3) && M == 16);
+}
+
 // Large-signal engine (signals that do not fit a workgroup's LDS tile, or large leaf
 // blocks): three passes through a block-contiguous workspace W with row stride ldw.
 //   pass 1 / pass 3 (stage + gather): a tile of a few signal rows is copied as is into LDS

@@ -52,9 +52,7 @@ static hipError_t launch_bf_io(const UProgram &P, const void *in, void *out, int
                : launch_bf<S, M, DIR, false, false, GEN, BF>(P, in, out, nsig, stream, num_cus);
 }
 
-bool butterfly_supported(int S, int M) {
-  return (S == 1 && (M == 16 || M == 32 || M == 48)) || (S == 2 && (M == 16 || M == 32)) || (S == 3 && M == 16);
-}
+bool butterfly_supported(const UProgram &P) { return butterfly_shape_compiled(P.S, P.M, P.gen != 0); }
 
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16) {

@@ -39,7 +39,7 @@ hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const 
                              const int32_t *omap, int ldy, hipStream_t stream);
 
 // Register-butterfly engine (uniform hypercube plans).
-bool butterfly_supported(int S, int M);
+bool butterfly_supported(const UProgram &P);   // a kernel is compiled for its shape
 // in16 / out16: the input / output array holds BF16 values (else FP32).
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
                             hipStream_t stream, int num_cus, bool in16, bool out16);

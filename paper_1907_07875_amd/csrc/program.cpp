@@ -536,7 +536,14 @@ static bool build_butterfly_two_stage(const GraphPlan &p, int direction, UProgra
 static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramImage &out);
 
 bool build_butterfly(const GraphPlan &p, int direction, UProgramImage &out, int precision) {
-  if (precision == GFT_FP32 && build_butterfly_uniform(p, direction, out)) return true;
+  // a uniform layout of a shape with no compiled kernel (e.g. two blocks of 48) falls
+  // through to the padded layouts, which take every uniform one- and two-stage plan too
+  UProgramImage u;
+  if (precision == GFT_FP32 && build_butterfly_uniform(p, direction, u) &&
+      butterfly_shape_compiled(u.prog.S, u.prog.M, false)) {
+    out = std::move(u);
+    return true;
+  }
   if (build_butterfly_one_stage(p, direction, out, precision)) return true;
   return precision == GFT_FP32 && build_butterfly_two_stage(p, direction, out);
 }

@@ -275,7 +275,9 @@ ONE_STAGE_GRAPHS = [wl.config3_graph(), wl.path(17), wl.cycle(31), wl.path(63),
                     wl.weighted_symmetric_path(36, wl.rng_for(9, 36)),
                     # 48-slot sides
                     wl.path(72), wl.cycle(84), wl.cycle(92), wl.symmetric_bipartite(72, wl.rng_for(4, 72)),
-                    wl.weighted_symmetric_path(90, wl.rng_for(9, 90))]
+                    wl.weighted_symmetric_path(90, wl.rng_for(9, 90)),
+                    # equal 48-node blocks: no uniform kernel of that shape, the padded layout
+                    wl.path(96)]
 
 
 @pytest.mark.parametrize("S", [1, 15, 17, 1003])
@@ -295,7 +297,9 @@ def test_one_stage_butterfly_general(g, S):
 
 TWO_STAGE_GRAPHS = [wl.grid(5, 5), wl.grid(6, 6), wl.grid(7, 7), wl.grid(3, 3), wl.grid(5, 7),
                     wl.grid(8, 5), wl.grid(9, 9), wl.grid(10, 10), wl.cycle_two_stage(20),
-                    wl.cycle_two_stage(44)]
+                    wl.cycle_two_stage(44),
+                    # equal 32-node blocks: no uniform kernel of that shape, the padded layout
+                    wl.grid(16, 8)]
 
 
 @pytest.mark.parametrize("S", [1, 17, 1003])
@@ -325,3 +329,16 @@ def test_one_stage_butterfly_storage(io, g):
     y = plan.forward(x)
     assert torch.equal(y, ref.forward(x.float()).to(y.dtype))
     assert torch.equal(plan.inverse(y), ref.inverse(y.float()).to(x.dtype))
+
+
+def test_every_mixed_batch_graph_runs_single():
+    """Each of the 146 graphs of the mixed batch, planned alone with the automatic engine
+    choice, runs (every shape the choice can land on has a compiled kernel) and matches
+    its plan's FP64 algebra."""
+    dev = device()
+    for g in wl.config4_graphs(wl.rng_for(4)):
+        plan = G.Plan.from_graph(g)
+        X = wl.gaussian(19, g.n, wl.rng_for(4, 7, g.n))
+        y = to_np(plan.forward(torch.from_numpy(X).to(dev)))
+        ref = plan.apply_host(X.astype(np.float64), 0)
+        assert O.relative_error(y, ref) <= TOL_FP32, f"{g.name}{g.n} on {plan.engine()}"
