@@ -74,7 +74,12 @@ constexpr int tile_words() { return 16 * ((M << S) + 4) + 4; }
 // LEAN: fewer live registers, for kernels that hold several forms at once: the LDS offsets
 // are kept as 16-bit pairs and a tile's loads are issued when the tile starts (no prefetch
 // of the next tile; other waves cover the latency).
-template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF, bool LEAN = false>
+// PF (not LEAN): tiles whose loads are in flight while a tile is computed.  One suffices
+// where many waves share a SIMD; a kernel held to few waves by its register budget keeps
+// more loads in flight per wave with PF register sets (the tile loop is unrolled PF times,
+// so that each set keeps fixed registers).
+template <int S, int M, int DIR, bool IN16, bool OUT16, bool GEN, bool BF, bool LEAN = false,
+          int PF = 1>
 __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *in, void *out,
                                                 int64_t nsig, int64_t wt, int64_t wend,
                                                 int64_t step, float *T) {
@@ -138,7 +143,8 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
   constexpr int EI = IN16 ? 8 : 4;          // values per 16-byte load
   constexpr int VI = N / (4 * EI);          // loads per lane per 16-signal tile (16n <= 16N)
   constexpr int H = EI / 4;                 // LDS groups of 4 values per load
-  u32x4 pre[VI];
+  static_assert(PF >= 1 && (PF == 1 || !LEAN), "prefetch depth");
+  u32x4 pre[PF][VI];
   // LDS words of this lane's load groups (-1: past the tile's 16 rows, never written)
   int ld_at[VI * H];
 #pragma unroll
@@ -150,7 +156,7 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
     }
   // Whole 16-byte groups only: a tile's last lim mod EI values (GEN partial tiles) are read
   // by scalar loads in the loop below.
-  auto issue = [&](int64_t t) {
+  auto issue = [&](int64_t t, u32x4(&dst)[VI]) {
     const int64_t rem = nsig - 16 * t;
     const int limv = ((int)(rem < 16 ? rem : 16) * n) & ~(EI - 1);
 #pragma unroll
@@ -158,12 +164,20 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
       const int e = EI * (lane + 64 * k);
       const int ec = e < limv ? e : limv - EI;
       if constexpr (IN16)
-        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * n + ec));
+        dst[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const uint16_t *>(in) + t * 16 * n + ec));
       else
-        pre[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * n + ec));
+        dst[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(static_cast<const float *>(in) + t * 16 * n + ec));
     }
   };
-  if (!LEAN && wt < wend) issue(wt);
+  // loads of the first PF tiles (tiles past the wave's last one re-read that tile rather
+  // than branch around the loads)
+  if (!LEAN && wt < wend) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int64_t t = wt + j * step;
+      issue(t < wend ? t : wend - 1, pre[j]);
+    }
+  }
 
   constexpr int EO = OUT16 ? 8 : 4;         // values per 16-byte store
   constexpr int VO = N / (4 * EO);
@@ -178,154 +192,159 @@ __device__ __forceinline__ void butterfly_tiles(const UProgram &P, const void *i
       st_at[k * HO + h] = packed || e < 16 * n ? tw(e) : 0;
     }
 
-  for (; wt < wend; wt += step) {
-    const int64_t rem = nsig - 16 * wt;
-    const int lim = (int)(rem < 16 ? rem : 16) * n;
-    if constexpr (LEAN) issue(wt);
+  while (wt < wend) {
 #pragma unroll
-    for (int k = 0; k < VI; ++k) {
-      // a group of 4 values never crosses a row (4 | N, and 4 | n where GEN rows are
-      // padded); a packed GEN tile is contiguous and the words past 16n it receives are
-      // never gathered
-      if constexpr (IN16) {
-        const u32x4 w = pre[k];
-        if (ld_at[2 * k] >= 0)
-          *reinterpret_cast<floatx4 *>(T + ld_at[2 * k]) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
-        if (ld_at[2 * k + 1] >= 0)
-          *reinterpret_cast<floatx4 *>(T + ld_at[2 * k + 1]) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
-      } else {
-        if (ld_at[k] >= 0) *reinterpret_cast<u32x4 *>(T + ld_at[k]) = pre[k];
-      }
-    }
-    if constexpr (GEN) {
-      for (int e = (lim & ~(EI - 1)) + lane; e < lim; e += 64) {   // partial tile's tail
-        if constexpr (IN16)
-          T[tw(e)] = __uint_as_float((uint32_t)static_cast<const uint16_t *>(in)[wt * 16 * n + e] << 16);
-        else
-          T[tw(e)] = static_cast<const float *>(in)[wt * 16 * n + e];
-      }
-    }
-    wave_lds_sync();
-    // next tile's loads (the last tile re-reads itself rather than branch around the loads)
-    if constexpr (!LEAN) {
-      const int64_t nxt = wt + step;
-      issue(nxt < wend ? nxt : wend - 1);
-    }
-
-    float d[Q];
+    for (int j = 0; j < PF; ++j, wt += step) {
+      if (wt >= wend) break;
+      u32x4(&cur)[VI] = pre[j];
+      const int64_t rem = nsig - 16 * wt;
+      const int lim = (int)(rem < 16 ? rem : 16) * n;
+      if constexpr (LEAN) issue(wt, cur);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) d[q] = T[gat(q)];
-
-    if (DIR == 0) {
-      // forward Haar stages, in stage order: slots lo and lo | bit, bit = 2^(S-1-t)
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-          const int bit = 1 << (S - 1 - t);
-          int k = 0;
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-            if (!(b & bit)) {
-              const uint32_t f = (uint32_t)(flips >> (kc * FB + t * PPS + k)) & 1u;
-              const float a = d[kc * NB + b], c = d[kc * NB + (b | bit)];
-              d[kc * NB + b] = a + c;
-              d[kc * NB + (b | bit)] = flip_sign(a - c, f);
-              ++k;
-            }
-        }
-    }
-
-    float res[Q];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (BF) {
-#pragma unroll
-          for (int k4 = 0; k4 < KC / 4; ++k4) {
-            const int f = (b * NT + nt) * (KC / 4) + k4;
-            const u32x2 aw = {__float_as_uint(af[2 * f]), __float_as_uint(af[2 * f + 1])};
-            const u32x2 bw = {bf16_bits(d[(4 * k4) * NB + b]) | (bf16_bits(d[(4 * k4 + 1) * NB + b]) << 16),
-                              bf16_bits(d[(4 * k4 + 2) * NB + b]) | (bf16_bits(d[(4 * k4 + 3) * NB + b]) << 16)};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, aw),
-                                                            __builtin_bit_cast(bf16x4, bw), acc, 0, 0, 0);
-          }
+      for (int k = 0; k < VI; ++k) {
+        // a group of 4 values never crosses a row (4 | N, and 4 | n where GEN rows are
+        // padded); a packed GEN tile is contiguous and the words past 16n it receives are
+        // never gathered
+        if constexpr (IN16) {
+          const u32x4 w = cur[k];
+          if (ld_at[2 * k] >= 0)
+            *reinterpret_cast<floatx4 *>(T + ld_at[2 * k]) = floatx4{bf16_lo(w[0]), bf16_hi(w[0]), bf16_lo(w[1]), bf16_hi(w[1])};
+          if (ld_at[2 * k + 1] >= 0)
+            *reinterpret_cast<floatx4 *>(T + ld_at[2 * k + 1]) = floatx4{bf16_lo(w[2]), bf16_hi(w[2]), bf16_lo(w[3]), bf16_hi(w[3])};
         } else {
-#pragma unroll
-          for (int kc = 0; kc < KC; ++kc)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[(b * NT + nt) * KC + kc], d[kc * NB + b],
-                                                       acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (DIR == 0) res[(b * NT + nt) * 4 + v] = acc[v];
-          else res[(nt * 4 + v) * NB + b] = acc[v];
+          if (ld_at[k] >= 0) *reinterpret_cast<u32x4 *>(T + ld_at[k]) = cur[k];
         }
       }
-
-    if (DIR == 1) {
-      // inverse Haar stages, in reverse stage order, on each orbit's 2^S slots
-#pragma unroll
-      for (int o = 0; o < NT * 4; ++o)
-#pragma unroll
-        for (int t = S - 1; t >= 0; --t) {
-          const int bit = 1 << (S - 1 - t);
-          int k = 0;
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-            if (!(b & bit)) {
-              const uint32_t f = (uint32_t)(flips >> (o * FB + t * PPS + k)) & 1u;
-              const float a = res[o * NB + b], c = flip_sign(res[o * NB + (b | bit)], f);
-              res[o * NB + b] = a + c;
-              res[o * NB + (b | bit)] = a - c;
-              ++k;
-            }
-        }
-    }
-
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) T[sat(q)] = res[q];
-    wave_lds_sync();
-    u32x4 o[VO];
-#pragma unroll
-    for (int k = 0; k < VO; ++k) {
-      const float *src = T + st_at[k * HO];
-      if constexpr (OUT16) {
-        const floatx4 a = *reinterpret_cast<const floatx4 *>(src);
-        const floatx4 b = *reinterpret_cast<const floatx4 *>(T + st_at[k * HO + 1]);
-        o[k] = u32x4{bf16_bits(a[0]) | (bf16_bits(a[1]) << 16), bf16_bits(a[2]) | (bf16_bits(a[3]) << 16),
-                     bf16_bits(b[0]) | (bf16_bits(b[1]) << 16), bf16_bits(b[2]) | (bf16_bits(b[3]) << 16)};
-      } else {
-        o[k] = *reinterpret_cast<const u32x4 *>(src);
-      }
-    }
-    auto dst_at = [&](int e) -> u32x4 * {
-      if constexpr (OUT16)
-        return reinterpret_cast<u32x4 *>(static_cast<uint16_t *>(out) + wt * 16 * n + e);
-      else
-        return reinterpret_cast<u32x4 *>(static_cast<float *>(out) + wt * 16 * n + e);
-    };
-    if (!GEN && lim == 16 * N) {   // full tile (wave-uniform branch)
-#pragma unroll
-      for (int k = 0; k < VO; ++k) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
-    } else {
-      const int limv = lim & ~(EO - 1);   // whole groups; GEN tail values stored one by one
-#pragma unroll
-      for (int k = 0; k < VO; ++k)
-        if (EO * (lane + 64 * k) < limv) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
       if constexpr (GEN) {
-        for (int e = limv + lane; e < lim; e += 64) {
-          if constexpr (OUT16)
-            static_cast<uint16_t *>(out)[wt * 16 * n + e] = (uint16_t)bf16_bits(T[tw(e)]);
+        for (int e = (lim & ~(EI - 1)) + lane; e < lim; e += 64) {   // partial tile's tail
+          if constexpr (IN16)
+            T[tw(e)] = __uint_as_float((uint32_t)static_cast<const uint16_t *>(in)[wt * 16 * n + e] << 16);
           else
-            static_cast<float *>(out)[wt * 16 * n + e] = T[tw(e)];
+            T[tw(e)] = static_cast<const float *>(in)[wt * 16 * n + e];
         }
       }
+      wave_lds_sync();
+      // loads of the tile PF steps ahead into the register set just emptied
+      if constexpr (!LEAN) {
+        const int64_t nxt = wt + PF * step;
+        issue(nxt < wend ? nxt : wend - 1, cur);
+      }
+
+      float d[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) d[q] = T[gat(q)];
+
+      if (DIR == 0) {
+        // forward Haar stages, in stage order: slots lo and lo | bit, bit = 2^(S-1-t)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+          for (int t = 0; t < S; ++t) {
+            const int bit = 1 << (S - 1 - t);
+            int k = 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              if (!(b & bit)) {
+                const uint32_t f = (uint32_t)(flips >> (kc * FB + t * PPS + k)) & 1u;
+                const float a = d[kc * NB + b], c = d[kc * NB + (b | bit)];
+                d[kc * NB + b] = a + c;
+                d[kc * NB + (b | bit)] = flip_sign(a - c, f);
+                ++k;
+              }
+          }
+      }
+
+      float res[Q];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+          if constexpr (BF) {
+#pragma unroll
+            for (int k4 = 0; k4 < KC / 4; ++k4) {
+              const int f = (b * NT + nt) * (KC / 4) + k4;
+              const u32x2 aw = {__float_as_uint(af[2 * f]), __float_as_uint(af[2 * f + 1])};
+              const u32x2 bw = {bf16_bits(d[(4 * k4) * NB + b]) | (bf16_bits(d[(4 * k4 + 1) * NB + b]) << 16),
+                                bf16_bits(d[(4 * k4 + 2) * NB + b]) | (bf16_bits(d[(4 * k4 + 3) * NB + b]) << 16)};
+              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, aw),
+                                                              __builtin_bit_cast(bf16x4, bw), acc, 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[(b * NT + nt) * KC + kc], d[kc * NB + b],
+                                                         acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (DIR == 0) res[(b * NT + nt) * 4 + v] = acc[v];
+            else res[(nt * 4 + v) * NB + b] = acc[v];
+          }
+        }
+
+      if (DIR == 1) {
+        // inverse Haar stages, in reverse stage order, on each orbit's 2^S slots
+#pragma unroll
+        for (int o = 0; o < NT * 4; ++o)
+#pragma unroll
+          for (int t = S - 1; t >= 0; --t) {
+            const int bit = 1 << (S - 1 - t);
+            int k = 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              if (!(b & bit)) {
+                const uint32_t f = (uint32_t)(flips >> (o * FB + t * PPS + k)) & 1u;
+                const float a = res[o * NB + b], c = flip_sign(res[o * NB + (b | bit)], f);
+                res[o * NB + b] = a + c;
+                res[o * NB + (b | bit)] = a - c;
+                ++k;
+              }
+          }
+      }
+
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < Q; ++q) T[sat(q)] = res[q];
+      wave_lds_sync();
+      u32x4 o[VO];
+#pragma unroll
+      for (int k = 0; k < VO; ++k) {
+        const float *src = T + st_at[k * HO];
+        if constexpr (OUT16) {
+          const floatx4 a = *reinterpret_cast<const floatx4 *>(src);
+          const floatx4 b = *reinterpret_cast<const floatx4 *>(T + st_at[k * HO + 1]);
+          o[k] = u32x4{bf16_bits(a[0]) | (bf16_bits(a[1]) << 16), bf16_bits(a[2]) | (bf16_bits(a[3]) << 16),
+                       bf16_bits(b[0]) | (bf16_bits(b[1]) << 16), bf16_bits(b[2]) | (bf16_bits(b[3]) << 16)};
+        } else {
+          o[k] = *reinterpret_cast<const u32x4 *>(src);
+        }
+      }
+      auto dst_at = [&](int e) -> u32x4 * {
+        if constexpr (OUT16)
+          return reinterpret_cast<u32x4 *>(static_cast<uint16_t *>(out) + wt * 16 * n + e);
+        else
+          return reinterpret_cast<u32x4 *>(static_cast<float *>(out) + wt * 16 * n + e);
+      };
+      if (!GEN && lim == 16 * N) {   // full tile (wave-uniform branch)
+#pragma unroll
+        for (int k = 0; k < VO; ++k) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
+      } else {
+        const int limv = lim & ~(EO - 1);   // whole groups; GEN tail values stored one by one
+#pragma unroll
+        for (int k = 0; k < VO; ++k)
+          if (EO * (lane + 64 * k) < limv) __builtin_nontemporal_store(o[k], dst_at(EO * (lane + 64 * k)));
+        if constexpr (GEN) {
+          for (int e = limv + lane; e < lim; e += 64) {
+            if constexpr (OUT16)
+              static_cast<uint16_t *>(out)[wt * 16 * n + e] = (uint16_t)bf16_bits(T[tw(e)]);
+            else
+              static_cast<float *>(out)[wt * 16 * n + e] = T[tw(e)];
+          }
+        }
+      }
+      wave_lds_sync();
     }
-    wave_lds_sync();
   }
 }
 

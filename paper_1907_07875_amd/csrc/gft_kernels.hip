@@ -407,23 +407,28 @@ __device__ __forceinline__ void run_tile(const DevProgram &P, const LdsTables &t
 // the two-stage 32-slot form still spills a little in its own path (measured: the batch
 // is faster with it than with those grids on their LDS programs).
 constexpr int kBatchTileWords = bfly::tile_words<2, 32>();   // the largest of these
+// Held to two waves per SIMD by the largest forms, the FP32 kernel keeps HBM busy on the
+// small forms by loading further ahead: 4 tiles for the one-stage 16-slot blocks, 3 for
+// the 64-slot forms (measured on the mixed batch: 199 -> 193 us).  The BF16 kernel (three
+// waves per SIMD) keeps one.
+constexpr int kPfSmall = 4, kPfMid = 3;
 template <int PREC, int DIR>
 __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *in, float *out,
                                                 int64_t nsig, int64_t t0, int64_t t1, float *T) {
   if constexpr (PREC == kFP32) {
     if (U.S == 1 && U.M == 16) {
-      if (U.gen) bfly::butterfly_tiles<1, 16, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
-      else bfly::butterfly_tiles<1, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+      if (U.gen) bfly::butterfly_tiles<1, 16, DIR, false, false, true, false, false, kPfSmall>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<1, 16, DIR, false, false, false, false, false, kPfSmall>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 1 && U.M == 32) {
-      if (U.gen) bfly::butterfly_tiles<1, 32, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
-      else bfly::butterfly_tiles<1, 32, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+      if (U.gen) bfly::butterfly_tiles<1, 32, DIR, false, false, true, false, false, kPfMid>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<1, 32, DIR, false, false, false, false, false, kPfMid>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 1 && U.M == 48 && U.gen) {
       bfly::butterfly_tiles<1, 48, DIR, false, false, true, false, true>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 2 && U.M == 32 && U.gen) {
       bfly::butterfly_tiles<2, 32, DIR, false, false, true, false, true>(U, in, out, nsig, t0, t1, 1, T);
     } else if (U.S == 2 && U.M == 16) {
-      if (U.gen) bfly::butterfly_tiles<2, 16, DIR, false, false, true, false>(U, in, out, nsig, t0, t1, 1, T);
-      else bfly::butterfly_tiles<2, 16, DIR, false, false, false, false>(U, in, out, nsig, t0, t1, 1, T);
+      if (U.gen) bfly::butterfly_tiles<2, 16, DIR, false, false, true, false, false, kPfMid>(U, in, out, nsig, t0, t1, 1, T);
+      else bfly::butterfly_tiles<2, 16, DIR, false, false, false, false, false, kPfMid>(U, in, out, nsig, t0, t1, 1, T);
     }
   } else if constexpr (PREC == kBF16) {
     if (U.gen && U.S == 1 && U.M == 16)
