@@ -16,6 +16,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -31,12 +32,6 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
 __device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
   const u32x2 w = {a | (b << 16), c | (d << 16)};
   return __builtin_bit_cast(bf16x4, w);
-}
-
-// BF16 k values 4s .. 4s+3 of an 8-value fragment
-__device__ __forceinline__ bf16x4 half_of(u32x4 w, int s) {
-  const u32x2 h = s == 0 ? u32x2{w[0], w[1]} : u32x2{w[2], w[3]};
-  return __builtin_bit_cast(bf16x4, h);
 }
 
 }  // namespace
@@ -148,7 +143,8 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
 // (As[m][k], Bs[n][k], rows padded by 16 bytes).  The contraction sums over k, so the k that
 // a lane supplies to each MFMA may be permuted as long as A and B agree: per 16 (FP32) or
 // 32 (BF16) k, lane (g, r) takes the consecutive k = 4g .. 4g+3 (four 16x16x4 steps) or
-// 8g .. 8g+7 (two 16x16x16 steps) and reads each fragment with one 16-byte LDS load.  BF16 operands are rounded once,
+// 8g .. 8g+7 (one 16x16x32 BF16 step, gfx950's double-rate form) and reads each fragment
+// with one 16-byte LDS load.  BF16 operands are rounded once,
 // when the tile is written to LDS (split BF16: hi and lo planes, three products).  LDS is
 // double buffered, so one barrier per K step; the next global tile is loaded into registers
 // (unconditionally: the last tile is re-read, since loads under a branch are waited for
@@ -333,18 +329,16 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
           if constexpr (PREC == 3) bl[j] = *reinterpret_cast<const u32x4 *>(base + 2 * Cfg::plane_bytes + boff + j * 16 * kRowBytes);
         }
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const bf16x4 a = half_of(ah[i], s), bb = half_of(bh[j], s);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
-              if constexpr (PREC == 3) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, half_of(bl[j], s), acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(half_of(al[i], s), bb, acc[i][j], 0, 0, 0);
-              }
+          for (int j = 0; j < 4; ++j) {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, ah[i]), bb = __builtin_bit_cast(bf16x8, bh[j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[i][j], 0, 0, 0);
+            if constexpr (PREC == 3) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]), bb, acc[i][j], 0, 0, 0);
             }
+          }
       }
     }
     store((kt + 1) & 1);     // the other buffer: last read before the previous barrier

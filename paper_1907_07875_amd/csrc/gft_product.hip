@@ -27,7 +27,9 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kPWaves = 4;
 constexpr int kFP32 = 0, kBF16 = 1, kSPLIT = 3;   // gft_precision values (include/gft.h)
@@ -61,6 +63,23 @@ __device__ __forceinline__ floatx4 mfma16(const Frag16 &a, const Frag16 &b, floa
   if constexpr (SPLIT) {
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a.hi), __builtin_bit_cast(bf16x4, b.lo), acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, a.lo), __builtin_bit_cast(bf16x4, b.hi), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// acc += A * B over two k chunks at once on gfx950's 16x16x32 BF16 MFMA: each lane gives
+// its four values of chunk 0 then its four of chunk 1, in A and in B alike.  Whatever k the
+// MFMA assigns to each of a lane's eight slots, A and B slots pair up as in two 16x16x16
+// steps, so the sum is the same contraction at half the MFMA issue count.
+template <bool SPLIT>
+__device__ __forceinline__ floatx4 mfma32(const Frag16 &a0, const Frag16 &a1, const Frag16 &b0,
+                                          const Frag16 &b1, floatx4 acc) {
+  auto cat = [](const u32x2 &x, const u32x2 &y) { return __builtin_bit_cast(bf16x8, u32x4{x[0], x[1], y[0], y[1]}); };
+  const bf16x8 ah = cat(a0.hi, a1.hi), bh = cat(b0.hi, b1.hi);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  if constexpr (SPLIT) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, cat(b0.lo, b1.lo), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat(a0.lo, a1.lo), bh, acc, 0, 0, 0);
   }
   return acc;
 }
@@ -203,7 +222,20 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
     for (int mt = 0; mt < MA; ++mt) {
 #pragma unroll
       for (int nt = 0; nt < MB; ++nt) y1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if constexpr (B16) {
+      if constexpr (B16 && MB % 2 == 0) {   // k chunks kk = 2 kp, 2 kp + 1 per MFMA
+#pragma unroll
+        for (int kp = 0; kp < MB / 2; ++kp) {
+          const float *z = T + (16 * mt + r16) * STR + 32 * kp + 4 * g4;
+          const Frag16 a0 = pack16(z[0], z[1], z[2], z[3]), a1 = pack16(z[16], z[17], z[18], z[19]);
+#pragma unroll
+          for (int nt = 0; nt < MB; ++nt) {
+            if constexpr (SAME)
+              y1[mt][nt] = mfma32<PREC == kSPLIT>(a0, a1, aq[nt][2 * kp], aq[nt][2 * kp + 1], y1[mt][nt]);
+            else
+              y1[mt][nt] = mfma32<PREC == kSPLIT>(a0, a1, bq[2 * kp][nt], bq[2 * kp + 1][nt], y1[mt][nt]);
+          }
+        }
+      } else if constexpr (B16) {
 #pragma unroll
         for (int kk = 0; kk < MB; ++kk) {
           const float *z = T + (16 * mt + r16) * STR + 16 * kk + 4 * g4;
@@ -238,7 +270,18 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
       floatx4 acc[MA];
 #pragma unroll
       for (int mo = 0; mo < MA; ++mo) acc[mo] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if constexpr (B16) {
+      if constexpr (B16 && MA % 2 == 0) {
+        // the result registers y1[mt][nt] are already the B operand of k chunk mt; chunks
+        // 2 mp and 2 mp + 1 go to one MFMA
+#pragma unroll
+        for (int mp = 0; mp < MA / 2; ++mp) {
+          const floatx4 y0 = y1[2 * mp][nt], y1v = y1[2 * mp + 1][nt];
+          const Frag16 b0 = pack16(y0[0], y0[1], y0[2], y0[3]), b1 = pack16(y1v[0], y1v[1], y1v[2], y1v[3]);
+#pragma unroll
+          for (int mo = 0; mo < MA; ++mo)
+            acc[mo] = mfma32<PREC == kSPLIT>(aq[mo][2 * mp], aq[mo][2 * mp + 1], b0, b1, acc[mo]);
+        }
+      } else if constexpr (B16) {
         // the result registers y1[mt][nt] are already the B operand of k chunk mt
 #pragma unroll
         for (int mt = 0; mt < MA; ++mt) {
