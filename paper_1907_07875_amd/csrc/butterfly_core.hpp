@@ -7,7 +7,7 @@
 // Fig. grid_coords under LR then UD symmetry is the case n = 64, S = 2, M = 16).  One-stage
 // plans of other shapes are laid out on padded slots (GEN below).
 // Each wave works alone on tiles of 16 signals, with no workgroup barriers:
-//   HBM --16B loads, prefetched one tile ahead--> registers (native vector type: arrays
+//   HBM --16B loads, prefetched PF tiles ahead--> registers (native vector type: arrays
 //   of the HIP float4 struct are not promoted out of scratch) --> wave-private LDS tile
 //   --gather--> registers in MFMA operand order: lane (g, r) holds, for signal r, the
 //   2^S slots of the orbits assigned to lane group g
