@@ -312,6 +312,16 @@ const char *gft_last_error(void);
 /* Library version string. */
 const char *gft_version(void);
 
+/* Streaming copy of `bytes` bytes from src to dst on `stream` (a hipStream_t; NULL = the
+ * null stream), stream-ordered and asynchronous.  Not an operation of the transform: the
+ * reference kernel for what moving data through HBM alone reaches on this device
+ * (non-temporal 16-byte loads and stores, as the transform kernels use for signal data),
+ * quoted beside the GFT kernels' HBM rooflines.  src, dst: device memory, 16-byte aligned,
+ * not overlapping, owned by the caller; bytes a multiple of 16 (0 is a no-op).  Errors:
+ * GFT_ERR_INVALID_ARG (size, NULL), GFT_ERR_ALIGNMENT (alignment, overlap), GFT_ERR_HIP
+ * (launch). */
+gft_status gft_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,7 @@ EXPORTS = [
     "gft_inverse_batch", "gft_plan_prepare", "gft_plan_engine", "gft_plan_tiles", "gft_plan_info", "gft_plan_num_graphs",
     "gft_find_pairing", "gft_plan_product",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
-    "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version",
+    "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version", "gft_stream_copy",
 ]
 
 
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_plan_destroy": ([P], i32),
         "gft_last_error": ([], ctypes.c_char_p),
         "gft_version": ([], ctypes.c_char_p),
+        "gft_stream_copy": ([P, P, i64, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -399,6 +400,21 @@ def gft_forward(plan: Plan, x, out=None, stream=None):
 def gft_inverse(plan: Plan, y, out=None, stream=None):
     """Signals U y from coefficients (C: ``gft_inverse``)."""
     return _apply("gft_inverse", plan, y, out, stream)
+
+
+def gft_stream_copy(src, dst, stream=None):
+    """Copy the bytes of tensor ``src`` into ``dst`` with the library's streaming copy kernel
+    (C: ``gft_stream_copy``), the HBM reference quoted beside the transform's rooflines."""
+    import torch
+    for t in (src, dst):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise TypeError("src and dst must be contiguous CUDA tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size in bytes")
+    _check(load_library().gft_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                          nbytes, _stream_ptr(stream)))
+    return dst
 
 
 def _apply_batch(fn_name, plan: Plan, x, signal_offsets, out, stream):

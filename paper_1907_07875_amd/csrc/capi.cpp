@@ -968,6 +968,23 @@ gft_status gft_plan_destroy(gft_plan_t plan) {
 
 const char *gft_last_error(void) { return g_last_error.c_str(); }
 
+gft_status gft_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  if (bytes < 0 || (bytes & 15)) return set_error(GFT_ERR_INVALID_ARG, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return ok();
+  if (!src || !dst) return set_error(GFT_ERR_INVALID_ARG, "src and dst must be non-NULL device pointers");
+  const uintptr_t ps = reinterpret_cast<uintptr_t>(src), pd = reinterpret_cast<uintptr_t>(dst);
+  if ((ps & 15) || (pd & 15)) return set_error(GFT_ERR_ALIGNMENT, "src and dst must be 16-byte aligned");
+  if (ps < pd + (uintptr_t)bytes && pd < ps + (uintptr_t)bytes)
+    return set_error(GFT_ERR_ALIGNMENT, "src and dst overlap");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
+  e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream), cus);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ok();
+}
+
 const char *gft_version(void) { return "libgft 0.1 (gfx950)"; }
 
 }  // extern "C"

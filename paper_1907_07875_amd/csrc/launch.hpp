@@ -49,4 +49,9 @@ int product_pad(int n);
 hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
                           hipStream_t stream, int num_cus);
 
+// Streaming copy of `bytes` (a multiple of 16) between 16-byte aligned, non-overlapping
+// device buffers (gft_copy.hip).
+hipError_t launch_stream_copy(const void *in, void *out, int64_t bytes, hipStream_t stream,
+                              int num_cus);
+
 }  // namespace gft
