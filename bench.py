@@ -485,7 +485,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: every signal is "
                           "independent, so N GPUs would each run this same kernel on 1/N of the "
-                          "batch with no exchange; multi-GPU runs are not part of this build"}))
+                          "batch with no exchange; runs on more than one GPU are not supported"}))
         sys.exit(2)
     {"grid8x8": bench_grid, "skeleton": bench_skeleton, "mixed": bench_mixed,
      "grid64": bench_grid64, "wpath1024": bench_wpath}[args.workload](args)

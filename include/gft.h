@@ -50,7 +50,7 @@ typedef enum {
   GFT_ERR_ORTHOGONALITY = 7,            /* plan-time check ||V^T V - I|| or residual failed*/
   GFT_ERR_ALIGNMENT = 8,                /* device pointer not 16-byte aligned, or x and y  */
                                         /* overlap without being equal                     */
-  GFT_ERR_UNSUPPORTED = 9,              /* shape or precision this build does not run      */
+  GFT_ERR_UNSUPPORTED = 9,              /* shape or precision the library does not run     */
   GFT_ERR_OOM = 10,                     /* host or device allocation failed                */
   GFT_ERR_HIP = 11                      /* a HIP runtime call failed                       */
 } gft_status;
