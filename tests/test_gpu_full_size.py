@@ -1,0 +1,82 @@
+"""Parity at the benchmark's full sizes, in the launch the bench times: the 25-node skeleton
+with 16384 x 3 x 300 = 14,745,600 signals (one launch over 1.47 GB) and the 1024-node
+weighted path with 65536 signals on the large engine.  Every signal is computed on the GPU;
+a seeded sample of rows is checked against the FP64 oracle (basis aligned per eigenvalue
+cluster), and properties that hold for every row are checked on all of them (FP32 blocks:
+per-signal energy, U being orthogonal).  Inputs are i.i.d. N(0,1) of the workloads' shapes:
+parity does not depend on the value distribution."""
+import numpy as np
+import pytest
+
+import paper_1907_07875_amd as G
+import workloads as wl
+from oracle import gft_oracle as O
+from tests.gpu_helpers import aligned_oracle_basis, device, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 2e-2, "split_bf16": 1e-5}
+
+
+def _gaussian_chunked(S, n, rng, chunk=1 << 20):
+    X = np.empty((S, n), dtype=np.float32)
+    for i in range(0, S, chunk):
+        X[i:i + chunk] = rng.standard_normal((min(chunk, S - i), n)).astype(np.float32)
+    return X
+
+
+def _sampled_parity(g, plan, X, y, xr, tol, nrows, seed):
+    lam, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-9)
+    rows = np.sort(wl.rng_for(*seed).choice(X.shape[0], nrows, replace=False))
+    ri = torch.from_numpy(rows).to(y.device)
+    Xs = X[rows].astype(np.float64)
+    err = O.relative_error(y[ri].double().cpu().numpy(), O.forward(Xs, Ua))
+    assert err <= tol, f"{g.name}: forward relative error {err:.3e} on {nrows} sampled rows"
+    rt = O.relative_error(xr[ri].double().cpu().numpy(), Xs)
+    assert rt <= 2 * tol, f"{g.name}: round trip error {rt:.3e}"
+    return err
+
+
+def _energy_all_rows(x, y, tol):
+    # per-signal ||y||^2 against ||x||^2, in FP64 chunk by chunk
+    worst = 0.0
+    for i in range(0, x.shape[0], 1 << 21):
+        ex = (x[i:i + (1 << 21)].double() ** 2).sum(dim=1)
+        ey = (y[i:i + (1 << 21)].double() ** 2).sum(dim=1)
+        worst = max(worst, torch.max(torch.abs(ey - ex) / ex).item())
+    assert worst <= tol, f"energy not kept: worst relative change {worst:.3e}"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_config3_skeleton_full_size(precision):
+    dev = device()
+    g = wl.config3_graph()
+    plan = G.Plan.from_graph(g, precision=precision)
+    S = 16384 * 3 * 300
+    X = _gaussian_chunked(S, g.n, wl.rng_for(3, 7))
+    x = torch.from_numpy(X).to(dev)
+    y = plan.forward(x)
+    xr = plan.inverse(y)
+    torch.cuda.synchronize()
+    _sampled_parity(g, plan, X, y, xr, TOL[precision], 4096, (3, 8))
+    if precision == "fp32":
+        _energy_all_rows(x, y, 1e-5)
+    del x, y, xr
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16", "bf16"])
+def test_config5b_weighted_path_full_size(precision):
+    dev = device()
+    g = wl.config5b_graph()
+    plan = G.Plan.from_graph(g, precision=precision)
+    assert plan.engine() == "large"
+    S = 65536
+    X = _gaussian_chunked(S, g.n, wl.rng_for(5, 9))
+    x = torch.from_numpy(X).to(dev)
+    y = plan.forward(x)
+    xr = plan.inverse(y)
+    torch.cuda.synchronize()
+    _sampled_parity(g, plan, X, y, xr, TOL[precision], 512, (5, 10))
+    if precision != "bf16":
+        _energy_all_rows(x, y, 1e-5)
