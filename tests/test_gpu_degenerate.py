@@ -1,4 +1,4 @@
-"""Degenerate graphs on the GPU against the FP64 oracle: a single node, two nodes with and
+"""Degenerate and signed graphs on the GPU against the FP64 oracle: a single node, two nodes with and
 without an edge (paired and not), an isolated node beside an edge, an edgeless graph with a
 pairing, and a batch mixing them with empty signal ranges.  The GFT of an edgeless graph is
 any orthonormal basis of one eigenspace (eigenvalue 0), so parity is checked after the
@@ -69,3 +69,26 @@ def test_degenerate_graphs_in_one_batch():
         pos += k
     xr = to_np(G.gft_inverse_batch(bp, y, off))
     assert O.relative_error(xr, flat.astype(np.float64)) <= 2e-5
+
+
+SIGNED = [
+    wl.path(9, weights=[1.0, -0.5, 2.0, 0.3, 0.3, 2.0, -0.5, 1.0],
+            loops=[0.2, -0.1, 0.0, 0.5, 1.0, 0.5, 0.0, -0.1, 0.2], name="signed_path"),
+    wl.path(40, weights=list(np.r_[np.linspace(-1, 1, 19), [0.7], np.linspace(1, -1, 19)]),
+            loops=list(np.r_[np.linspace(0.5, -0.5, 20), np.linspace(-0.5, 0.5, 20)]), name="signed_path"),
+]
+
+
+@pytest.mark.parametrize("g", SIGNED, ids=lambda g: f"{g.name}{g.n}")
+def test_signed_weights_and_self_loops_parity(g):
+    """Negative edge weights and self-loops (an indefinite Laplacian, which the
+    decomposition accepts): every engine the plan can take matches the oracle."""
+    dev = device()
+    for engine in ("auto", "generic"):
+        plan = G.Plan.from_graph(g, engine=engine)
+        lam, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-9)
+        assert lam.min() < 0 or g.n > 9
+        X = wl.gaussian(300, g.n, wl.rng_for(13, g.n))
+        y = plan.forward(torch.from_numpy(X).to(dev))
+        assert O.relative_error(to_np(y), O.forward(X.astype(np.float64), Ua)) <= 1e-5, engine
+        assert O.relative_error(to_np(plan.inverse(y)), X.astype(np.float64)) <= 2e-5, engine
