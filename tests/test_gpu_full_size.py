@@ -109,3 +109,34 @@ def test_grid8x8_beyond_32bit_offsets():
     assert rt <= 2 * TOL["fp32"], f"round trip error {rt:.3e}"
     del x, y, xr
     torch.cuda.empty_cache()
+
+
+def test_batch_beyond_32bit_offsets():
+    """One batch launch over 4.97 G values per array (8x8 grid and 48-node path on the
+    register phase, then a 12x12 grid on its LDS program whose data runs past element
+    2^32): sampled rows of every graph, its last rows included, against the oracle."""
+    dev = device()
+    graphs = [wl.grid(8, 8), wl.path(48), wl.grid(12, 12)]
+    counts = [1 << 25, 1 << 25, (1 << 23) + 3]
+    bp = G.gft_plan_batch(graphs)
+    total = sum(c * g.n for c, g in zip(counts, graphs))
+    gen = torch.Generator(device=dev).manual_seed(32)
+    x = torch.randn(total, device=dev, dtype=torch.float32, generator=gen)
+    off = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).to(dev)
+    y = G.gft_forward_batch(bp, x, off)
+    xr = G.gft_inverse_batch(bp, y, off)
+    torch.cuda.synchronize()
+    base = 0
+    for k, (g, c) in enumerate(zip(graphs, counts)):
+        lam, Ua = aligned_oracle_basis(g, G.Plan.from_graph(g).basis(), sv_tol=1e-9)
+        rows = np.unique(np.r_[wl.rng_for(32, k).choice(c, 256, replace=False), np.arange(c - 20, c)])
+        idx = torch.from_numpy(base + rows[:, None] * g.n + np.arange(g.n)[None, :]).to(dev)
+        Xs = x[idx].double().cpu().numpy()
+        err = O.relative_error(y[idx].double().cpu().numpy(), O.forward(Xs, Ua))
+        assert err <= TOL["fp32"], f"{g.name}{g.n}: forward relative error {err:.3e}"
+        rt = O.relative_error(xr[idx].double().cpu().numpy(), Xs)
+        assert rt <= 2 * TOL["fp32"], f"{g.name}{g.n}: round trip error {rt:.3e}"
+        base += c * g.n
+    assert base > 1 << 32
+    del x, y, xr
+    torch.cuda.empty_cache()
