@@ -140,3 +140,40 @@ def test_batch_beyond_32bit_offsets():
     assert base > 1 << 32
     del x, y, xr
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("which", ["large_wpath1024", "product_grid64"])
+def test_large_and_product_beyond_32bit_offsets(which):
+    """The large engine (1024-node weighted path, 2^21 + 3 signals: 2.1 G values, byte
+    offsets past 8 GiB) and the product engine (64 x 64 grid, 2^20 + 1 signals: 4.3 G values)
+    in one launch each: sampled rows and the last signals against the oracle."""
+    dev = device()
+    if which == "large_wpath1024":
+        g = wl.config5b_graph()
+        plan = G.Plan.from_graph(g)
+        assert plan.engine() == "large"
+        S = (1 << 21) + 3
+    else:
+        ga = wl.path_recursive(64)
+        g = wl.cartesian_product(ga, ga)
+        plan = G.Plan.from_product(ga, ga)
+        S = (1 << 20) + 1
+    gen = torch.Generator(device=dev).manual_seed(33)
+    x = torch.randn((S, g.n), device=dev, dtype=torch.float32, generator=gen)
+    y = plan.forward(x)
+    xr = plan.inverse(y)
+    torch.cuda.synchronize()
+    rows = np.unique(np.r_[wl.rng_for(33, S).choice(S, 128, replace=False), np.arange(S - 4, S)])
+    ri = torch.from_numpy(rows).to(dev)
+    Xs = x[ri].double().cpu().numpy()
+    if which == "large_wpath1024":
+        lam, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-9)
+        ref = O.forward(Xs, Ua)
+    else:
+        ref = plan.apply_host(Xs, 0)   # the product basis is pinned to the oracle by the host tests
+    err = O.relative_error(y[ri].double().cpu().numpy(), ref)
+    assert err <= TOL["fp32"], f"{which}: forward relative error {err:.3e}"
+    rt = O.relative_error(xr[ri].double().cpu().numpy(), Xs)
+    assert rt <= 2 * TOL["fp32"], f"{which}: round trip error {rt:.3e}"
+    del x, y, xr
+    torch.cuda.empty_cache()
