@@ -198,3 +198,43 @@ def test_captured_graph_replays_equal_eager():
         assert torch.equal(ys, eager_s)
         assert torch.equal(xr, eager_r)
         _ = (xs * 2).sum().item()                        # unrelated eager work between replays
+
+
+def test_captured_graph_other_engines():
+    """hipGraph capture of the generic engine, the padded one-stage butterfly with BF16
+    blocks and a product plan in one graph; eager work between replays, every replay equals
+    the eager result bit for bit."""
+    dev = device()
+    rng = wl.rng_for(4, 6)
+    gen_plan = G.Plan.from_graph(wl.grid(11, 11), engine="generic")
+    bf_plan = G.Plan.from_graph(wl.config3_graph(), precision="bf16")
+    pr_plan = G.Plan.from_product(wl.path(16), wl.path_recursive(16))
+    plans = [gen_plan, bf_plan, pr_plan]
+    for p in plans:
+        p.prepare()
+    assert gen_plan.engine() == "generic" and bf_plan.engine() == "butterfly" and pr_plan.engine() == "product"
+    xs = [torch.from_numpy(wl.gaussian(S, p.n, rng)).to(dev) for S, p in zip((1234, 4000, 777), plans)]
+    ys = [torch.empty_like(x) for x in xs]
+    eager = [p.forward(x).clone() for p, x in zip(plans, xs)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for p, x, y in zip(plans, xs, ys):
+            p.forward(x, out=y)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for p, x, y in zip(plans, xs, ys):
+            p.forward(x, out=y)
+    for _ in range(3):
+        for y in ys:
+            y.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(ys, eager):
+            assert torch.equal(y, e)
+        # eager work between replays, on the same buffers' neighbours
+        for p, x in zip(plans, xs):
+            p.inverse(p.forward(x))
+        torch.cuda.synchronize()
