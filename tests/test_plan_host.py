@@ -394,3 +394,22 @@ def test_find_pairing_no_symmetry():
     assert _find(g) == []
     st = _find(wl.path(6), laplacian="normalized", max_stages=1)
     np.testing.assert_array_equal(st[0], np.arange(5, -1, -1))
+
+
+def test_stream_copy_argument_checks_launch_nothing():
+    """gft_stream_copy rejects bad arguments before it touches a device (so this runs on a
+    host without a GPU); only invalid calls and the zero-byte no-op are made here."""
+    lib = G.load_library()
+    V = ctypes.c_void_p
+    cases = [
+        ((4096, 8192, 100), "GFT_ERR_INVALID_ARG"),     # not a multiple of 16
+        ((4096, 8192, -16), "GFT_ERR_INVALID_ARG"),
+        ((0, 8192, 4096), "GFT_ERR_INVALID_ARG"),       # NULL source
+        ((4096, 0, 4096), "GFT_ERR_INVALID_ARG"),       # NULL destination
+        ((4100, 8192, 1024), "GFT_ERR_ALIGNMENT"),
+        ((4096, 4096 + 2048, 4096), "GFT_ERR_ALIGNMENT"),   # overlap
+    ]
+    for (a, b, nb), want in cases:
+        st = lib.gft_stream_copy(V(a), V(b), nb, V(0))
+        assert G.STATUS[st] == want, (a, b, nb, G.STATUS[st])
+    assert lib.gft_stream_copy(V(4096), V(8192), 0, V(0)) == 0
