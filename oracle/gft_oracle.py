@@ -381,6 +381,9 @@ def relative_error(A, B):
 
 
 def max_row_relative_error(A, B):
+    """Largest per-signal relative error max_s ||a_s - b_s|| / ||b_s|| over the rows (signals)
+    of A and B: the signal-by-signal form of ``relative_error`` (a row of B that is zero counts
+    with a denominator of 1e-300)."""
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     num = np.linalg.norm(A - B, axis=1)

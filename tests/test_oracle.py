@@ -200,6 +200,51 @@ def test_paper_error_metrics():
     assert O.epsilon_metric(U @ S, U, X) < 1e-24
 
 
+def test_paper_error_metrics_worked_examples():
+    """delta, epsilon and RE of Sec. VI-B on small bases worked out by hand, with non-zero
+    error, so that a wrong normalisation (1/n for 1/sqrt(n), a sum for the mean over signals)
+    or a missing absolute value fails.
+
+    2x2: U = I and U_hat the rotation by 60 degrees, columns (1/2, sqrt3/2), (-sqrt3/2, 1/2).
+      |U_hat^T U| - I = [[-1/2, sqrt3/2], [sqrt3/2, -1/2]]: squared Frobenius norm 2, so
+      delta = sqrt(2) / sqrt(2) = 1; RE = ||U - U_hat||_F / ||U||_F = sqrt(2) / sqrt(2) = 1.
+      Signals x1 = (1, 0), x2 = (0, 2): true coefficients (1, 0) and (0, 2), the rotated
+      basis gives (1/2, -sqrt3/2) and (sqrt3, 1); the squared differences of magnitudes sum
+      to 1/4 + 3/4 = 1 and 3 + 1 = 4, so epsilon = (1 + 4) / 2 = 5/2.
+    3x3: U_hat = [[0.6, -0.8, 0], [0.8, 0.6, 0], [0, 0, 1]]: |U_hat^T| - I has entries
+      -0.4, -0.4, 0.8, 0.8 and zeros, squared norm 1.6, so delta = sqrt(1.6 / 3); a sign
+      flip of any column of U_hat leaves delta unchanged (RE then changes).
+    """
+    c, s = 0.5, math.sqrt(3.0) / 2.0
+    U = np.eye(2)
+    Uh = np.array([[c, -s], [s, c]])
+    assert O.delta_metric(Uh, U) == pytest.approx(1.0, abs=1e-15)
+    assert O.re_metric(Uh, U) == pytest.approx(1.0, abs=1e-15)
+    X = np.array([[1.0, 0.0], [0.0, 2.0]])
+    assert O.epsilon_metric(Uh, U, X) == pytest.approx(2.5, abs=1e-14)
+    U3 = np.eye(3)
+    V3 = np.array([[0.6, -0.8, 0.0], [0.8, 0.6, 0.0], [0.0, 0.0, 1.0]])
+    assert O.delta_metric(V3, U3) == pytest.approx(math.sqrt(1.6 / 3.0), abs=1e-15)
+    V3f = V3 @ np.diag([1.0, -1.0, -1.0])
+    assert O.delta_metric(V3f, U3) == pytest.approx(math.sqrt(1.6 / 3.0), abs=1e-15)
+    assert O.re_metric(V3f, U3) > O.re_metric(V3, U3)
+    # epsilon on the 3x3 pair: x = (1, 1, 1) has true coefficients (1, 1, 1) and rotated
+    # ones (1.4, -0.2, 1): (1 - 1.4)^2 + (1 - 0.2)^2 = 0.16 + 0.64 = 0.8 (one signal)
+    assert O.epsilon_metric(V3, U3, np.ones((1, 3))) == pytest.approx(0.8, abs=1e-14)
+
+
+def test_max_row_relative_error_worked_example():
+    """Per-signal relative error on rows worked out by hand: row 0 ||(0, 4)|| / ||(3, 0)|| =
+    4/3, row 1 ||(0, -1)|| / ||(0, 2)|| = 1/2, so the maximum is 4/3 (the batch Frobenius form
+    gives sqrt(17/13), the column-wise one sqrt(17)/2: both differ)."""
+    A = np.array([[3.0, 4.0], [0.0, 1.0]])
+    B = np.array([[3.0, 0.0], [0.0, 2.0]])
+    assert O.max_row_relative_error(A, B) == pytest.approx(4.0 / 3.0, abs=1e-15)
+    assert O.relative_error(A, B) == pytest.approx(math.sqrt(17.0 / 13.0), abs=1e-15)
+    assert O.max_row_relative_error(B, B) == 0.0
+    assert O.max_row_relative_error(np.zeros((0, 2)), np.zeros((0, 2))) == 0.0
+
+
 # ------------------------------------------------------------------ Haar stages (Sec. III)
 
 def test_haar_unit_is_scaled_sum_and_difference():
