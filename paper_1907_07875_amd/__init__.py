@@ -426,8 +426,15 @@ def _apply_batch(fn_name, plan: Plan, x, signal_offsets, out, stream):
     if not (isinstance(signal_offsets, torch.Tensor) and signal_offsets.is_cuda
             and signal_offsets.dtype == torch.int64 and signal_offsets.numel() == len(plan.sizes) + 1):
         raise TypeError("signal_offsets must be an int64 CUDA tensor of num_graphs + 1 entries")
+    if signal_offsets.device != x.device:
+        raise ValueError("signal_offsets must be on the device of x")
     if out is None:
         out = torch.empty_like(x)
+    elif not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float32
+              and out.is_contiguous()):
+        raise TypeError("out must be a contiguous float32 CUDA tensor")
+    elif out.device != x.device or out.numel() != x.numel():
+        raise ValueError("out must be on the device of x and hold as many values as x")
     _check(getattr(load_library(), fn_name)(plan.handle, ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(out.data_ptr()),
                                              ctypes.c_void_p(signal_offsets.data_ptr()),

@@ -381,8 +381,9 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   if (use_large)
     for (int d = 0; d < 2; ++d) {
       if (!build_large(plan->graphs[0], d, lgi[d]))
-        return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine takes at most " +
-                                                  std::to_string(kLargeMaxCols) + " workspace columns");
+        return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine takes rows of at most " +
+                                                  std::to_string(kLargeMaxCols) +
+                                                  " values and workspace columns (one FP32 row in LDS)");
       for (int k = 0; k < 2; ++k) {
         loff[d][2 * k] = blob.add(lgi[d].stages[k].data(), lgi[d].stages[k].size() * 4);
         loff[d][2 * k + 1] = blob.add(lgi[d].gather[k].data(), lgi[d].gather[k].size() * 4);
@@ -538,21 +539,41 @@ gft_status check_buffers(const void *a, int64_t abytes, const void *b, int64_t b
   return GFT_OK;
 }
 
-gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S, void *stream) {
+// Workspace of a large-engine apply over S signals: W1 (and W2 unless the GEMM epilogue
+// writes the output order itself) of S rows of ldw FP32 words.
+bool large_fused(const LargeImage &L) {
+  // With no Haar stage in pass 3 and few leaf blocks the GEMM writes the final positions
+  // itself (no W2, no pass 3).  With many blocks whose outputs interleave in the output
+  // order, each output line collects partial writes from many workgroups and the m-panel
+  // tile order spoils the reuse of the block matrices in L2: measured slower on the 64x64
+  // grid (49 blocks), faster on the 1024-node path (2 blocks).
+  return L.pass[1].num_stages == 0 && L.blocks.size() <= kFuseMaxBlocks;
+}
+
+size_t large_ws_bytes(const LargeImage &L, int64_t S) {
+  return (large_fused(L) ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
+}
+
+gft_status check_apply_args(gft_plan_t plan, const void *in, void *out, int64_t S, int dir) {
   if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
   if (plan->batch) return set_error(GFT_ERR_INVALID_ARG, "batch plans use gft_forward_batch / gft_inverse_batch");
   if (S < 0) return set_error(GFT_ERR_INVALID_ARG, "num_signals must be >= 0");
-  if (S == 0) return ok();
+  if (S == 0) return GFT_OK;
   const int64_t n = plan->graphs[0].n;
   if (S > (int64_t(1) << 40) / n) return set_error(GFT_ERR_INVALID_ARG, "num_signals too large");
   // forward reads signals (in_dtype) and writes coefficients (out_dtype); inverse the reverse
   const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
   const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
-  gft_status st = check_buffers(in, S * n * (in16 ? 2 : 4), out, S * n * (out16 ? 2 : 4), in16 == out16);
-  if (st != GFT_OK) return st;
-  DeviceImage *img = nullptr;
-  st = device_image(plan, &img);
-  if (st != GFT_OK) return st;
+  return check_buffers(in, S * n * (in16 ? 2 : 4), out, S * n * (out16 ? 2 : 4), in16 == out16);
+}
+
+// Launch the plan's kernels on S > 0 signals.  ws: the large engine's workspace (at least
+// large_ws_bytes), or null to take it from the stream-ordered pool for this call.
+gft_status launch_image(gft_plan_t plan, DeviceImage *img, int dir, const void *in, void *out,
+                        int64_t S, void *stream, void *ws) {
+  const int64_t n = plan->graphs[0].n;
+  const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
+  const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
   hipError_t e;
   if (img->product) {
     e = launch_product(dir == 0 ? img->pfwd : img->pinv, static_cast<const float *>(in),
@@ -560,16 +581,12 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   } else if (img->large) {
     const LargeImage &L = img->lg[dir];
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    // With no Haar stage in pass 3 and few leaf blocks the GEMM writes the final positions
-    // itself (no W2, no pass 3).  With many blocks whose outputs interleave in the output
-    // order, each output line collects partial writes from many workgroups and the m-panel
-    // tile order spoils the reuse of the block matrices in L2: measured slower on the 64x64
-    // grid (49 blocks), faster on the 1024-node path (2 blocks).
-    const bool fused = L.pass[1].num_stages == 0 && L.blocks.size() <= kFuseMaxBlocks;
-    const size_t ws_bytes = (fused ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
-    void *ws = nullptr;
-    e = hipMallocAsync(&ws, ws_bytes, st);
-    if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
+    const bool fused = large_fused(L);
+    const bool pooled = ws == nullptr;
+    if (pooled) {
+      e = hipMallocAsync(&ws, large_ws_bytes(L, S), st);
+      if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
+    }
     float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
     const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
     e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st);
@@ -581,8 +598,10 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
                             fused ? L.dev_omap : nullptr, (int)n, st);
     if (e == hipSuccess && !fused)
       e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st);
-    const hipError_t ef = hipFreeAsync(ws, st);
-    if (e == hipSuccess) e = ef;
+    if (pooled) {
+      const hipError_t ef = hipFreeAsync(ws, st);
+      if (e == hipSuccess) e = ef;
+    }
   } else if (img->butterfly) {
     e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, in, out, S,
                          static_cast<hipStream_t>(stream), img->num_cus, in16, out16);
@@ -593,6 +612,15 @@ gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S,
   }
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
+}
+
+gft_status apply(gft_plan_t plan, int dir, const void *in, void *out, int64_t S, void *stream) {
+  gft_status st = check_apply_args(plan, in, out, S, dir);
+  if (st != GFT_OK || S == 0) return st != GFT_OK ? st : ok();
+  DeviceImage *img = nullptr;
+  st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  return launch_image(plan, img, dir, in, out, S, stream, nullptr);
 }
 
 // FP64 fast basis of a graph plan: U[i * n + k] is node i of basis vector k (column k is the
@@ -649,6 +677,23 @@ void product_apply_host(const gft_plan_s &P, int direction, const double *x, dou
   }
 }
 
+// Signals wider than a generic-engine tile run on the large-signal engine only, whose rows
+// (input and block-padded workspace) must fit one workgroup's LDS: reject at planning what
+// no engine can run.
+constexpr int kWideSignal = 2560;   // no 16-signal FP32 tile of wider signals fits 160 KB
+
+gft_status check_runnable(const GraphPlan &g) {
+  if (g.n <= kWideSignal) return GFT_OK;
+  const int64_t cols = large_workspace_cols(g);
+  if (g.n > kLargeMaxCols || cols > kLargeMaxCols)
+    return set_error(GFT_ERR_UNSUPPORTED,
+                     "n = " + std::to_string(g.n) + " with " + std::to_string(cols) +
+                         " block-padded workspace columns: no engine takes signals of more than " +
+                         std::to_string(kWideSignal) + " values whose rows exceed " +
+                         std::to_string(kLargeMaxCols) + " columns (one FP32 row in LDS)");
+  return GFT_OK;
+}
+
 gft_status get_graph(gft_plan_t plan, int32_t index, const GraphPlan **g) {
   if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
   if (index < 0 || index >= (int32_t)plan->graphs.size())
@@ -673,6 +718,8 @@ gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing, const gf
     auto p = std::make_unique<gft_plan_s>();
     p->opts = o;
     p->graphs.push_back(build_graph_plan(*graph, pairing, o));
+    st = check_runnable(p->graphs[0]);
+    if (st != GFT_OK) return st;
     *out = p.release();
   } catch (const PlanError &err) {
     return set_error(err.status, err.message);

@@ -705,9 +705,16 @@ static bool build_butterfly_uniform(const GraphPlan &p, int direction, UProgramI
 
 namespace gft {
 
+int64_t large_workspace_cols(const GraphPlan &p) {
+  int64_t cols = 0;
+  for (const HostBlock &B : p.blocks) cols += (B.size + 7) & ~7;
+  return cols;
+}
+
 bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   LargeImage im;
   const int n = p.n;
+  if (n > kLargeMaxCols || large_workspace_cols(p) > kLargeMaxCols) return false;
   im.n = n;
   // block-contiguous workspace layout, each block's span padded to a multiple of 8 (16-byte
   // rows of BF16 workspace and matrices)

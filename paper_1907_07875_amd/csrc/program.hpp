@@ -68,11 +68,16 @@ struct LargeImage {
   const int32_t *dev_omap = nullptr;
 };
 
-// Largest tile row (workspace columns) of the large-signal engine: op indices are 16-bit.
-constexpr int kLargeMaxCols = 65535;
+// Widest tile row (input columns or workspace columns) of the large-signal engine: each
+// stage pass stages at least one whole FP32 row in LDS (160 KB), and op indices are 16-bit.
+constexpr int kLargeMaxCols = (int)(kMaxLdsBytes / 4);
+
+// Workspace columns of the large-signal engine for plan `p`: every leaf block's span
+// padded to a multiple of 8.
+int64_t large_workspace_cols(const GraphPlan &p);
 
 // Build the large-signal engine image of `p` for direction 0 (forward) or 1 (inverse).
-// Returns false when the workspace row would exceed kLargeMaxCols.
+// Returns false when the input row or the workspace row would exceed kLargeMaxCols.
 bool build_large(const GraphPlan &p, int direction, LargeImage &out);
 
 }  // namespace gft

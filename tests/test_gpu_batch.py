@@ -60,6 +60,44 @@ def test_config4_mixed_batch_forward_inverse():
     assert O.relative_error(xr, flat.astype(np.float64)) <= 2e-5
 
 
+def test_config4_bench_counts_sampled():
+    """The benchmark's mixed batch as timed: all 146 graphs with their log-uniform counts of
+    256..65536 signals (about 67 M values), one forward and one inverse launch.  Per graph,
+    sampled rows (first, last and 28 drawn) against the aligned oracle, forward and inverse
+    (the inverse of the GPU's own coefficients against the oracle's inverse of them), and the
+    energy of every graph's slice."""
+    dev = device()
+    graphs = wl.config4_graphs(wl.rng_for(4))
+    counts = wl.config4_signal_counts(len(graphs), wl.rng_for(4, 1))
+    assert counts.min() >= 256 and counts.max() <= 65536
+    rng = wl.rng_for(4, 2)
+    xs = [wl.gaussian(int(s), g.n, rng) for g, s in zip(graphs, counts)]
+    flat = np.concatenate([x.reshape(-1) for x in xs])
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    plan = G.gft_plan_batch(graphs)
+    x = torch.from_numpy(flat).to(dev)
+    offs = torch.from_numpy(off).to(dev)
+    y = G.gft_forward_batch(plan, x, offs)
+    xr = G.gft_inverse_batch(plan, y, offs)
+    torch.cuda.synchronize()
+    pick = wl.rng_for(4, 8)
+    for i, ((a, b), g, X) in enumerate(zip(_slices(graphs, counts), graphs, xs)):
+        S = int(counts[i])
+        rows = np.unique(np.r_[0, 1, S - 2, S - 1, pick.choice(S, 28, replace=False)])
+        yv = y[a:b].view(S, g.n)
+        Yg = to_np(yv[torch.from_numpy(rows).to(dev)])
+        Xg = to_np(xr[a:b].view(S, g.n)[torch.from_numpy(rows).to(dev)])
+        _, Ua = aligned_oracle_basis(g, plan.basis(i), sv_tol=1e-9)
+        ref = O.forward(X[rows].astype(np.float64), Ua)
+        err = O.relative_error(Yg, ref)
+        assert err <= 1e-5 and O.max_row_relative_error(Yg, ref) <= 1e-5, f"graph {i} ({g.name}{g.n}): {err:.3e}"
+        ref_i = O.inverse(Yg, Ua)
+        assert O.relative_error(Xg, ref_i) <= 1e-5, f"graph {i} ({g.name}{g.n}): inverse"
+        e_in = float(torch.sum(x[a:b].double() ** 2))
+        e_out = float(torch.sum(y[a:b].double() ** 2))
+        assert abs(e_out - e_in) <= 1e-5 * e_in, f"graph {i}: energy {e_in} -> {e_out}"
+
+
 def _batch_engine(g):
     """The engine a batch plan runs graph g on: the register-butterfly forms the batch kernel
     compiles (one stage with sides of at most 48 nodes, or two stages on 16- or 32-slot

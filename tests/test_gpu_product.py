@@ -5,8 +5,7 @@ The oracle's eigenbasis of the product Laplacian is rotated onto the plan's basi
 each eigenvalue cluster (products of symmetric factors have many repeated eigenvalues
 lambda_p + mu_q = lambda_q + mu_p); every coefficient of every signal is compared.  FP32
 tolerance: relative error <= 1e-5.  The 64 x 64 grid at the benchmark's 65536 signals is
-checked on sampled signals against the plan's FP64 host algebra, whose basis the host tests
-pin to the oracle.
+checked on sampled signals against the oracle's eigenbasis of the 4096-node grid.
 """
 import numpy as np
 import pytest
@@ -14,7 +13,7 @@ import pytest
 import paper_1907_07875_amd as G
 import workloads as wl
 from oracle import gft_oracle as O
-from tests.gpu_helpers import device, gpu_basis, to_np, torch
+from tests.gpu_helpers import aligned_oracle_basis, device, gpu_basis, to_np, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -71,13 +70,8 @@ def test_product_reduced_precision(pair, precision, tol):
     ga, gb = pair
     plan = G.Plan.from_product(ga, gb, precision=precision)
     g = wl.cartesian_product(ga, gb)
-    if g.n <= 1024:
-        lam_o, U_o = O.gft(O.laplacian_of(g))
-        Ua, min_sv = O.align(U_o, plan.basis(), lam_o)
-        assert min_sv > 1 - 1e-9
-        ref = lambda X: O.forward(X, Ua)          # noqa: E731
-    else:
-        ref = lambda X: plan.apply_host(X, 0)     # noqa: E731  (basis pinned by the host tests)
+    _, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-8)
+    ref = lambda X: O.forward(X, Ua)          # noqa: E731
     X = wl.gaussian(333, g.n, wl.rng_for(9, g.n, 21))
     y = plan.forward(torch.from_numpy(X).to(dev))
     err = O.relative_error(to_np(y), ref(X.astype(np.float64)))
@@ -90,16 +84,17 @@ def test_product_reduced_precision(pair, precision, tol):
 
 def test_product_grid64_full_size_sampled():
     """64 x 64 grid as path64 x path64 (each axis with its halving reversal stages), 65536
-    signals in one launch: sampled rows against the plan's FP64 algebra, round trip on all."""
+    signals in one launch: sampled rows against the aligned oracle, round trip on all."""
     dev = device()
     ga = wl.path_recursive(64)
     plan = G.Plan.from_product(ga, ga)
     S, n = 65536, 4096
+    _, Ua = aligned_oracle_basis(wl.cartesian_product(ga, ga), plan.basis(), sv_tol=1e-8)
     X = wl.gaussian(S, n, wl.rng_for(5, 7))
     x = torch.from_numpy(X).to(dev)
     y = plan.forward(x)
     rows = np.sort(wl.rng_for(5, 8).choice(S, 256, replace=False))
-    Yh = plan.apply_host(X[rows].astype(np.float64), 0)
+    Yh = O.forward(X[rows].astype(np.float64), Ua)
     assert O.relative_error(to_np(y[torch.from_numpy(rows).to(dev)]), Yh) <= TOL
     xr = plan.inverse(y)
     assert O.relative_error(to_np(xr[torch.from_numpy(rows).to(dev)]), X[rows].astype(np.float64)) <= 2 * TOL

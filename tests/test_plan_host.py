@@ -176,6 +176,22 @@ def test_error_bad_options():
     assert (p.in_dtype, p.out_dtype) == ("bf16", "bf16")
 
 
+def test_wide_signals_beyond_one_lds_row_rejected_at_planning():
+    """Signals wider than a generic-engine tile run on the large-signal engine, which stages
+    whole FP32 rows (input and block-padded workspace) in 160 KB of LDS: at most 40960
+    columns.  An edgeless graph has one block per node, each padded to 8 workspace
+    columns: 5120 nodes fill exactly 40960, 5121 exceed it and no engine can run the plan."""
+    ok = G.gft_plan(5120, [], [], [])
+    assert ok.info()["num_blocks"] == 5120
+    e = None
+    try:
+        G.gft_plan(5121, [], [], [])
+    except G.GFTError as err:
+        e = err
+    assert e is not None and e.status_name == "GFT_ERR_UNSUPPORTED" and "40960" in str(e)
+    assert _status(lambda: G.gft_plan(40961, [], [], [])) == "GFT_ERR_UNSUPPORTED"
+
+
 def test_null_arguments_rejected():
     lib = G.load_library()
     h = ctypes.c_void_p()
