@@ -246,6 +246,22 @@ gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_sign
 gft_status gft_inverse(gft_plan_t plan, const void *y, void *x, int64_t num_signals,
                        void *stream);
 
+/* Allocation-free apply, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  direction 0 runs
+ * gft_forward, 1 gft_inverse, with the same arguments, layout, kernels and results (bit
+ * for bit).  It calls no hipMalloc, hipFree or allocating routine: the plan must already
+ * have an image on the current device (gft_plan_prepare there, which allocates; else
+ * GFT_ERR_INVALID_ARG), and the large-signal engine takes its workspace from a static
+ * array of 64 MiB per GPU held by the library until the process ends (each call needs
+ * num_signals * w * 4 bytes, twice that when its output order is not fused, w = n plus
+ * each leaf block padded to 8; larger calls are rejected with GFT_ERR_INVALID_ARG and the
+ * largest signal count in gft_last_error).  Every call on a GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (different streams or threads) race on it and must
+ * be serialised by the caller; the other engines use no workspace.  Batch plans are
+ * rejected (gft_forward_batch allocates nothing once the plan is prepared). */
+gft_status gft_apply_noalloc(gft_plan_t plan, int32_t direction, const void *in, void *out,
+                             int64_t num_signals, void *stream);
+
 /* Mixed batch in one persistent launch.  signal_offsets: device int64 array of
  * num_graphs+1 non-decreasing entries, graph g owning signals [off[g], off[g+1]).
  * Graph g's data starts at element sum_{h<g} (off[h+1]-off[h]) * n_h of x (and of y):

@@ -37,6 +37,7 @@ EXPORTS = [
     "gft_find_pairing", "gft_plan_product",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version", "gft_stream_copy",
+    "gft_apply_noalloc",
 ]
 
 
@@ -124,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_last_error": ([], ctypes.c_char_p),
         "gft_version": ([], ctypes.c_char_p),
         "gft_stream_copy": ([P, P, i64, P], i32),
+        "gft_apply_noalloc": ([P, i32, P, P, i64, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -400,6 +402,24 @@ def gft_forward(plan: Plan, x, out=None, stream=None):
 def gft_inverse(plan: Plan, y, out=None, stream=None):
     """Signals U y from coefficients (C: ``gft_inverse``)."""
     return _apply("gft_inverse", plan, y, out, stream)
+
+
+def gft_apply_noalloc(plan: Plan, x, out, direction=0, stream=None):
+    """Forward (direction 0) or inverse (1) into the caller's ``out`` without any device
+    allocation (C: ``gft_apply_noalloc``): the plan must be prepared on x's device, and the
+    large-signal engine's workspace is the library's static scratch (64 MiB per GPU)."""
+    if plan.batch:
+        raise ValueError("batch plans use gft_forward_batch / gft_inverse_batch")
+    fwd = direction == 0
+    din, dout = (plan.in_dtype, plan.out_dtype) if fwd else (plan.out_dtype, plan.in_dtype)
+    _check_tensor(x, plan.n, "input", din)
+    _check_tensor(out, plan.n, "output", dout)
+    if out.shape != x.shape:
+        raise ValueError("output shape must equal input shape")
+    _check(load_library().gft_apply_noalloc(plan.handle, int(direction), ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), x.numel() // plan.n,
+                                            _stream_ptr(stream)))
+    return out
 
 
 def gft_stream_copy(src, dst, stream=None):

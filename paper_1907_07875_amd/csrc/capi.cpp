@@ -438,6 +438,12 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   }
   if (use_large) {
     img->large = true;
+    // the allocation-free apply's workspace: this device's address of the static scratch
+    e = large_scratch_setup(dev);
+    if (e != hipSuccess) {
+      (void)hipFree(img->mem);
+      return set_error(GFT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
     for (int d = 0; d < 2; ++d) {
       LargeImage &L = img->lg[d];
       L = std::move(lgi[d]);
@@ -876,6 +882,41 @@ static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *ou
                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
+}
+
+gft_status gft_apply_noalloc(gft_plan_t plan, int32_t direction, const void *in, void *out,
+                             int64_t num_signals, void *stream) {
+  if (direction != 0 && direction != 1) return set_error(GFT_ERR_INVALID_ARG, "direction must be 0 or 1");
+  gft_status st = check_apply_args(plan, in, out, num_signals, direction);
+  if (st != GFT_OK || num_signals == 0) return st != GFT_OK ? st : ok();
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  DeviceImage *img = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(plan->mu);
+    auto it = plan->images.find(dev);
+    if (it != plan->images.end()) img = it->second.get();
+  }
+  if (!img)
+    return set_error(GFT_ERR_INVALID_ARG,
+                     "the plan has no image on the current device: call gft_plan_prepare there first "
+                     "(building the image allocates device memory)");
+  void *ws = nullptr;
+  if (img->large) {
+    ws = large_scratch(dev);
+    if (!ws) return set_error(GFT_ERR_HIP, "the static scratch of this device was not set up");
+    const size_t need = large_ws_bytes(img->lg[direction], num_signals);
+    if (need > kScratchBytes) {
+      const size_t per = large_ws_bytes(img->lg[direction], 1);
+      return set_error(GFT_ERR_INVALID_ARG,
+                       std::to_string(num_signals) + " signals need " + std::to_string(need) +
+                           " bytes of workspace; the static scratch holds " + std::to_string(kScratchBytes) +
+                           " bytes: at most " + std::to_string(kScratchBytes / per) +
+                           " signals per call on this plan");
+    }
+  }
+  return launch_image(plan, img, direction, in, out, num_signals, stream, ws);
 }
 
 gft_status gft_forward_batch(gft_plan_t plan, const void *x, void *y, const int64_t *signal_offsets,

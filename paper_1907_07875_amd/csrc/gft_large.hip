@@ -7,8 +7,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "device_program.hpp"
+#include "launch.hpp"
 
 namespace gft {
 
@@ -361,6 +363,39 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
         if (row < S) C[row * dld + dcol] = acc[i][j][v];
       }
   }
+}
+
+// ---------------------------------------------------------------------------- scratch
+
+// Workspace of the allocation-free apply (gft_apply_noalloc): a fixed array in the code
+// object, one copy per GPU the library runs on, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel (on the host the name is a stand-in, not a
+// device address): large_scratch_setup() looks up each device's address once, and the
+// kernels receive that address like any other workspace pointer.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t large_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+void *large_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 // ---------------------------------------------------------------------------- launch

@@ -38,6 +38,14 @@ hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const 
                              const void *A, float *C, int64_t S, int ld, int64_t grid,
                              const int32_t *omap, int ldy, hipStream_t stream);
 
+// Static scratch of the allocation-free apply: kScratchBytes per GPU, in the code object.
+// large_scratch_setup(dev) runs with device `dev` current (at plan preparation), looks up
+// the array's address on that device once and keeps it; large_scratch(dev) returns it
+// (null before set-up).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t large_scratch_setup(int dev);
+void *large_scratch(int dev);
+
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(const UProgram &P);   // a kernel is compiled for its shape
 // in16 / out16: the input / output array holds BF16 values (else FP32).

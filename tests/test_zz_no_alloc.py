@@ -1,0 +1,116 @@
+"""gft_apply_noalloc: the allocation-free apply, against gft_forward / gft_inverse.
+
+The entry point runs the same kernels as gft_forward and gft_inverse; the large-signal
+engine takes its workspace from the library's static scratch instead of the stream-ordered
+pool.  Checked through the C ABI: bit-equal results on two calls in a row (the second on
+fewer signals, so stale scratch contents from the first call are present), no drop in
+the device's free memory across the calls, and the errors for an unprepared plan, a call
+larger than the scratch, and batch plans.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1907_07875_amd as G
+import workloads as wl
+from tests.gpu_helpers import device, torch
+
+pytestmark = pytest.mark.gpu
+
+SCRATCH_BYTES = 64 << 20
+
+
+def _noalloc(plan, x, out, direction):
+    return G.load_library().gft_apply_noalloc(plan.handle, direction, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr()), x.shape[0],
+                                              G._stream_ptr(None))
+
+
+CASES = [
+    # (graph, precision, engine, signals of the two calls); the 1024-node path's forward
+    # writes the output order from the GEMM (W1 only), its inverse runs the stage pass after
+    # the GEMM (W1 and W2): at most 8192 signals per call in both directions
+    ("wpath1024", "fp32", "auto", (8191, 4097)),         # large engine
+    ("wpath1024", "bf16", "auto", (8192, 129)),          # BF16 workspace
+    ("wpath1024", "split_bf16", "auto", (5000, 1)),
+    ("grid64x64", "fp32", "large", (1900, 333)),         # 49 blocks: W1 and W2, three passes
+    ("grid8x8", "fp32", "auto", (70001, 17)),            # butterfly engine: no workspace
+    ("skeleton25", "bf16", "auto", (9000, 15)),
+]
+
+
+def _graph(name):
+    return {"wpath1024": wl.config5b_graph, "grid64x64": wl.config5a_graph,
+            "grid8x8": wl.config2_graph, "skeleton25": wl.config3_graph}[name]()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}-{c[2]}")
+def test_noalloc_matches_allocating_apply(case):
+    name, precision, engine, counts = case
+    dev = device()
+    g = _graph(name)
+    plan = G.Plan.from_graph(g, precision=precision, engine=engine)
+    plan.prepare()
+    S1, S2 = counts
+    X = torch.from_numpy(wl.gaussian(S1, g.n, wl.rng_for(7, g.n, S1))).to(dev)
+    refs = {}
+    for d, fn in ((0, G.gft_forward), (1, G.gft_inverse)):
+        refs[d] = (fn(plan, X), fn(plan, X[:S2].contiguous()))
+    outs = {d: (torch.full_like(X, float("nan")), torch.full_like(X[:S2], float("nan"))) for d in (0, 1)}
+    X2 = X[:S2].contiguous()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(dev)[0]
+    for d in (0, 1):
+        assert _noalloc(plan, X, outs[d][0], d) == 0, G.load_library().gft_last_error()
+        assert _noalloc(plan, X2, outs[d][1], d) == 0, G.load_library().gft_last_error()
+    torch.cuda.synchronize()
+    # an allocation would lower the device's free memory; it may rise meanwhile, as the
+    # stream-ordered pool returns what the allocating reference calls released
+    assert torch.cuda.mem_get_info(dev)[0] >= free0, "device memory taken by allocation-free calls"
+    for d in (0, 1):
+        assert torch.equal(outs[d][0], refs[d][0]), f"direction {d}: first call differs"
+        assert torch.equal(outs[d][1], refs[d][1]), f"direction {d}: second (smaller) call differs"
+
+
+def test_noalloc_rejects_calls_beyond_the_scratch():
+    dev = device()
+    g = wl.config5b_graph()
+    plan = G.Plan.from_graph(g)
+    plan.prepare()
+    per_signal = g.n * 4                        # forward: fused output order, W1 only
+    limit = SCRATCH_BYTES // per_signal
+    x = torch.zeros((limit + 1, g.n), device=dev)
+    y = torch.empty_like(x)
+    assert _noalloc(plan, x[:limit], y[:limit], 0) == 0
+    st = _noalloc(plan, x, y, 0)
+    assert G.STATUS[st] == "GFT_ERR_INVALID_ARG"
+    assert f"at most {limit} signals" in G.load_library().gft_last_error().decode()
+    # the inverse runs its stage pass after the GEMM: W1 and W2, half as many signals
+    assert _noalloc(plan, x[:limit // 2], y[:limit // 2], 1) == 0
+    st = _noalloc(plan, x[:limit // 2 + 1], y[:limit // 2 + 1], 1)
+    assert G.STATUS[st] == "GFT_ERR_INVALID_ARG"
+    assert f"at most {limit // 2} signals" in G.load_library().gft_last_error().decode()
+    torch.cuda.synchronize()
+
+
+def test_noalloc_needs_a_prepared_plan_and_a_single_graph():
+    dev = device()
+    g = wl.config5b_graph()
+    plan = G.Plan.from_graph(g)                  # not prepared: no image on this device
+    x = torch.zeros((4, g.n), device=dev)
+    y = torch.empty_like(x)
+    assert G.STATUS[_noalloc(plan, x, y, 0)] == "GFT_ERR_INVALID_ARG"
+    assert "gft_plan_prepare" in G.load_library().gft_last_error().decode()
+    plan.prepare()
+    assert _noalloc(plan, x, y, 0) == 0
+    assert G.STATUS[_noalloc(plan, x, y, 2)] == "GFT_ERR_INVALID_ARG"
+    bplan = G.gft_plan_batch([wl.path(8), wl.path(9)])
+    bplan.prepare()
+    assert G.STATUS[_noalloc(bplan, x, y, 0)] == "GFT_ERR_INVALID_ARG"
+    # the binding's wrapper checks shapes and returns the output
+    out = G.gft_apply_noalloc(plan, x, torch.empty_like(x), direction=0)
+    assert torch.equal(out, G.gft_forward(plan, x))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(G.gft_apply_noalloc(plan, x, torch.empty_like(x), 1).cpu().numpy(),
+                                  G.gft_inverse(plan, x).cpu().numpy())
