@@ -57,8 +57,9 @@ def parse():
     ap.add_argument("--signals", type=int, default=None, help="override the signal count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly", "product"],
-                    help="product: the 64x64 grid as a product plan of two 64-node paths")
+    ap.add_argument("--engine", default="auto", choices=["auto", "generic", "butterfly", "large", "product"],
+                    help="grid64: large runs the 12-stage plan's dense leaf blocks on the large engine; "
+                         "product plans the grid with gft_plan_product from two 64-node paths")
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "split_bf16"])
     ap.add_argument("--io", default="fp32", choices=["fp32", "bf16"],
                     help="storage type of signals and coefficients (single-graph workloads)")
@@ -375,28 +376,39 @@ def bench_skeleton(args):
 
 
 def _large_workload(args, graph, S, name, desc):
-    import numpy as np
     import paper_1907_07875_amd as G
     import workloads as wl
     X = wl.gaussian(S, graph.n, wl.rng_for(5, 7))
-    st = G.Plan.from_graph(graph).info()
-    sum_b2 = st["mults"] - st["num_z_scalings"]
-    # per signal: 2 flops per block multiply-add, plus the Haar units' add/sub
-    flops = 2.0 * sum_b2 + 2.0 * st["num_units"]
-    bench_single(args, graph, X, args.precision or "fp32",
+    precision = args.precision or "fp32"
+    engine = args.engine if args.engine in ("large", "product", "generic") else "auto"
+    plan = G.Plan.from_graph(graph, engine=engine, precision=precision)
+    plan.prepare()
+    st = plan.info()
+    eng = plan.engine()
+    if eng == "product":
+        # separable engine: the two factor GFTs as dense products, 2 n (na + nb) flops
+        import math
+        na = int(round(math.sqrt(graph.n)))
+        flops = 2.0 * graph.n * (na + graph.n // na) if na * na == graph.n else 2.0 * st["separable_mults"]
+    else:
+        # per signal: 2 flops per block multiply-add, plus the Haar units' add/sub
+        flops = 2.0 * (st["mults"] - st["num_z_scalings"]) + 2.0 * st["num_units"]
+    bench_single(args, graph, X, precision,
                  {"workload": name, "graph": desc, "stages": st["num_stages"],
                   "leaf_blocks": st["num_blocks"], "max_block": st["max_block"],
+                  "kron_leaves": st["num_kron_leaves"], "separable_mults": st["separable_mults"],
                   "dense_flops_per_signal": 2.0 * graph.n * graph.n, "fast_flops_per_signal": flops},
                  256, "first 256 signals of the same workload",
                  kernel_names={"large": "large engine: permute_stages + block_gemm (+ permute_stages "
-                                          "unless the output order is fused)"},
-                 flops_per_signal=flops)
+                                          "unless the output order is fused)",
+                               "product": "gft_product<64,64> (separable Kronecker leaves)"},
+                 flops_per_signal=flops, make_plan=lambda: plan)
 
 
 def bench_grid64(args):
     import workloads as wl
     if args.engine == "product":
-        return bench_grid64_product(args)
+        return bench_grid64_product(args)   # the explicit product plan (gft_plan_product)
     _large_workload(args, wl.config5a_graph(), args.signals or 65536, "grid64x64_fwd_inv",
                     "64x64 grid, LR/UD reversals recursed on the + branch (12 stages)")
 

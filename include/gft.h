@@ -132,8 +132,10 @@ typedef enum {
  * of a compiled shape with FP32 blocks, or a one-stage plan with 8 <= n <= 96 and sides of
  * at most 48 nodes (FP32 or BF16 blocks), or a two-stage plan whose orbits and leaf blocks
  * fit 16 or 32 slots per side (FP32 blocks); else the large-signal engine when a tile of 16
- * signals does not fit a workgroup's LDS or a leaf block has 192 nodes or more; else the
- * generic engine.  Batch plans run each graph that a register-butterfly form of the batch
+ * signals does not fit a workgroup's LDS or a leaf block has 192 nodes or more (the
+ * product engine instead when every leaf block has a Kronecker basis, see num_kron_leaves,
+ * with factors of at most 64 nodes, FP32 storage and FP32, BF16 or split BF16 blocks); else
+ * the generic engine.  Batch plans run each graph that a register-butterfly form of the batch
  * kernel covers (one stage with sides of at most 48 nodes, two stages on 16- or 32-slot
  * sides, FP32 blocks; BF16 blocks: one stage) in its register phase and the others on their
  * generic-engine programs; GFT_ENGINE_GENERIC puts every graph on the latter. */
@@ -149,8 +151,11 @@ typedef enum {
                               /* has Haar stages or there are more than 8 leaf blocks),  */
                               /* w = n plus each leaf block padded to                    */
                               /* a multiple of 8; FP16 is unsupported                    */
-  GFT_ENGINE_PRODUCT = 4      /* reported for product-graph plans (gft_plan_product);    */
-                              /* not an options.engine value                             */
+  GFT_ENGINE_PRODUCT = 4      /* separable engine: U_a^T X U_b per signal on MFMA.  The  */
+                              /* engine of product-graph plans (gft_plan_product); as   */
+                              /* options.engine it runs a gft_plan whose leaves have    */
+                              /* Kronecker bases (else GFT_ERR_UNSUPPORTED at the first */
+                              /* apply)                                                 */
 } gft_engine;
 
 typedef struct {
@@ -184,6 +189,11 @@ typedef struct {
   double max_orth_error;   /* max over blocks of ||V_b^T V_b - I||_max                */
   int32_t num_right_units; /* right Haar units (included in num_units and adds)       */
   int32_t num_right_leaves;/* leaf components applied with right Haar units           */
+  int32_t num_kron_leaves; /* leaf blocks with Kronecker bases V_a (x) V_b: the graph is */
+                           /* a row-major Cartesian product whose stages act along one  */
+                           /* axis each (Sec. V-D); 0 or num_blocks                     */
+  int64_t separable_mults; /* mults with those leaves applied separably, V_a^T Z V_b:   */
+                           /* sum b_a b_b (b_a + b_b) + num_z_scalings (else = mults)   */
 } gft_plan_stats;
 
 /* Build a plan for one graph.  Validates the graph and every stage, forms the sub-graph

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgft.so")
 GFT_FP32, GFT_BF16, GFT_FP16, GFT_SPLIT_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": GFT_FP32, "bf16": GFT_BF16, "fp16": GFT_FP16, "split_bf16": GFT_SPLIT_BF16}
 ORDER_EIGENVALUE, ORDER_BLOCK = 0, 1
-ENGINES = {"auto": 0, "generic": 1, "butterfly": 2, "large": 3}
+ENGINES = {"auto": 0, "generic": 1, "butterfly": 2, "large": 3, "product": 4}
 DTYPES = {"fp32": 0, "bf16": 1}
 LAPLACIANS = {"combinatorial": 0, "normalized": 1}
 
@@ -73,7 +73,8 @@ class PlanStats(ctypes.Structure):
                 ("max_block", ctypes.c_int32), ("num_z_scalings", ctypes.c_int32),
                 ("adds", ctypes.c_int64), ("mults", ctypes.c_int64),
                 ("max_residual", ctypes.c_double), ("max_orth_error", ctypes.c_double),
-                ("num_right_units", ctypes.c_int32), ("num_right_leaves", ctypes.c_int32)]
+                ("num_right_units", ctypes.c_int32), ("num_right_leaves", ctypes.c_int32),
+                ("num_kron_leaves", ctypes.c_int32), ("separable_mults", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

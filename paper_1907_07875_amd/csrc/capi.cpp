@@ -83,6 +83,9 @@ struct gft_plan_s {
   GraphPlan fa, fb;
   std::vector<double> ua, ub;
   std::vector<int32_t> order;
+  // Plans whose leaf blocks have Kronecker bases (graphs[0].kron): the factor plans' FP64
+  // bases, for the separable engine.
+  std::vector<double> kua, kub;
   std::mutex mu;
   std::map<int, std::unique_ptr<DeviceImage>> images;
 
@@ -122,8 +125,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.precision is not a gft_precision value");
   if (o.order != GFT_ORDER_EIGENVALUE && o.order != GFT_ORDER_BLOCK)
     return set_error(GFT_ERR_INVALID_ARG, "options.order must be 0 or 1");
-  if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_LARGE)
-    return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2 or 3");
+  if (o.engine < GFT_ENGINE_AUTO || o.engine > GFT_ENGINE_PRODUCT)
+    return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2, 3 or 4");
   if (o.right_haar != GFT_RIGHT_HAAR_AUTO && o.right_haar != GFT_RIGHT_HAAR_OFF)
     return set_error(GFT_ERR_INVALID_ARG, "options.right_haar must be a gft_right_haar value");
   if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL && o.laplacian != GFT_LAPLACIAN_NORMALIZED)
@@ -197,14 +200,25 @@ void autotune_generic(DeviceImage *img, int dir, size_t budget, bool in16, bool 
   (void)hipFree(buf);
 }
 
-// Device image of a product-graph plan on device `dev` (caller holds plan->mu): per
-// direction the zero-padded factor matrices (forward B = U_b, A = U_a^T; inverse B = U_b^T,
-// A = U_a) and the LDS word of every output-order coefficient.
-gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
+// The two factors of a separable plan: FP64 bases (node i of basis vector k at [i * n + k],
+// factor output order) and the factor coefficient pair order[k] = p * nb + q of every
+// output coefficient k.
+struct Factors {
+  int na = 0, nb = 0;
+  const std::vector<double> *ua = nullptr, *ub = nullptr;
+  const std::vector<int32_t> *order = nullptr;
+};
+
+// Device image of a separable plan on device `dev` (caller holds plan->mu): per direction
+// the zero-padded factor matrices (forward B = U_b, A = U_a^T; inverse B = U_b^T, A = U_a)
+// and the LDS word of every output-order coefficient.
+gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImage **out) {
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(CU count)");
-  const int na = plan->fa.n, nb = plan->fb.n, n = na * nb;
+  const int na = F.na, nb = F.nb, n = na * nb;
+  const std::vector<double> &ua = *F.ua, &ub = *F.ub;
+  const std::vector<int32_t> &order = *F.order;
   const int NA = product_pad(na), NB = product_pad(nb), stride = NB + 1;
   Blob blob;
   size_t off[2][3];
@@ -212,19 +226,19 @@ gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
     std::vector<float> A((size_t)NA * NA, 0.0f), B((size_t)NB * NB, 0.0f);
     for (int i = 0; i < na; ++i)
       for (int k = 0; k < na; ++k) {
-        const float u = (float)plan->ua[(size_t)i * na + k];   // node i of vector k
+        const float u = (float)ua[(size_t)i * na + k];   // node i of vector k
         if (d == 0) A[(size_t)k * NA + i] = u;
         else A[(size_t)i * NA + k] = u;
       }
     for (int j = 0; j < nb; ++j)
       for (int q = 0; q < nb; ++q) {
-        const float u = (float)plan->ub[(size_t)j * nb + q];
+        const float u = (float)ub[(size_t)j * nb + q];
         if (d == 0) B[(size_t)j * NB + q] = u;
         else B[(size_t)q * NB + j] = u;
       }
     std::vector<uint16_t> perm(n);
     for (int k = 0; k < n; ++k) {
-      const int p = plan->order[k] / nb, q = plan->order[k] % nb;
+      const int p = order[k] / nb, q = order[k] % nb;
       perm[k] = (uint16_t)(p * stride + q);
     }
     off[d][0] = blob.add(A.data(), A.size() * 4);
@@ -249,7 +263,7 @@ gft_status product_image(gft_plan_s *plan, int dev, DeviceImage **out) {
     P.nb = nb;
     P.dir = d;
     P.stride = stride;
-    P.same = na == nb && plan->ua == plan->ub;
+    P.same = na == nb && ua == ub;
     P.prec = plan->opts.precision;
     P.amat = reinterpret_cast<const float *>(base + off[d][0]);
     P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
@@ -272,7 +286,10 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     *out = it->second.get();
     return GFT_OK;
   }
-  if (plan->product) return product_image(plan, dev, out);
+  if (plan->product) {
+    const Factors F{plan->fa.n, plan->fb.n, &plan->ua, &plan->ub, &plan->order};
+    return product_image(plan, F, dev, out);
+  }
   int max_lds = 0, cus = 0;
   e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, "hipDeviceGetAttribute(shared memory)");
@@ -340,6 +357,21 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   }
   if (plan->opts.engine == GFT_ENGINE_LARGE && plan->batch)
     return set_error(GFT_ERR_UNSUPPORTED, "batch plans run the generic engine");
+
+  // Separable engine for plans whose leaf blocks all have Kronecker bases (Sec. V-D): in
+  // place of the large engine, or when asked for.
+  const KronPlan *K = plan->batch ? nullptr : plan->graphs[0].kron.get();
+  const bool sep_ok = K && prec != GFT_FP16 && plan->opts.in_dtype == GFT_DTYPE_FP32 &&
+                      plan->opts.out_dtype == GFT_DTYPE_FP32 && product_pad(K->na) && product_pad(K->nb);
+  if (plan->opts.engine == GFT_ENGINE_PRODUCT || (plan->opts.engine == GFT_ENGINE_AUTO && use_large && sep_ok)) {
+    if (!sep_ok)
+      return set_error(GFT_ERR_UNSUPPORTED,
+                       "the separable engine runs single-graph plans whose leaf blocks have Kronecker "
+                       "bases (a row-major Cartesian product with stages along the axes, factors of at "
+                       "most 64 nodes), FP32 storage and FP32, BF16 or split BF16 blocks");
+    const Factors F{K->na, K->nb, &plan->kua, &plan->kub, &K->order};
+    return product_image(plan, F, dev, out);
+  }
 
   std::vector<ProgramImage> imgs;
   for (size_t g = 0; g < plan->graphs.size(); ++g)
@@ -724,8 +756,13 @@ gft_status gft_plan(const gft_graph *graph, const gft_pairing *pairing, const gf
     auto p = std::make_unique<gft_plan_s>();
     p->opts = o;
     p->graphs.push_back(build_graph_plan(*graph, pairing, o));
-    st = check_runnable(p->graphs[0]);
-    if (st != GFT_OK) return st;
+    if (const KronPlan *K = p->graphs[0].kron.get()) {
+      p->kua = plan_basis(*K->fa);
+      p->kub = plan_basis(*K->fb);
+    } else {
+      st = check_runnable(p->graphs[0]);
+      if (st != GFT_OK) return st;
+    }
     *out = p.release();
   } catch (const PlanError &err) {
     return set_error(err.status, err.message);

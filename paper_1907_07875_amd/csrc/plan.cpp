@@ -368,10 +368,112 @@ std::vector<std::vector<int>> components(const Sub &H, double tol) {
   return out;
 }
 
+// A graph read as a row-major Cartesian product G_a x G_b (node (i, j) = i * nb + j): the
+// factors' edges, weights and self-loops, and the given stages sorted by axis.
+struct ProductSplit {
+  int32_t na = 0, nb = 0;
+  std::vector<int32_t> src[2], dst[2];
+  std::vector<double> w[2], loop[2];
+  std::vector<int32_t> phi[2];   // stages along axis a (rows) and axis b (columns)
+  int32_t stages[2] = {0, 0};
+};
+
+// Is g, with its stages, such a product for this (na, nb)?  Every edge must join two nodes
+// of one row (an axis-b edge) or of one column (an axis-a edge), with the same weight in
+// every row (column); self-loops must split as s(i, j) = s_a(i) + s_b(j); every stage must
+// move one coordinate only, by the same involution in every row (column).  Weights and
+// loops are compared to `tol` (relative to the largest magnitude).
+bool product_split(const gft_graph &g, const gft_pairing *pairing, int32_t na, int32_t nb, double tol,
+                   ProductSplit &ps) {
+  const int32_t n = g.n;
+  double wmax = 0.0;
+  for (int32_t e = 0; e < g.num_edges; ++e) wmax = std::max(wmax, std::fabs(g.weight[e]));
+  if (g.self_loop)
+    for (int32_t i = 0; i < n; ++i) wmax = std::max(wmax, std::fabs(g.self_loop[i]));
+  const double eps = tol * std::max(wmax, 1e-300);
+  // factor weight matrices and, per factor edge, how many rows (columns) carry it
+  const int32_t m[2] = {na, nb};
+  std::vector<double> W[2];
+  std::vector<int32_t> cnt[2];
+  for (int a = 0; a < 2; ++a) {
+    W[a].assign((size_t)m[a] * m[a], 0.0);
+    cnt[a].assign((size_t)m[a] * m[a], 0);
+  }
+  for (int32_t e = 0; e < g.num_edges; ++e) {
+    const int32_t u = g.src[e], v = g.dst[e];
+    const int32_t iu = u / nb, ju = u % nb, iv = v / nb, jv = v % nb;
+    int ax;
+    int32_t p, q;
+    if (iu == iv) {
+      ax = 1;
+      p = std::min(ju, jv);
+      q = std::max(ju, jv);
+    } else if (ju == jv) {
+      ax = 0;
+      p = std::min(iu, iv);
+      q = std::max(iu, iv);
+    } else {
+      return false;
+    }
+    const size_t k = (size_t)p * m[ax] + q;
+    if (cnt[ax][k] == 0) W[ax][k] = g.weight[e];
+    else if (!(std::fabs(W[ax][k] - g.weight[e]) <= eps)) return false;
+    ++cnt[ax][k];
+  }
+  for (int a = 0; a < 2; ++a) {
+    ps.src[a].clear();
+    ps.dst[a].clear();
+    ps.w[a].clear();
+    for (int32_t p = 0; p < m[a]; ++p)
+      for (int32_t q = p + 1; q < m[a]; ++q) {
+        const int32_t c = cnt[a][(size_t)p * m[a] + q];
+        if (c == 0) continue;
+        if (c != m[1 - a]) return false;   // the edge must repeat in every row (column)
+        ps.src[a].push_back(p);
+        ps.dst[a].push_back(q);
+        ps.w[a].push_back(W[a][(size_t)p * m[a] + q]);
+      }
+  }
+  ps.loop[0].assign(na, 0.0);
+  ps.loop[1].assign(nb, 0.0);
+  if (g.self_loop) {
+    for (int32_t j = 0; j < nb; ++j) ps.loop[1][j] = g.self_loop[j];
+    for (int32_t i = 0; i < na; ++i) ps.loop[0][i] = g.self_loop[(size_t)i * nb] - g.self_loop[0];
+    for (int32_t i = 0; i < na; ++i)
+      for (int32_t j = 0; j < nb; ++j)
+        if (!(std::fabs(g.self_loop[(size_t)i * nb + j] - ps.loop[0][i] - ps.loop[1][j]) <= eps)) return false;
+  }
+  ps.na = na;
+  ps.nb = nb;
+  ps.phi[0].clear();
+  ps.phi[1].clear();
+  ps.stages[0] = ps.stages[1] = 0;
+  const int32_t k = pairing ? pairing->num_stages : 0;
+  for (int32_t s = 0; s < k; ++s) {
+    const int32_t *phi = pairing->phi + (size_t)s * n;
+    bool ident = true, along_a = true, along_b = true;
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t t = phi[v];
+      if (t < 0 || t >= n) return false;
+      ident &= t == v;
+      const int32_t i = v / nb, j = v % nb, ti = t / nb, tj = t % nb;
+      along_a &= tj == j && ti == phi[(size_t)i * nb] / nb && phi[(size_t)i * nb] % nb == 0;
+      along_b &= ti == i && tj == phi[j] % nb && phi[j] / nb == 0;
+    }
+    if (ident) continue;
+    const int ax = along_a ? 0 : (along_b ? 1 : -1);
+    if (ax < 0) return false;
+    for (int32_t c = 0; c < m[ax]; ++c)
+      ps.phi[ax].push_back(ax == 0 ? phi[(size_t)c * nb] / nb : phi[c] % nb);
+    ++ps.stages[ax];
+  }
+  return true;
+}
+
 }  // namespace
 
 GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
-                           const gft_options &opts) {
+                           const gft_options &opts, bool recognize_products) {
   validate_graph(g);
   const int32_t n = g.n;
   const int32_t num_stages = pairing ? pairing->num_stages : 0;
@@ -406,6 +508,59 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
       for (int32_t j = 0; j < n; ++j) subs[0].L[(size_t)i * n + j] /= std::sqrt(d[i] * d[j]);
   }
   const double scale_L = std::max(max_abs(subs[0].L), 1e-300);
+
+  // Cartesian product with stages along the axes: plan the two factors (their leaves give
+  // the leaf blocks' Kronecker bases below).  Only the combinatorial Laplacian is a
+  // Kronecker sum.  The factors are planned without right Haar units (their leaves stay
+  // dense blocks), and a Kronecker leaf is preferred to a right Haar split of the product
+  // leaf: it is applied separably.
+  std::shared_ptr<GraphPlan> kfa, kfb;
+  int32_t kna = 0, knb = 0;
+  if (recognize_products && opts.laplacian == GFT_LAPLACIAN_COMBINATORIAL && n >= 4) {
+    ProductSplit ps;
+    for (int32_t na = std::max<int32_t>(2, (n + 63) / 64); na <= 64 && na * 2 <= n && !kfa; ++na) {
+      if (n % na != 0 || n / na > 64) continue;
+      if (!product_split(g, pairing, na, n / na, sym_tol, ps)) continue;
+      std::shared_ptr<GraphPlan> f[2];
+      try {
+        for (int a = 0; a < 2; ++a) {
+          gft_graph fg{a == 0 ? ps.na : ps.nb, (int32_t)ps.src[a].size(), ps.src[a].data(), ps.dst[a].data(),
+                       ps.w[a].data(), ps.loop[a].data()};
+          gft_pairing fp{ps.stages[a], ps.phi[a].data()};
+          gft_options fo = opts;
+          fo.order = GFT_ORDER_EIGENVALUE;
+          fo.right_haar = GFT_RIGHT_HAAR_OFF;
+          f[a] = std::make_shared<GraphPlan>(build_graph_plan(fg, &fp, fo, false));
+        }
+      } catch (const PlanError &) {
+        continue;   // a factor's stages are not valid on their own: plan the graph as given
+      }
+      if (f[0] && f[1]) {
+        kfa = f[0];
+        kfb = f[1];
+        kna = ps.na;
+        knb = ps.nb;
+      }
+    }
+  }
+  // factor block and local index of every factor node
+  std::vector<int32_t> kblk[2], kpos[2];
+  for (int a = 0; a < 2 && kfa; ++a) {
+    const GraphPlan &F = a == 0 ? *kfa : *kfb;
+    kblk[a].assign(F.n, -1);
+    kpos[a].assign(F.n, -1);
+    for (int32_t b = 0; b < (int32_t)F.blocks.size(); ++b)
+      for (int32_t p = 0; p < F.blocks[b].size; ++p) {
+        kblk[a][F.blocks[b].nodes[p]] = b;
+        kpos[a][F.blocks[b].nodes[p]] = p;
+      }
+  }
+  struct KronBlock {
+    int32_t ba, bb;
+    std::vector<int32_t> ka, kb;   // factor local indices of each local eigenvector
+  };
+  std::vector<KronBlock> kron_blocks;
+  bool all_kron = (bool)kfa;
 
   std::vector<int32_t> owner(n, 0), local(n, 0);
   for (int32_t s = 0; s < num_stages; ++s) {
@@ -489,9 +644,48 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
         B.nodes.push_back(H.nodes[comp[p]]);
         for (int q = 0; q < b; ++q) Lb[(size_t)p * b + q] = H.L[(size_t)comp[p] * m + comp[q]];
       }
+      // Kronecker leaf: the block's nodes are exactly rows(B_a) x columns(B_b) of one block
+      // of each factor plan; its basis V_a (x) V_b, ordered by lambda + mu (ties by the
+      // factor indices).
+      bool kron = false;
+      KronBlock kb{-1, -1, {}, {}};
+      if (all_kron) {
+        const int32_t i0 = B.nodes[0] / knb, j0 = B.nodes[0] % knb;
+        kb.ba = kblk[0][i0];
+        kb.bb = kblk[1][j0];
+        const HostBlock &A = kfa->blocks[kb.ba], &C = kfb->blocks[kb.bb];
+        kron = A.size * C.size == b;
+        for (int p = 0; p < b && kron; ++p) {
+          const int32_t i = B.nodes[p] / knb, j = B.nodes[p] % knb;
+          // nodes ascend: p = (local row) * |B_b| + local column
+          kron = kblk[0][i] == kb.ba && kblk[1][j] == kb.bb && kpos[0][i] * C.size + kpos[1][j] == p;
+        }
+        if (kron) {
+          std::vector<int32_t> idx((size_t)b);
+          std::iota(idx.begin(), idx.end(), 0);
+          std::stable_sort(idx.begin(), idx.end(), [&](int32_t u, int32_t v) {
+            return A.lambda[u / C.size] + C.lambda[u % C.size] < A.lambda[v / C.size] + C.lambda[v % C.size];
+          });
+          B.lambda.resize(b);
+          B.V.assign((size_t)b * b, 0.0);
+          for (int k = 0; k < b; ++k) {
+            const int32_t ka = idx[k] / C.size, kc = idx[k] % C.size;
+            kb.ka.push_back(ka);
+            kb.kb.push_back(kc);
+            B.lambda[k] = A.lambda[ka] + C.lambda[kc];
+            for (int pa = 0; pa < A.size; ++pa)
+              for (int pc = 0; pc < C.size; ++pc)
+                B.V[(size_t)(pa * C.size + pc) * b + k] = A.V[(size_t)pa * A.size + ka] * C.V[(size_t)pc * C.size + kc];
+          }
+        } else {
+          all_kron = false;
+        }
+      }
       RightSplit rs;
-      const bool right = opts.right_haar == GFT_RIGHT_HAAR_AUTO && right_split(b, Lb, tol, rs);
-      if (right) {
+      const bool right = !kron && opts.right_haar == GFT_RIGHT_HAAR_AUTO && right_split(b, Lb, tol, rs);
+      if (kron) {
+        // basis set above; checked below like any leaf basis
+      } else if (right) {
         B.lambda = rs.lamU;
         B.V = rs.U;            // checked below as any leaf basis
       } else if (!symmetric_eigen(b, Lb, B.lambda, B.V)) {
@@ -543,8 +737,10 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
         right_pairs.push_back({(int32_t)plan.blocks.size(), (int32_t)plan.blocks.size() + 1, rs.pairs});
         plan.blocks.push_back(std::move(E));
         plan.blocks.push_back(std::move(F));
+        all_kron = false;
         continue;
       }
+      if (kron) kron_blocks.push_back(std::move(kb));
       plan.blocks.push_back(std::move(B));
     }
   }
@@ -615,6 +811,30 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
   st.mults = sum_b2 + st.num_z_scalings;
   st.max_residual = max_res;
   st.max_orth_error = max_orth;
+  st.num_kron_leaves = 0;
+  st.separable_mults = st.mults;
+  if (all_kron && kron_blocks.size() == plan.blocks.size()) {
+    // coefficient (block b, local k) is factor coefficient pair (p, q): the factors'
+    // output positions of (B_a, ka) and (B_b, kb)
+    auto K = std::make_shared<KronPlan>();
+    K->na = kna;
+    K->nb = knb;
+    K->fa = kfa;
+    K->fb = kfb;
+    K->order.assign(n, -1);
+    int64_t sep = 0;
+    for (size_t b = 0; b < plan.blocks.size(); ++b) {
+      const KronBlock &kb = kron_blocks[b];
+      const HostBlock &A = kfa->blocks[kb.ba], &C = kfb->blocks[kb.bb];
+      sep += (int64_t)A.size * C.size * (A.size + C.size);
+      for (int32_t k = 0; k < plan.blocks[b].size; ++k)
+        K->order[plan.blocks[b].out_pos[k]] = A.out_pos[kb.ka[k]] * knb + C.out_pos[kb.kb[k]];
+    }
+    K->separable_mults = sep;
+    st.num_kron_leaves = (int32_t)plan.blocks.size();
+    st.separable_mults = sep + st.num_z_scalings;
+    plan.kron = std::move(K);
+  }
   return plan;
 }
 

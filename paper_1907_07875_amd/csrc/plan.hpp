@@ -13,6 +13,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,23 @@ struct HostBlock {
   std::vector<int32_t> out_pos;     // output position of eigenvector k
 };
 
+struct GraphPlan;
+
+// Leaf blocks that are Kronecker products.  The Laplacian of a Cartesian product G_a x G_b
+// (node (i, j) labelled i * nb + j) is L_a (x) I + I (x) L_b, and a stage that acts along
+// one axis, phi((i, j)) = (phi_a(i), j) or (i, phi_b(j)), splits it into sub-graphs that
+// are again products (Sec. V-D: grids decompose axis by axis).  So every leaf block is a
+// product B_a x B_b of leaf blocks of the two factor plans (their stages being the stages
+// along each axis, in order), and V_a (x) V_b is an eigenbasis of it (eigenvalue
+// lambda + mu) and U_a (x) U_b the plan's whole basis: the leaves are separable and the
+// transform is U_a^T X U_b per signal X (na x nb).
+struct KronPlan {
+  int32_t na = 0, nb = 0;
+  std::shared_ptr<const GraphPlan> fa, fb;   // factor plans (eigenvalue output order)
+  std::vector<int32_t> order;                // coefficient k is factor pair (order[k] / nb, order[k] % nb)
+  int64_t separable_mults = 0;               // sum over leaves of b_a b_b (b_a + b_b)
+};
+
 struct GraphPlan {
   int32_t n = 0;
   int32_t num_stages_given = 0;
@@ -52,6 +70,7 @@ struct GraphPlan {
   std::vector<HostBlock> blocks;
   std::vector<double> lambda_out;   // eigenvalues in output order
   gft_plan_stats stats{};
+  std::shared_ptr<const KronPlan> kron;   // set when every leaf block is a Kronecker product
 };
 
 // Search up to max_stages pairings stage by stage (each stage searched inside every current
@@ -60,9 +79,11 @@ struct GraphPlan {
 int find_pairing(const gft_graph &g, const gft_options &opts, int max_stages, int64_t budget,
                  std::vector<int32_t> &phi_out);
 
-// Build the plan of one graph.  Throws PlanError.
+// Build the plan of one graph.  Throws PlanError.  recognize_products: look for the
+// row-major Cartesian product structure above (factors of 2 to 64 nodes) and, when found,
+// give the leaf blocks their Kronecker bases.
 GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
-                           const gft_options &opts);
+                           const gft_options &opts, bool recognize_products = true);
 
 // FP64 host application of the factorisation (direction 0 forward, 1 inverse).
 void apply_host(const GraphPlan &p, int direction, const double *x, double *y, int64_t S);

@@ -102,3 +102,76 @@ def test_product_grid64_full_size_sampled():
     e_in = (x.double() ** 2).sum(dim=1)
     e_out = (y.double() ** 2).sum(dim=1)
     assert torch.max(torch.abs(e_out - e_in) / e_in).item() <= 1e-5
+
+
+# ------------------------------------------------- gft_plan with Kronecker leaves (separable)
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_bf16", 1e-5), ("bf16", 2e-2)])
+def test_grid64_twelve_stage_plan_runs_separably(precision, tol):
+    """The 64 x 64 grid planned by gft_plan with its 12 halving stages: its 49 leaf blocks
+    have Kronecker bases, so the automatic engine choice runs it separably (U_a^T X U_b) in
+    place of the large engine's dense leaf GEMMs.  Sampled signals of a 65536-signal launch
+    against the aligned oracle of the 4096-node grid, forward and inverse."""
+    dev = device()
+    g = wl.config5a_graph()
+    plan = G.Plan.from_graph(g, precision=precision)
+    assert plan.engine() == "product" and plan.info()["num_kron_leaves"] == 49
+    _, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-8)
+    S = 65536
+    X = wl.gaussian(S, g.n, wl.rng_for(5, 17))
+    x = torch.from_numpy(X).to(dev)
+    y = plan.forward(x)
+    rows = np.unique(np.r_[0, S - 1, wl.rng_for(5, 18).choice(S, 190, replace=False)])
+    ri = torch.from_numpy(rows).to(dev)
+    ref = O.forward(X[rows].astype(np.float64), Ua)
+    err = O.relative_error(to_np(y[ri]), ref)
+    assert err <= tol, f"{precision}: forward relative error {err:.3e}"
+    if precision == "bf16":
+        assert err > 1e-5, "BF16 error suspiciously small: products may not run in BF16"
+    yi = y[ri].contiguous()
+    xr = to_np(plan.inverse(yi))
+    assert O.relative_error(xr, O.inverse(to_np(yi), Ua)) <= tol
+    # the same plan on the large engine applies the same basis
+    big = G.Plan.from_graph(g, precision=precision, engine="large")
+    assert big.engine() == "large"
+    yl = to_np(big.forward(x[ri].contiguous()))
+    assert O.relative_error(yl, ref) <= tol
+
+
+@pytest.mark.parametrize("S", [1, 37, 1000])
+@pytest.mark.parametrize("pair", [(wl.path(8), wl.path(8)), (wl.path_recursive(16), wl.path_recursive(16)),
+                                  (wl.weighted_symmetric_path(12, wl.rng_for(9, 12)), wl.path(7)),
+                                  (wl.config3_graph(), wl.weighted_symmetric_path(9, wl.rng_for(9, 9))),
+                                  (wl.path(5), wl.cycle(12))], ids=_ids)
+def test_separable_engine_forced_on_staged_products(pair, S):
+    """Staged products planned by gft_plan, forced onto the separable engine (engine 4):
+    every coefficient against the aligned oracle, forward, inverse and round trip; the
+    engine's basis equals the plan's FP64 basis."""
+    dev = device()
+    ga, gb = pair
+    g = wl.product_with_stages(ga, gb)
+    plan = G.gft_plan(g.n, g.src, g.dst, g.weight, g.self_loop, g.stages, engine=4)
+    assert plan.engine() == "product"
+    Uplan = plan.basis()
+    _, Ua = aligned_oracle_basis(g, Uplan, sv_tol=1e-9)
+    assert np.abs(gpu_basis(plan, dev) - Uplan).max() <= 2e-6
+    X = wl.gaussian(S, g.n, wl.rng_for(9, g.n, S, 31))
+    x = torch.from_numpy(X).to(dev)
+    y = plan.forward(x)
+    C_ref = O.forward(X.astype(np.float64), Ua)
+    assert O.relative_error(to_np(y), C_ref) <= TOL
+    C32 = C_ref.astype(np.float32)
+    xr = plan.inverse(torch.from_numpy(C32).to(dev))
+    assert O.relative_error(to_np(xr), O.inverse(C32.astype(np.float64), Ua)) <= TOL
+    assert O.relative_error(to_np(plan.inverse(y)), X.astype(np.float64)) <= 2 * TOL
+
+
+def test_separable_engine_refused_without_kronecker_leaves():
+    dev = device()
+    g = wl.config3_graph()
+    plan = G.gft_plan(g.n, g.src, g.dst, g.weight, g.self_loop, g.stages, engine=4)
+    with pytest.raises(G.GFTError) as e:
+        plan.forward(torch.zeros((4, g.n), device=dev))
+    assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
+    # the 8x8 grid has Kronecker leaves but keeps the register butterfly when not forced
+    assert G.Plan.from_graph(wl.config2_graph()).engine() == "butterfly"

@@ -111,3 +111,82 @@ def test_product_basis_is_the_grid_eigenbasis_at_4096():
     L = O.laplacian_of(wl.cartesian_product(ga, ga))
     assert np.abs(L @ U - U * lam[None, :]).max() <= 1e-10
     assert np.abs(U.T @ U - np.eye(4096)).max() <= 1e-10
+
+
+# ---------------------------------------------------------------- Kronecker leaves in gft_plan
+
+STAGED_PRODUCTS = [
+    (wl.path(8), wl.path(8)),                                              # the 8x8 grid
+    (wl.path_recursive(16), wl.path_recursive(16)),                        # 8 stages
+    (wl.weighted_symmetric_path(12, wl.rng_for(9, 12)), wl.path(7)),       # weights, self-loops
+    (wl.config3_graph(), wl.weighted_symmetric_path(9, wl.rng_for(9, 9))),
+    (wl.path(5), wl.cycle(12)),                                            # V_Z nodes on axis a
+]
+
+
+@pytest.mark.parametrize("pair", STAGED_PRODUCTS, ids=_ids)
+def test_gft_plan_recognises_products_and_gives_separable_leaves(pair):
+    """gft_plan on a row-major Cartesian product whose stages act along one axis each: every
+    leaf block gets a Kronecker basis, and the plan is an exact GFT of the product graph
+    (oracle eigenvalues, Laplacian residual, orthogonality, aligned coefficients); every
+    basis vector, reshaped to na x nb, is the outer product of one eigenvector of each
+    factor Laplacian (checked against the oracle's factor eigendecompositions)."""
+    ga, gb = pair
+    g = wl.product_with_stages(ga, gb)
+    plan = G.Plan.from_graph(g)
+    st = plan.info()
+    assert st["num_kron_leaves"] == st["num_blocks"] > 0
+    L = O.laplacian_of(g)
+    lam_o, U_o = O.gft(L)
+    lam = plan.eigenvalues()
+    np.testing.assert_allclose(lam, lam_o, atol=1e-10 * max(1.0, np.abs(lam_o).max()))
+    U = plan.basis()
+    np.testing.assert_allclose(U.T @ U, np.eye(g.n), atol=1e-12)
+    assert np.abs(L @ U - U * lam[None, :]).max() <= 1e-11 * max(1.0, np.abs(L).max())
+    X = wl.gaussian(30, g.n, wl.rng_for(9, g.n, 12), dtype=np.float64)
+    Ua, min_sv = O.align(U_o, U, lam_o)
+    assert min_sv > 1 - 1e-9
+    assert O.relative_error(plan.apply_host(X, 0), O.forward(X, Ua)) <= 1e-9
+    # separability: each basis vector is u_a (x) u_b with L_a u_a = l_a u_a, L_b u_b = l_b u_b
+    La, Lb = O.laplacian_of(ga), O.laplacian_of(gb)
+    for k in range(g.n):
+        M = U[:, k].reshape(ga.n, gb.n)
+        sv = np.linalg.svd(M, compute_uv=False)
+        assert sv[0] == pytest.approx(1.0, abs=1e-10) and (len(sv) < 2 or sv[1] <= 1e-10)
+        A, _, Bt = np.linalg.svd(M)
+        ua, ub = A[:, 0], Bt[0]
+        la, lb = ua @ La @ ua, ub @ Lb @ ub
+        assert np.abs(La @ ua - la * ua).max() <= 1e-10 and np.abs(Lb @ ub - lb * ub).max() <= 1e-10
+        assert la + lb == pytest.approx(lam[k], abs=1e-10)
+
+
+def test_grid64_recursive_plan_has_separable_leaf_count():
+    """The 64x64 grid with 12 halving stages: 49 leaf blocks, each b_i x b_j with b in
+    (32, 16, 8, 4, 2, 1, 1) per axis.  Dense leaf products cost sum (b_i b_j)^2 =
+    (sum b^2)^2 = 1366^2 multiplications per signal (Table tab:runtime convention); applied
+    separably, b_i b_j (b_i + b_j) summed, 2 * 1366 * 64 = 174848."""
+    plan = G.Plan.from_graph(wl.config5a_graph())
+    st = plan.info()
+    assert st["num_blocks"] == st["num_kron_leaves"] == 49
+    assert st["mults"] - st["num_z_scalings"] == 1366 ** 2
+    assert st["separable_mults"] - st["num_z_scalings"] == 2 * 1366 * 64 == 174848
+
+
+def test_non_products_and_cross_axis_stages_keep_dense_leaves():
+    """A stage that mixes the axes (the transposition (k, l) -> (l, k) of a square grid),
+    edge weights that differ between rows, a non-product graph: no Kronecker leaves, the plan
+    as given."""
+    g = wl.grid(6, 6)
+    tr = np.arange(36).reshape(6, 6).T.reshape(-1).astype(np.int32)
+    g.stages = [tr]
+    plan = G.Plan.from_graph(g)
+    assert plan.info()["num_kron_leaves"] == 0
+    lam_o, _ = O.gft(O.laplacian_of(g))
+    np.testing.assert_allclose(plan.eigenvalues(), lam_o, atol=1e-10)
+    h = wl.grid(4, 4)
+    w = h.weight.copy()
+    w[0] = 2.0                                # one row's edge differs from the other rows'
+    h = wl._graph(16, np.stack([h.src, h.dst], 1), w, stages=[], name="grid_w")
+    assert G.Plan.from_graph(h).info()["num_kron_leaves"] == 0
+    assert G.Plan.from_graph(wl.config3_graph()).info()["num_kron_leaves"] == 0
+    assert G.Plan.from_graph(wl.cycle(16)).info()["num_kron_leaves"] == 0

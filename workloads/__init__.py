@@ -273,6 +273,25 @@ def cartesian_product(ga: Graph, gb: Graph, name="product") -> Graph:
     return _graph(na * nb, edges, w, loops, None, name)
 
 
+def product_with_stages(ga: Graph, gb: Graph, name="product_staged") -> Graph:
+    """Cartesian product of ga and gb (labels as :func:`cartesian_product`) carrying the
+    factors' stages lifted to their axes, alternating axis b then axis a while both last:
+    ga's stage phi_a becomes (i, j) -> (phi_a(i), j), gb's phi_b becomes (i, j) -> (i, phi_b(j))."""
+    g = cartesian_product(ga, gb, name=name)
+    na, nb = ga.n, gb.n
+    i, j = np.divmod(np.arange(na * nb), nb)
+    lifted_a = [(np.asarray(p)[i] * nb + j).astype(np.int32) for p in ga.stages]
+    lifted_b = [(i * nb + np.asarray(p)[j]).astype(np.int32) for p in gb.stages]
+    stages = []
+    for t in range(max(len(lifted_a), len(lifted_b))):
+        if t < len(lifted_b):
+            stages.append(lifted_b[t])
+        if t < len(lifted_a):
+            stages.append(lifted_a[t])
+    g.stages = stages
+    return g
+
+
 def skeleton25(name="skeleton25") -> Graph:
     """25-node skeleton tree: 5-node spine plus mirror-symmetric arms and legs of 5 nodes.
 
