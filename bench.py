@@ -227,6 +227,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     plan.prepare()
     eng = plan.engine()
     tiles = plan.tiles()
+    launch = plan.tuning()
     stream = torch.cuda.current_stream()
     ya, yb, xr = torch.empty_like(xa), torch.empty_like(xa), torch.empty_like(xa)
     bufs = [(xa, ya), (xb, yb)]
@@ -272,7 +273,7 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
-            "kernel": kname + " (forward)", "engine": eng, "signals_per_tile": list(tiles),
+            "kernel": kname + " (forward)", "engine": eng, "signals_per_tile": list(tiles), "launch": launch,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms}
     if flops_per_signal is not None:
         # the binding roofline: MFMA when the leaf products' arithmetic intensity (flop per
@@ -385,11 +386,16 @@ def _large_workload(args, graph, S, name, desc):
     plan.prepare()
     st = plan.info()
     eng = plan.engine()
-    if eng == "product":
-        # separable engine: the two factor GFTs as dense products, 2 n (na + nb) flops
+    tuning = plan.tuning()
+    if eng == "product" and tuning["variant"] == 0:
+        # separable engine, dense factors: two factor GFTs as dense products, 2 n (na + nb)
         import math
         na = int(round(math.sqrt(graph.n)))
-        flops = 2.0 * graph.n * (na + graph.n // na) if na * na == graph.n else 2.0 * st["separable_mults"]
+        flops = 2.0 * graph.n * (na + graph.n // na)
+    elif eng == "product":
+        # staged factors: the Kronecker leaves' block products b_a b_b (b_a + b_b) summed,
+        # plus the Haar units' add/sub
+        flops = 2.0 * (st["separable_mults"] - st["num_z_scalings"]) + 2.0 * st["num_units"]
     else:
         # per signal: 2 flops per block multiply-add, plus the Haar units' add/sub
         flops = 2.0 * (st["mults"] - st["num_z_scalings"]) + 2.0 * st["num_units"]
@@ -397,6 +403,7 @@ def _large_workload(args, graph, S, name, desc):
                  {"workload": name, "graph": desc, "stages": st["num_stages"],
                   "leaf_blocks": st["num_blocks"], "max_block": st["max_block"],
                   "kron_leaves": st["num_kron_leaves"], "separable_mults": st["separable_mults"],
+                  "launch": tuning,
                   "dense_flops_per_signal": 2.0 * graph.n * graph.n, "fast_flops_per_signal": flops},
                  256, "first 256 signals of the same workload",
                  kernel_names={"large": "large engine: permute_stages + block_gemm (+ permute_stages "
@@ -461,6 +468,7 @@ def bench_mixed(args):
     E = flat.size
     plan = G.gft_plan_batch(graphs, precision=precision)
     plan.prepare()
+    launch = plan.tuning()
     xa = torch.from_numpy(flat).to(dev)
     xb = torch.roll(xa, shifts=1).contiguous()
     ya, yb, xr = torch.empty_like(xa), torch.empty_like(xa), torch.empty_like(xa)
@@ -495,7 +503,7 @@ def bench_mixed(args):
                    "signals": int(counts.sum()), "elements": int(E), "precision": precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"gft_apply_batch<{precision}> (forward)",
+                     "kernel": f"gft_apply_batch<{precision}> (forward)", "launch": launch,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": fwd_ms},
     }
     if not args.no_dense:

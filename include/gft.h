@@ -174,7 +174,42 @@ typedef struct {
                            /* (else GFT_ERR_UNSUPPORTED); in place needs equal types  */
   int32_t laplacian;       /* gft_laplacian                                           */
   int32_t right_haar;      /* gft_right_haar                                          */
+  int32_t autotune;        /* gft_autotune: launch choices timed at preparation (0,  */
+                           /* the default) or the built-in ones (1); see             */
+                           /* gft_plan_tuning                                         */
 } gft_options;
+
+typedef enum {
+  GFT_AUTOTUNE_ON = 0,     /* time the candidates at preparation, or reuse the cache  */
+  GFT_AUTOTUNE_OFF = 1     /* built-in launch choices                                 */
+} gft_autotune;
+
+/* Where a plan's launch choices on a device came from. */
+typedef enum {
+  GFT_TUNE_BUILTIN = 0,    /* built-in choices (autotune off, or nothing to choose)   */
+  GFT_TUNE_TIMED = 1,      /* candidates timed at preparation on this device          */
+  GFT_TUNE_CACHED = 2      /* taken from the tuning cache (same device kind, same     */
+                           /* plan image): no timing                                  */
+} gft_tune_source;
+
+/* Launch choices of a plan on the current device (gft_plan_tuning).  None of them changes
+ * the arithmetic of a signal: every choice gives bit-identical results. */
+typedef struct {
+  int32_t engine;          /* gft_engine the plan runs on                             */
+  int32_t fwd_tile;        /* signals per tile: generic engine 16 * m (tuned), butterfly */
+  int32_t inv_tile;        /* 16 (per wave), product 1 (per wave), large 0, batch 0    */
+  int32_t grid_fwd;        /* butterfly and product engines: most workgroups launched */
+  int32_t grid_inv;        /* (tuned; the tile loop strides over the rest); else 0    */
+  int32_t variant;         /* product: 1 staged factors, 0 dense; large: 1 forward    */
+                           /* output order written by the GEMM epilogue, 0 by a third */
+                           /* pass (tuned where both exist); else 0                   */
+  int32_t batch_rounds;    /* batch: rounds of resident workgroups (tuned)            */
+  int32_t batch_cost16;    /* batch: register-phase fixed cost per signal in          */
+                           /* sixteenths of the padded slot count (tuned)             */
+  int32_t large_tile_kb;   /* large: stage-pass tile size in KB (tuned)               */
+  int32_t source;          /* gft_tune_source                                         */
+  double tune_ms;          /* host milliseconds spent timing candidates (0 if none)   */
+} gft_tuning;
 
 typedef struct {
   int32_t n;
@@ -233,10 +268,15 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
  * lambda_p + mu_q for basis vector (p, q)): the separable form of the grid GFTs of
  * Sec. V-D, whose axis-wise stages leave leaf blocks that are Kronecker products of the
  * axes' leaves.  Each factor is planned as by gft_plan (its stages, if any, shape its
- * basis); the transform runs as y = U_a^T X U_b per signal X (n_a x n_b, row-major), the
- * factors applied as dense matrices on MFMA (options.precision: FP32, BF16 or split BF16
- * products with FP32 accumulation), then the coefficients in output order (ascending
- * lambda_p + mu_q, ties by p then q; GFT_ORDER_BLOCK: p * n_b + q).
+ * basis); the transform runs as y = U_a^T X U_b per signal X (n_a x n_b, row-major) on MFMA
+ * (options.precision: FP32, BF16 or split BF16 products with FP32 accumulation), then the
+ * coefficients in output order (ascending lambda_p + mu_q, ties by p then q;
+ * GFT_ORDER_BLOCK: p * n_b + q).  The factors run as dense matrices, or in their fast
+ * form where it is compiled: two 64-node factors whose stages are the halving reversals
+ * (stage t pairs i < R/2 with R - 1 - i, R = 64 >> t) with FP32 products run the stages as
+ * add/sub on the signal and the leaf blocks (32, 16, 8, 4, 2, 1, 1 nodes) as block-diagonal
+ * matrices, skipping their zero 16x16 tiles (3/8 of the dense MFMA work).  The environment
+ * variable GFT_PRODUCT_FORM=dense or staged forces either form where both exist.
  * Requires n_a, n_b <= 64, FP32 storage, the combinatorial Laplacian and options.engine 0
  * (else GFT_ERR_UNSUPPORTED; FP16 precision is unsupported too).  gft_plan_info reports the two factor GFTs
  * as num_blocks = 2 with their dense costs; gft_plan_blocks is unsupported.  Host-only. */
@@ -303,6 +343,18 @@ gft_status gft_plan_engine(gft_plan_t plan, int32_t *engine_out);
  * 16 for the butterfly engine (per wave); 0 for the large-signal engine; 1 for product
  * plans (one signal per wave).  Needs a GPU. */
 gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile);
+
+/* Launch choices of the plan on the current device (builds the image like
+ * gft_plan_prepare).  With options.autotune = GFT_AUTOTUNE_ON preparation times the
+ * candidates of the plan's engine on a synthetic batch (generic: every tile height that
+ * fits in LDS; butterfly and product: grids of 1/2, 3/4, 1 and 2 times the resident
+ * workgroups; batch: 1 to 4 rounds of resident workgroups x register-phase cost 8, 11 or
+ * 14 sixteenths; large: fused or three-pass output order x stage-pass tiles of 20, 40 or
+ * 80 KB) and keeps the fastest (3% better than the built-in choice at least), unless the
+ * tuning cache holds a choice for the same device kind and plan image.  The cache lives in
+ * memory and in the text file named by the environment variable GFT_TUNE_CACHE (default
+ * $HOME/.cache/libgft/tuning-v1.txt; empty or "off": memory only).  Needs a GPU. */
+gft_status gft_plan_tuning(gft_plan_t plan, gft_tuning *out);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */
 gft_status gft_plan_info(gft_plan_t plan, int32_t index, gft_plan_stats *out);

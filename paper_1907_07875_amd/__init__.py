@@ -37,7 +37,7 @@ EXPORTS = [
     "gft_find_pairing", "gft_plan_product",
     "gft_plan_size", "gft_plan_eigenvalues", "gft_plan_basis", "gft_plan_apply_host",
     "gft_plan_blocks", "gft_plan_destroy", "gft_last_error", "gft_version", "gft_stream_copy",
-    "gft_apply_noalloc",
+    "gft_apply_noalloc", "gft_plan_tuning",
 ]
 
 
@@ -64,7 +64,20 @@ class _Options(ctypes.Structure):
                 ("tile_override", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("sym_tol", ctypes.c_double), ("in_dtype", ctypes.c_int32),
                 ("out_dtype", ctypes.c_int32), ("laplacian", ctypes.c_int32),
-                ("right_haar", ctypes.c_int32)]
+                ("right_haar", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("fwd_tile", ctypes.c_int32), ("inv_tile", ctypes.c_int32),
+                ("grid_fwd", ctypes.c_int32), ("grid_inv", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("batch_rounds", ctypes.c_int32), ("batch_cost16", ctypes.c_int32),
+                ("large_tile_kb", ctypes.c_int32), ("source", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["engine"] = {1: "generic", 2: "butterfly", 3: "large", 4: "product"}.get(d["engine"], d["engine"])
+        d["source"] = {0: "builtin", 1: "timed", 2: "cached"}.get(d["source"], d["source"])
+        return d
 
 
 class PlanStats(ctypes.Structure):
@@ -127,6 +140,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gft_version": ([], ctypes.c_char_p),
         "gft_stream_copy": ([P, P, i64, P], i32),
         "gft_apply_noalloc": ([P, i32, P, P, i64, P], i32),
+        "gft_plan_tuning": ([P, ctypes.POINTER(Tuning)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -171,12 +185,12 @@ def _pairing_struct(n, stages, keep):
 
 
 def _options(precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto",
-             in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial", right_haar=True):
+             in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial", right_haar=True, autotune=True):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
     lap = LAPLACIANS[laplacian] if isinstance(laplacian, str) else int(laplacian)
     return _Options(prec, int(order), int(tile), eng, float(sym_tol), DTYPES[in_dtype], DTYPES[out_dtype], lap,
-                    0 if right_haar else 1)
+                    0 if right_haar else 1, 0 if autotune else 1)
 
 
 def _stream_ptr(stream):
@@ -202,19 +216,19 @@ class Plan:
     @classmethod
     def from_graph(cls, graph, precision="fp32", order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0,
                    engine="auto", in_dtype="fp32", out_dtype="fp32", laplacian="combinatorial",
-                   right_haar=True):
+                   right_haar=True, autotune=True):
         """Plan one graph (an object with n, src, dst, weight, self_loop, stages)."""
         return gft_plan(graph.n, graph.src, graph.dst, graph.weight, graph.self_loop,
                         graph.stages, precision=precision, order=order, tile=tile, sym_tol=sym_tol,
                         engine=engine, in_dtype=in_dtype, out_dtype=out_dtype, laplacian=laplacian,
-                        right_haar=right_haar)
+                        right_haar=right_haar, autotune=autotune)
 
     @classmethod
     def from_product(cls, graph_a, graph_b, precision="fp32", order=ORDER_EIGENVALUE, sym_tol=0.0,
-                     right_haar=True):
+                     right_haar=True, autotune=True):
         """Plan the Cartesian product of two graphs (node (i, j) = i * graph_b.n + j)."""
         return gft_plan_product(graph_a, graph_b, order=order, sym_tol=sym_tol, right_haar=right_haar,
-                                precision=precision)
+                                precision=precision, autotune=autotune)
 
     @property
     def n(self) -> int:
@@ -280,6 +294,12 @@ class Plan:
         _check(load_library().gft_plan_engine(self._h, ctypes.byref(e)))
         return {1: "generic", 2: "butterfly", 3: "large", 4: "product"}[e.value]
 
+    def tuning(self) -> dict:
+        """Launch choices on the current device and where they came from (C: gft_plan_tuning)."""
+        t = Tuning()
+        _check(load_library().gft_plan_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
     def tiles(self):
         """(forward, inverse) signals per tile on the current device (0 = large engine)."""
         f, i = ctypes.c_int32(), ctypes.c_int32()
@@ -296,21 +316,21 @@ class Plan:
 
 def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
              order=ORDER_EIGENVALUE, tile=0, sym_tol=0.0, engine="auto", in_dtype="fp32",
-             out_dtype="fp32", laplacian="combinatorial", right_haar=True) -> Plan:
+             out_dtype="fp32", laplacian="combinatorial", right_haar=True, autotune=True) -> Plan:
     """Plan the fast GFT of one graph (C: ``gft_plan``).  ``in_dtype`` / ``out_dtype``
     ("fp32" or "bf16") are the storage types of signals and coefficients."""
     lib = load_library()
     keep = []
     g = _graph_struct(n, src, dst, weight, self_loop, keep)
     p = _pairing_struct(n, stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar, autotune)
     h = ctypes.c_void_p()
     _check(lib.gft_plan(ctypes.byref(g), ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(n)], False, precision, in_dtype, out_dtype)
 
 
 def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, right_haar=True,
-                     precision="fp32", laplacian="combinatorial", engine="auto") -> Plan:
+                     precision="fp32", laplacian="combinatorial", engine="auto", autotune=True) -> Plan:
     """Plan the GFT of the Cartesian product of two graphs (C: ``gft_plan_product``): each
     argument is an object with n, src, dst, weight, self_loop, stages."""
     lib = load_library()
@@ -320,7 +340,7 @@ def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, righ
     gb = _graph_struct(graph_b.n, graph_b.src, graph_b.dst, graph_b.weight, graph_b.self_loop, keep)
     pb = _pairing_struct(graph_b.n, graph_b.stages, keep)
     o = _options(precision=precision, order=order, sym_tol=sym_tol, engine=engine,
-                 laplacian=laplacian, right_haar=right_haar)
+                 laplacian=laplacian, right_haar=right_haar, autotune=autotune)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_product(ctypes.byref(ga), ctypes.byref(pa), ctypes.byref(gb), ctypes.byref(pb),
                                 ctypes.byref(o), ctypes.byref(h)))
@@ -344,7 +364,7 @@ def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_ste
 
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
                    sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32",
-                   laplacian="combinatorial", right_haar=True) -> Plan:
+                   laplacian="combinatorial", right_haar=True, autotune=True) -> Plan:
     """Plan several graphs for one persistent launch (C: ``gft_plan_batch``; FP32 storage)."""
     lib = load_library()
     keep = []
@@ -353,7 +373,7 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     for i, gr in enumerate(graphs):
         G[i] = _graph_struct(gr.n, gr.src, gr.dst, gr.weight, gr.self_loop, keep)
         Pr[i] = _pairing_struct(gr.n, gr.stages, keep)
-    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar)
+    o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar, autotune)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
     return Plan(h.value, [int(g.n) for g in graphs], True, precision)

@@ -12,7 +12,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libgft.so")
 
 SOURCES = ["gft_kernels.hip", "gft_butterfly.hip", "gft_large.hip", "gft_product.hip", "gft_copy.hip", "capi.cpp",
-           "plan.cpp", "program.cpp", "eigen.cpp"]
+           "plan.cpp", "program.cpp", "eigen.cpp", "tune.cpp"]
 
 # Packed FP32 instructions stay disabled: hipcc emits them from plain float code and some
 # of their forms have given silently wrong results on this hardware.

@@ -2,7 +2,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <functional>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -15,6 +19,7 @@
 #include "launch.hpp"
 #include "plan.hpp"
 #include "program.hpp"
+#include "tune.hpp"
 
 using namespace gft;
 
@@ -48,15 +53,26 @@ struct DeviceImage {
   bool large = false;
   LargeImage lg[2];
   // product-graph plans: the two factor matrices and the output permutation per direction
-  bool product = false;
+  // (staged: the factors' stages and block-diagonal leaf matrices)
+  bool product = false, product_staged = false;
   PProgram pfwd{}, pinv{};
   // batch plans: device arrays of the G forward and G inverse programs, and of their
   // register-butterfly programs (S = 0 where a graph runs its LDS program; null if none)
   const DevProgram *dev_fwd = nullptr, *dev_inv = nullptr;
   const UProgram *dev_ufwd = nullptr, *dev_uinv = nullptr;
   size_t batch_lds = 0;
-  int batch_grid = 1;
+  int batch_occ = 1;       // resident batch workgroups per CU
   int reg_groups = 0;
+  // Launch choices (gft_plan_tuning): built-in values, replaced at preparation by the
+  // fastest candidates on this device or by the tuning cache's choice for this image.
+  std::string key;                     // tuning-cache key: device kind, engine, image hash
+  int grid[2] = {0, 0};                // butterfly / product: most workgroups (0: resident)
+  int batch_rounds = 2;                // batch grid = rounds x resident workgroups
+  int batch_cost16 = 11;               // register-phase fixed cost, sixteenths of N
+  bool lfused[2] = {false, false};     // large: GEMM epilogue writes the output order
+  int ltile_kb[2] = {40, 40};          // large: stage-pass tile size
+  int tune_source = GFT_TUNE_BUILTIN;
+  double tune_ms = 0.0;
 };
 
 // Byte blob assembled on the host and uploaded in one copy; offsets are 256-aligned.
@@ -117,7 +133,6 @@ gft_options default_options(const gft_options *o) {
   return d;
 }
 
-constexpr int kBatchRounds = 2;   // batch grid = rounds x resident workgroups
 constexpr size_t kFuseMaxBlocks = 8;   // large engine: fused output permutation up to here
 
 gft_status check_options(const gft_options &o) {
@@ -129,6 +144,8 @@ gft_status check_options(const gft_options &o) {
     return set_error(GFT_ERR_INVALID_ARG, "options.engine must be 0, 1, 2, 3 or 4");
   if (o.right_haar != GFT_RIGHT_HAAR_AUTO && o.right_haar != GFT_RIGHT_HAAR_OFF)
     return set_error(GFT_ERR_INVALID_ARG, "options.right_haar must be a gft_right_haar value");
+  if (o.autotune != GFT_AUTOTUNE_ON && o.autotune != GFT_AUTOTUNE_OFF)
+    return set_error(GFT_ERR_INVALID_ARG, "options.autotune must be a gft_autotune value");
   if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL && o.laplacian != GFT_LAPLACIAN_NORMALIZED)
     return set_error(GFT_ERR_INVALID_ARG, "options.laplacian must be a gft_laplacian value");
   if ((o.in_dtype != GFT_DTYPE_FP32 && o.in_dtype != GFT_DTYPE_BF16) ||
@@ -140,78 +157,196 @@ gft_status check_options(const gft_options &o) {
   return GFT_OK;
 }
 
-// Tile autotuning of the generic engine, a plan-time step: every tile height 16*mt whose
-// LDS footprint fits `budget` is timed on a zero-filled synthetic batch (16M values) on this
-// device, on a stream of its own: after a warm-up, the candidates take turns over several
-// rounds and each keeps its best time (clock ramps and noise then hit all alike); another
-// height replaces the built-in choice only when it is at least 3% faster.  The transform's
-// arithmetic does not depend on mt (the same products in the same order), so the choice
-// changes speed only.  On any HIP error the built-in choice stays.
-void autotune_generic(DeviceImage *img, int dir, size_t budget, bool in16, bool out16) {
-  DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
-  int &cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
-  const int64_t n = P.n;
-  const int64_t S = std::max<int64_t>((int64_t)(16 << 20) / n, 16 * 8 * (int64_t)img->num_cus);
-  void *buf = nullptr;
-  hipStream_t st = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  if (hipMalloc(&buf, 2 * (size_t)S * n * 4) != hipSuccess) return;
-  bool okay = hipMemset(buf, 0, 2 * (size_t)S * n * 4) == hipSuccess &&
-              hipStreamCreate(&st) == hipSuccess && hipEventCreate(&ev[0]) == hipSuccess &&
-              hipEventCreate(&ev[1]) == hipSuccess;
-  const float *in = static_cast<const float *>(buf);
-  float *outp = static_cast<float *>(buf) + (size_t)S * n;
-  std::vector<DevProgram> cand;
-  std::vector<int> caps;
-  for (int mt : {8, 4, 2, 1}) {
-    DevProgram C = P;
-    C.mt = mt;
-    if (program_lds_bytes(C) > budget) continue;
-    cand.push_back(C);
-    caps.push_back(img->num_cus * apply_occupancy(C));
-  }
-  std::vector<float> best(cand.size(), 0.0f);
-  int base = -1;
-  for (size_t c = 0; c < cand.size(); ++c)
-    if (cand[c].mt == P.mt) base = (int)c;
-  for (int w = 0; w < 6 && okay && base >= 0; ++w)      // warm-up: clocks, code, caches
-    okay = launch_apply(cand[base], in, outp, S, st, caps[base], in16, out16) == hipSuccess;
-  for (int round = 0; round < 4 && okay; ++round)
-    for (size_t c = 0; c < cand.size() && okay; ++c) {
-      okay = hipEventRecord(ev[0], st) == hipSuccess;
-      for (int r = 0; r < 2 && okay; ++r)
-        okay = launch_apply(cand[c], in, outp, S, st, caps[c], in16, out16) == hipSuccess;
-      float ms = 0.0f;
-      okay = okay && hipEventRecord(ev[1], st) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
-             hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess;
-      if (okay && (best[c] == 0.0f || ms < best[c])) best[c] = ms;
+// ---------------------------------------------------------------------------- tuning
+
+// Zero-filled device memory for timing candidates; freed on scope exit.
+struct TuneMem {
+  void *p = nullptr;
+  explicit TuneMem(size_t bytes) {
+    if (hipMalloc(&p, bytes) != hipSuccess || hipMemset(p, 0, bytes) != hipSuccess) {
+      if (p) (void)hipFree(p);
+      p = nullptr;
     }
-  if (okay && base >= 0) {
-    int pick = base;
-    for (size_t c = 0; c < cand.size(); ++c)
-      if (best[c] < 0.97f * best[pick]) pick = (int)c;
-    P.mt = cand[pick].mt;
-    cap = caps[pick];
   }
-  (void)hipGetLastError();
-  for (hipEvent_t e : ev)
-    if (e) (void)hipEventDestroy(e);
-  if (st) (void)hipStreamDestroy(st);
-  (void)hipFree(buf);
+  ~TuneMem() {
+    if (p) (void)hipFree(p);
+  }
+  TuneMem(const TuneMem &) = delete;
+  TuneMem &operator=(const TuneMem &) = delete;
+};
+
+// A timing stream; destroyed on scope exit.
+struct TuneStream {
+  hipStream_t st = nullptr;
+  TuneStream() {
+    if (hipStreamCreate(&st) != hipSuccess) st = nullptr;
+  }
+  ~TuneStream() {
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+// Signals of a timing batch of about 16 M values (at least `floor` signals).
+int64_t tune_signals(int64_t n, int64_t floor) { return std::max<int64_t>((int64_t)(16 << 20) / n, floor); }
+
+// Key of an image in the tuning cache: device kind, engine, storage and precision, and a
+// hash of the uploaded image (programs, matrices and tables) with the plan's sizes.
+std::string tune_key(int dev, char engine, const gft_options &o, const std::vector<char> &blob,
+                     const std::vector<int32_t> &sizes) {
+  uint64_t h = fnv1a(blob.data(), blob.size());
+  h = fnv1a(sizes.data(), sizes.size() * sizeof(int32_t), h);
+  char hex[17];
+  std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
+  return device_tag(dev) + "|" + engine + "|p" + std::to_string(o.precision) + "i" + std::to_string(o.in_dtype) +
+         "o" + std::to_string(o.out_dtype) + "t" + std::to_string(o.tile_override) + "|" + hex;
 }
 
-// The two factors of a separable plan: FP64 bases (node i of basis vector k at [i * n + k],
-// factor output order) and the factor coefficient pair order[k] = p * nb + q of every
-// output coefficient k.
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Generic engine: tile height 16 m, every m whose LDS footprint fits `budget` (the products
+// run in the same order for any m).
+bool tune_generic(DeviceImage *img, size_t budget, bool io16[2][2], std::vector<int32_t> &choice) {
+  TuneStream ts;
+  if (!ts.st) return false;
+  for (int dir = 0; dir < 2; ++dir) {
+    DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
+    int &cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
+    const int64_t S = tune_signals(P.n, 16 * 8 * (int64_t)img->num_cus);
+    TuneMem mem(2 * (size_t)S * P.n * 4);
+    if (!mem.p) return false;
+    const float *in = static_cast<const float *>(mem.p);
+    float *outp = static_cast<float *>(mem.p) + (size_t)S * P.n;
+    std::vector<DevProgram> cand;
+    std::vector<int> caps;
+    int base = -1;
+    for (int mt : {8, 4, 2, 1}) {
+      DevProgram C = P;
+      C.mt = mt;
+      if (program_lds_bytes(C) > budget) continue;
+      if (mt == P.mt) base = (int)cand.size();
+      cand.push_back(C);
+      caps.push_back(img->num_cus * apply_occupancy(C));
+    }
+    if (base < 0) return false;
+    const int pick = time_candidates((int)cand.size(), base, [&](int c, hipStream_t st) {
+      return launch_apply(cand[c], in, outp, S, st, caps[c], io16[dir][0], io16[dir][1]);
+    }, ts.st);
+    if (pick < 0) return false;
+    P.mt = cand[pick].mt;
+    cap = caps[pick];
+    choice.push_back(P.mt);
+  }
+  return true;
+}
+
+void apply_generic(DeviceImage *img, const std::vector<int32_t> &choice) {
+  for (int dir = 0; dir < 2; ++dir) {
+    DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
+    P.mt = choice[dir];
+    (dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0]) = img->num_cus * apply_occupancy(P);
+  }
+}
+
+// Butterfly and product engines: the persistent grid, 1/2, 3/4, 1 or 2 times the resident
+// workgroups (each tile is computed the same way by whichever wave takes it).
+bool tune_grid(DeviceImage *img, int n, const std::function<int(int)> &occupancy,
+               const std::function<hipError_t(int, const void *, void *, int64_t, hipStream_t, int)> &launch,
+               std::vector<int32_t> &choice) {
+  TuneStream ts;
+  if (!ts.st) return false;
+  const int64_t S = tune_signals(n, 4096);
+  TuneMem mem(2 * (size_t)S * n * 4);
+  if (!mem.p) return false;
+  const float *in = static_cast<const float *>(mem.p);
+  float *outp = static_cast<float *>(mem.p) + (size_t)S * n;
+  for (int dir = 0; dir < 2; ++dir) {
+    const int res = occupancy(dir) * img->num_cus;
+    const int cand[4] = {std::max(1, res / 2), std::max(1, (3 * res) / 4), res, 2 * res};
+    const int pick = time_candidates(4, 2, [&](int c, hipStream_t st) {
+      return launch(dir, in, outp, S, st, cand[c]);
+    }, ts.st);
+    if (pick < 0) return false;
+    img->grid[dir] = pick == 2 ? 0 : cand[pick];
+    choice.push_back(img->grid[dir]);
+  }
+  return true;
+}
+
+// Large engine: output order by the GEMM epilogue or by a third pass (where the last pass
+// has no Haar stage), x stage-pass tiles of 20, 40 or 80 KB.
+bool tune_large(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice);
+
+void run_tuning(gft_plan_s *plan, DeviceImage *img, size_t budget);
+
+// Batch kernel: 1 to 4 rounds of resident workgroups x register-phase cost 8, 11 or 14
+// sixteenths of the slot count, on a synthetic batch of the plan's graphs (log-uniform
+// 256 .. 65536 signals each, scaled to at most 32 M values).
+bool tune_batch(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice);
+
+// The two factors of a separable plan: their plans, FP64 bases (node i of basis vector k
+// at [i * n + k], factor output order) and the factor coefficient pair order[k] = p * nb + q
+// of every output coefficient k.
 struct Factors {
   int na = 0, nb = 0;
+  const GraphPlan *fa = nullptr, *fb = nullptr;
   const std::vector<double> *ua = nullptr, *ub = nullptr;
   const std::vector<int32_t> *order = nullptr;
 };
 
+// A factor in its fast form, after its Haar stages: its leaf blocks as one block-diagonal
+// matrix Q[pos][c] (pos: node position after the stages, c: coefficient in block order,
+// each block scaled by 2^(-depth/2)); bo[p]: block-order index of factor output position p.
+struct StagedFactor {
+  std::vector<double> Q;
+  std::vector<int32_t> bo;
+};
+
+StagedFactor staged_factor(const GraphPlan &F) {
+  StagedFactor sf;
+  const int m = F.n;
+  sf.Q.assign((size_t)m * m, 0.0);
+  sf.bo.assign(m, -1);
+  int c0 = 0;
+  for (const HostBlock &B : F.blocks) {
+    for (int j = 0; j < B.size; ++j)
+      for (int k = 0; k < B.size; ++k)
+        sf.Q[(size_t)B.nodes[j] * m + c0 + k] = B.scale * B.V[(size_t)j * B.size + k];
+    for (int k = 0; k < B.size; ++k) sf.bo[B.out_pos[k]] = c0 + k;
+    c0 += B.size;
+  }
+  return sf;
+}
+
+// Are a 64-node factor's stages the halving reversals the product kernel compiles (stage t
+// pairs node i < R/2 with R - 1 - i, R = 64 >> t, six stages, no fixed node), and do its
+// leaf matrix's non-zero entries lie in that kernel's tiles ((0,0), (1,1), and the 2 x 2
+// group {2, 3} of 16 x 16 tiles)?
+bool halving_factor(const GraphPlan &F, const std::vector<double> &Q) {
+  if (F.n != 64 || F.stages.size() != 6) return false;
+  for (int t = 0; t < 6; ++t) {
+    const HostStage &st = F.stages[t];
+    const int R = 64 >> t;
+    if (!st.znodes.empty() || (int)st.pair_x.size() != R / 2) return false;
+    for (int u = 0; u < R / 2; ++u)
+      if (st.pair_x[u] != u || st.pair_y[u] != R - 1 - u) return false;
+  }
+  for (int r = 0; r < 64; ++r)
+    for (int c = 0; c < 64; ++c) {
+      const int tr = r / 16, tc = c / 16;
+      if (Q[(size_t)r * 64 + c] != 0.0 && tr != tc && !(tr >= 2 && tc >= 2)) return false;
+    }
+  return true;
+}
+
 // Device image of a separable plan on device `dev` (caller holds plan->mu): per direction
-// the zero-padded factor matrices (forward B = U_b, A = U_a^T; inverse B = U_b^T, A = U_a)
-// and the LDS word of every output-order coefficient.
+// the zero-padded factor matrices (dense form: forward B = U_b, A = U_a^T; inverse B = U_b^T,
+// A = U_a; staged form: the same with the block-diagonal leaf matrices Q in place of U, and
+// the stages compiled into the kernel) and the LDS word of every output-order coefficient.
+// The staged form runs where the kernel has it compiled (two 64-node factors with the
+// halving stages: 3/8 of the dense MFMA work) with FP32 products; GFT_PRODUCT_FORM=dense or
+// staged in the environment forces either form where both exist (tests, measurements).
 gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImage **out) {
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -220,25 +355,50 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
   const std::vector<double> &ua = *F.ua, &ub = *F.ub;
   const std::vector<int32_t> &order = *F.order;
   const int NA = product_pad(na), NB = product_pad(nb), stride = NB + 1;
-  Blob blob;
-  size_t off[2][3];
-  for (int d = 0; d < 2; ++d) {
-    std::vector<float> A((size_t)NA * NA, 0.0f), B((size_t)NB * NB, 0.0f);
+  const StagedFactor sa = staged_factor(*F.fa), sb = staged_factor(*F.fb);
+
+  // the two forms' matrices (direction d, dense/staged)
+  auto build = [&](int d, bool staged, std::vector<float> &A, std::vector<float> &B) {
+    A.assign((size_t)NA * NA, 0.0f);
+    B.assign((size_t)NB * NB, 0.0f);
+    const std::vector<double> &xa = staged ? sa.Q : ua, &xb = staged ? sb.Q : ub;
     for (int i = 0; i < na; ++i)
       for (int k = 0; k < na; ++k) {
-        const float u = (float)ua[(size_t)i * na + k];   // node i of vector k
+        const float u = (float)xa[(size_t)i * na + k];   // row: node (position), column: vector
         if (d == 0) A[(size_t)k * NA + i] = u;
         else A[(size_t)i * NA + k] = u;
       }
     for (int j = 0; j < nb; ++j)
       for (int q = 0; q < nb; ++q) {
-        const float u = (float)ub[(size_t)j * nb + q];
+        const float u = (float)xb[(size_t)j * nb + q];
         if (d == 0) B[(size_t)j * NB + q] = u;
         else B[(size_t)q * NB + j] = u;
       }
+  };
+  // FP32 products are MFMA-bound in the dense form (0.70 ms on the 64 x 64 grid against
+  // 0.49 ms staged); BF16 and split BF16 are bound by memory and conversions and gain
+  // nothing from the staged form (measured 0.43 vs 0.45 ms, 0.54 vs 0.56 ms)
+  const bool compiled = halving_factor(*F.fa, sa.Q) && halving_factor(*F.fb, sb.Q);
+  bool staged = compiled && plan->opts.precision == GFT_FP32;
+  if (const char *f = std::getenv("GFT_PRODUCT_FORM")) {
+    if (!std::strcmp(f, "dense")) staged = false;
+    else if (!std::strcmp(f, "staged")) staged = compiled;
+  }
+
+  Blob blob;
+  size_t off[2][3];
+  bool same[2];
+  for (int d = 0; d < 2; ++d) {
+    std::vector<float> A, B;
+    build(d, staged, A, B);
+    same[d] = na == nb && (staged ? sa.Q == sb.Q : ua == ub);
     std::vector<uint16_t> perm(n);
     for (int k = 0; k < n; ++k) {
-      const int p = order[k] / nb, q = order[k] % nb;
+      int p = order[k] / nb, q = order[k] % nb;
+      if (staged) {
+        p = sa.bo[p];
+        q = sb.bo[q];
+      }
       perm[k] = (uint16_t)(p * stride + q);
     }
     off[d][0] = blob.add(A.data(), A.size() * 4);
@@ -248,6 +408,7 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
   auto img = std::make_unique<DeviceImage>();
   img->device = dev;
   img->num_cus = std::max(1, cus);
+  img->product_staged = staged;
   e = hipMalloc(&img->mem, blob.bytes.size());
   if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMalloc of the plan image failed");
   e = hipMemcpy(img->mem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice);
@@ -263,16 +424,241 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
     P.nb = nb;
     P.dir = d;
     P.stride = stride;
-    P.same = na == nb && ua == ub;
+    P.same = same[d];
     P.prec = plan->opts.precision;
     P.amat = reinterpret_cast<const float *>(base + off[d][0]);
     P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
     P.perm = reinterpret_cast<const uint16_t *>(base + off[d][2]);
+    P.tile_pattern = staged ? 1 : 0;
   }
   img->product = true;
+  img->key = tune_key(dev, 'P', plan->opts, blob.bytes, {na, nb, staged ? 1 : 0});
+  run_tuning(plan, img.get(), 0);
   *out = img.get();
   plan->images[dev] = std::move(img);
   return GFT_OK;
+}
+
+// Built-in output order of a large-engine apply: with no Haar stage in pass 3 and few leaf
+// blocks the GEMM writes the final positions itself (no W2, no pass 3).  With many blocks
+// whose outputs interleave in the output order, each output line collects partial writes
+// from many workgroups and the m-panel tile order spoils the reuse of the block matrices in
+// L2: measured slower on the 64x64 grid (49 blocks), faster on the 1024-node path (2
+// blocks).  The tuner may choose either where the last pass has no stage.
+bool large_fusable(const LargeImage &L) { return L.pass[1].num_stages == 0; }
+bool large_fused(const LargeImage &L) { return large_fusable(L) && L.blocks.size() <= kFuseMaxBlocks; }
+
+// Workspace of a large-engine apply over S signals: W1 (and W2 unless the GEMM epilogue
+// writes the output order) of S rows of ldw FP32 words.
+size_t large_ws_bytes(const LargeImage &L, bool fused, int64_t S) {
+  return (fused ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
+}
+
+// The large engine's launches for one apply: stage/gather pass, grouped GEMM, and the
+// gather pass unless `fused`; ws holds large_ws_bytes.
+hipError_t launch_large(const gft_plan_s *plan, const DeviceImage *img, int dir, const void *in, void *out,
+                        int64_t S, hipStream_t st, void *ws, bool fused, int tile_kb) {
+  const LargeImage &L = img->lg[dir];
+  float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
+  const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
+  hipError_t e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st,
+                                       tile_kb);
+  if (e == hipSuccess)
+    e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
+                          (int)L.blocks.size(), ws16 ? (const void *)L.dev_mats16 : (const void *)L.dev_mats,
+                          W1, fused ? static_cast<float *>(out) : W2, S, L.ldw,
+                          block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S),
+                          fused ? L.dev_omap : nullptr, L.n, st);
+  if (e == hipSuccess && !fused) e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st, tile_kb);
+  return e;
+}
+
+bool tune_large(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice) {
+  TuneStream ts;
+  if (!ts.st) return false;
+  const int n = plan->graphs[0].n;
+  const int64_t S = tune_signals(n, 1024);
+  const size_t ws = large_ws_bytes(img->lg[0], false, S) > large_ws_bytes(img->lg[1], false, S)
+                        ? large_ws_bytes(img->lg[0], false, S) : large_ws_bytes(img->lg[1], false, S);
+  TuneMem mem(2 * (size_t)S * n * 4 + ws);
+  if (!mem.p) return false;
+  const float *in = static_cast<const float *>(mem.p);
+  float *outp = static_cast<float *>(mem.p) + (size_t)S * n;
+  void *wsp = static_cast<char *>(mem.p) + 2 * (size_t)S * n * 4;
+  for (int dir = 0; dir < 2; ++dir) {
+    struct Cand {
+      bool fused;
+      int kb;
+    };
+    std::vector<Cand> cand;
+    int base = 0;
+    for (int f = 0; f < (large_fusable(img->lg[dir]) ? 2 : 1); ++f)
+      for (int kb : {20, 40, 80}) {
+        if ((f == 1) == img->lfused[dir] && kb == img->ltile_kb[dir]) base = (int)cand.size();
+        cand.push_back({f == 1, kb});
+      }
+    const int pick = time_candidates((int)cand.size(), base, [&](int c, hipStream_t st) {
+      return launch_large(plan, img, dir, in, outp, S, st, wsp, cand[c].fused, cand[c].kb);
+    }, ts.st);
+    if (pick < 0) return false;
+    img->lfused[dir] = cand[pick].fused;
+    img->ltile_kb[dir] = cand[pick].kb;
+    choice.push_back(cand[pick].fused ? 1 : 0);
+    choice.push_back(cand[pick].kb);
+  }
+  return true;
+}
+
+bool tune_batch(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice) {
+  TuneStream ts;
+  if (!ts.st) return false;
+  const int G = (int)plan->graphs.size();
+  // log-uniform counts from a fixed linear congruential sequence
+  std::vector<int64_t> cnt(G);
+  uint64_t x = 0x9e3779b97f4a7c15ull;
+  int64_t total = 0;
+  for (int g = 0; g < G; ++g) {
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    const double u = (double)(x >> 11) / 9007199254740992.0;
+    cnt[g] = (int64_t)std::exp(std::log(256.0) + u * (std::log(65536.0) - std::log(256.0)));
+    total += cnt[g] * plan->graphs[g].n;
+  }
+  const int64_t cap = (int64_t)32 << 20;
+  if (total > cap)
+    for (int g = 0; g < G; ++g) cnt[g] = std::max<int64_t>(16, (int64_t)((double)cnt[g] * cap / total));
+  std::vector<int64_t> off(G + 1, 0);
+  int64_t E = 0;
+  for (int g = 0; g < G; ++g) {
+    off[g + 1] = off[g] + cnt[g];
+    E += cnt[g] * plan->graphs[g].n;
+  }
+  TuneMem mem(2 * (size_t)E * 4 + off.size() * 8);
+  if (!mem.p) return false;
+  const float *in = static_cast<const float *>(mem.p);
+  float *outp = static_cast<float *>(mem.p) + E;
+  int64_t *doff = reinterpret_cast<int64_t *>(static_cast<char *>(mem.p) + 2 * (size_t)E * 4);
+  if (hipMemcpy(doff, off.data(), off.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return false;
+  struct Cand {
+    int rounds, cost16;
+  };
+  std::vector<Cand> cand;
+  int base = 0;
+  for (int r = 1; r <= 4; ++r)
+    for (int c : {8, 11, 14}) {
+      if (r == img->batch_rounds && c == img->batch_cost16) base = (int)cand.size();
+      cand.push_back({r, c});
+    }
+  const int pick = time_candidates((int)cand.size(), base, [&](int c, hipStream_t st) {
+    return launch_apply_batch(plan->opts.precision, 0, img->dev_fwd, img->dev_ufwd, G, doff, E, in, outp,
+                              img->batch_lds, cand[c].rounds * img->num_cus * img->batch_occ, img->reg_groups,
+                              cand[c].cost16, st);
+  }, ts.st);
+  if (pick < 0) return false;
+  img->batch_rounds = cand[pick].rounds;
+  img->batch_cost16 = cand[pick].cost16;
+  choice = {img->batch_rounds, img->batch_cost16};
+  return true;
+}
+
+// Tune the image's launch choices (options.autotune on), or take them from the cache.  On
+// any failure the built-in choices stay.
+void run_tuning(gft_plan_s *plan, DeviceImage *img, size_t budget) {
+  const gft_options &o = plan->opts;
+  if (o.autotune == GFT_AUTOTUNE_OFF) return;
+  enum { GENERIC, BUTTERFLY, PRODUCT, LARGE, BATCH } kind =
+      plan->batch ? BATCH : img->product ? PRODUCT : img->butterfly ? BUTTERFLY : img->large ? LARGE : GENERIC;
+  if (kind == GENERIC && o.tile_override != 0) return;   // the caller fixed the tile
+  if (kind == BATCH && !img->dev_ufwd) {
+    // no register phase: only the rounds matter, still tuned below
+  }
+  bool io16[2][2];
+  for (int d = 0; d < 2; ++d) {
+    io16[d][0] = (d == 0 ? o.in_dtype : o.out_dtype) == GFT_DTYPE_BF16;
+    io16[d][1] = (d == 0 ? o.out_dtype : o.in_dtype) == GFT_DTYPE_BF16;
+  }
+  // a cached choice, validated before use
+  std::vector<int32_t> v;
+  if (tune_cache_get(img->key, v)) {
+    bool valid = false;
+    switch (kind) {
+      case GENERIC:
+        valid = v.size() == 2;
+        for (int d = 0; d < 2 && valid; ++d) {
+          DevProgram C = d == 0 ? img->fwd[0] : img->inv[0];
+          C.mt = v[d];
+          valid = (v[d] == 1 || v[d] == 2 || v[d] == 4 || v[d] == 8) && program_lds_bytes(C) <= budget;
+        }
+        if (valid) apply_generic(img, v);
+        break;
+      case BUTTERFLY:
+      case PRODUCT:
+        valid = v.size() == 2 && v[0] >= 0 && v[1] >= 0;
+        if (valid) img->grid[0] = v[0], img->grid[1] = v[1];
+        break;
+      case LARGE:
+        valid = v.size() == 4;
+        for (int d = 0; d < 2 && valid; ++d)
+          valid = (v[2 * d] == 0 || (v[2 * d] == 1 && large_fusable(img->lg[d]))) &&
+                  (v[2 * d + 1] == 20 || v[2 * d + 1] == 40 || v[2 * d + 1] == 80);
+        if (valid)
+          for (int d = 0; d < 2; ++d) img->lfused[d] = v[2 * d] == 1, img->ltile_kb[d] = v[2 * d + 1];
+        break;
+      case BATCH:
+        valid = v.size() == 2 && v[0] >= 1 && v[0] <= 4 && v[1] >= 1 && v[1] <= 64;
+        if (valid) img->batch_rounds = v[0], img->batch_cost16 = v[1];
+        break;
+    }
+    if (valid) {
+      img->tune_source = GFT_TUNE_CACHED;
+      return;
+    }
+  }
+  // time the candidates
+  const double t0 = now_ms();
+  std::vector<int32_t> choice;
+  bool done = false;
+  const std::vector<int> mts = kind == GENERIC ? std::vector<int>{img->fwd[0].mt, img->inv[0].mt} : std::vector<int>{};
+  switch (kind) {
+    case GENERIC:
+      done = tune_generic(img, budget, io16, choice);
+      if (!done) apply_generic(img, {mts[0], mts[1]});
+      break;
+    case BUTTERFLY:
+      done = tune_grid(img, plan->graphs[0].n,
+                       [&](int d) { return butterfly_occupancy(d == 0 ? img->bfwd : img->binv, io16[d][0], io16[d][1]); },
+                       [&](int d, const void *in, void *out, int64_t S, hipStream_t st, int cap) {
+                         return launch_butterfly(d == 0 ? img->bfwd : img->binv, in, out, S, st, img->num_cus,
+                                                 io16[d][0], io16[d][1], cap);
+                       },
+                       choice);
+      if (!done) img->grid[0] = img->grid[1] = 0;
+      break;
+    case PRODUCT:
+      done = tune_grid(img, plan->graphs[0].n,
+                       [&](int d) { return product_occupancy(d == 0 ? img->pfwd : img->pinv); },
+                       [&](int d, const void *in, void *out, int64_t S, hipStream_t st, int cap) {
+                         return launch_product(d == 0 ? img->pfwd : img->pinv, static_cast<const float *>(in),
+                                               static_cast<float *>(out), S, st, img->num_cus, cap);
+                       },
+                       choice);
+      if (!done) img->grid[0] = img->grid[1] = 0;
+      break;
+    case LARGE: {
+      const bool f0 = img->lfused[0], f1 = img->lfused[1];
+      done = tune_large(plan, img, choice);
+      if (!done) img->lfused[0] = f0, img->lfused[1] = f1, img->ltile_kb[0] = img->ltile_kb[1] = 40;
+      break;
+    }
+    case BATCH:
+      done = tune_batch(plan, img, choice);
+      if (!done) img->batch_rounds = 2, img->batch_cost16 = 11;
+      break;
+  }
+  (void)hipGetLastError();
+  if (!done) return;
+  tune_cache_put(img->key, choice);
+  img->tune_source = GFT_TUNE_TIMED;
+  img->tune_ms = now_ms() - t0;
 }
 
 // Get (building on first use) the image of `plan` on the current device.
@@ -287,7 +673,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     return GFT_OK;
   }
   if (plan->product) {
-    const Factors F{plan->fa.n, plan->fb.n, &plan->ua, &plan->ub, &plan->order};
+    const Factors F{plan->fa.n, plan->fb.n, &plan->fa, &plan->fb, &plan->ua, &plan->ub, &plan->order};
     return product_image(plan, F, dev, out);
   }
   int max_lds = 0, cus = 0;
@@ -369,7 +755,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                        "the separable engine runs single-graph plans whose leaf blocks have Kronecker "
                        "bases (a row-major Cartesian product with stages along the axes, factors of at "
                        "most 64 nodes), FP32 storage and FP32, BF16 or split BF16 blocks");
-    const Factors F{K->na, K->nb, &plan->kua, &plan->kub, &K->order};
+    const Factors F{K->na, K->nb, K->fa.get(), K->fb.get(), &plan->kua, &plan->kub, &K->order};
     return product_image(plan, F, dev, out);
   }
 
@@ -493,6 +879,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       L.mats.shrink_to_fit();
       L.mats16.clear();
       L.mats16.shrink_to_fit();
+      img->lfused[d] = large_fused(L);
     }
   }
   if (plan->batch) {
@@ -544,21 +931,22 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       img->dev_uinv = img->dev_ufwd + G;
     }
     img->batch_lds = batch_lds_bytes(G, maxlds, any_reg);
-    const int occ = batch_occupancy(plan->opts.precision, img->batch_lds);
-    // two rounds of resident workgroups: the hardware hands the second round's byte-equal
-    // shares of the LDS-program graphs to CUs as they free up, which evens out graphs of
-    // different cost per byte, while each share stays long enough to amortise loading its
-    // program (measured on the mixed batch: four rounds 193 us, three 195 us, two 187 us);
-    // the register phase runs on the first round
-    img->batch_grid = kBatchRounds * img->num_cus * occ;
-    img->reg_groups = any_reg ? img->num_cus * occ : 0;
+    img->batch_occ = batch_occupancy(plan->opts.precision, img->batch_lds);
+    // built-in: two rounds of resident workgroups (the hardware hands the second round's
+    // byte-equal shares of the LDS-program graphs to CUs as they free up, which evens out
+    // graphs of different cost per byte, while each share stays long enough to amortise
+    // loading its program; measured on the mixed batch: four rounds 193 us, three 195 us,
+    // two 187 us); the register phase runs on the first round
+    img->batch_rounds = 2;
+    img->reg_groups = any_reg ? img->num_cus * img->batch_occ : 0;
   }
-  if (!plan->batch && !img->butterfly && !img->large && plan->opts.tile_override == 0)
-    for (int d = 0; d < 2; ++d) {
-      const bool i16 = (d == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
-      const bool o16 = (d == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
-      autotune_generic(img.get(), d, budget, i16, o16);
-    }
+  {
+    std::vector<int32_t> sizes;
+    for (const GraphPlan &g : plan->graphs) sizes.push_back(g.n);
+    const char kind = plan->batch ? 'B' : (img->butterfly ? 'F' : (img->large ? 'L' : 'G'));
+    img->key = tune_key(dev, kind, plan->opts, blob.bytes, sizes);
+  }
+  run_tuning(plan, img.get(), budget);
   *out = img.get();
   plan->images[dev] = std::move(img);
   return GFT_OK;
@@ -577,21 +965,6 @@ gft_status check_buffers(const void *a, int64_t abytes, const void *b, int64_t b
   return GFT_OK;
 }
 
-// Workspace of a large-engine apply over S signals: W1 (and W2 unless the GEMM epilogue
-// writes the output order itself) of S rows of ldw FP32 words.
-bool large_fused(const LargeImage &L) {
-  // With no Haar stage in pass 3 and few leaf blocks the GEMM writes the final positions
-  // itself (no W2, no pass 3).  With many blocks whose outputs interleave in the output
-  // order, each output line collects partial writes from many workgroups and the m-panel
-  // tile order spoils the reuse of the block matrices in L2: measured slower on the 64x64
-  // grid (49 blocks), faster on the 1024-node path (2 blocks).
-  return L.pass[1].num_stages == 0 && L.blocks.size() <= kFuseMaxBlocks;
-}
-
-size_t large_ws_bytes(const LargeImage &L, int64_t S) {
-  return (large_fused(L) ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
-}
-
 gft_status check_apply_args(gft_plan_t plan, const void *in, void *out, int64_t S, int dir) {
   if (!plan) return set_error(GFT_ERR_INVALID_ARG, "plan is NULL");
   if (plan->batch) return set_error(GFT_ERR_INVALID_ARG, "batch plans use gft_forward_batch / gft_inverse_batch");
@@ -605,48 +978,37 @@ gft_status check_apply_args(gft_plan_t plan, const void *in, void *out, int64_t 
   return check_buffers(in, S * n * (in16 ? 2 : 4), out, S * n * (out16 ? 2 : 4), in16 == out16);
 }
 
-// Launch the plan's kernels on S > 0 signals.  ws: the large engine's workspace (at least
-// large_ws_bytes), or null to take it from the stream-ordered pool for this call.
+// Launch the plan's kernels on S > 0 signals with the image's launch choices.  ws: the
+// large engine's workspace (at least large_ws_bytes), or null to take it from the
+// stream-ordered pool for this call.
 gft_status launch_image(gft_plan_t plan, DeviceImage *img, int dir, const void *in, void *out,
                         int64_t S, void *stream, void *ws) {
-  const int64_t n = plan->graphs[0].n;
   const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
   const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (img->product) {
     e = launch_product(dir == 0 ? img->pfwd : img->pinv, static_cast<const float *>(in),
-                       static_cast<float *>(out), S, static_cast<hipStream_t>(stream), img->num_cus);
+                       static_cast<float *>(out), S, st, img->num_cus, img->grid[dir]);
   } else if (img->large) {
-    const LargeImage &L = img->lg[dir];
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool fused = large_fused(L);
+    const bool fused = img->lfused[dir];
     const bool pooled = ws == nullptr;
     if (pooled) {
-      e = hipMallocAsync(&ws, large_ws_bytes(L, S), st);
+      e = hipMallocAsync(&ws, large_ws_bytes(img->lg[dir], fused, S), st);
       if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
     }
-    float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
-    const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
-    e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st);
-    if (e == hipSuccess)
-      e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
-                            (int)L.blocks.size(), ws16 ? (const void *)L.dev_mats16 : (const void *)L.dev_mats,
-                            W1, fused ? static_cast<float *>(out) : W2, S, L.ldw,
-                            block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S),
-                            fused ? L.dev_omap : nullptr, (int)n, st);
-    if (e == hipSuccess && !fused)
-      e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st);
+    e = launch_large(plan, img, dir, in, out, S, st, ws, fused, img->ltile_kb[dir]);
     if (pooled) {
       const hipError_t ef = hipFreeAsync(ws, st);
       if (e == hipSuccess) e = ef;
     }
   } else if (img->butterfly) {
-    e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, in, out, S,
-                         static_cast<hipStream_t>(stream), img->num_cus, in16, out16);
+    e = launch_butterfly(dir == 0 ? img->bfwd : img->binv, in, out, S, st, img->num_cus, in16, out16,
+                         img->grid[dir]);
   } else {
     const DevProgram &P = dir == 0 ? img->fwd[0] : img->inv[0];
     const int cap = dir == 0 ? img->grid_cap_fwd[0] : img->grid_cap_inv[0];
-    e = launch_apply(P, in, out, S, static_cast<hipStream_t>(stream), cap, in16, out16);
+    e = launch_apply(P, in, out, S, st, cap, in16, out16);
   }
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
@@ -915,7 +1277,8 @@ static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *ou
                                     dir == 0 ? img->dev_ufwd : img->dev_uinv,
                                     (int)plan->graphs.size(), signal_offsets, total_elements,
                                     static_cast<const float *>(in), static_cast<float *>(out),
-                                    img->batch_lds, img->batch_grid, img->reg_groups,
+                                    img->batch_lds, img->batch_rounds * img->num_cus * img->batch_occ,
+                                    img->reg_groups, img->batch_cost16,
                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return set_error(GFT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return ok();
@@ -943,9 +1306,9 @@ gft_status gft_apply_noalloc(gft_plan_t plan, int32_t direction, const void *in,
   if (img->large) {
     ws = large_scratch(dev);
     if (!ws) return set_error(GFT_ERR_HIP, "the static scratch of this device was not set up");
-    const size_t need = large_ws_bytes(img->lg[direction], num_signals);
+    const size_t need = large_ws_bytes(img->lg[direction], img->lfused[direction], num_signals);
     if (need > kScratchBytes) {
-      const size_t per = large_ws_bytes(img->lg[direction], 1);
+      const size_t per = large_ws_bytes(img->lg[direction], img->lfused[direction], 1);
       return set_error(GFT_ERR_INVALID_ARG,
                        std::to_string(num_signals) + " signals need " + std::to_string(need) +
                            " bytes of workspace; the static scratch holds " + std::to_string(kScratchBytes) +
@@ -999,6 +1362,40 @@ gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile)
     *fwd_tile = 16 * img->fwd[0].mt;
     *inv_tile = 16 * img->inv[0].mt;
   }
+  return ok();
+}
+
+gft_status gft_plan_tuning(gft_plan_t plan, gft_tuning *out) {
+  if (!plan || !out) return set_error(GFT_ERR_INVALID_ARG, "plan and out must be non-NULL");
+  DeviceImage *img = nullptr;
+  gft_status st = device_image(plan, &img);
+  if (st != GFT_OK) return st;
+  gft_tuning t{};
+  t.engine = img->product ? GFT_ENGINE_PRODUCT
+             : img->butterfly ? GFT_ENGINE_BUTTERFLY : (img->large ? GFT_ENGINE_LARGE : GFT_ENGINE_GENERIC);
+  if (img->product) {
+    t.fwd_tile = t.inv_tile = 1;
+    t.variant = img->product_staged ? 1 : 0;
+    t.grid_fwd = img->grid[0];
+    t.grid_inv = img->grid[1];
+  } else if (img->butterfly) {
+    t.fwd_tile = t.inv_tile = 16;
+    t.grid_fwd = img->grid[0];
+    t.grid_inv = img->grid[1];
+  } else if (img->large) {
+    t.variant = img->lfused[0] ? 1 : 0;
+    t.large_tile_kb = img->ltile_kb[0];
+  } else if (!plan->batch) {
+    t.fwd_tile = 16 * img->fwd[0].mt;
+    t.inv_tile = 16 * img->inv[0].mt;
+  }
+  if (plan->batch) {
+    t.batch_rounds = img->batch_rounds;
+    t.batch_cost16 = img->batch_cost16;
+  }
+  t.source = img->tune_source;
+  t.tune_ms = img->tune_ms;
+  *out = t;
   return ok();
 }
 

@@ -148,6 +148,11 @@ struct PProgram {
   const float *bmat;        // NB x NB row-major, zero beyond nb
   const uint16_t *perm;     // na * nb entries: LDS word p * stride + q of output-order
                             // coefficient k (its factor indices p, q)
+  // 0: dense factors.  1: staged 64-node factors whose stages are the halving reversals
+  // (R = 64, 32, ..., 2: node i < R/2 paired with R - 1 - i), compiled into the kernel;
+  // amat and bmat then hold the block-diagonal leaf matrices (rows and columns: node
+  // positions and block-order coefficients) and the stages run as add/sub on the signal.
+  int32_t tile_pattern;
 };
 
 }  // namespace gft

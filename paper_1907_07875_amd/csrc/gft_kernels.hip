@@ -440,10 +440,10 @@ __device__ __forceinline__ void batch_butterfly(const UProgram &U, const float *
 
 // Cost of one signal in the register phase, in element-equivalents: a 16-signal tile takes
 // about the longer of its HBM traffic (n values) and a fixed part that grows with the
-// padded slot count N = M 2^S (measured per graph shape on this kernel: the fixed part
-// equals about 11 N / 16 values' worth of traffic).
-__device__ __forceinline__ int64_t reg_cost(const UProgram &U) {
-  const int fixed = (11 * (U.M << U.S)) / 16;
+// padded slot count N = M 2^S: cost16 N / 16 values' worth of traffic (measured per graph
+// shape on this kernel: about 11; the plan-time tuner may pick another).
+__device__ __forceinline__ int64_t reg_cost(const UProgram &U, int cost16) {
+  const int fixed = (cost16 * (U.M << U.S)) / 16;
   return U.n > fixed ? U.n : fixed;
 }
 
@@ -464,7 +464,7 @@ template <int PREC, int DIR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void gft_apply_batch(
     const DevProgram *__restrict__ progs, const UProgram *__restrict__ uprogs, int G,
     const int64_t *__restrict__ sig_off, int64_t total_elems, const float *in, float *out,
-    int reg_groups) {
+    int reg_groups, int cost16) {
   extern __shared__ __attribute__((aligned(16))) int32_t smem[];
   const int GP = (G + 2) & ~1;                                 // G + 1 rounded to even
   int64_t *elem = reinterpret_cast<int64_t *>(smem);           // all graphs
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   auto elems = [&](int g, int64_t &cost) -> int64_t {
     const int64_t ns = sig_off[g + 1] - sig_off[g];
     const int64_t s = ns > 0 ? ns : 0;
-    cost = (uprogs != nullptr && uprogs[g].S > 0) ? s * reg_cost(uprogs[g]) : 0;
+    cost = (uprogs != nullptr && uprogs[g].S > 0) ? s * reg_cost(uprogs[g], cost16) : 0;
     return s * (int64_t)progs[g].n;
   };
   int64_t accA = 0, accR = 0, accL = 0;
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         const int64_t gb = elemR[g], ge = elemR[g + 1];
         if (ge <= gb || elem[g + 1] > total_elems) continue;
         const UProgram U = uprogs[g];
-        const int64_t cs = reg_cost(U), te = 16 * cs;          // cost per signal, per tile
+        const int64_t cs = reg_cost(U, cost16), te = 16 * cs;  // cost per signal, per tile
         const int64_t t0 = e0 > gb ? (e0 - gb + te - 1) / te : 0;
         const int64_t t1 = ((e1 < ge ? e1 : ge) - gb + te - 1) / te;
         if (t0 < t1)
@@ -747,7 +747,7 @@ size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase) {
 template <int PREC, int DIR>
 static hipError_t launch_batch_pd(const DevProgram *progs, const UProgram *uprogs, int G,
                                   const int64_t *sig_off, int64_t total_elems, const float *in,
-                                  float *out, size_t lds, int grid, int reg_groups,
+                                  float *out, size_t lds, int grid, int reg_groups, int cost16,
                                   hipStream_t stream) {
   if (lds + 24 * (kThreads / 64) > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)gft_apply_batch<PREC, DIR>,
@@ -755,17 +755,17 @@ static hipError_t launch_batch_pd(const DevProgram *progs, const UProgram *uprog
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((gft_apply_batch<PREC, DIR>), dim3(grid), dim3(kThreads), lds, stream, progs,
-                     uprogs, G, sig_off, total_elems, in, out, reg_groups);
+                     uprogs, G, sig_off, total_elems, in, out, reg_groups, cost16);
   return hipGetLastError();
 }
 
 template <int PREC>
 static hipError_t launch_batch_p(int dir, const DevProgram *progs, const UProgram *uprogs, int G,
                                  const int64_t *sig_off, int64_t total_elems, const float *in,
-                                 float *out, size_t lds, int grid, int reg_groups,
+                                 float *out, size_t lds, int grid, int reg_groups, int cost16,
                                  hipStream_t stream) {
-  return dir == 0 ? launch_batch_pd<PREC, 0>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream)
-                  : launch_batch_pd<PREC, 1>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
+  return dir == 0 ? launch_batch_pd<PREC, 0>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream)
+                  : launch_batch_pd<PREC, 1>(progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream);
 }
 
 int batch_occupancy(int prec, size_t lds) {
@@ -791,12 +791,14 @@ bool batch_butterfly_supported(int prec, const UProgram &U) {
 
 hipError_t launch_apply_batch(int prec, int dir, const DevProgram *progs, const UProgram *uprogs,
                               int G, const int64_t *sig_off, int64_t total_elems, const float *in,
-                              float *out, size_t lds, int grid, int reg_groups, hipStream_t stream) {
+                              float *out, size_t lds, int grid, int reg_groups, int cost16,
+                              hipStream_t stream) {
+  if (cost16 < 1 || cost16 > 64) return hipErrorInvalidValue;
   switch (prec) {
-    case kFP32: return launch_batch_p<kFP32>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
-    case kBF16: return launch_batch_p<kBF16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
-    case kFP16: return launch_batch_p<kFP16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
-    case kSPLIT: return launch_batch_p<kSPLIT>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, stream);
+    case kFP32: return launch_batch_p<kFP32>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream);
+    case kBF16: return launch_batch_p<kBF16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream);
+    case kFP16: return launch_batch_p<kFP16>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream);
+    case kSPLIT: return launch_batch_p<kSPLIT>(dir, progs, uprogs, G, sig_off, total_elems, in, out, lds, grid, reg_groups, cost16, stream);
     default: return hipErrorInvalidValue;
   }
 }

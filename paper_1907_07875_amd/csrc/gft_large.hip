@@ -400,15 +400,16 @@ void *large_scratch(int dev) {
 
 // ---------------------------------------------------------------------------- launch
 
-int permute_rows(const PermPass &P) {
-  // about 40 KB of LDS per tile (four workgroups per CU), 1 to 16 rows
-  const int rows = (40 * 1024) / (4 * P.in_cols);
+int permute_rows(const PermPass &P, int tile_kb) {
+  // about 40 KB of LDS per tile (four workgroups per CU) unless the tuner says otherwise,
+  // 1 to 16 rows
+  const int rows = ((tile_kb > 0 ? tile_kb : 40) * 1024) / (4 * P.in_cols);
   return rows < 1 ? 1 : (rows > 16 ? 16 : rows);
 }
 
 hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
-                                 int64_t S, int num_cus, hipStream_t stream) {
-  const int rows = permute_rows(P);
+                                 int64_t S, int num_cus, hipStream_t stream, int tile_kb) {
+  const int rows = permute_rows(P, tile_kb);
   const size_t lds = (size_t)rows * P.in_cols * 4;
   const void *fn = out16 ? (const void *)gft_permute_stages<true> : (const void *)gft_permute_stages<false>;
   if (lds > 64 * 1024) {

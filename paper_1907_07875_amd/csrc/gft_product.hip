@@ -15,6 +15,11 @@
 // Both matrices stay in registers as MFMA fragments (v_mfma_f32_16x16x4_f32: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the result D[4 (l / 16) + v][l % 16]).  Padding
 // rows and columns of the tile and of the matrices are zero, so they stay zero.
+// Staged factors: a factor with Haar stages is applied in its fast form, the stages as
+// add/sub on the tile (rows for axis a, columns for axis b; before the products forward,
+// after them inverse) and its leaf blocks as one block-diagonal matrix whose all-zero
+// 16x16 tiles the products skip (a compiled tile pattern): the 64 x 64 grid's halving
+// stages leave blocks of 32, 16, 8, 4, 2, 1, 1 per axis, 6 of 16 tiles.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -92,6 +97,90 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Halving reversal stages of a 64-node axis, compiled: stage R (R = 64, 32, ..., 2) pairs
+// node i < R / 2 with R - 1 - i (V_X = i) and computes x + y at i, x - y at R - 1 - i,
+// unscaled (the 2^(-depth/2) of the leaves is in their matrices).  The inverse runs the
+// same pairs from R = 2 up to R = 64.
+//
+// Columns (axis b), on a signal row held in the load layout: lane l holds columns 4c .. 4c+3
+// (c = l % 16) of its rows, so the partner of column 4c + e at R >= 8 is element 3 - e of
+// lane 15 - c, 7 - c, 3 - c or 1 - c of the same 16-lane row (DPP row mirror, row half
+// mirror and the quad permutations 3210 and 1032); at R = 4 and 2 it is in the lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL, int Q>   // Q = R / 4 lanes of 4 columns take part
+__device__ __forceinline__ void col_stage(floatx4 &v, int c) {
+  // every lane reads its partner's values (DPP needs its source lanes active)
+  const floatx4 p = {dpp_f<CTRL>(v[3]), dpp_f<CTRL>(v[2]), dpp_f<CTRL>(v[1]), dpp_f<CTRL>(v[0])};
+  if (c < Q) {
+    const bool xs = c < Q / 2;   // the lane holds the V_X side
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = xs ? v[e] + p[e] : p[e] - v[e];
+  }
+}
+
+__device__ __forceinline__ void col_stage4(floatx4 &v, int c) {   // R = 4: (0, 3), (1, 2)
+  if (c == 0) v = floatx4{v[0] + v[3], v[1] + v[2], v[1] - v[2], v[0] - v[3]};
+}
+
+__device__ __forceinline__ void col_stage2(floatx4 &v, int c) {   // R = 2: (0, 1)
+  if (c == 0) v = floatx4{v[0] + v[1], v[0] - v[1], v[2], v[3]};
+}
+
+template <bool INV>
+__device__ __forceinline__ void halving_cols(floatx4 &v, int c) {
+  if constexpr (!INV) {
+    col_stage<0x140, 16>(v, c);   // R = 64: row mirror, lane 15 - c
+    col_stage<0x141, 8>(v, c);    // R = 32: row half mirror, lane 7 - c
+    col_stage<0x1B, 4>(v, c);     // R = 16: quad permutation 3210, lane 3 - c
+    col_stage<0xB1, 2>(v, c);     // R = 8: quad permutation 1032, lane 1 - c
+    col_stage4(v, c);
+    col_stage2(v, c);
+  } else {
+    col_stage2(v, c);
+    col_stage4(v, c);
+    col_stage<0xB1, 2>(v, c);
+    col_stage<0x1B, 4>(v, c);
+    col_stage<0x141, 8>(v, c);
+    col_stage<0x140, 16>(v, c);
+  }
+}
+
+// Rows (axis a): lane c reads column c of the wave's tile (64 rows, stride STR) into
+// registers, runs the stages there and writes it back: 64 reads and 64 writes per lane, each
+// 64-lane access 64 consecutive words of one row.
+template <bool INV, int STR>
+__device__ __forceinline__ void halving_rows(float *T, int c) {
+  float col[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) col[i] = T[i * STR + c];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int R = INV ? (2 << t) : (64 >> t);
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      const float x = col[i], y = col[R - 1 - i];
+      col[i] = x + y;
+      col[R - 1 - i] = x - y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 64; ++i) T[i * STR + c] = col[i];
+}
+
+// Tile pattern TP of the products' T x T grid of 16 x 16 tiles (T = NA / 16 or NB / 16):
+// 0 every tile (dense factors); 1 staged 64-node factors with the halving stages above,
+// whose block-diagonal leaf matrices (blocks of 32, 16, 8, 4, 2, 1, 1 nodes in ascending
+// node order) fill tiles (0,0), (1,1) and the 2 x 2 group {2, 3}.  The tile loops are fully
+// unrolled, so the test folds away and zero tiles cost no MFMA and no fragment registers.
+template <int TP, int T>
+__device__ __forceinline__ constexpr bool tile_nz(int r, int c) {
+  return TP == 0 || r == c || (T == 4 && r >= 2 && c >= 2);
+}
+
 template <int NA, int NB>
 constexpr size_t product_lds_bytes(int n) {
   return (size_t)kPWaves * NA * (NB + 1) * sizeof(float) + (((size_t)n * 2 + 15) & ~(size_t)15);
@@ -103,10 +192,11 @@ constexpr size_t product_lds_bytes(int n) {
 // fragments then serve both products.  PREC: FP32 (16x16x4 FP32 MFMA), BF16 or split BF16
 // (16x16x16 BF16 MFMA with FP32 accumulation; the data operand of each product is rounded
 // to BF16, or split into hi + lo, as it enters the MFMA).
-template <int NA, int NB, int DIR, bool SAME, int PREC>
+template <int NA, int NB, int DIR, bool SAME, int PREC, int TP>
 __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2))) void gft_product(
     PProgram P, const float *in, float *out, int64_t nsig) {
   static_assert(!SAME || NA == NB, "one matrix needs equal factor sizes");
+  static_assert(TP == 0 || (NA == 64 && NB == 64), "tile pattern 1: 64 x 64 factors only");
   constexpr bool B16 = PREC != kFP32;
   constexpr int STR = NB + 1;
   constexpr int TW = NA * STR;
@@ -197,6 +287,10 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
         const int v = lane + 64 * k;
         ld[k] = __builtin_nontemporal_load(src + (v < nv ? v : nv - 1));
       }
+      if constexpr (TP != 0 && DIR == 0) {   // staged: the column stages in the load registers
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) halving_cols<false>(ld[k], r16);
+      }
 #pragma unroll
       for (int k = 0; k < MAXV; ++k) {
         const int v = lane + 64 * k;
@@ -215,6 +309,10 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
       for (int e = lane; e < n; e += 64) T[lds_in(e)] = in[s * n + e];
     }
     wave_sync();
+    if constexpr (TP != 0 && DIR == 0) {   // staged: the row stages through the tile
+      halving_rows<false, STR>(T, lane);
+      wave_sync();
+    }
 
     // Y1 = Z * B
     floatx4 y1[MA][MB];
@@ -229,10 +327,18 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
           const Frag16 a0 = pack16(z[0], z[1], z[2], z[3]), a1 = pack16(z[16], z[17], z[18], z[19]);
 #pragma unroll
           for (int nt = 0; nt < MB; ++nt) {
-            if constexpr (SAME)
-              y1[mt][nt] = mfma32<PREC == kSPLIT>(a0, a1, aq[nt][2 * kp], aq[nt][2 * kp + 1], y1[mt][nt]);
-            else
-              y1[mt][nt] = mfma32<PREC == kSPLIT>(a0, a1, bq[2 * kp][nt], bq[2 * kp + 1][nt], y1[mt][nt]);
+            const bool on0 = tile_nz<TP, MB>(2 * kp, nt), on1 = tile_nz<TP, MB>(2 * kp + 1, nt);
+            Frag16 b0, b1;
+            if constexpr (SAME) {
+              b0 = aq[nt][2 * kp];
+              b1 = aq[nt][2 * kp + 1];
+            } else {
+              b0 = bq[2 * kp][nt];
+              b1 = bq[2 * kp + 1][nt];
+            }
+            if (on0 && on1) y1[mt][nt] = mfma32<PREC == kSPLIT>(a0, a1, b0, b1, y1[mt][nt]);
+            else if (on0) y1[mt][nt] = mfma16<PREC == kSPLIT>(a0, b0, y1[mt][nt]);
+            else if (on1) y1[mt][nt] = mfma16<PREC == kSPLIT>(a1, b1, y1[mt][nt]);
           }
         }
       } else if constexpr (B16) {
@@ -242,6 +348,7 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
           const Frag16 a = pack16(z[0], z[1], z[2], z[3]);
 #pragma unroll
           for (int nt = 0; nt < MB; ++nt) {
+            if (!tile_nz<TP, MB>(kk, nt)) continue;
             if constexpr (SAME) y1[mt][nt] = mfma16<PREC == kSPLIT>(a, aq[nt][kk], y1[mt][nt]);
             else y1[mt][nt] = mfma16<PREC == kSPLIT>(a, bq[kk][nt], y1[mt][nt]);
           }
@@ -254,6 +361,7 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
             const float a = T[(16 * mt + r16) * STR + 16 * mk + 4 * g4 + v];
 #pragma unroll
             for (int nt = 0; nt < MB; ++nt) {
+              if (!tile_nz<TP, MB>(mk, nt)) continue;
               float b;
               if constexpr (SAME) b = af[nt][mk][v];
               else b = bf[mk][v][nt];
@@ -278,8 +386,12 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
           const floatx4 y0 = y1[2 * mp][nt], y1v = y1[2 * mp + 1][nt];
           const Frag16 b0 = pack16(y0[0], y0[1], y0[2], y0[3]), b1 = pack16(y1v[0], y1v[1], y1v[2], y1v[3]);
 #pragma unroll
-          for (int mo = 0; mo < MA; ++mo)
-            acc[mo] = mfma32<PREC == kSPLIT>(aq[mo][2 * mp], aq[mo][2 * mp + 1], b0, b1, acc[mo]);
+          for (int mo = 0; mo < MA; ++mo) {
+            const bool on0 = tile_nz<TP, MA>(mo, 2 * mp), on1 = tile_nz<TP, MA>(mo, 2 * mp + 1);
+            if (on0 && on1) acc[mo] = mfma32<PREC == kSPLIT>(aq[mo][2 * mp], aq[mo][2 * mp + 1], b0, b1, acc[mo]);
+            else if (on0) acc[mo] = mfma16<PREC == kSPLIT>(aq[mo][2 * mp], b0, acc[mo]);
+            else if (on1) acc[mo] = mfma16<PREC == kSPLIT>(aq[mo][2 * mp + 1], b1, acc[mo]);
+          }
         }
       } else if constexpr (B16) {
         // the result registers y1[mt][nt] are already the B operand of k chunk mt
@@ -288,7 +400,8 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
           const floatx4 y = y1[mt][nt];
           const Frag16 b = pack16(y[0], y[1], y[2], y[3]);
 #pragma unroll
-          for (int mo = 0; mo < MA; ++mo) acc[mo] = mfma16<PREC == kSPLIT>(aq[mo][mt], b, acc[mo]);
+          for (int mo = 0; mo < MA; ++mo)
+            if (tile_nz<TP, MA>(mo, mt)) acc[mo] = mfma16<PREC == kSPLIT>(aq[mo][mt], b, acc[mo]);
         }
       } else {
 #pragma unroll
@@ -297,7 +410,8 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
           for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int mo = 0; mo < MA; ++mo)
-              acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mo][mt][v], y1[mt][nt][v], acc[mo], 0, 0, 0);
+              if (tile_nz<TP, MA>(mo, mt))
+                acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mo][mt][v], y1[mt][nt][v], acc[mo], 0, 0, 0);
       }
 #pragma unroll
       for (int mo = 0; mo < MA; ++mo)
@@ -305,8 +419,22 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
         for (int v = 0; v < 4; ++v) T[(16 * mo + 4 * g4 + v) * STR + 16 * nt + r16] = acc[mo][v];
     }
     wave_sync();
+    if constexpr (TP != 0 && DIR == 1) {   // staged: the row stages through the tile
+      halving_rows<true, STR>(T, lane);
+      wave_sync();
+    }
 
-    if (vec) {
+    if (TP != 0 && DIR == 1) {   // staged inverse (full 64 x 64 signals): the column stages
+      floatx4 *dst = reinterpret_cast<floatx4 *>(out + s * n);
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) {
+        const int v = lane + 64 * k;
+        const float *row = T + natural(4 * v);
+        floatx4 o = {row[0], row[1], row[2], row[3]};
+        halving_cols<true>(o, r16);
+        __builtin_nontemporal_store(o, dst + v);
+      }
+    } else if (vec) {
       floatx4 *dst = reinterpret_cast<floatx4 *>(out + s * n);
 #pragma unroll 2
       for (int v = lane; v < nv; v += 64) {
@@ -323,58 +451,75 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
 
 // ---------------------------------------------------------------------------- launch
 
-template <int NA, int NB, int DIR, bool SAME, int PREC>
+// grid_cap > 0: launch at most that many workgroups; num_cus < 0: only report the
+// occupancy through *occ_out.
+template <int NA, int NB, int DIR, bool SAME, int PREC, int TP>
 static hipError_t launch_pdp(const PProgram &P, const float *in, float *out, int64_t nsig,
-                             hipStream_t stream, int num_cus) {
+                             hipStream_t stream, int num_cus, int grid_cap, int *occ_out) {
   const size_t lds = product_lds_bytes<NA, NB>(P.na * P.nb);
-  const void *k = (const void *)gft_product<NA, NB, DIR, SAME, PREC>;
+  const void *k = (const void *)gft_product<NA, NB, DIR, SAME, PREC, TP>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR, SAME, PREC>, 64 * kPWaves, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gft_product<NA, NB, DIR, SAME, PREC, TP>, 64 * kPWaves, lds) !=
           hipSuccess || occ < 1)
     occ = 1;
+  if (occ_out) *occ_out = occ;
+  if (num_cus < 0) return hipSuccess;
   const int64_t want = (nsig + kPWaves - 1) / kPWaves;
-  const int64_t cap = (int64_t)occ * (num_cus > 0 ? num_cus : 1);
+  const int64_t cap = grid_cap > 0 ? grid_cap : (int64_t)occ * (num_cus > 0 ? num_cus : 1);
   const int grid = (int)(want < cap ? want : cap);
-  hipLaunchKernelGGL((gft_product<NA, NB, DIR, SAME, PREC>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
+  hipLaunchKernelGGL((gft_product<NA, NB, DIR, SAME, PREC, TP>), dim3(grid > 0 ? grid : 1), dim3(64 * kPWaves), lds,
                      stream, P, in, out, nsig);
   return hipGetLastError();
 }
 
-template <int NA, int NB, int DIR, bool SAME>
-static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
-                            hipStream_t stream, int num_cus) {
+template <int NA, int NB, int DIR, bool SAME, int TP>
+static hipError_t launch_pdt(const PProgram &P, const float *in, float *out, int64_t nsig,
+                             hipStream_t stream, int num_cus, int grid_cap, int *occ_out) {
   switch (P.prec) {
-    case kFP32: return launch_pdp<NA, NB, DIR, SAME, kFP32>(P, in, out, nsig, stream, num_cus);
-    case kBF16: return launch_pdp<NA, NB, DIR, SAME, kBF16>(P, in, out, nsig, stream, num_cus);
-    case kSPLIT: return launch_pdp<NA, NB, DIR, SAME, kSPLIT>(P, in, out, nsig, stream, num_cus);
+    case kFP32: return launch_pdp<NA, NB, DIR, SAME, kFP32, TP>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
+    case kBF16: return launch_pdp<NA, NB, DIR, SAME, kBF16, TP>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
+    case kSPLIT: return launch_pdp<NA, NB, DIR, SAME, kSPLIT, TP>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <int NA, int NB, int DIR, bool SAME>
+static hipError_t launch_pd(const PProgram &P, const float *in, float *out, int64_t nsig,
+                            hipStream_t stream, int num_cus, int grid_cap, int *occ_out) {
+  if constexpr (NA == 64 && NB == 64) {
+    if (P.tile_pattern == 1) {
+      if (P.na != 64 || P.nb != 64) return hipErrorInvalidValue;
+      return launch_pdt<NA, NB, DIR, SAME, 1>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
+    }
+  }
+  if (P.tile_pattern != 0) return hipErrorInvalidValue;
+  return launch_pdt<NA, NB, DIR, SAME, 0>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
+}
+
 template <int NA, int NB>
 static hipError_t launch_pab(const PProgram &P, const float *in, float *out, int64_t nsig,
-                             hipStream_t stream, int num_cus) {
+                             hipStream_t stream, int num_cus, int grid_cap, int *occ_out) {
   if constexpr (NA == NB) {
     if (P.same)
-      return P.dir == 0 ? launch_pd<NA, NB, 0, true>(P, in, out, nsig, stream, num_cus)
-                        : launch_pd<NA, NB, 1, true>(P, in, out, nsig, stream, num_cus);
+      return P.dir == 0 ? launch_pd<NA, NB, 0, true>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out)
+                        : launch_pd<NA, NB, 1, true>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
   }
-  return P.dir == 0 ? launch_pd<NA, NB, 0, false>(P, in, out, nsig, stream, num_cus)
-                    : launch_pd<NA, NB, 1, false>(P, in, out, nsig, stream, num_cus);
+  return P.dir == 0 ? launch_pd<NA, NB, 0, false>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out)
+                    : launch_pd<NA, NB, 1, false>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
 }
 
 int product_pad(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0)); }
 
-hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
-                          hipStream_t stream, int num_cus) {
+static hipError_t dispatch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
+                                   hipStream_t stream, int num_cus, int grid_cap, int *occ_out) {
   const int NA = product_pad(P.na), NB = product_pad(P.nb);
   if (P.stride != NB + 1) return hipErrorInvalidValue;
 #define GFT_PROD_CASE(a, b) \
-  if (NA == a && NB == b) return launch_pab<a, b>(P, in, out, nsig, stream, num_cus);
+  if (NA == a && NB == b) return launch_pab<a, b>(P, in, out, nsig, stream, num_cus, grid_cap, occ_out);
   GFT_PROD_CASE(16, 16)
   GFT_PROD_CASE(16, 32)
   GFT_PROD_CASE(16, 64)
@@ -386,6 +531,17 @@ hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_
   GFT_PROD_CASE(64, 64)
 #undef GFT_PROD_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
+                          hipStream_t stream, int num_cus, int grid_cap) {
+  return dispatch_product(P, in, out, nsig, stream, num_cus, grid_cap, nullptr);
+}
+
+int product_occupancy(const PProgram &P) {
+  int occ = 1;
+  if (dispatch_product(P, nullptr, nullptr, 0, nullptr, -1, 0, &occ) != hipSuccess) return 1;
+  return occ;
 }
 
 }  // namespace gft

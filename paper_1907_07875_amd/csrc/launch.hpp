@@ -22,14 +22,18 @@ int apply_occupancy(const DevProgram &P);
 size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase);
 int batch_occupancy(int prec, size_t lds);
 bool batch_butterfly_supported(int prec, const UProgram &U);
+// cost16: register-phase fixed cost per signal in sixteenths of the padded slot count.
 hipError_t launch_apply_batch(int prec, int dir, const DevProgram *progs, const UProgram *uprogs,
                               int G, const int64_t *sig_off, int64_t total_elems, const float *in,
-                              float *out, size_t lds, int grid, int reg_groups, hipStream_t stream);
+                              float *out, size_t lds, int grid, int reg_groups, int cost16,
+                              hipStream_t stream);
 
 // Large-signal engine.
-int permute_rows(const PermPass &P);   // signal rows per LDS tile of a stage/gather pass
+// Signal rows per LDS tile of a stage/gather pass: as many as fill about tile_kb KB (0: the
+// built-in 40 KB), 1 to 16.
+int permute_rows(const PermPass &P, int tile_kb = 0);
 hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
-                                 int64_t S, int num_cus, hipStream_t stream);
+                                 int64_t S, int num_cus, hipStream_t stream, int tile_kb = 0);
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
 // prec: 0 FP32, 1 BF16 (A and matrices stored in BF16), 3 split BF16 (FP32 storage)
 // omap non-null: column c of block b is written to column omap[b.omap + c] of C (row
@@ -49,13 +53,16 @@ void *large_scratch(int dev);
 // Register-butterfly engine (uniform hypercube plans).
 bool butterfly_supported(const UProgram &P);   // a kernel is compiled for its shape
 // in16 / out16: the input / output array holds BF16 values (else FP32).
+// grid_cap: most workgroups launched (0: every resident workgroup, occupancy x CUs).
 hipError_t launch_butterfly(const UProgram &P, const void *in, void *out, int64_t nsig,
-                            hipStream_t stream, int num_cus, bool in16, bool out16);
+                            hipStream_t stream, int num_cus, bool in16, bool out16, int grid_cap = 0);
+int butterfly_occupancy(const UProgram &P, bool in16, bool out16);   // resident workgroups per CU
 
 // Product-graph engine: factor sizes padded to 16, 32 or 64 (0 above 64).
 int product_pad(int n);
 hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
-                          hipStream_t stream, int num_cus);
+                          hipStream_t stream, int num_cus, int grid_cap = 0);
+int product_occupancy(const PProgram &P);   // resident workgroups per CU
 
 // Streaming copy of `bytes` (a multiple of 16) between 16-byte aligned, non-overlapping
 // device buffers (gft_copy.hip).

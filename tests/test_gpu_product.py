@@ -175,3 +175,39 @@ def test_separable_engine_refused_without_kronecker_leaves():
     assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
     # the 8x8 grid has Kronecker leaves but keeps the register butterfly when not forced
     assert G.Plan.from_graph(wl.config2_graph()).engine() == "butterfly"
+
+
+FORM_PAIRS = [(wl.path_recursive(64), wl.path_recursive(64)),         # one fragment set, 6 of 16 tiles
+              (wl.path_recursive(32), wl.path_recursive(64)),
+              (wl.path_recursive(16), wl.weighted_symmetric_path(40, wl.rng_for(9, 40))),
+              (wl.path(5), wl.cycle(12))]                               # V_Z nodes, padded 16 x 16
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_bf16", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("form", ["dense", "staged"])
+@pytest.mark.parametrize("pair", FORM_PAIRS, ids=_ids)
+def test_separable_factor_forms(pair, form, precision, tol, monkeypatch):
+    """Both forms of the factors on the separable engine: dense factor GFTs, and staged
+    factors (Haar stages as add/sub on the tile, leaf blocks as block-diagonal matrices
+    whose zero tiles are skipped), forced through GFT_PRODUCT_FORM; every coefficient
+    against the aligned oracle, forward, inverse of the oracle's coefficients, round trip."""
+    monkeypatch.setenv("GFT_PRODUCT_FORM", form)
+    dev = device()
+    ga, gb = pair
+    g = wl.product_with_stages(ga, gb)
+    plan = G.gft_plan(g.n, g.src, g.dst, g.weight, g.self_loop, g.stages, engine="product",
+                      precision=precision)
+    plan.prepare()
+    assert plan.engine() == "product"
+    _, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-8)
+    X = wl.gaussian(517, g.n, wl.rng_for(9, g.n, 41))
+    x = torch.from_numpy(X).to(dev)
+    y = plan.forward(x)
+    C_ref = O.forward(X.astype(np.float64), Ua)
+    err = O.relative_error(to_np(y), C_ref)
+    assert err <= tol, f"{form} {precision}: forward relative error {err:.3e}"
+    C32 = C_ref.astype(np.float32)
+    xr = plan.inverse(torch.from_numpy(C32).to(dev))
+    err_i = O.relative_error(to_np(xr), O.inverse(C32.astype(np.float64), Ua))
+    assert err_i <= tol, f"{form} {precision}: inverse relative error {err_i:.3e}"
+    assert O.relative_error(to_np(plan.inverse(y)), X.astype(np.float64)) <= 2 * tol

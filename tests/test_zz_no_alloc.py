@@ -78,7 +78,8 @@ def test_noalloc_rejects_calls_beyond_the_scratch():
     g = wl.config5b_graph()
     plan = G.Plan.from_graph(g)
     plan.prepare()
-    per_signal = g.n * 4                        # forward: fused output order, W1 only
+    # forward: W1 only when the GEMM writes the output order (the tuned variant), else W1, W2
+    per_signal = g.n * 4 * (1 if plan.tuning()["variant"] == 1 else 2)
     limit = SCRATCH_BYTES // per_signal
     x = torch.zeros((limit + 1, g.n), device=dev)
     y = torch.empty_like(x)
@@ -86,11 +87,12 @@ def test_noalloc_rejects_calls_beyond_the_scratch():
     st = _noalloc(plan, x, y, 0)
     assert G.STATUS[st] == "GFT_ERR_INVALID_ARG"
     assert f"at most {limit} signals" in G.load_library().gft_last_error().decode()
-    # the inverse runs its stage pass after the GEMM: W1 and W2, half as many signals
-    assert _noalloc(plan, x[:limit // 2], y[:limit // 2], 1) == 0
-    st = _noalloc(plan, x[:limit // 2 + 1], y[:limit // 2 + 1], 1)
+    # the inverse runs its stage pass after the GEMM: W1 and W2
+    inv = SCRATCH_BYTES // (g.n * 4 * 2)
+    assert _noalloc(plan, x[:inv], y[:inv], 1) == 0
+    st = _noalloc(plan, x[:inv + 1], y[:inv + 1], 1)
     assert G.STATUS[st] == "GFT_ERR_INVALID_ARG"
-    assert f"at most {limit // 2} signals" in G.load_library().gft_last_error().decode()
+    assert f"at most {inv} signals" in G.load_library().gft_last_error().decode()
     torch.cuda.synchronize()
 
 
