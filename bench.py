@@ -43,8 +43,8 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 PROFILED_TRAFFIC = {"sources": ["paper_1907_07875_amd/csrc/gft_butterfly.hip",
                                 "paper_1907_07875_amd/csrc/butterfly_core.hpp",
                                 "paper_1907_07875_amd/csrc/device_program.hpp"],
-                    "sha256_16": "5f9ea450d9c2c07c",
-                    "bytes_per_launch": 2.0 * 131164.31 * 1024 + 262150.27 * 1024}
+                    "sha256_16": "5cfef7152b1b8935",
+                    "bytes_per_launch": 2.0 * 131161.1 * 1024 + 262149.2 * 1024}
 
 
 def parse():

@@ -229,6 +229,9 @@ typedef struct {
                            /* axis each (Sec. V-D); 0 or num_blocks                     */
   int64_t separable_mults; /* mults with those leaves applied separably, V_a^T Z V_b:   */
                            /* sum b_a b_b (b_a + b_b) + num_z_scalings (else = mults)   */
+  int32_t num_closed_form_leaves; /* leaves whose basis is the closed form DCT-II (a    */
+                           /* uniform path plus c I) or DST-IV (the same with a self-   */
+                           /* loop 2w at one end), not an eigensolve (Sec. V-C)         */
 } gft_plan_stats;
 
 /* Build a plan for one graph.  Validates the graph and every stage, forms the sub-graph

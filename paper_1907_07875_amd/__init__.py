@@ -87,7 +87,8 @@ class PlanStats(ctypes.Structure):
                 ("adds", ctypes.c_int64), ("mults", ctypes.c_int64),
                 ("max_residual", ctypes.c_double), ("max_orth_error", ctypes.c_double),
                 ("num_right_units", ctypes.c_int32), ("num_right_leaves", ctypes.c_int32),
-                ("num_kron_leaves", ctypes.c_int32), ("separable_mults", ctypes.c_int64)]
+                ("num_kron_leaves", ctypes.c_int32), ("separable_mults", ctypes.c_int64),
+                ("num_closed_form_leaves", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -149,17 +149,28 @@ __device__ __forceinline__ void halving_cols(floatx4 &v, int c) {
   }
 }
 
-// Rows (axis a): lane c reads column c of the wave's tile (64 rows, stride STR) into
-// registers, runs the stages there and writes it back: 64 reads and 64 writes per lane, each
-// 64-lane access 64 consecutive words of one row.
+// Rows (axis a): lane c works on column c of the wave's tile (64 rows, stride STR).  The
+// R = 64 stage pairs rows i and 63 - i in place in LDS; the other stages act on rows 0..31
+// only, which the lane reads into registers, combines there and writes back (holding the
+// whole column in registers instead made the forward kernel spill).  Each 64-lane access
+// touches 64 consecutive words of one row.
 template <bool INV, int STR>
 __device__ __forceinline__ void halving_rows(float *T, int c) {
-  float col[64];
+  auto stage64 = [&]() {
+#pragma unroll 8
+    for (int i = 0; i < 32; ++i) {
+      const float x = T[i * STR + c], y = T[(63 - i) * STR + c];
+      T[i * STR + c] = x + y;
+      T[(63 - i) * STR + c] = x - y;
+    }
+  };
+  if constexpr (!INV) stage64();
+  float col[32];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) col[i] = T[i * STR + c];
+  for (int i = 0; i < 32; ++i) col[i] = T[i * STR + c];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    const int R = INV ? (2 << t) : (64 >> t);
+  for (int t = 0; t < 5; ++t) {
+    const int R = INV ? (2 << t) : (32 >> t);
 #pragma unroll
     for (int i = 0; i < R / 2; ++i) {
       const float x = col[i], y = col[R - 1 - i];
@@ -168,7 +179,8 @@ __device__ __forceinline__ void halving_rows(float *T, int c) {
     }
   }
 #pragma unroll
-  for (int i = 0; i < 64; ++i) T[i * STR + c] = col[i];
+  for (int i = 0; i < 32; ++i) T[i * STR + c] = col[i];
+  if constexpr (INV) stage64();
 }
 
 // Tile pattern TP of the products' T x T grid of 16 x 16 tiles (T = NA / 16 or NB / 16):

@@ -368,6 +368,70 @@ std::vector<std::vector<int>> components(const Sub &H, double tol) {
   return out;
 }
 
+// Closed-form leaf bases (Sec. V-C): a leaf whose Laplacian is c I plus the Laplacian of a
+// path with one edge weight w > 0 has the DCT-II eigenbasis, node i of the path (from one
+// end) carrying sqrt((2 - [k = 0]) / b) cos(pi k (2i + 1) / (2b)) in eigenvector k, with
+// eigenvalue c + 2w (1 - cos(pi k / b)); with an extra self-loop 2w at one end (the leaf
+// on the difference side of a path's reversal, whose end next to the axis gains it) it is
+// DST-IV from that end: sqrt(2 / b) sin(pi (2i + 1)(2k + 1) / (4b)), eigenvalue
+// c + 2w (1 - cos(pi (2k + 1) / (2b))).  Entries are compared to `tol`.  Returns the kind
+// (1 DCT-II, 2 DST-IV) with the basis (V[j * b + k], j in the leaf's node order) and the
+// ascending eigenvalues, or 0.
+int closed_form_leaf(int b, const std::vector<double> &L, double tol, std::vector<double> &lambda,
+                     std::vector<double> &V) {
+  if (b < 2) return 0;
+  // path structure: every off-diagonal entry -w or 0, two ends of one neighbour
+  double w = 0.0;
+  std::vector<std::vector<int>> nb(b);
+  for (int i = 0; i < b; ++i)
+    for (int j = i + 1; j < b; ++j) {
+      const double v = L[(size_t)i * b + j];
+      if (std::fabs(v) <= tol) continue;
+      if (w == 0.0) w = -v;
+      if (!(w > tol) || std::fabs(v + w) > tol) return 0;
+      nb[i].push_back(j);
+      nb[j].push_back(i);
+    }
+  int end = -1;
+  for (int i = 0; i < b; ++i) {
+    if (nb[i].empty() || nb[i].size() > 2) return 0;
+    if (nb[i].size() == 1 && end < 0) end = i;
+  }
+  if (end < 0) return 0;   // a cycle
+  std::vector<int> order{end};
+  for (int prev = -1, cur = end; (int)order.size() < b;) {
+    int next = -1;
+    for (int x : nb[cur])
+      if (x != prev) next = x;
+    if (next < 0) return 0;   // not connected
+    order.push_back(next);
+    prev = cur;
+    cur = next;
+  }
+  auto d = [&](int i) { return L[(size_t)order[i] * b + order[i]]; };
+  // DST-IV from the end with the larger diagonal
+  if (d(b - 1) > d(0)) std::reverse(order.begin(), order.end());
+  const double c = d(b - 1) - w;   // the free end: w + c
+  bool uniform = true;
+  for (int i = 1; i + 1 < b; ++i) uniform &= std::fabs(d(i) - (2 * w + c)) <= tol;
+  if (!uniform) return 0;
+  int kind = 0;
+  if (std::fabs(d(0) - (w + c)) <= tol) kind = 1;
+  else if (std::fabs(d(0) - (3 * w + c)) <= tol) kind = 2;
+  if (!kind) return 0;
+  const double pi = 3.14159265358979323846;
+  lambda.assign(b, 0.0);
+  V.assign((size_t)b * b, 0.0);
+  for (int k = 0; k < b; ++k) {
+    lambda[k] = kind == 1 ? c + 2 * w * (1 - std::cos(pi * k / b)) : c + 2 * w * (1 - std::cos(pi * (2 * k + 1) / (2.0 * b)));
+    for (int i = 0; i < b; ++i)
+      V[(size_t)order[i] * b + k] =
+          kind == 1 ? std::sqrt((k == 0 ? 1.0 : 2.0) / b) * std::cos(pi * k * (2 * i + 1) / (2.0 * b))
+                    : std::sqrt(2.0 / b) * std::sin(pi * (2 * i + 1) * (2 * k + 1) / (4.0 * b));
+  }
+  return kind;
+}
+
 // A graph read as a row-major Cartesian product G_a x G_b (node (i, j) = i * nb + j): the
 // factors' edges, weights and self-loops, and the given stages sorted by axis.
 struct ProductSplit {
@@ -561,6 +625,7 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
   };
   std::vector<KronBlock> kron_blocks;
   bool all_kron = (bool)kfa;
+  int32_t num_closed = 0;   // leaves with a closed-form (DCT-II / DST-IV) basis
 
   std::vector<int32_t> owner(n, 0), local(n, 0);
   for (int32_t s = 0; s < num_stages; ++s) {
@@ -681,9 +746,13 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
           all_kron = false;
         }
       }
+      // a right Haar split is cheaper than any dense basis of the leaf (two-node leaves
+      // with a constant diagonal are both a uniform path and a right Haar unit: Sec. III)
       RightSplit rs;
       const bool right = !kron && opts.right_haar == GFT_RIGHT_HAAR_AUTO && right_split(b, Lb, tol, rs);
-      if (kron) {
+      const int closed = kron || right ? 0 : closed_form_leaf(b, Lb, tol, B.lambda, B.V);
+      if (closed) ++num_closed;
+      if (kron || closed) {
         // basis set above; checked below like any leaf basis
       } else if (right) {
         B.lambda = rs.lamU;
@@ -812,6 +881,7 @@ GraphPlan build_graph_plan(const gft_graph &g, const gft_pairing *pairing,
   st.max_residual = max_res;
   st.max_orth_error = max_orth;
   st.num_kron_leaves = 0;
+  st.num_closed_form_leaves = num_closed;
   st.separable_mults = st.mults;
   if (all_kron && kron_blocks.size() == plan.blocks.size()) {
     // coefficient (block b, local k) is factor coefficient pair (p, q): the factors'

@@ -429,3 +429,31 @@ def test_stream_copy_argument_checks_launch_nothing():
         st = lib.gft_stream_copy(V(a), V(b), nb, V(0))
         assert G.STATUS[st] == want, (a, b, nb, G.STATUS[st])
     assert lib.gft_stream_copy(V(4096), V(8192), 0, V(0)) == 0
+
+
+def test_closed_form_leaves_are_dct2_and_dst4():
+    """Leaves that are uniform paths (plus a constant self-loop) take the DCT-II basis in
+    closed form, those with an extra self-loop 2w at one end DST-IV, instead of an
+    eigensolve (Sec. V-C).  Pinned by the oracle's closed forms: the 8-node path with its
+    reversal stage (leaves DCT-II(4) and DST-IV(4)) has the DCT-II(8) basis up to sign; a
+    6-node path of weight 0.3 with self-loops 0.7 everywhere has the DCT-II(6) basis and the
+    eigenvalues 0.7 + 0.3 (2 - 2 cos(pi k / 6)); weighted or odd-length leaves (a V_Z node
+    scales edges by sqrt 2) keep the eigensolver."""
+    plan = G.Plan.from_graph(wl.config1_graph())
+    assert plan.info()["num_closed_form_leaves"] == 2
+    U = plan.basis()
+    np.testing.assert_allclose(np.abs(U.T @ O.dct2_matrix(8)), np.eye(8), atol=1e-14)
+    np.testing.assert_allclose(plan.eigenvalues(), O.path_eigenvalues(8), atol=1e-14)
+    g = wl.path(6, weights=[0.3] * 5)
+    p = G.gft_plan(6, g.src, g.dst, g.weight, np.full(6, 0.7))
+    assert p.info()["num_closed_form_leaves"] == 1
+    np.testing.assert_allclose(p.eigenvalues(), 0.7 + 0.3 * O.path_eigenvalues(6), atol=1e-14)
+    np.testing.assert_allclose(np.abs(p.basis().T @ O.dct2_matrix(6)), np.eye(6), atol=1e-14)
+    # the halving recursion of a 64-path: every leaf of two or more nodes is DST-IV
+    pr = G.Plan.from_graph(wl.path_recursive(64))
+    assert pr.info()["num_closed_form_leaves"] == 5
+    lam, U64 = O.gft(O.laplacian_of(wl.path_recursive(64)))
+    Ua, sv = O.align(U64, pr.basis(), lam)
+    assert sv > 1 - 1e-12 and np.abs(pr.basis() - Ua).max() <= 1e-12
+    assert G.Plan.from_graph(wl.path(9)).info()["num_closed_form_leaves"] == 0
+    assert G.Plan.from_graph(wl.config5b_graph()).info()["num_closed_form_leaves"] == 0
