@@ -150,7 +150,8 @@ typedef enum {
                               /* stream order) of S*w floats (2*S*w when the last pass   */
                               /* has Haar stages or there are more than 8 leaf blocks),  */
                               /* w = n plus each leaf block padded to                    */
-                              /* a multiple of 8; FP16 is unsupported                    */
+                              /* a multiple of 8 (the workspace stays FP32 or BF16 with  */
+                              /* BF16 blocks whatever the storage); FP16 is unsupported  */
   GFT_ENGINE_PRODUCT = 4      /* separable engine: U_a^T X U_b per signal on MFMA.  The  */
                               /* engine of product-graph plans (gft_plan_product); as   */
                               /* options.engine it runs a gft_plan whose leaves have    */
@@ -169,9 +170,11 @@ typedef struct {
   int32_t in_dtype;        /* gft_dtype of signals x: read by the forward, written by */
                            /* the inverse                                             */
   int32_t out_dtype;       /* gft_dtype of coefficients y: written by the forward,    */
-                           /* read by the inverse.  BF16 storage runs on the          */
-                           /* butterfly and generic engines of single-graph plans     */
-                           /* (else GFT_ERR_UNSUPPORTED); in place needs equal types  */
+                           /* read by the inverse.  BF16 storage runs on every engine:*/
+                           /* any combination on the butterfly, generic and large     */
+                           /* engines; product and batch plans store signals and      */
+                           /* coefficients in one type (else GFT_ERR_UNSUPPORTED at   */
+                           /* planning); in place needs equal types                   */
   int32_t laplacian;       /* gft_laplacian                                           */
   int32_t right_haar;      /* gft_right_haar                                          */
   int32_t autotune;        /* gft_autotune: launch choices timed at preparation (0,  */

@@ -226,10 +226,10 @@ class Plan:
 
     @classmethod
     def from_product(cls, graph_a, graph_b, precision="fp32", order=ORDER_EIGENVALUE, sym_tol=0.0,
-                     right_haar=True, autotune=True):
+                     right_haar=True, autotune=True, in_dtype="fp32", out_dtype="fp32"):
         """Plan the Cartesian product of two graphs (node (i, j) = i * graph_b.n + j)."""
         return gft_plan_product(graph_a, graph_b, order=order, sym_tol=sym_tol, right_haar=right_haar,
-                                precision=precision, autotune=autotune)
+                                precision=precision, autotune=autotune, in_dtype=in_dtype, out_dtype=out_dtype)
 
     @property
     def n(self) -> int:
@@ -331,7 +331,8 @@ def gft_plan(n, src, dst, weight, self_loop=None, stages=None, precision="fp32",
 
 
 def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, right_haar=True,
-                     precision="fp32", laplacian="combinatorial", engine="auto", autotune=True) -> Plan:
+                     precision="fp32", laplacian="combinatorial", engine="auto", autotune=True,
+                     in_dtype="fp32", out_dtype="fp32") -> Plan:
     """Plan the GFT of the Cartesian product of two graphs (C: ``gft_plan_product``): each
     argument is an object with n, src, dst, weight, self_loop, stages."""
     lib = load_library()
@@ -341,11 +342,12 @@ def gft_plan_product(graph_a, graph_b, order=ORDER_EIGENVALUE, sym_tol=0.0, righ
     gb = _graph_struct(graph_b.n, graph_b.src, graph_b.dst, graph_b.weight, graph_b.self_loop, keep)
     pb = _pairing_struct(graph_b.n, graph_b.stages, keep)
     o = _options(precision=precision, order=order, sym_tol=sym_tol, engine=engine,
-                 laplacian=laplacian, right_haar=right_haar, autotune=autotune)
+                 laplacian=laplacian, right_haar=right_haar, autotune=autotune, in_dtype=in_dtype,
+                 out_dtype=out_dtype)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_product(ctypes.byref(ga), ctypes.byref(pa), ctypes.byref(gb), ctypes.byref(pb),
                                 ctypes.byref(o), ctypes.byref(h)))
-    return Plan(h.value, [int(graph_a.n) * int(graph_b.n)], False, precision, "fp32", "fp32")
+    return Plan(h.value, [int(graph_a.n) * int(graph_b.n)], False, precision, in_dtype, out_dtype)
 
 
 def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_steps=0,
@@ -366,7 +368,8 @@ def gft_find_pairing(n, src, dst, weight, self_loop=None, max_stages=16, max_ste
 def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, tile=0,
                    sym_tol=0.0, engine="auto", in_dtype="fp32", out_dtype="fp32",
                    laplacian="combinatorial", right_haar=True, autotune=True) -> Plan:
-    """Plan several graphs for one persistent launch (C: ``gft_plan_batch``; FP32 storage)."""
+    """Plan several graphs for one persistent launch (C: ``gft_plan_batch``); signals and
+    coefficients share one storage type, ``in_dtype`` = ``out_dtype`` ("fp32" or "bf16")."""
     lib = load_library()
     keep = []
     G = (_Graph * len(graphs))()
@@ -377,7 +380,7 @@ def gft_plan_batch(graphs: Sequence, precision="fp32", order=ORDER_EIGENVALUE, t
     o = _options(precision, order, tile, sym_tol, engine, in_dtype, out_dtype, laplacian, right_haar, autotune)
     h = ctypes.c_void_p()
     _check(lib.gft_plan_batch(len(graphs), G, Pr, ctypes.byref(o), ctypes.byref(h)))
-    return Plan(h.value, [int(g.n) for g in graphs], True, precision)
+    return Plan(h.value, [int(g.n) for g in graphs], True, precision, in_dtype, out_dtype)
 
 
 def _torch_dtype(name):
@@ -463,8 +466,9 @@ def _apply_batch(fn_name, plan: Plan, x, signal_offsets, out, stream):
     import torch
     if not plan.batch:
         raise ValueError("single-graph plans use gft_forward / gft_inverse")
-    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
-        raise TypeError("x must be a contiguous float32 CUDA tensor")
+    dt = _torch_dtype(plan.in_dtype)
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous()):
+        raise TypeError(f"x must be a contiguous {dt} CUDA tensor")
     if not (isinstance(signal_offsets, torch.Tensor) and signal_offsets.is_cuda
             and signal_offsets.dtype == torch.int64 and signal_offsets.numel() == len(plan.sizes) + 1):
         raise TypeError("signal_offsets must be an int64 CUDA tensor of num_graphs + 1 entries")
@@ -472,9 +476,8 @@ def _apply_batch(fn_name, plan: Plan, x, signal_offsets, out, stream):
         raise ValueError("signal_offsets must be on the device of x")
     if out is None:
         out = torch.empty_like(x)
-    elif not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float32
-              and out.is_contiguous()):
-        raise TypeError("out must be a contiguous float32 CUDA tensor")
+    elif not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == dt and out.is_contiguous()):
+        raise TypeError(f"out must be a contiguous {dt} CUDA tensor")
     elif out.device != x.device or out.numel() != x.numel():
         raise ValueError("out must be on the device of x and hold as many values as x")
     _check(getattr(load_library(), fn_name)(plan.handle, ctypes.c_void_p(x.data_ptr()),

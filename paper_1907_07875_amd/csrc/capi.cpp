@@ -378,7 +378,8 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
   // FP32 products are MFMA-bound in the dense form (0.70 ms on the 64 x 64 grid against
   // 0.49 ms staged); BF16 and split BF16 are bound by memory and conversions and gain
   // nothing from the staged form (measured 0.43 vs 0.45 ms, 0.54 vs 0.56 ms)
-  const bool compiled = halving_factor(*F.fa, sa.Q) && halving_factor(*F.fb, sb.Q);
+  const bool io16 = plan->opts.in_dtype == GFT_DTYPE_BF16;   // both BF16 (checked at planning)
+  const bool compiled = !io16 && halving_factor(*F.fa, sa.Q) && halving_factor(*F.fb, sb.Q);
   bool staged = compiled && plan->opts.precision == GFT_FP32;
   if (const char *f = std::getenv("GFT_PRODUCT_FORM")) {
     if (!std::strcmp(f, "dense")) staged = false;
@@ -429,7 +430,7 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
     P.amat = reinterpret_cast<const float *>(base + off[d][0]);
     P.bmat = reinterpret_cast<const float *>(base + off[d][1]);
     P.perm = reinterpret_cast<const uint16_t *>(base + off[d][2]);
-    P.tile_pattern = staged ? 1 : 0;
+    P.tile_pattern = io16 ? 2 : (staged ? 1 : 0);
   }
   img->product = true;
   img->key = tune_key(dev, 'P', plan->opts, blob.bytes, {na, nb, staged ? 1 : 0});
@@ -461,15 +462,18 @@ hipError_t launch_large(const gft_plan_s *plan, const DeviceImage *img, int dir,
   const LargeImage &L = img->lg[dir];
   float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
   const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
-  hipError_t e = launch_permute_stages(L.pass[0], static_cast<const float *>(in), W1, ws16, S, img->num_cus, st,
-                                       tile_kb);
+  // storage: the forward reads signals (in_dtype) and writes coefficients (out_dtype)
+  const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
+  const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
+  hipError_t e = launch_permute_stages(L.pass[0], in, in16, W1, ws16, S, img->num_cus, st, tile_kb);
   if (e == hipSuccess)
     e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
                           (int)L.blocks.size(), ws16 ? (const void *)L.dev_mats16 : (const void *)L.dev_mats,
-                          W1, fused ? static_cast<float *>(out) : W2, S, L.ldw,
+                          W1, fused ? out : (void *)W2, fused && out16, S, L.ldw,
                           block_gemm_grid(L.block_sizes.data(), (int)L.blocks.size(), S),
                           fused ? L.dev_omap : nullptr, L.n, st);
-  if (e == hipSuccess && !fused) e = launch_permute_stages(L.pass[1], W2, out, false, S, img->num_cus, st, tile_kb);
+  if (e == hipSuccess && !fused)
+    e = launch_permute_stages(L.pass[1], W2, false, out, out16, S, img->num_cus, st, tile_kb);
   return e;
 }
 
@@ -549,7 +553,8 @@ bool tune_batch(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice
       cand.push_back({r, c});
     }
   const int pick = time_candidates((int)cand.size(), base, [&](int c, hipStream_t st) {
-    return launch_apply_batch(plan->opts.precision, 0, img->dev_fwd, img->dev_ufwd, G, doff, E, in, outp,
+    return launch_apply_batch(plan->opts.precision, 0, plan->opts.in_dtype == GFT_DTYPE_BF16, img->dev_fwd,
+                              img->dev_ufwd, G, doff, E, in, outp,
                               img->batch_lds, cand[c].rounds * img->num_cus * img->batch_occ, img->reg_groups,
                               cand[c].cost16, st);
   }, ts.st);
@@ -738,8 +743,6 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                  (!fits || plan->graphs[0].stats.max_block >= 192));
     if (use_large && plan->opts.precision == GFT_FP16)
       return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine runs FP32, BF16 or split BF16 blocks");
-    if (use_large && (plan->opts.in_dtype != GFT_DTYPE_FP32 || plan->opts.out_dtype != GFT_DTYPE_FP32))
-      return set_error(GFT_ERR_UNSUPPORTED, "the large-signal engine reads and writes FP32 storage only");
   }
   if (plan->opts.engine == GFT_ENGINE_LARGE && plan->batch)
     return set_error(GFT_ERR_UNSUPPORTED, "batch plans run the generic engine");
@@ -747,14 +750,15 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   // Separable engine for plans whose leaf blocks all have Kronecker bases (Sec. V-D): in
   // place of the large engine, or when asked for.
   const KronPlan *K = plan->batch ? nullptr : plan->graphs[0].kron.get();
-  const bool sep_ok = K && prec != GFT_FP16 && plan->opts.in_dtype == GFT_DTYPE_FP32 &&
-                      plan->opts.out_dtype == GFT_DTYPE_FP32 && product_pad(K->na) && product_pad(K->nb);
+  const bool sep_ok = K && prec != GFT_FP16 && plan->opts.in_dtype == plan->opts.out_dtype &&
+                      product_pad(K->na) && product_pad(K->nb);
   if (plan->opts.engine == GFT_ENGINE_PRODUCT || (plan->opts.engine == GFT_ENGINE_AUTO && use_large && sep_ok)) {
     if (!sep_ok)
       return set_error(GFT_ERR_UNSUPPORTED,
                        "the separable engine runs single-graph plans whose leaf blocks have Kronecker "
                        "bases (a row-major Cartesian product with stages along the axes, factors of at "
-                       "most 64 nodes), FP32 storage and FP32, BF16 or split BF16 blocks");
+                       "most 64 nodes), one storage type for signals and coefficients and FP32, BF16 or "
+                       "split BF16 blocks");
     const Factors F{K->na, K->nb, K->fa.get(), K->fb.get(), &plan->kua, &plan->kub, &K->order};
     return product_image(plan, F, dev, out);
   }
@@ -931,7 +935,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       img->dev_uinv = img->dev_ufwd + G;
     }
     img->batch_lds = batch_lds_bytes(G, maxlds, any_reg);
-    img->batch_occ = batch_occupancy(plan->opts.precision, img->batch_lds);
+    img->batch_occ = batch_occupancy(plan->opts.precision, img->batch_lds, plan->opts.in_dtype == GFT_DTYPE_BF16);
     // built-in: two rounds of resident workgroups (the hardware hands the second round's
     // byte-equal shares of the LDS-program graphs to CUs as they free up, which evens out
     // graphs of different cost per byte, while each share stays long enough to amortise
@@ -1166,8 +1170,8 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs, const gft
   const gft_options o = default_options(opts);
   gft_status st = check_options(o);
   if (st != GFT_OK) return st;
-  if (o.in_dtype != GFT_DTYPE_FP32 || o.out_dtype != GFT_DTYPE_FP32)
-    return set_error(GFT_ERR_UNSUPPORTED, "batch plans read and write FP32 storage only");
+  if (o.in_dtype != o.out_dtype)
+    return set_error(GFT_ERR_UNSUPPORTED, "batch plans store signals and coefficients in one type (FP32 or BF16)");
   try {
     auto p = std::make_unique<gft_plan_s>();
     p->opts = o;
@@ -1197,8 +1201,8 @@ gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing
   if (st != GFT_OK) return st;
   if (o.precision != GFT_FP32 && o.precision != GFT_BF16 && o.precision != GFT_SPLIT_BF16)
     return set_error(GFT_ERR_UNSUPPORTED, "product plans run FP32, BF16 or split BF16 factor products");
-  if (o.in_dtype != GFT_DTYPE_FP32 || o.out_dtype != GFT_DTYPE_FP32)
-    return set_error(GFT_ERR_UNSUPPORTED, "product plans read and write FP32 storage");
+  if (o.in_dtype != o.out_dtype)
+    return set_error(GFT_ERR_UNSUPPORTED, "product plans store signals and coefficients in one type (FP32 or BF16)");
   if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL)
     return set_error(GFT_ERR_UNSUPPORTED,
                      "the normalized Laplacian of a product graph is not a Kronecker sum");
@@ -1268,15 +1272,16 @@ static gft_status apply_batch(gft_plan_t plan, int dir, const void *in, void *ou
   if (total_elements == 0) return ok();
   if (!signal_offsets) return set_error(GFT_ERR_INVALID_ARG, "signal_offsets is NULL");
   if (total_elements > (int64_t(1) << 40)) return set_error(GFT_ERR_INVALID_ARG, "total_elements too large");
-  gft_status st = check_buffers(in, total_elements * 4, out, total_elements * 4, true);
+  const bool io16 = plan->opts.in_dtype == GFT_DTYPE_BF16;   // signals and coefficients alike
+  const int64_t esz = io16 ? 2 : 4;
+  gft_status st = check_buffers(in, total_elements * esz, out, total_elements * esz, true);
   if (st != GFT_OK) return st;
   DeviceImage *img = nullptr;
   st = device_image(plan, &img);
   if (st != GFT_OK) return st;
-  hipError_t e = launch_apply_batch(plan->opts.precision, dir, dir == 0 ? img->dev_fwd : img->dev_inv,
+  hipError_t e = launch_apply_batch(plan->opts.precision, dir, io16, dir == 0 ? img->dev_fwd : img->dev_inv,
                                     dir == 0 ? img->dev_ufwd : img->dev_uinv,
-                                    (int)plan->graphs.size(), signal_offsets, total_elements,
-                                    static_cast<const float *>(in), static_cast<float *>(out),
+                                    (int)plan->graphs.size(), signal_offsets, total_elements, in, out,
                                     img->batch_lds, img->batch_rounds * img->num_cus * img->batch_occ,
                                     img->reg_groups, img->batch_cost16,
                                     static_cast<hipStream_t>(stream));

@@ -46,9 +46,11 @@ __device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, 
 // the tile by one thread (the ops of a stage are disjoint), and the store gathers each
 // output column from its tile column, threads owning columns (float4 stores when out_cols
 // is a multiple of 4) so each index-table entry is read once per tile.  OUT16: the output
-// is rounded to BF16 (round to nearest even), the workspace of BF16 leaf blocks.
-template <bool OUT16>
-__global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const float *in,
+// is rounded to BF16 (round to nearest even): the workspace of BF16 leaf blocks, or BF16
+// storage of the result.  IN16: the input rows hold BF16 values (BF16 storage), widened
+// exactly into the FP32 tile.
+template <bool IN16, bool OUT16>
+__global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const void *in_raw,
                                                                void *out_raw, int64_t S,
                                                                int rows) {
   extern __shared__ __attribute__((aligned(16))) float tile[];
@@ -59,8 +61,25 @@ __global__ __launch_bounds__(kThreads) void gft_permute_stages(PermPass P, const
     const int64_t r0 = t * rows;
     const int nr = (int)((S - r0) < rows ? (S - r0) : rows);
     // load
-    const float *src = in + r0 * ic;
-    if ((ic & 3) == 0) {
+    const float *src = static_cast<const float *>(in_raw) + r0 * ic;
+    if constexpr (IN16) {
+      const uint16_t *s16 = static_cast<const uint16_t *>(in_raw) + r0 * ic;
+      if ((ic & 7) == 0) {
+        const int tot = nr * (ic >> 3);
+        const u32x4 *s8 = reinterpret_cast<const u32x4 *>(s16);
+        for (int e = tid; e < tot; e += kThreads) {
+          const u32x4 w = __builtin_nontemporal_load(s8 + e);
+          floatx4 *t4 = reinterpret_cast<floatx4 *>(tile + 8 * e);
+          t4[0] = floatx4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                          __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+          t4[1] = floatx4{__uint_as_float(w[2] << 16), __uint_as_float(w[2] & 0xffff0000u),
+                          __uint_as_float(w[3] << 16), __uint_as_float(w[3] & 0xffff0000u)};
+        }
+      } else {
+        const int tot = nr * ic;
+        for (int e = tid; e < tot; e += kThreads) tile[e] = __uint_as_float((uint32_t)s16[e] << 16);
+      }
+    } else if ((ic & 3) == 0) {
       const int tot = nr * (ic >> 2);
       const floatx4 *s4 = reinterpret_cast<const floatx4 *>(src);
       floatx4 *t4 = reinterpret_cast<floatx4 *>(tile);
@@ -167,10 +186,10 @@ template <int PREC, int BK_> struct GemmCfg {
   static constexpr int lds_bytes = 2 * buf_bytes;           // double buffered
 };
 
-template <int PREC, int BK>
+template <int PREC, int BK, bool OUT16>
 __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restrict__ blocks,
                                                            int nblocks, const void *mats_raw,
-                                                           const void *A_raw, float *C, int64_t S,
+                                                           const void *A_raw, void *C_raw, int64_t S,
                                                            int ld, const int32_t *omap, int ldy) {
   using Cfg = GemmCfg<PREC, BK>;
   constexpr int kRowBytes = Cfg::row_bytes;
@@ -348,7 +367,9 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
   }
   // epilogue: lane (g, r) holds rows 4g + v, column r of each 16x16 tile; column c goes to
   // the workspace (C, row stride ld) or, with omap, to output position omap[blk.omap + c]
-  // of the final array (C, row stride ldy)
+  // of the final array (C, row stride ldy; OUT16: BF16 storage, rounded to nearest even)
+  float *C = static_cast<float *>(C_raw);
+  uint16_t *C16 = static_cast<uint16_t *>(C_raw);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = col0 + wn * 64 + 16 * j + r;
@@ -360,7 +381,10 @@ __global__ __launch_bounds__(kThreads) void gft_block_gemm(const LBlock *__restr
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + wm * 64 + 16 * i + 4 * g + v;
-        if (row < S) C[row * dld + dcol] = acc[i][j][v];
+        if (row < S) {
+          if constexpr (OUT16) C16[row * dld + dcol] = (uint16_t)bf16_bits(acc[i][j][v]);
+          else C[row * dld + dcol] = acc[i][j][v];
+        }
       }
   }
 }
@@ -407,25 +431,31 @@ int permute_rows(const PermPass &P, int tile_kb) {
   return rows < 1 ? 1 : (rows > 16 ? 16 : rows);
 }
 
-hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
-                                 int64_t S, int num_cus, hipStream_t stream, int tile_kb) {
+template <bool IN16, bool OUT16>
+static hipError_t launch_perm_io(const PermPass &P, const void *in, void *out, int64_t S, int num_cus,
+                                 hipStream_t stream, int tile_kb) {
   const int rows = permute_rows(P, tile_kb);
   const size_t lds = (size_t)rows * P.in_cols * 4;
-  const void *fn = out16 ? (const void *)gft_permute_stages<true> : (const void *)gft_permute_stages<false>;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)gft_permute_stages<IN16, OUT16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const int64_t tiles = (S + rows - 1) / rows;
   const int64_t cap = (int64_t)num_cus * 8;
   const int grid = (int)(tiles < cap ? tiles : cap);
-  if (out16)
-    hipLaunchKernelGGL(gft_permute_stages<true>, dim3(grid), dim3(kThreads), lds, stream, P, in,
-                       out, S, rows);
-  else
-    hipLaunchKernelGGL(gft_permute_stages<false>, dim3(grid), dim3(kThreads), lds, stream, P, in,
-                       out, S, rows);
+  hipLaunchKernelGGL((gft_permute_stages<IN16, OUT16>), dim3(grid), dim3(kThreads), lds, stream, P, in,
+                     out, S, rows);
   return hipGetLastError();
+}
+
+hipError_t launch_permute_stages(const PermPass &P, const void *in, bool in16, void *out, bool out16,
+                                 int64_t S, int num_cus, hipStream_t stream, int tile_kb) {
+  if (in16)
+    return out16 ? launch_perm_io<true, true>(P, in, out, S, num_cus, stream, tile_kb)
+                 : launch_perm_io<true, false>(P, in, out, S, num_cus, stream, tile_kb);
+  return out16 ? launch_perm_io<false, true>(P, in, out, S, num_cus, stream, tile_kb)
+               : launch_perm_io<false, false>(P, in, out, S, num_cus, stream, tile_kb);
 }
 
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S) {
@@ -435,30 +465,37 @@ int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S) {
   return tiles;
 }
 
-template <int PREC, int BK>
+template <int PREC, int BK, bool OUT16>
 static hipError_t launch_gemm_prec(const LBlock *blocks, int nblocks, const void *mats,
-                                   const void *A, float *C, int64_t S, int ld, int64_t grid,
+                                   const void *A, void *C, int64_t S, int ld, int64_t grid,
                                    const int32_t *omap, int ldy, hipStream_t stream) {
   const int lds = GemmCfg<PREC, BK>::lds_bytes;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)gft_block_gemm<PREC, BK>,
+    hipError_t e = hipFuncSetAttribute((const void *)gft_block_gemm<PREC, BK, OUT16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((gft_block_gemm<PREC, BK>), dim3((unsigned)grid), dim3(kThreads), lds, stream,
+  hipLaunchKernelGGL((gft_block_gemm<PREC, BK, OUT16>), dim3((unsigned)grid), dim3(kThreads), lds, stream,
                      blocks, nblocks, mats, A, C, S, ld, omap, ldy);
   return hipGetLastError();
 }
 
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
-                             const void *A, float *C, int64_t S, int ld, int64_t grid,
+                             const void *A, void *C, bool out16, int64_t S, int ld, int64_t grid,
                              const int32_t *omap, int ldy, hipStream_t stream) {
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  if (out16 && !omap) return hipErrorInvalidValue;   // the workspace stays FP32
+  if (out16) switch (prec) {
+      case 0: return launch_gemm_prec<0, 16, true>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+      case 1: return launch_gemm_prec<1, 32, true>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+      case 3: return launch_gemm_prec<3, 32, true>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+      default: return hipErrorInvalidValue;
+    }
   switch (prec) {
-    case 0: return launch_gemm_prec<0, 16>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
-    case 1: return launch_gemm_prec<1, 32>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
-    case 3: return launch_gemm_prec<3, 32>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+    case 0: return launch_gemm_prec<0, 16, false>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+    case 1: return launch_gemm_prec<1, 32, false>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
+    case 3: return launch_gemm_prec<3, 32, false>(blocks, nblocks, mats, A, C, S, ld, grid, omap, ldy, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -20,26 +20,34 @@ int apply_occupancy(const DevProgram &P);
 // register-butterfly program (device array `uprogs`, entry S = 0 for the others; or null)
 // run on the first reg_groups workgroups' waves, the rest on the LDS programs.
 size_t batch_lds_bytes(int G, size_t max_program_lds, bool reg_phase);
-int batch_occupancy(int prec, size_t lds);
+int batch_occupancy(int prec, size_t lds, bool io16);
+// BF16 storage (gft_batch16.hip).
+int batch_occupancy_io16(int prec, size_t lds);
+hipError_t launch_apply_batch_io16(int prec, int dir, const DevProgram *progs, const UProgram *uprogs, int G,
+                                   const int64_t *sig_off, int64_t total_elems, const void *in, void *out,
+                                   size_t lds, int grid, int reg_groups, int cost16, hipStream_t stream);
 bool batch_butterfly_supported(int prec, const UProgram &U);
-// cost16: register-phase fixed cost per signal in sixteenths of the padded slot count.
-hipError_t launch_apply_batch(int prec, int dir, const DevProgram *progs, const UProgram *uprogs,
-                              int G, const int64_t *sig_off, int64_t total_elems, const float *in,
-                              float *out, size_t lds, int grid, int reg_groups, int cost16,
+// cost16: register-phase fixed cost per signal in sixteenths of the padded slot count;
+// io16: signals and coefficients stored in BF16 (else FP32).
+hipError_t launch_apply_batch(int prec, int dir, bool io16, const DevProgram *progs, const UProgram *uprogs,
+                              int G, const int64_t *sig_off, int64_t total_elems, const void *in,
+                              void *out, size_t lds, int grid, int reg_groups, int cost16,
                               hipStream_t stream);
 
 // Large-signal engine.
 // Signal rows per LDS tile of a stage/gather pass: as many as fill about tile_kb KB (0: the
 // built-in 40 KB), 1 to 16.
 int permute_rows(const PermPass &P, int tile_kb = 0);
-hipError_t launch_permute_stages(const PermPass &P, const float *in, void *out, bool out16,
+// in16 / out16: BF16 input rows / BF16 output rows (else FP32).
+hipError_t launch_permute_stages(const PermPass &P, const void *in, bool in16, void *out, bool out16,
                                  int64_t S, int num_cus, hipStream_t stream, int tile_kb = 0);
 int64_t block_gemm_grid(const int32_t *sizes, int nblocks, int64_t S);
 // prec: 0 FP32, 1 BF16 (A and matrices stored in BF16), 3 split BF16 (FP32 storage)
 // omap non-null: column c of block b is written to column omap[b.omap + c] of C (row
-// stride ldy) instead of the workspace (the output permutation fused into the epilogue).
+// stride ldy) instead of the workspace (the output permutation fused into the epilogue);
+// out16 (with omap only): C holds BF16 values.
 hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const void *mats,
-                             const void *A, float *C, int64_t S, int ld, int64_t grid,
+                             const void *A, void *C, bool out16, int64_t S, int ld, int64_t grid,
                              const int32_t *omap, int ldy, hipStream_t stream);
 
 // Static scratch of the allocation-free apply: kScratchBytes per GPU, in the code object.
@@ -63,6 +71,10 @@ int product_pad(int n);
 hipError_t launch_product(const PProgram &P, const float *in, float *out, int64_t nsig,
                           hipStream_t stream, int num_cus, int grid_cap = 0);
 int product_occupancy(const PProgram &P);   // resident workgroups per CU
+// BF16 storage (tile_pattern 2), gft_product16.hip.
+hipError_t launch_product_io16(const PProgram &P, const void *in, void *out, int64_t nsig,
+                               hipStream_t stream, int num_cus, int grid_cap);
+int product_occupancy_io16(const PProgram &P);
 
 // Streaming copy of `bytes` (a multiple of 16) between 16-byte aligned, non-overlapping
 // device buffers (gft_copy.hip).

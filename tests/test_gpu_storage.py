@@ -100,9 +100,87 @@ def test_in_place_rules():
     assert G.STATUS.get(st) == "GFT_ERR_ALIGNMENT"
 
 
-def test_large_engine_rejects_bf16_storage():
-    device()
-    plan = G.Plan.from_graph(wl.path(64), engine="large", in_dtype="bf16")
+@pytest.mark.parametrize("din,dout", COMBOS)
+@pytest.mark.parametrize("which", ["wpath1024", "grid64_large"])
+def test_large_engine_storage(which, din, dout):
+    """The large engine with BF16 storage: the stage pass widens BF16 rows exactly, and the
+    GEMM epilogue (forward, output order written by the GEMM) or the last stage pass rounds
+    to BF16; bit-equal to the FP32-storage plan rounded, and within the oracle bound."""
+    dev = device()
+    g = wl.config5b_graph() if which == "wpath1024" else wl.grid_recursive(16)
+    plan = G.Plan.from_graph(g, engine="large", in_dtype=din, out_dtype=dout)
+    ref = G.Plan.from_graph(g, engine="large")
+    assert plan.engine() == "large"
+    X = wl.gaussian(301, g.n, wl.rng_for(5, g.n, 41))
+    x = _signals(X, din, dev)
+    y = plan.forward(x)
+    assert y.dtype == TD[dout]
+    assert torch.equal(y, ref.forward(x.float()).to(TD[dout]))
+    xr = plan.inverse(y)
+    assert xr.dtype == TD[din]
+    assert torch.equal(xr, ref.inverse(y.float()).to(TD[din]))
+    _, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-9)
+    assert O.relative_error(to_np(y), O.forward(to_np(x), Ua)) <= TOL_OUT[dout]
+    assert O.relative_error(to_np(xr), O.inverse(to_np(y), Ua)) <= TOL_OUT[din]
+
+
+@pytest.mark.parametrize("pair", [(wl.path(8), wl.path(8)), (wl.path(6), wl.path(5)), (wl.path(40), wl.path(24)),
+                                  (wl.path_recursive(64), wl.path_recursive(64))],
+                         ids=lambda p: f"{p[0].name}{p[0].n}x{p[1].name}{p[1].n}")
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_product_engine_bf16_storage(pair, precision, monkeypatch):
+    """Product plans with BF16 signals and coefficients (dense factors; n = 30 takes the
+    scalar path): bit-equal to the FP32-storage plan of the same form rounded, within the
+    oracle bound; mixed storage types are refused."""
+    monkeypatch.setenv("GFT_PRODUCT_FORM", "dense")
+    dev = device()
+    ga, gb = pair
+    plan = G.Plan.from_product(ga, gb, precision=precision, in_dtype="bf16", out_dtype="bf16")
+    ref = G.Plan.from_product(ga, gb, precision=precision)
+    g = wl.cartesian_product(ga, gb)
+    X = wl.gaussian(333, g.n, wl.rng_for(5, g.n, 43))
+    x = _signals(X, "bf16", dev)
+    y = plan.forward(x)
+    assert y.dtype == torch.bfloat16
+    assert torch.equal(y, ref.forward(x.float()).to(torch.bfloat16))
+    xr = plan.inverse(y)
+    assert torch.equal(xr, ref.inverse(y.float()).to(torch.bfloat16))
+    _, Ua = aligned_oracle_basis(g, plan.basis(), sv_tol=1e-8)
+    tol = TOL_OUT["bf16"] if precision == "fp32" else 2e-2
+    assert O.relative_error(to_np(y), O.forward(to_np(x), Ua)) <= tol
     with pytest.raises(G.GFTError) as e:
-        plan.prepare()
+        G.Plan.from_product(ga, gb, in_dtype="bf16", out_dtype="fp32")
     assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batch_bf16_storage(precision):
+    """A mixed batch with BF16 signals and coefficients (register phase and LDS programs):
+    bit-equal to the FP32-storage batch rounded, every graph within the oracle bound."""
+    dev = device()
+    rng = wl.rng_for(4, 21)
+    graphs = [wl.path(7), wl.grid(8, 8), wl.config3_graph(), wl.cycle(40), wl.symmetric_bipartite(120, wl.rng_for(4, 120)),
+              wl.grid(12, 12), wl.path(64), wl.grid(5, 5), wl.path(90)]
+    counts = np.array([300, 2000, 900, 1, 70, 500, 1200, 33, 250])
+    xs = [wl.gaussian(int(c), g.n, rng) for g, c in zip(graphs, counts)]
+    flat = np.concatenate([a.reshape(-1) for a in xs])
+    offs = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).to(dev)
+    plan = G.gft_plan_batch(graphs, precision=precision, in_dtype="bf16", out_dtype="bf16")
+    ref = G.gft_plan_batch(graphs, precision=precision)
+    x = _signals(flat, "bf16", dev)
+    y = G.gft_forward_batch(plan, x, offs)
+    assert y.dtype == torch.bfloat16
+    assert torch.equal(y, G.gft_forward_batch(ref, x.float(), offs).to(torch.bfloat16))
+    xr = G.gft_inverse_batch(plan, y, offs)
+    assert torch.equal(xr, G.gft_inverse_batch(ref, y.float(), offs).to(torch.bfloat16))
+    yn, xn = to_np(y), to_np(x)
+    pos = 0
+    tol = TOL_OUT["bf16"] if precision == "fp32" else 2e-2
+    for i, (g, c) in enumerate(zip(graphs, counts)):
+        a, b = pos, pos + int(c) * g.n
+        pos = b
+        _, Ua = aligned_oracle_basis(g, plan.basis(i), sv_tol=1e-9)
+        err = O.relative_error(yn[a:b].reshape(-1, g.n), O.forward(xn[a:b].reshape(-1, g.n), Ua))
+        assert err <= tol, f"graph {i} ({g.name}{g.n}): {err:.3e}"
+    with pytest.raises(TypeError):
+        G.gft_forward_batch(plan, x.float(), offs)
