@@ -283,8 +283,11 @@ gft_status gft_plan_batch(int32_t num_graphs, const gft_graph *graphs,
  * add/sub on the signal and the leaf blocks (32, 16, 8, 4, 2, 1, 1 nodes) as block-diagonal
  * matrices, skipping their zero 16x16 tiles (3/8 of the dense MFMA work).  The environment
  * variable GFT_PRODUCT_FORM=dense or staged forces either form where both exist.
- * Requires n_a, n_b <= 64, FP32 storage, the combinatorial Laplacian and options.engine 0
- * (else GFT_ERR_UNSUPPORTED; FP16 precision is unsupported too).  gft_plan_info reports the two factor GFTs
+ * Requires n_a, n_b <= 64, one storage type for signals and coefficients, and
+ * options.engine 0 (else GFT_ERR_UNSUPPORTED; FP16 precision is unsupported too).  The
+ * normalized Laplacian (Sec. II-B) is accepted when both factors are regular (constant
+ * weighted degree d_a, d_b): the product's is then L / (d_a + d_b), the same basis with the
+ * eigenvalues scaled; otherwise it is no Kronecker sum (GFT_ERR_UNSUPPORTED).  gft_plan_info reports the two factor GFTs
  * as num_blocks = 2 with their dense costs; gft_plan_blocks is unsupported.  Host-only. */
 gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing_a,
                             const gft_graph *graph_b, const gft_pairing *pairing_b,

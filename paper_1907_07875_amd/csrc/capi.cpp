@@ -1203,22 +1203,53 @@ gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing
     return set_error(GFT_ERR_UNSUPPORTED, "product plans run FP32, BF16 or split BF16 factor products");
   if (o.in_dtype != o.out_dtype)
     return set_error(GFT_ERR_UNSUPPORTED, "product plans store signals and coefficients in one type (FP32 or BF16)");
-  if (o.laplacian != GFT_LAPLACIAN_COMBINATORIAL)
-    return set_error(GFT_ERR_UNSUPPORTED,
-                     "the normalized Laplacian of a product graph is not a Kronecker sum");
+  // The normalized Laplacian D^{-1/2} L D^{-1/2} of a product is a Kronecker sum only when
+  // the degree d_a(i) + d_b(j) is constant, i.e. both factors are regular: then it is
+  // L / (d_a + d_b), with the combinatorial product's basis and its eigenvalues scaled.
+  double norm_scale = 1.0;
+  if (o.laplacian == GFT_LAPLACIAN_NORMALIZED) {
+    auto regular_degree = [](const gft_graph &g, double &deg) {
+      std::vector<double> d(g.n, 0.0);
+      for (int32_t e = 0; e < g.num_edges; ++e) {
+        d[g.src[e]] += g.weight[e];
+        d[g.dst[e]] += g.weight[e];
+      }
+      deg = d.empty() ? 0.0 : d[0];
+      for (double x : d)
+        if (std::fabs(x - deg) > 1e-12 * std::max(1.0, std::fabs(deg))) return false;
+      return true;
+    };
+    double da = 0.0, db = 0.0;
+    if (graph_a->n <= 0 || graph_b->n <= 0 || (graph_a->num_edges > 0 && (!graph_a->src || !graph_a->dst || !graph_a->weight)) ||
+        (graph_b->num_edges > 0 && (!graph_b->src || !graph_b->dst || !graph_b->weight)))
+      return set_error(GFT_ERR_INVALID_ARG, "graph_a and graph_b need n > 0 and their edge arrays");
+    for (int32_t e = 0; e < graph_a->num_edges; ++e)
+      if (graph_a->src[e] < 0 || graph_a->src[e] >= graph_a->n || graph_a->dst[e] < 0 || graph_a->dst[e] >= graph_a->n)
+        return set_error(GFT_ERR_GRAPH, "graph_a: an edge has a label outside [0, n)");
+    for (int32_t e = 0; e < graph_b->num_edges; ++e)
+      if (graph_b->src[e] < 0 || graph_b->src[e] >= graph_b->n || graph_b->dst[e] < 0 || graph_b->dst[e] >= graph_b->n)
+        return set_error(GFT_ERR_GRAPH, "graph_b: an edge has a label outside [0, n)");
+    if (!regular_degree(*graph_a, da) || !regular_degree(*graph_b, db) || !(da + db > 0.0))
+      return set_error(GFT_ERR_UNSUPPORTED,
+                       "the normalized Laplacian of a product graph is a Kronecker sum only when both "
+                       "factors are regular (constant weighted degree)");
+    norm_scale = 1.0 / (da + db);
+  }
   if (o.engine != GFT_ENGINE_AUTO)
     return set_error(GFT_ERR_UNSUPPORTED, "product plans run their own engine (options.engine must be 0)");
+  gft_options of = o;   // factors: combinatorial (the normalized product is scaled below)
+  of.laplacian = GFT_LAPLACIAN_COMBINATORIAL;
   try {
     auto p = std::make_unique<gft_plan_s>();
     p->opts = o;
     p->product = true;
     try {
-      p->fa = build_graph_plan(*graph_a, pairing_a, o);
+      p->fa = build_graph_plan(*graph_a, pairing_a, of);
     } catch (const PlanError &err) {
       return set_error(err.status, "graph_a: " + err.message);
     }
     try {
-      p->fb = build_graph_plan(*graph_b, pairing_b, o);
+      p->fb = build_graph_plan(*graph_b, pairing_b, of);
     } catch (const PlanError &err) {
       return set_error(err.status, "graph_b: " + err.message);
     }
@@ -1240,7 +1271,7 @@ gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing
     GraphPlan g;
     g.n = n;
     g.lambda_out.resize(n);
-    for (int k = 0; k < n; ++k) g.lambda_out[k] = lam[p->order[k]];
+    for (int k = 0; k < n; ++k) g.lambda_out[k] = norm_scale * lam[p->order[k]];
     g.stats.n = n;
     g.stats.num_blocks = 2;                 // the two factor GFTs, applied as dense matrices
     g.stats.max_block = std::max(na, nb);

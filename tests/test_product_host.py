@@ -190,3 +190,24 @@ def test_non_products_and_cross_axis_stages_keep_dense_leaves():
     assert G.Plan.from_graph(h).info()["num_kron_leaves"] == 0
     assert G.Plan.from_graph(wl.config3_graph()).info()["num_kron_leaves"] == 0
     assert G.Plan.from_graph(wl.cycle(16)).info()["num_kron_leaves"] == 0
+
+
+def test_normalized_laplacian_of_regular_products():
+    """Sec. II-B: D^{-1/2} L D^{-1/2} of a product of regular factors (cycles: every node of
+    weighted degree 2w) is L / (d_a + d_b): the product plan's basis with the eigenvalues
+    scaled, pinned against the oracle's normalized Laplacian of the explicit product graph;
+    a product with a non-regular factor (a path) is refused."""
+    ga = wl.cycle(6)
+    gb = wl._graph(8, [(i, (i + 1) % 8) for i in range(8)], [0.5] * 8, stages=[wl.reversal(8)], name="cycle_w")
+    plan = G.gft_plan_product(ga, gb, laplacian="normalized")
+    g = wl.cartesian_product(ga, gb)
+    lam, U = O.gft(O.normalized_laplacian_of(g))
+    np.testing.assert_allclose(plan.eigenvalues(), lam, atol=1e-12)
+    Uh = plan.basis()
+    Ua, sv = O.align(U, Uh, lam)
+    assert sv > 1 - 1e-9
+    X = wl.gaussian(9, g.n, wl.rng_for(9, g.n, 5), dtype=np.float64)
+    assert O.relative_error(plan.apply_host(X, 0), O.forward(X, Ua)) <= 1e-10
+    with pytest.raises(G.GFTError) as e:
+        G.gft_plan_product(wl.path(5), ga, laplacian="normalized")
+    assert e.value.status_name == "GFT_ERR_UNSUPPORTED"
