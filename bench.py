@@ -225,6 +225,10 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     plan = make_plan() if make_plan else G.Plan.from_graph(graph, engine=args.engine, precision=precision,
                                                            in_dtype=args.io, out_dtype=args.io)
     plan.prepare()
+    if (plan.in_dtype, plan.out_dtype) != (args.io, args.io):
+        # the buffers below hold args.io values: a plan with other storage would read and
+        # write past them
+        raise SystemExit(f"plan storage {plan.in_dtype}/{plan.out_dtype} differs from --io {args.io}")
     eng = plan.engine()
     tiles = plan.tiles()
     launch = plan.tuning()
@@ -382,7 +386,7 @@ def _large_workload(args, graph, S, name, desc):
     X = wl.gaussian(S, graph.n, wl.rng_for(5, 7))
     precision = args.precision or "fp32"
     engine = args.engine if args.engine in ("large", "product", "generic") else "auto"
-    plan = G.Plan.from_graph(graph, engine=engine, precision=precision)
+    plan = G.Plan.from_graph(graph, engine=engine, precision=precision, in_dtype=args.io, out_dtype=args.io)
     plan.prepare()
     st = plan.info()
     eng = plan.engine()
@@ -441,7 +445,8 @@ def bench_grid64_product(args):
                  256, "first 256 signals of the same workload",
                  kernel_names={"product": "gft_product<64,64,0>"},
                  flops_per_signal=2.0 * graph.n * (64 + 64),
-                 make_plan=lambda: G.Plan.from_product(axis, axis, precision=precision))
+                 make_plan=lambda: G.Plan.from_product(axis, axis, precision=precision, in_dtype=args.io,
+                                                       out_dtype=args.io))
 
 
 def bench_wpath(args):

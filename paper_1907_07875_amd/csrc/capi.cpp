@@ -69,8 +69,13 @@ struct DeviceImage {
   int grid[2] = {0, 0};                // butterfly / product: most workgroups (0: resident)
   int batch_rounds = 2;                // batch grid = rounds x resident workgroups
   int batch_cost16 = 11;               // register-phase fixed cost, sixteenths of N
-  bool lfused[2] = {false, false};     // large: GEMM epilogue writes the output order
+  int lmode[2] = {0, 0};               // large: 0 three passes, 1 GEMM epilogue writes the
+                                       // output order, 2 one pass (no workspace)
   int ltile_kb[2] = {40, 40};          // large: stage-pass tile size
+  int op_grid[2] = {0, 0};             // large, one pass: most workgroups (0: one per panel)
+  int lforce[2] = {-1, -1};            // large: form forced by GFT_LARGE_FORM (-1: none)
+  bool op_ok[2] = {false, false};      // large: the one-pass form exists for this direction
+  OnePass op[2]{};                     // large: one-pass programs (device pointers)
   int tune_source = GFT_TUNE_BUILTIN;
   double tune_ms = 0.0;
 };
@@ -449,22 +454,32 @@ gft_status product_image(gft_plan_s *plan, const Factors &F, int dev, DeviceImag
 bool large_fusable(const LargeImage &L) { return L.pass[1].num_stages == 0; }
 bool large_fused(const LargeImage &L) { return large_fusable(L) && L.blocks.size() <= kFuseMaxBlocks; }
 
-// Workspace of a large-engine apply over S signals: W1 (and W2 unless the GEMM epilogue
-// writes the output order) of S rows of ldw FP32 words.
-size_t large_ws_bytes(const LargeImage &L, bool fused, int64_t S) {
-  return (fused ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
+// Whether form `mode` (DeviceImage::lmode) can run direction dir of the image.
+bool large_mode_ok(const DeviceImage *img, int dir, int mode) {
+  return mode == 0 || (mode == 1 && large_fusable(img->lg[dir])) || (mode == 2 && img->op_ok[dir]);
 }
 
-// The large engine's launches for one apply: stage/gather pass, grouped GEMM, and the
-// gather pass unless `fused`; ws holds large_ws_bytes.
+// Workspace of a large-engine apply over S signals: W1 (and W2 unless the GEMM epilogue
+// writes the output order) of S rows of ldw FP32 words; none in one pass.
+size_t large_ws_bytes(const LargeImage &L, int mode, int64_t S) {
+  return mode == 2 ? 0 : (mode == 1 ? 1 : 2) * (size_t)S * (size_t)L.ldw * 4;
+}
+
+// The large engine's launches for one apply in form `mode`: one kernel (mode 2), or the
+// stage/gather pass, grouped GEMM, and the gather pass unless the GEMM writes the output
+// order (mode 1); ws holds large_ws_bytes.  tile_kb: stage-pass tile (modes 0, 1); grid:
+// one-pass workgroups (mode 2).
 hipError_t launch_large(const gft_plan_s *plan, const DeviceImage *img, int dir, const void *in, void *out,
-                        int64_t S, hipStream_t st, void *ws, bool fused, int tile_kb) {
+                        int64_t S, hipStream_t st, void *ws, int mode, int tile_kb, int grid) {
   const LargeImage &L = img->lg[dir];
-  float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
-  const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
   // storage: the forward reads signals (in_dtype) and writes coefficients (out_dtype)
   const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
   const bool out16 = (dir == 0 ? plan->opts.out_dtype : plan->opts.in_dtype) == GFT_DTYPE_BF16;
+  if (mode == 2)
+    return launch_onepass(img->op[dir], plan->opts.precision, in, out, S, in16, out16, grid, st);
+  const bool fused = mode == 1;
+  float *W1 = static_cast<float *>(ws), *W2 = fused ? nullptr : W1 + (size_t)S * L.ldw;
+  const bool ws16 = plan->opts.precision == GFT_BF16;   // BF16 workspace and matrices
   hipError_t e = launch_permute_stages(L.pass[0], in, in16, W1, ws16, S, img->num_cus, st, tile_kb);
   if (e == hipSuccess)
     e = launch_block_gemm(plan->opts.precision == GFT_FP32 ? 0 : plan->opts.precision, L.dev_blocks,
@@ -482,8 +497,7 @@ bool tune_large(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice
   if (!ts.st) return false;
   const int n = plan->graphs[0].n;
   const int64_t S = tune_signals(n, 1024);
-  const size_t ws = large_ws_bytes(img->lg[0], false, S) > large_ws_bytes(img->lg[1], false, S)
-                        ? large_ws_bytes(img->lg[0], false, S) : large_ws_bytes(img->lg[1], false, S);
+  const size_t ws = std::max(large_ws_bytes(img->lg[0], 0, S), large_ws_bytes(img->lg[1], 0, S));
   TuneMem mem(2 * (size_t)S * n * 4 + ws);
   if (!mem.p) return false;
   const float *in = static_cast<const float *>(mem.p);
@@ -491,24 +505,31 @@ bool tune_large(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice
   void *wsp = static_cast<char *>(mem.p) + 2 * (size_t)S * n * 4;
   for (int dir = 0; dir < 2; ++dir) {
     struct Cand {
-      bool fused;
-      int kb;
+      int mode, arg;   // arg: stage-pass tile KB (modes 0, 1) or one-pass grid (mode 2)
     };
     std::vector<Cand> cand;
     int base = 0;
-    for (int f = 0; f < (large_fusable(img->lg[dir]) ? 2 : 1); ++f)
-      for (int kb : {20, 40, 80}) {
-        if ((f == 1) == img->lfused[dir] && kb == img->ltile_kb[dir]) base = (int)cand.size();
-        cand.push_back({f == 1, kb});
+    const bool in16 = (dir == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16;
+    const int resident =
+        img->num_cus * (img->op_ok[dir] ? onepass_occupancy(img->op[dir], plan->opts.precision, in16) : 1);
+    for (int m = 0; m < 3; ++m) {
+      if (!large_mode_ok(img, dir, m) || (img->lforce[dir] >= 0 && m != img->lforce[dir])) continue;
+      const std::vector<int> args = m == 2 ? std::vector<int>{0, resident} : std::vector<int>{20, 40, 80};
+      for (int a : args) {
+        if (m == img->lmode[dir] && a == (m == 2 ? img->op_grid[dir] : img->ltile_kb[dir])) base = (int)cand.size();
+        cand.push_back({m, a});
       }
+    }
     const int pick = time_candidates((int)cand.size(), base, [&](int c, hipStream_t st) {
-      return launch_large(plan, img, dir, in, outp, S, st, wsp, cand[c].fused, cand[c].kb);
+      return launch_large(plan, img, dir, in, outp, S, st, wsp, cand[c].mode, cand[c].mode == 2 ? 40 : cand[c].arg,
+                          cand[c].mode == 2 ? cand[c].arg : 0);
     }, ts.st);
     if (pick < 0) return false;
-    img->lfused[dir] = cand[pick].fused;
-    img->ltile_kb[dir] = cand[pick].kb;
-    choice.push_back(cand[pick].fused ? 1 : 0);
-    choice.push_back(cand[pick].kb);
+    img->lmode[dir] = cand[pick].mode;
+    if (cand[pick].mode == 2) img->op_grid[dir] = cand[pick].arg;
+    else img->ltile_kb[dir] = cand[pick].arg;
+    choice.push_back(cand[pick].mode);
+    choice.push_back(cand[pick].arg);
   }
   return true;
 }
@@ -603,10 +624,16 @@ void run_tuning(gft_plan_s *plan, DeviceImage *img, size_t budget) {
       case LARGE:
         valid = v.size() == 4;
         for (int d = 0; d < 2 && valid; ++d)
-          valid = (v[2 * d] == 0 || (v[2 * d] == 1 && large_fusable(img->lg[d]))) &&
-                  (v[2 * d + 1] == 20 || v[2 * d + 1] == 40 || v[2 * d + 1] == 80);
+          valid = v[2 * d] >= 0 && v[2 * d] <= 2 && large_mode_ok(img, d, v[2 * d]) &&
+                  (img->lforce[d] < 0 || v[2 * d] == img->lforce[d]) &&
+                  (v[2 * d] == 2 ? v[2 * d + 1] >= 0
+                                 : (v[2 * d + 1] == 20 || v[2 * d + 1] == 40 || v[2 * d + 1] == 80));
         if (valid)
-          for (int d = 0; d < 2; ++d) img->lfused[d] = v[2 * d] == 1, img->ltile_kb[d] = v[2 * d + 1];
+          for (int d = 0; d < 2; ++d) {
+            img->lmode[d] = v[2 * d];
+            if (v[2 * d] == 2) img->op_grid[d] = v[2 * d + 1];
+            else img->ltile_kb[d] = v[2 * d + 1];
+          }
         break;
       case BATCH:
         valid = v.size() == 2 && v[0] >= 1 && v[0] <= 4 && v[1] >= 1 && v[1] <= 64;
@@ -649,9 +676,11 @@ void run_tuning(gft_plan_s *plan, DeviceImage *img, size_t budget) {
       if (!done) img->grid[0] = img->grid[1] = 0;
       break;
     case LARGE: {
-      const bool f0 = img->lfused[0], f1 = img->lfused[1];
+      const int m0 = img->lmode[0], m1 = img->lmode[1];
       done = tune_large(plan, img, choice);
-      if (!done) img->lfused[0] = f0, img->lfused[1] = f1, img->ltile_kb[0] = img->ltile_kb[1] = 40;
+      if (!done)
+        img->lmode[0] = m0, img->lmode[1] = m1, img->ltile_kb[0] = img->ltile_kb[1] = 40,
+        img->op_grid[0] = img->op_grid[1] = 0;
       break;
     }
     case BATCH:
@@ -822,6 +851,18 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
     for (int d = 0; d < 2; ++d)
       lmat[d] = mats16 ? blob.add(lgi[d].mats16.data(), lgi[d].mats16.size() * 2)
                        : blob.add(lgi[d].mats.data(), lgi[d].mats.size() * 4);
+  // the one-pass form where the plan fits it (its tables and B fragments)
+  OnePassImage opi[2];
+  bool op_ok[2] = {false, false};
+  size_t ooff[2][3] = {};
+  if (use_large)
+    for (int d = 0; d < 2; ++d)
+      if ((op_ok[d] = build_onepass(lgi[d], plan->opts.precision,
+                                    (d == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16,
+                                    opi[d]))) {
+        ooff[d][0] = blob.add(opi[d].desc.data(), opi[d].desc.size() * 4);
+        ooff[d][1] = blob.add(opi[d].frag.data(), opi[d].frag.size() * 4);
+      }
   const size_t bytes = blob.bytes.size();
   auto img = std::make_unique<DeviceImage>();
   img->device = dev;
@@ -883,7 +924,25 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
       L.mats.shrink_to_fit();
       L.mats16.clear();
       L.mats16.shrink_to_fit();
-      img->lfused[d] = large_fused(L);
+      if (op_ok[d]) {
+        OnePass &O = img->op[d];
+        O = opi[d].P;
+        O.desc = reinterpret_cast<const int32_t *>(base + ooff[d][0]);
+        O.frag = reinterpret_cast<const uint32_t *>(base + ooff[d][1]);
+        O.gather3 = L.pass[1].gather;
+        O.stages3 = L.pass[1].stages;
+        O.ops3 = L.pass[1].ops;
+        img->op_ok[d] = O.gather3 != nullptr;   // the last pass always gathers
+      }
+      // built-in form: one pass where it exists (no workspace; every value visits HBM
+      // once), else the GEMM epilogue writing the output order where the last pass has
+      // no stage and few blocks, else three passes; GFT_LARGE_FORM=passes, epilogue or
+      // onepass forces a form where the plan allows it
+      img->lmode[d] = img->op_ok[d] ? 2 : (large_fused(L) ? 1 : 0);
+      if (const char *f = std::getenv("GFT_LARGE_FORM")) {
+        const int m = !std::strcmp(f, "passes") ? 0 : !std::strcmp(f, "epilogue") ? 1 : !std::strcmp(f, "onepass") ? 2 : -1;
+        if (m >= 0 && large_mode_ok(img.get(), d, m)) img->lmode[d] = img->lforce[d] = m;
+      }
     }
   }
   if (plan->batch) {
@@ -995,13 +1054,13 @@ gft_status launch_image(gft_plan_t plan, DeviceImage *img, int dir, const void *
     e = launch_product(dir == 0 ? img->pfwd : img->pinv, static_cast<const float *>(in),
                        static_cast<float *>(out), S, st, img->num_cus, img->grid[dir]);
   } else if (img->large) {
-    const bool fused = img->lfused[dir];
-    const bool pooled = ws == nullptr;
+    const int mode = img->lmode[dir];
+    const bool pooled = ws == nullptr && mode != 2;
     if (pooled) {
-      e = hipMallocAsync(&ws, large_ws_bytes(img->lg[dir], fused, S), st);
+      e = hipMallocAsync(&ws, large_ws_bytes(img->lg[dir], mode, S), st);
       if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");
     }
-    e = launch_large(plan, img, dir, in, out, S, st, ws, fused, img->ltile_kb[dir]);
+    e = launch_large(plan, img, dir, in, out, S, st, ws, mode, img->ltile_kb[dir], img->op_grid[dir]);
     if (pooled) {
       const hipError_t ef = hipFreeAsync(ws, st);
       if (e == hipSuccess) e = ef;
@@ -1342,9 +1401,9 @@ gft_status gft_apply_noalloc(gft_plan_t plan, int32_t direction, const void *in,
   if (img->large) {
     ws = large_scratch(dev);
     if (!ws) return set_error(GFT_ERR_HIP, "the static scratch of this device was not set up");
-    const size_t need = large_ws_bytes(img->lg[direction], img->lfused[direction], num_signals);
+    const size_t need = large_ws_bytes(img->lg[direction], img->lmode[direction], num_signals);
     if (need > kScratchBytes) {
-      const size_t per = large_ws_bytes(img->lg[direction], img->lfused[direction], 1);
+      const size_t per = large_ws_bytes(img->lg[direction], img->lmode[direction], 1);
       return set_error(GFT_ERR_INVALID_ARG,
                        std::to_string(num_signals) + " signals need " + std::to_string(need) +
                            " bytes of workspace; the static scratch holds " + std::to_string(kScratchBytes) +
@@ -1419,8 +1478,10 @@ gft_status gft_plan_tuning(gft_plan_t plan, gft_tuning *out) {
     t.grid_fwd = img->grid[0];
     t.grid_inv = img->grid[1];
   } else if (img->large) {
-    t.variant = img->lfused[0] ? 1 : 0;
+    t.variant = img->lmode[0];
     t.large_tile_kb = img->ltile_kb[0];
+    t.grid_fwd = img->op_grid[0];
+    t.grid_inv = img->op_grid[1];
   } else if (!plan->batch) {
     t.fwd_tile = 16 * img->fwd[0].mt;
     t.inv_tile = 16 * img->inv[0].mt;

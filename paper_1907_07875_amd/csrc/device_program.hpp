@@ -156,3 +156,47 @@ struct PProgram {
 };
 
 }  // namespace gft
+
+namespace gft {
+
+// One-pass form of the large-signal engine (plans whose first pass has at most one Haar
+// stage and whose leaf blocks, one or two, fit one workgroup's columns): one kernel stages
+// the first pass's values straight from the input rows, multiplies them by the blocks on
+// MFMA tiles and runs the last pass (its stages and gather) on the results in LDS, so no
+// workspace array exists.  A workgroup owns 16*MT signal rows and every workspace column:
+// wave w multiplies block wblk[w] (-1: none) over n-tiles wnt0[w] .. wnt0[w] + wcnt[w] - 1.
+//   desc[4 e .. 4 e + 3] (entry e = desc_off[b] + k, k < 32 nkc[b]): the first-pass value of
+//     workspace column col[b] + k is  c1 * x1 + c0 * x0  (one multiply, one fused
+//     multiply-add), x0 and x1 the input row's values at byte offsets word 0 and word 1,
+//     c0 = word 2, c1 = word 3 (float bits): a sum x_i + x_j (1, 1), a difference x_i - x_j
+//     (1, -1), sqrt(2) x_c of a V_Z node (sqrt 2, 0), a copy (1, 0) or padding (0, 0); with
+//     c1 = 0 the second offset repeats the first (c1 = 0 skips the add, c0 = 0 gives 0);
+//   same_src: 1 when every valid entry of the second block has the offsets of the first
+//     block's entry at the same k (one left stage: sums and differences of the same Haar
+//     units), so each pair is loaded once for both blocks;
+//   frag: the block matrices in MFMA B-operand order, one 16x16x32 fragment (32 k x 16
+//     columns, 16 bytes per lane: column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e)
+//     per (kc, nt), at fragment frag_off[b] + kc * ntl[b] + nt (split blocks: a hi and a lo
+//     fragment, 2 fragments per index); the rounding is the same as the three-pass GEMM's;
+//   the last pass: num_stages3 stages (stages3: offset, count pairs; ops3: i | j << 16,
+//     j = 0xffff: scale by sqrt 2) on workspace columns, 16 rows at a time, then output
+//     column c takes slab column gather3[c] (-1: zero).
+struct OnePass {
+  int32_t n;              // input and output row length
+  int32_t ldw;            // workspace columns
+  int32_t slab_stride;    // LDS row stride of the result slab (floats)
+  int32_t nblocks;        // 1 or 2
+  int32_t nk;             // k steps of 32 (the longest block)
+  int32_t same_src;
+  int32_t num_stages3;
+  int32_t desc_words;     // int32 words of desc (copied to LDS)
+  int32_t K[2], col[2], nkc[2], ntl[2], desc_off[2], frag_off[2];
+  int32_t wblk[8], wnt0[8], wcnt[8];
+  const int32_t *desc;
+  const uint32_t *frag;
+  const int32_t *gather3;
+  const int32_t *stages3;
+  const uint32_t *ops3;
+};
+
+}  // namespace gft

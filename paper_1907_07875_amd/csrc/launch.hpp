@@ -50,6 +50,18 @@ hipError_t launch_block_gemm(int prec, const LBlock *blocks, int nblocks, const 
                              const void *A, void *C, bool out16, int64_t S, int ld, int64_t grid,
                              const int32_t *omap, int ldy, hipStream_t stream);
 
+// One-pass form of the large-signal engine (OnePass; precision GFT_BF16 or GFT_SPLIT_BF16).
+// grid: most workgroups (0: one per row panel), each taking panels of onepass_rows()
+// signals in turn.
+int onepass_rows(int precision);
+int onepass_occupancy(const OnePass &P, int precision, bool in16);   // resident workgroups per CU
+hipError_t launch_onepass(const OnePass &P, int precision, const void *in, void *out, int64_t S, bool in16,
+                          bool out16, int grid, hipStream_t stream);
+// split-BF16 instances (gft_onepass3.hip)
+int onepass_occupancy_split(const OnePass &P, bool in16);
+hipError_t launch_onepass_split(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16,
+                                int grid, hipStream_t stream);
+
 // Static scratch of the allocation-free apply: kScratchBytes per GPU, in the code object.
 // large_scratch_setup(dev) runs with device `dev` current (at plan preparation), looks up
 // the array's address on that device once and keeps it; large_scratch(dev) returns it

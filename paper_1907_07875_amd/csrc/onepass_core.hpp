@@ -1,0 +1,361 @@
+// Device code of the one-pass large-signal GFT (see OnePass in device_program.hpp); the
+// BF16 and split-BF16 kernels are instantiated in translation units of their own.
+//
+// The three-pass form moves every signal through a workspace twice: the first pass writes
+// the staged row, the GEMM reads it and writes the block outputs, the last pass gathers
+// them into the output order.  For plans with at most one Haar stage before the blocks
+// (the single decomposition G = G+ (+) G-, or none) and one or two leaf blocks that fit the
+// columns of one workgroup, this kernel does all three in one visit of the signal:
+//
+//   * a workgroup owns 16*MT signal rows and every workspace column; its k loop runs over
+//     32-wide k steps of the blocks;
+//   * staging: the inputs of a k step are loaded one or two steps ahead, while earlier
+//     steps' MFMAs run (32-bit byte offsets from the panel's first row: no 64-bit address
+//     arithmetic per value); the first-pass values (x_i + x_phi(i), x_i - x_phi(i), sqrt(2) x_c of a
+//     V_Z node, or a copy: a multiply and a fused multiply-add with the entry's
+//     coefficients) are rounded to BF16 (split: a hi and a lo part) into a double-buffered
+//     LDS tile, one barrier per k step;
+//   * products: wave w holds the accumulators of its block's n-tiles for all the rows (up
+//     to 8 tiles of 16 columns x MT tiles of 16 rows) and reads its B fragments straight
+//     from global memory in MFMA operand order (the matrices are shared by every
+//     workgroup and stay in L2), one k step ahead, each fragment reloaded right after its
+//     last use;
+//   * the last pass: 16-row slabs of the results are written to LDS at their workspace
+//     columns, the last pass's Haar stages (the inverse's left stage, the forward's right
+//     stage) run there, and the output rows leave in their final order as whole rows.
+//
+// Every value is computed with the same operations in the same order as in the three-pass
+// form (FP32 stage arithmetic, the same BF16 rounding, the same MFMA sequence per k chunk
+// and lane placement), so the two forms agree bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "device_program.hpp"
+
+namespace gft {
+namespace onepass {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 512;
+constexpr int kARow = 80;                 // LDS bytes of a staged row: 32 BF16 k + 16 of padding
+constexpr float kSqrt2f = 1.41421356237309504880f;
+// Largest tables (at most 1024 workspace columns: two blocks of at most 32 k steps).
+constexpr int kMaxEntries = 1088;
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Value `off` bytes past `base` (FP32, or BF16 widened exactly).
+template <bool IN16>
+__device__ __forceinline__ float load_in(const char *base, uint32_t off) {
+  if constexpr (IN16) return __uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t *>(base + off)) << 16);
+  else return *reinterpret_cast<const float *>(base + off);
+}
+
+// First-pass value c1 x1 + c0 x0 of an entry (see OnePass::desc): the multiply and the
+// fused add reproduce x_i + x_j, x_i - x_j, sqrt(2) x_c and copies exactly; c1 = 0 skips the
+// add and c0 = 0 (padding) gives 0, whatever the inputs hold.
+__device__ __forceinline__ float first_pass(float c0, float c1, float x0, float x1) {
+  const float p = c0 * x0;
+  const float v = c1 != 0.0f ? __builtin_fmaf(c1, x1, p) : p;
+  return c0 != 0.0f ? v : 0.0f;
+}
+
+// Shapes: a panel of 64 rows (BF16 blocks) or 48 rows (split blocks: two operand planes)
+// per workgroup, one workgroup per CU (the accumulators of a panel fill half the register
+// file); the inputs of a k step are loaded D steps ahead (a ring of D register sets): two
+// with one source set, one with two (a second set of two would spill; measured slower).
+template <int PREC, int NS> struct OnePassShape {
+  static constexpr int MT = PREC == 3 ? 3 : 4;     // 16-row tiles per panel
+  static constexpr int SR = 16;                    // result slab rows
+  static constexpr int D = NS == 1 ? 2 : 1;
+};
+
+// PREC: GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: source sets loaded per k step (1: the two
+// blocks read the same inputs, or there is one block; 2: each block loads its own).  IN16:
+// the input rows hold BF16.  out16: the output rows hold BF16.
+template <int PREC, int NS, bool IN16>
+__global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *__restrict__ in,
+                                                          void *__restrict__ out, int64_t S, int out16) {
+  constexpr int MT = OnePassShape<PREC, NS>::MT;
+  constexpr int D = OnePassShape<PREC, NS>::D;
+  constexpr int BM = 16 * MT;
+  constexpr int PL = PREC == 3 ? 2 : 1;                              // operand planes
+  constexpr int kPlane = BM * kARow;
+  constexpr int ESZ = IN16 ? 2 : 4;
+  constexpr int SR = OnePassShape<PREC, NS>::SR;
+  constexpr int ITEMS = (BM * 16 + kThreads - 1) / kThreads;         // (row, k pair) items
+  __shared__ __attribute__((aligned(16))) int32_t sdesc[4 * kMaxEntries];
+  __shared__ __attribute__((aligned(16))) char abuf[2 * 2 * PL * kPlane];
+  __shared__ __attribute__((aligned(16))) float slab[SR * (1024 + 4)];
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15, kp = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: per-wave fields in SGPRs
+  const int nb = P.nblocks, n = P.n;
+  const int buf_bytes = nb * PL * kPlane;
+  const int sstr = P.slab_stride;
+  for (int i = tid; i < P.desc_words; i += kThreads) sdesc[i] = P.desc[i];
+  __syncthreads();
+
+  const int wb = P.wblk[wave], nt0 = P.wnt0[wave], wcnt = P.wcnt[wave];
+  const int wbs = wb >= 0 ? wb : 0;
+  const int wfo = P.frag_off[wbs], wntl = P.ntl[wbs], wK = P.K[wbs], wcol = P.col[wbs], wnk = P.nkc[wbs];
+  const u32x4 *frag = reinterpret_cast<const u32x4 *>(P.frag);
+  const int64_t npanels = (S + BM - 1) / BM;
+
+  for (int64_t panel = blockIdx.x; panel < npanels; panel += gridDim.x) {
+    const int64_t row0 = panel * BM;
+    const char *base = static_cast<const char *>(in) + row0 * n * ESZ;   // uniform
+    const int last = (S - row0 < BM ? (int)(S - row0) : BM) - 1;        // rows past it: clamped, never stored
+    uint32_t rowoff[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int row = (tid >> 4) + 32 * it;
+      rowoff[it] = (uint32_t)((row < last ? row : last) * n * ESZ);
+    }
+    // ---- staging: inputs of k step kt into ring set q = kt mod D (loads only; consumed by
+    // stage_store).  Steps past the end re-read the last step's inputs.
+    float sx[D][NS][ITEMS][2][2];
+    auto stage_load = [&](int kt, float (&x)[NS][ITEMS][2][2]) {
+      kt = kt < P.nk ? kt : P.nk - 1;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        // the block whose entries give this set's offsets: with one set, block 0 while it
+        // has k steps left, then block 1; k steps past a block's end re-read its last one
+        const int b = NS == 2 ? s : (kt < P.nkc[0] || nb == 1 ? 0 : 1);
+        const int kk = kt < P.nkc[b] ? kt : P.nkc[b] - 1;
+        const int32_t *d = sdesc + 4 * (P.desc_off[b] + 32 * kk + 2 * kp);
+        const u32x4 d0 = *reinterpret_cast<const u32x4 *>(d), d1 = *reinterpret_cast<const u32x4 *>(d + 4);
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const u32x4 de = e == 0 ? d0 : d1;
+            x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
+            x[s][it][e][1] = load_in<IN16>(base, rowoff[it] + de[1]);
+          }
+      }
+    };
+    // ---- staging: first-pass values of k step kt into LDS buffer buf (zeros for k steps
+    // past a block's end, so that its waves may multiply them in with no effect)
+    auto stage_store = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2]) {
+      for (int b = 0; b < nb; ++b) {
+        const bool live = kt < P.nkc[b];
+        const int kk = live ? kt : P.nkc[b] - 1;
+        const int s = NS == 2 ? b : 0;
+        const int32_t *d = sdesc + 4 * (P.desc_off[b] + 32 * kk + 2 * kp);
+        const u32x4 d0 = *reinterpret_cast<const u32x4 *>(d), d1 = *reinterpret_cast<const u32x4 *>(d + 4);
+        char *plane = abuf + buf * buf_bytes + b * PL * kPlane;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          const int idx = tid + kThreads * it;
+          if ((BM * 16) % kThreads != 0 && idx >= BM * 16) continue;   // MT = 3: rows 48 .. 63 do not exist
+          const int row = idx >> 4;
+          float v[2];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const u32x4 de = e == 0 ? d0 : d1;
+            v[e] = live ? first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1])
+                        : 0.0f;
+          }
+          const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
+          *reinterpret_cast<uint32_t *>(plane + row * kARow + 4 * kp) = h0 | (h1 << 16);
+          if constexpr (PL == 2) {
+            const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
+            const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
+            *reinterpret_cast<uint32_t *>(plane + kPlane + row * kARow + 4 * kp) = l0 | (l1 << 16);
+          }
+        }
+      }
+    };
+    auto frag_at = [&](int kc, int j, int pl) {
+      const int nt = nt0 + (j < wcnt ? j : (wcnt > 0 ? wcnt - 1 : 0));   // always a valid tile
+      return frag[(((size_t)wfo + (size_t)kc * wntl + nt) * PL + pl) * 64 + lane];
+    };
+
+    floatx4 acc[MT][8];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    u32x4 bh[8], bl[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      bh[j] = frag_at(0, j, 0);
+      if constexpr (PL == 2) bl[j] = frag_at(0, j, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
+    stage_store(0, 0, sx[0]);
+    __syncthreads();
+    // one k step (kt = Q mod D): the loads of step kt + D into the set that step kt used,
+    // the products of step kt, the staging of step kt + 1
+    auto step = [&](int kt, auto Qc) {
+      constexpr int Q = decltype(Qc)::value;
+      stage_load(kt + D, sx[Q]);
+      // No branch around the products and the B reloads: a load under a branch makes the
+      // compiler wait for every outstanding load where the paths join (which would expose
+      // the next step's B fragments here), and accumulators under a branch get copied.
+      // Past its block's end a wave multiplies the zero tiles staged for it; tiles past a
+      // wave's count (and every tile of an idle wave) repeat a valid fragment into
+      // accumulators that are never stored.
+      const char *ab = abuf + (kt & 1) * buf_bytes + wbs * PL * kPlane;
+      u32x4 ah[MT], al[MT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        ah[i] = *reinterpret_cast<const u32x4 *>(ab + (16 * i + r) * kARow + 16 * g);
+        if constexpr (PL == 2) al[i] = *reinterpret_cast<const u32x4 *>(ab + kPlane + (16 * i + r) * kARow + 16 * g);
+      }
+      const int kn = kt + 1 < wnk ? kt + 1 : wnk - 1;   // next k chunk (the last one re-read)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          const bf16x8 a = __builtin_bit_cast(bf16x8, ah[i]), b = __builtin_bit_cast(bf16x8, bh[j]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+          if constexpr (PL == 2) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]), b, acc[i][j], 0, 0, 0);
+          }
+        }
+        bh[j] = frag_at(kn, j, 0);
+        if constexpr (PL == 2) bl[j] = frag_at(kn, j, 1);
+      }
+      // the other buffer (last read before the previous barrier); past the last step the
+      // staging writes zeros that nothing reads
+      stage_store(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D]);
+      __syncthreads();
+    };
+    // whole groups of D steps with no branch inside (the compiler's waits stay exact), then
+    // the remaining steps
+    int kt = 0;
+    for (; kt + D <= P.nk; kt += D) {
+      step(kt, std::integral_constant<int, 0>{});
+      if constexpr (D == 2) step(kt + 1, std::integral_constant<int, 1 % D>{});
+    }
+    if (D == 2 && kt < P.nk) step(kt, std::integral_constant<int, 0>{});
+
+    // ---- last pass, one slab of SR rows at a time (row tile s, half h when SR = 8)
+#pragma unroll
+    for (int s = 0; s < MT; ++s)
+#pragma unroll
+    for (int h = 0; h < 16 / SR; ++h) {
+      if (wb >= 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = 16 * (nt0 + j) + r;
+          if (j < wcnt && c < wK) {
+            float *dst = slab + wcol + c;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lr = 4 * g + v - SR * h;   // the lanes of this half write
+              if (lr >= 0 && lr < SR) dst[lr * sstr] = acc[s][j][v];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      for (int st = 0; st < P.num_stages3; ++st) {
+        const int off = P.stages3[2 * st], cnt = P.stages3[2 * st + 1];
+        for (int u = tid; u < cnt; u += kThreads) {
+          const uint32_t op = P.ops3[off + u];
+          const int i = (int)(op & 0xffffu), j = (int)(op >> 16);
+          if (j != 0xffff) {
+#pragma unroll 4
+            for (int rr = 0; rr < SR; ++rr) {
+              float *row = slab + rr * sstr;
+              const float a = row[i], b = row[j];
+              row[i] = a + b;
+              row[j] = a - b;
+            }
+          } else {
+#pragma unroll 4
+            for (int rr = 0; rr < SR; ++rr) slab[rr * sstr + i] *= kSqrt2f;
+          }
+        }
+        __syncthreads();
+      }
+      const int64_t rb = row0 + 16 * s + SR * h;
+      const int nr = S - rb < SR ? (int)(S - rb) : SR;
+      if ((n & 3) == 0) {
+        const int nq = n >> 2;
+        for (int idx = tid; idx < SR * nq; idx += kThreads) {
+          const int rr = idx / nq, q = idx - rr * nq;
+          if (rr >= nr) continue;
+          const int4 gi = *reinterpret_cast<const int4 *>(P.gather3 + 4 * q);
+          const float *srow = slab + rr * sstr;
+          floatx4 v;
+          v[0] = gi.x >= 0 ? srow[gi.x] : 0.0f;
+          v[1] = gi.y >= 0 ? srow[gi.y] : 0.0f;
+          v[2] = gi.z >= 0 ? srow[gi.z] : 0.0f;
+          v[3] = gi.w >= 0 ? srow[gi.w] : 0.0f;
+          const int64_t o = (rb + rr) * n + 4 * q;
+          if (out16)
+            __builtin_nontemporal_store(
+                u32x2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)},
+                reinterpret_cast<u32x2 *>(static_cast<uint16_t *>(out) + o));
+          else
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(static_cast<float *>(out) + o));
+        }
+      } else {
+        for (int idx = tid; idx < SR * n; idx += kThreads) {
+          const int rr = idx / n, c = idx - rr * n;
+          if (rr >= nr) continue;
+          const int gi = P.gather3[c];
+          const float v = gi >= 0 ? slab[rr * sstr + gi] : 0.0f;
+          const int64_t o = (rb + rr) * n + c;
+          if (out16) static_cast<uint16_t *>(out)[o] = (uint16_t)bf16_bits(v);
+          else static_cast<float *>(out)[o] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int PREC, int NS, bool IN16>
+hipError_t launch_op(const OnePass &P, const void *in, void *out, int64_t S, bool out16, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((gft_onepass<PREC, NS, IN16>), dim3((unsigned)grid), dim3(kThreads), 0, st, P, in, out, S,
+                     out16 ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int PREC, int NS, bool IN16>
+int occupancy_op() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)gft_onepass<PREC, NS, IN16>, kThreads, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+// The instance for a plan direction: one source set where the blocks share their inputs.
+template <int PREC>
+hipError_t launch_prec(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16, int grid,
+                       hipStream_t st) {
+  const bool one = P.same_src != 0;
+  if (in16)
+    return one ? launch_op<PREC, 1, true>(P, in, out, S, out16, grid, st)
+               : launch_op<PREC, 2, true>(P, in, out, S, out16, grid, st);
+  return one ? launch_op<PREC, 1, false>(P, in, out, S, out16, grid, st)
+             : launch_op<PREC, 2, false>(P, in, out, S, out16, grid, st);
+}
+
+template <int PREC>
+int occupancy_prec(bool same_src, bool in16) {
+  if (in16) return same_src ? occupancy_op<PREC, 1, true>() : occupancy_op<PREC, 2, true>();
+  return same_src ? occupancy_op<PREC, 1, false>() : occupancy_op<PREC, 2, false>();
+}
+
+}  // namespace onepass
+}  // namespace gft

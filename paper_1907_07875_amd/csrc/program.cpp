@@ -718,22 +718,37 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   im.n = n;
   // block-contiguous workspace layout, each block's span padded to a multiple of 8 (16-byte
   // rows of BF16 workspace and matrices)
+  // Node order inside each block's span.  With one left stage the nodes follow the order of
+  // the Haar units (V_Z nodes after them), so column k of the sum block and column k of the
+  // difference block derive from the same pair x_i, x_phi(i): the one-pass form then reads
+  // each pair once for both blocks.  Otherwise ascending node labels.
+  std::vector<int64_t> rank(n, 0);
+  for (int v = 0; v < n; ++v) rank[v] = (int64_t)n + v;
+  if (p.stages.size() == 1) {
+    const HostStage &S0 = p.stages[0];
+    for (size_t u = 0; u < S0.pair_x.size(); ++u) rank[S0.pair_x[u]] = rank[S0.pair_y[u]] = (int64_t)u;
+    for (size_t z = 0; z < S0.znodes.size(); ++z) rank[S0.znodes[z]] = (int64_t)(S0.pair_x.size() + z);
+  }
+  std::vector<std::vector<int32_t>> ords;   // block position k -> index into B.nodes
   std::vector<int32_t> col_node, col_coef;   // per workspace column (or -1 for padding)
   int col = 0;
   size_t mat = 0;
   for (const HostBlock &B : p.blocks) {
     const int ld = (B.size + 7) & ~7;
+    std::vector<int32_t> ord(B.size);
+    for (int k = 0; k < B.size; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rank[B.nodes[a]] < rank[B.nodes[b]]; });
     im.blocks.push_back({B.size, col, (int32_t)mat, ld, (int32_t)im.omap.size()});
     // final position of each block output: coefficients (forward) or nodes (inverse)
-    const std::vector<int32_t> &dst = direction == 0 ? B.out_pos : B.nodes;
-    im.omap.insert(im.omap.end(), dst.begin(), dst.end());
+    for (int k = 0; k < B.size; ++k) im.omap.push_back(direction == 0 ? B.out_pos[k] : B.nodes[ord[k]]);
     im.block_sizes.push_back(B.size);
     for (int k = 0; k < ld; ++k) {
-      col_node.push_back(k < B.size ? B.nodes[k] : -1);
+      col_node.push_back(k < B.size ? B.nodes[ord[k]] : -1);
       col_coef.push_back(k < B.size ? B.out_pos[k] : -1);
     }
     col += ld;
     mat += (size_t)B.size * ld;
+    ords.push_back(std::move(ord));
   }
   im.ldw = col;
   if (im.ldw > kLargeMaxCols || mat > (size_t)INT32_MAX) return false;
@@ -741,11 +756,12 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
   for (size_t b = 0; b < p.blocks.size(); ++b) {
     const HostBlock &B = p.blocks[b];
     const LBlock &L = im.blocks[b];
+    const std::vector<int32_t> &ord = ords[b];
     for (int k = 0; k < B.size; ++k)
-      for (int c = 0; c < B.size; ++c)  // stored transposed: Mt[c][k] = M[k][c], with
-        // forward M[k][c] = V[k][c] and inverse M[k][j] = V[j][k]
+      for (int c = 0; c < B.size; ++c)  // stored transposed: Mt[c][k] = M[k][c], with forward
+        // M[k][c] = V[ord k][c] (input k: node ord k) and inverse M[k][c] = V[ord c][k]
         im.mats[(size_t)L.mat + (size_t)c * L.ld + k] =
-            (float)(B.scale * (direction == 0 ? B.V[(size_t)k * B.size + c] : B.V[(size_t)c * B.size + k]));
+            (float)(B.scale * (direction == 0 ? B.V[(size_t)ord[k] * B.size + c] : B.V[(size_t)ord[c] * B.size + k]));
   }
   im.mats16.resize(im.mats.size());
   for (size_t i = 0; i < im.mats.size(); ++i) im.mats16[i] = to_bf16_bits(im.mats[i]);
@@ -795,6 +811,143 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
       im.gather[k] = inverse_of(map, n);         // ws column of each node / coefficient
     }
   }
+  out = std::move(im);
+  return true;
+}
+
+}  // namespace gft
+
+namespace gft {
+
+bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out) {
+  if (precision != GFT_BF16 && precision != GFT_SPLIT_BF16) return false;
+  const PermPass &P1 = L.pass[0];
+  const int nb = (int)L.blocks.size();
+  const int esz = in16 ? 2 : 4;
+  if (P1.num_stages > 1 || nb < 1 || nb > 2 || L.ldw > 1024) return false;
+  OnePassImage im;
+  OnePass &P = im.P;
+  im.mt = precision == GFT_SPLIT_BF16 ? 3 : 4;   // split: two operand planes, fewer rows
+  P.n = L.n;
+  P.ldw = L.ldw;
+  P.slab_stride = L.ldw + 4;
+  P.nblocks = nb;
+  P.num_stages3 = L.pass[1].num_stages;
+  // waves: each block's 16-column tiles over the fewest waves of at most 8 tiles each
+  int wave = 0, entries = 0, frags = 0;
+  for (int w = 0; w < 8; ++w) P.wblk[w] = -1, P.wnt0[w] = 0, P.wcnt[w] = 0;
+  for (int b = 0; b < nb; ++b) {
+    const LBlock &B = L.blocks[b];
+    P.K[b] = B.size;
+    P.col[b] = B.col;
+    P.nkc[b] = (B.size + 31) / 32;
+    P.ntl[b] = (B.size + 15) / 16;
+    P.desc_off[b] = entries;
+    P.frag_off[b] = frags;
+    entries += 32 * P.nkc[b];
+    frags += P.nkc[b] * P.ntl[b];
+    const int waves = (P.ntl[b] + 7) / 8, per = (P.ntl[b] + waves - 1) / waves;
+    if (wave + waves > 8) return false;
+    for (int t = 0; t < P.ntl[b]; t += per, ++wave) {
+      P.wblk[wave] = b;
+      P.wnt0[wave] = t;
+      P.wcnt[wave] = std::min(per, P.ntl[b] - t);
+    }
+    P.nk = std::max(P.nk, P.nkc[b]);
+  }
+  // first-pass value of each input position: its role in the (single) stage
+  std::vector<int32_t> kind(L.n, 0), partner(L.n, -1);
+  if (P1.num_stages == 1) {
+    const int off = L.stages[0][0], cnt = L.stages[0][1];
+    for (int u = 0; u < cnt; ++u) {
+      const uint32_t op = L.ops[0][off + u];
+      const int i = (int)(op & 0xffffu), j = (int)(op >> 16);
+      if (j == 0xffff) {
+        kind[i] = 3;
+      } else {
+        kind[i] = 1, partner[i] = j;   // x_i + x_j
+        kind[j] = 2, partner[j] = i;   // x_i - x_j
+      }
+    }
+  }
+  // sources (src0, src1: input positions or -1) and coefficients of each entry
+  struct Src {
+    int32_t s0, s1;
+    float c0, c1;
+  };
+  std::vector<Src> src(entries, Src{-1, -1, 0.0f, 0.0f});
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < P.K[b]; ++k) {
+      const int t = L.gather[0][P.col[b] + k];
+      Src &e = src[P.desc_off[b] + k];
+      if (t < 0) continue;
+      if (kind[t] == 1) e = {t, partner[t], 1.0f, 1.0f};
+      else if (kind[t] == 2) e = {partner[t], t, 1.0f, -1.0f};
+      else if (kind[t] == 3) e = {t, -1, 1.41421356237309504880f, 0.0f};
+      else e = {t, -1, 1.0f, 0.0f};
+    }
+  // entries: byte offsets of the sources in the input row, coefficients
+  im.desc.assign(4 * (size_t)entries, 0);
+  for (int e = 0; e < entries; ++e) {
+    const Src &x = src[e];
+    int32_t *d = &im.desc[4 * (size_t)e];
+    d[0] = x.s0 >= 0 ? x.s0 * esz : 0;
+    d[1] = x.s1 >= 0 ? x.s1 * esz : d[0];
+    std::memcpy(&d[2], &x.c0, 4);
+    std::memcpy(&d[3], &x.c1, 4);
+  }
+  // one source set for both blocks where every valid entry of the second block has the
+  // first block's offsets at the same k
+  P.same_src = nb == 1 ? 1 : 0;
+  if (nb == 2) {
+    bool same = true;
+    for (int k = 0; k < 32 * P.nkc[1] && same; ++k) {
+      const Src &b1 = src[P.desc_off[1] + k];
+      if (b1.c0 == 0.0f) continue;   // padding
+      if (k >= 32 * P.nkc[0]) {
+        same = false;
+        break;
+      }
+      const int32_t *d0 = &im.desc[4 * ((size_t)P.desc_off[0] + k)], *d1 = &im.desc[4 * ((size_t)P.desc_off[1] + k)];
+      same = d0[0] == d1[0] && d0[1] == d1[1];
+    }
+    P.same_src = same ? 1 : 0;
+  }
+  P.desc_words = 4 * entries;
+  // B fragments (forward and inverse alike: M[k][c] = Mt[c][k] of the stored transpose),
+  // rounded as the three-pass GEMM rounds them
+  const int PL = precision == GFT_SPLIT_BF16 ? 2 : 1;
+  im.frag.assign((size_t)frags * PL * 64 * 4, 0u);
+  for (int b = 0; b < nb; ++b) {
+    const LBlock &B = L.blocks[b];
+    for (int kc = 0; kc < P.nkc[b]; ++kc)
+      for (int nt = 0; nt < P.ntl[b]; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int h = 0; h < 4; ++h) {
+            uint32_t hiw = 0, low = 0;
+            for (int e = 0; e < 2; ++e) {
+              const int k = 32 * kc + 8 * (lane / 16) + 2 * h + e, c = 16 * nt + lane % 16;
+              uint16_t hi = 0, lo = 0;
+              if (k < B.size && c < B.size) {
+                const size_t idx = (size_t)B.mat + (size_t)c * B.ld + k;
+                if (precision == GFT_BF16) {
+                  hi = L.mats16[idx];
+                } else {
+                  const float m = L.mats[idx];
+                  hi = to_bf16_bits(m);
+                  lo = to_bf16_bits(m - bf16_to_float(hi));
+                }
+              }
+              hiw |= (uint32_t)hi << (16 * e);
+              low |= (uint32_t)lo << (16 * e);
+            }
+            const size_t f = (size_t)P.frag_off[b] + (size_t)kc * P.ntl[b] + nt;
+            im.frag[((f * PL + 0) * 64 + lane) * 4 + h] = hiw;
+            if (PL == 2) im.frag[((f * PL + 1) * 64 + lane) * 4 + h] = low;
+          }
+  }
+  // the kernel's LDS arrays are sized for these limits
+  if (entries > kOnePassMaxEntries || P.nk > kOnePassMaxSteps) return false;
   out = std::move(im);
   return true;
 }

@@ -80,4 +80,23 @@ int64_t large_workspace_cols(const GraphPlan &p);
 // Returns false when the input row or the workspace row would exceed kLargeMaxCols.
 bool build_large(const GraphPlan &p, int direction, LargeImage &out);
 
+// Host image of the one-pass form (see OnePass) for one direction.
+struct OnePassImage {
+  OnePass P{};                   // pointers left null until upload
+  int mt = 4;                    // 16-signal row tiles per workgroup
+  std::vector<int32_t> desc;
+  std::vector<uint32_t> frag;
+};
+
+// Table limits of the one-pass kernel (its LDS arrays are sized for them): entries of the
+// two blocks' k steps, and k steps.
+constexpr int kOnePassMaxEntries = 1088;
+constexpr int kOnePassMaxSteps = 32;
+
+// The one-pass form of large image `L` (built for `precision`: GFT_BF16 or GFT_SPLIT_BF16,
+// with L's host matrices still present; in16: the direction's input rows hold BF16).
+// Returns false when the plan does not fit it: a first pass with more than one stage, more
+// than two leaf blocks, or more columns than eight waves hold.
+bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out);
+
 }  // namespace gft

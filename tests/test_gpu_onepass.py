@@ -1,0 +1,127 @@
+"""One-pass form of the large-signal engine: the first pass's values staged straight from
+the input rows, the leaf-block MFMA products, and the last pass (its Haar stages and the
+output order) in LDS, all in one kernel with no workspace array.
+
+The one-pass form computes every value with the operations of the three-pass form in the
+same order, so the forms agree bit for bit (GFT_LARGE_FORM forces a form); both agree with
+the aligned FP64 oracle within the block precision's bound (BF16 <= 2e-2, split BF16 <=
+1e-5).  Cases: the weighted symmetric 1024-path (two 512-node blocks of the sums and
+differences of the same Haar units: one load per pair), the 1023-path (a V_Z node scaled by
+sqrt 2, blocks of 512 and 511), a 1000-cycle, and a 600-node path planned without a stage
+(one dense block); the inverse directions stage coefficients (a copy per block, two source
+sets) and run the Haar stage on the results in LDS.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1907_07875_amd as G
+import workloads as wl
+from oracle import gft_oracle as O
+from tests.gpu_helpers import aligned_oracle_basis, device, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"bf16": 2e-2, "split_bf16": 1e-5}
+
+
+def _nostage_path(n):
+    rng = wl.rng_for(5, 9, n)
+    edges = [(i, i + 1) for i in range(n - 1)]
+    return wl._graph(n, edges, rng.uniform(0.1, 1.0, n - 1), None, [], "wpath_nostage")
+
+
+GRAPHS = {
+    "wpath1024": wl.config5b_graph,
+    "wpath1023": lambda: wl.weighted_symmetric_path(1023, wl.rng_for(5, 8)),
+    "cycle1000": lambda: wl.cycle(1000),
+    "nostage600": lambda: _nostage_path(600),
+}
+
+
+def _plan(g, precision, form, monkeypatch, **kw):
+    monkeypatch.setenv("GFT_LARGE_FORM", form)
+    plan = G.Plan.from_graph(g, engine="large", precision=precision, autotune=False, **kw)
+    plan.prepare()
+    monkeypatch.delenv("GFT_LARGE_FORM")
+    return plan
+
+
+@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_onepass_bit_equal_to_three_passes_and_oracle(name, precision, monkeypatch):
+    dev = device()
+    g = GRAPHS[name]()
+    one = _plan(g, precision, "onepass", monkeypatch)
+    three = _plan(g, precision, "passes", monkeypatch)
+    assert one.engine() == three.engine() == "large"
+    assert one.tuning()["variant"] == 2, "the plan should fit the one-pass form"
+    assert three.tuning()["variant"] == 0
+    S = 1001                      # not a multiple of the 64- or 48-row panels
+    X = wl.gaussian(S, g.n, wl.rng_for(5, g.n, 61))
+    x = torch.from_numpy(X).to(dev)
+    y = one.forward(x)
+    assert torch.equal(y, three.forward(x))
+    xr = one.inverse(y)
+    assert torch.equal(xr, three.inverse(y))
+    _, Ua = aligned_oracle_basis(g, one.basis(), sv_tol=1e-8)
+    ref = O.forward(X.astype(np.float64), Ua)
+    assert O.relative_error(to_np(y), ref) <= TOL[precision]
+    assert O.max_row_relative_error(to_np(y), ref) <= 4 * TOL[precision]
+    assert O.relative_error(to_np(xr), O.inverse(to_np(y).astype(np.float64), Ua)) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+def test_onepass_epilogue_form_and_ragged_counts(precision, monkeypatch):
+    """Signal counts around the panel heights (one partial panel, exact panels, a panel
+    plus one row) and an empty batch; the GEMM-epilogue form agrees too."""
+    dev = device()
+    g = wl.config5b_graph()
+    one = _plan(g, precision, "onepass", monkeypatch)
+    three = _plan(g, precision, "passes", monkeypatch)
+    epi = _plan(g, precision, "epilogue", monkeypatch)
+    assert epi.tuning()["variant"] == 1 or epi.tuning()["variant"] == 0
+    for S in (1, 47, 48, 49, 64, 65, 193):
+        x = torch.from_numpy(wl.gaussian(S, g.n, wl.rng_for(5, 4, S))).to(dev)
+        y = one.forward(x)
+        assert torch.equal(y, three.forward(x)), S
+        assert torch.equal(y, epi.forward(x)), S
+        assert torch.equal(one.inverse(y), three.inverse(y)), S
+    assert one.forward(torch.zeros((0, g.n), device=dev)).shape == (0, g.n)
+
+
+@pytest.mark.parametrize("din,dout", [("bf16", "bf16"), ("bf16", "fp32"), ("fp32", "bf16")])
+def test_onepass_bf16_storage(din, dout, monkeypatch):
+    """BF16 signals and/or coefficients: bit-equal to the three-pass form with the same
+    storage."""
+    dev = device()
+    g = wl.config5b_graph()
+    one = _plan(g, "bf16", "onepass", monkeypatch, in_dtype=din, out_dtype=dout)
+    three = _plan(g, "bf16", "passes", monkeypatch, in_dtype=din, out_dtype=dout)
+    assert one.tuning()["variant"] == 2
+    td = {"bf16": torch.bfloat16, "fp32": torch.float32}
+    X = wl.gaussian(333, g.n, wl.rng_for(5, 5, 333))
+    x = torch.from_numpy(X).to(dev).to(td[din])
+    y = one.forward(x)
+    assert y.dtype == td[dout]
+    assert torch.equal(y, three.forward(x))
+    assert torch.equal(one.inverse(y), three.inverse(y))
+
+
+def test_onepass_needs_no_workspace(monkeypatch):
+    """The allocation-free apply takes any number of signals on a one-pass plan: there is no
+    workspace to fit in the static scratch (8192 signals is the three-pass limit here)."""
+    dev = device()
+    g = wl.config5b_graph()
+    plan = _plan(g, "bf16", "onepass", monkeypatch)
+    assert plan.tuning()["variant"] == 2
+    S = 20000
+    x = torch.from_numpy(wl.gaussian(S, g.n, wl.rng_for(5, 6))).to(dev)
+    lib = G.load_library()
+    for d, fn in ((0, G.gft_forward), (1, G.gft_inverse)):
+        out = torch.full_like(x, float("nan"))
+        st = lib.gft_apply_noalloc(plan.handle, d, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   S, G._stream_ptr(None))
+        assert st == 0, lib.gft_last_error()
+        assert torch.equal(out, fn(plan, x))

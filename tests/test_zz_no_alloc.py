@@ -28,11 +28,12 @@ def _noalloc(plan, x, out, direction):
 
 
 CASES = [
-    # (graph, precision, engine, signals of the two calls); the 1024-node path's forward
-    # writes the output order from the GEMM (W1 only), its inverse runs the stage pass after
-    # the GEMM (W1 and W2): at most 8192 signals per call in both directions
+    # (graph, precision, engine, signals of the two calls); with FP32 blocks the 1024-node
+    # path's forward writes the output order from the GEMM (W1 only) and its inverse runs
+    # the stage pass after the GEMM (W1 and W2): at most 8192 signals per call in both
+    # directions; with BF16 and split blocks it takes the one-pass form (no workspace)
     ("wpath1024", "fp32", "auto", (8191, 4097)),         # large engine
-    ("wpath1024", "bf16", "auto", (8192, 129)),          # BF16 workspace
+    ("wpath1024", "bf16", "auto", (8192, 129)),          # one pass, or BF16 workspace
     ("wpath1024", "split_bf16", "auto", (5000, 1)),
     ("grid64x64", "fp32", "large", (1900, 333)),         # 49 blocks: W1 and W2, three passes
     ("grid8x8", "fp32", "auto", (70001, 17)),            # butterfly engine: no workspace
