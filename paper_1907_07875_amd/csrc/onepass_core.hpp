@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15, kp = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: per-wave fields in SGPRs
   const int nb = P.nblocks, n = P.n;
-  const int buf_bytes = nb * PL * kPlane;
+  constexpr int buf_bytes = 2 * PL * kPlane;                        // room for two blocks
   const int sstr = P.slab_stride;
   for (int i = tid; i < P.desc_words; i += kThreads) sdesc[i] = P.desc[i];
   __syncthreads();
@@ -148,35 +148,43 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     };
     // ---- staging: first-pass values of k step kt into LDS buffer buf (zeros for k steps
     // past a block's end, so that its waves may multiply them in with no effect)
-    auto stage_store = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2]) {
-      for (int b = 0; b < nb; ++b) {
-        const bool live = kt < P.nkc[b];
-        const int kk = live ? kt : P.nkc[b] - 1;
+    // (both block slots always: with one block the second repeats the first into a plane
+    // nothing reads, so that the staging is branch-free and can interleave with products)
+    auto stage_unit = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2], int b, int it) {
+      {
+        const int bb = b < nb ? b : nb - 1;
+        const bool live = kt < P.nkc[bb];
+        const int kk = live ? kt : P.nkc[bb] - 1;
+        const uint32_t keep = live ? 0xffffffffu : 0u;   // zeros past the block's end (no branch)
         const int s = NS == 2 ? b : 0;
-        const int32_t *d = sdesc + 4 * (P.desc_off[b] + 32 * kk + 2 * kp);
+        const int32_t *d = sdesc + 4 * (P.desc_off[bb] + 32 * kk + 2 * kp);
         const u32x4 d0 = *reinterpret_cast<const u32x4 *>(d), d1 = *reinterpret_cast<const u32x4 *>(d + 4);
         char *plane = abuf + buf * buf_bytes + b * PL * kPlane;
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
+        {
           const int idx = tid + kThreads * it;
-          if ((BM * 16) % kThreads != 0 && idx >= BM * 16) continue;   // MT = 3: rows 48 .. 63 do not exist
+          if ((BM * 16) % kThreads != 0 && idx >= BM * 16) return;   // MT = 3: rows 48 .. 63 do not exist
           const int row = idx >> 4;
           float v[2];
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const u32x4 de = e == 0 ? d0 : d1;
-            v[e] = live ? first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1])
-                        : 0.0f;
+            v[e] = first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1]);
           }
           const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
-          *reinterpret_cast<uint32_t *>(plane + row * kARow + 4 * kp) = h0 | (h1 << 16);
+          *reinterpret_cast<uint32_t *>(plane + row * kARow + 4 * kp) = (h0 | (h1 << 16)) & keep;
           if constexpr (PL == 2) {
             const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
             const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
-            *reinterpret_cast<uint32_t *>(plane + kPlane + row * kARow + 4 * kp) = l0 | (l1 << 16);
+            *reinterpret_cast<uint32_t *>(plane + kPlane + row * kARow + 4 * kp) = (l0 | (l1 << 16)) & keep;
           }
         }
       }
+    };
+    auto stage_store = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2]) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) stage_unit(kt, buf, x, b, it);
     };
     auto frag_at = [&](int kc, int j, int pl) {
       const int nt = nt0 + (j < wcnt ? j : (wcnt > 0 ? wcnt - 1 : 0));   // always a valid tile
@@ -217,6 +225,12 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         if constexpr (PL == 2) al[i] = *reinterpret_cast<const u32x4 *>(ab + kPlane + (16 * i + r) * kARow + 16 * g);
       }
       const int kn = kt + 1 < wnk ? kt + 1 : wnk - 1;   // next k chunk (the last one re-read)
+      // The staging of step kt + 1 into the other buffer (last read before the previous
+      // barrier; past the last step it writes zeros that nothing reads) is independent of
+      // this step's products: its 2 x ITEMS units go between the MFMA groups, fenced from
+      // the scheduler, so the matrix core runs each group while the wave issues the VALU
+      // work of a unit.
+      constexpr int kUnits = 2 * ITEMS, kEvery = 8 / kUnits;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
 #pragma unroll
@@ -230,10 +244,13 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         }
         bh[j] = frag_at(kn, j, 0);
         if constexpr (PL == 2) bl[j] = frag_at(kn, j, 1);
+        if (j % kEvery == kEvery - 1) {
+          const int u = j / kEvery;
+          __builtin_amdgcn_sched_barrier(0);
+          stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
-      // the other buffer (last read before the previous barrier); past the last step the
-      // staging writes zeros that nothing reads
-      stage_store(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D]);
       __syncthreads();
     };
     // whole groups of D steps with no branch inside (the compiler's waits stay exact), then
