@@ -171,9 +171,13 @@ namespace gft {
 //     c0 = word 2, c1 = word 3 (float bits): a sum x_i + x_j (1, 1), a difference x_i - x_j
 //     (1, -1), sqrt(2) x_c of a V_Z node (sqrt 2, 0), a copy (1, 0) or padding (0, 0); with
 //     c1 = 0 the second offset repeats the first (c1 = 0 skips the add, c0 = 0 gives 0);
-//   same_src: 1 when every valid entry of the second block has the offsets of the first
-//     block's entry at the same k (one left stage: sums and differences of the same Haar
-//     units), so each pair is loaded once for both blocks;
+//   src_mode: how the inputs of a k step are loaded: 1, one set for both blocks (every valid
+//     entry of the second block has the offsets of the first block's entry at the same k:
+//     one left stage, sums and differences of the same Haar units; or one block); 3, one
+//     load of two adjacent values per entry, at the first block's offset (both blocks copy
+//     and their sources are neighbours: the inverse of one-stage plans whose two blocks'
+//     coefficients alternate), the first value to block pair_swap, the second to the other;
+//     2, one set per block;
 //   frag: the block matrices in MFMA B-operand order, one 16x16x32 fragment (32 k x 16
 //     columns, 16 bytes per lane: column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e)
 //     per (kc, nt), at fragment frag_off[b] + kc * ntl[b] + nt (split blocks: a hi and a lo
@@ -187,7 +191,8 @@ struct OnePass {
   int32_t slab_stride;    // LDS row stride of the result slab (floats)
   int32_t nblocks;        // 1 or 2
   int32_t nk;             // k steps of 32 (the longest block)
-  int32_t same_src;
+  int32_t src_mode;
+  int32_t pair_swap;      // src_mode 3: 1 when the second block's source comes first
   int32_t num_stages3;
   int32_t desc_words;     // int32 words of desc (copied to LDS)
   int32_t K[2], col[2], nkc[2], ntl[2], desc_off[2], frag_off[2];

@@ -11,7 +11,7 @@ int onepass_rows(int precision) {
 
 int onepass_occupancy(const OnePass &P, int precision, bool in16) {
   if (precision == 3) return onepass_occupancy_split(P, in16);
-  return onepass::occupancy_prec<1>(P.same_src != 0, in16);
+  return onepass::occupancy_prec<1>(P.src_mode, in16);
 }
 
 hipError_t launch_onepass(const OnePass &P, int precision, const void *in, void *out, int64_t S, bool in16,

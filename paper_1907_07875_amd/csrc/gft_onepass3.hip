@@ -4,7 +4,7 @@
 
 namespace gft {
 
-int onepass_occupancy_split(const OnePass &P, bool in16) { return onepass::occupancy_prec<3>(P.same_src != 0, in16); }
+int onepass_occupancy_split(const OnePass &P, bool in16) { return onepass::occupancy_prec<3>(P.src_mode, in16); }
 
 hipError_t launch_onepass_split(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16,
                                 int grid, hipStream_t st) {

@@ -63,6 +63,20 @@ __device__ __forceinline__ float load_in(const char *base, uint32_t off) {
   else return *reinterpret_cast<const float *>(base + off);
 }
 
+// The value `off` bytes past `base` and the one after it, with one aligned load.
+template <bool IN16>
+__device__ __forceinline__ void load_pair(const char *base, uint32_t off, float &a, float &b) {
+  if constexpr (IN16) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(base + off);
+    a = __uint_as_float(w << 16);
+    b = __uint_as_float(w & 0xffff0000u);
+  } else {
+    const float2 v = *reinterpret_cast<const float2 *>(base + off);
+    a = v.x;
+    b = v.y;
+  }
+}
+
 // First-pass value c1 x1 + c0 x0 of an entry (see OnePass::desc): the multiply and the
 // fused add reproduce x_i + x_j, x_i - x_j, sqrt(2) x_c and copies exactly; c1 = 0 skips the
 // add and c0 = 0 (padding) gives 0, whatever the inputs hold.
@@ -75,16 +89,18 @@ __device__ __forceinline__ float first_pass(float c0, float c1, float x0, float 
 // Shapes: a panel of 64 rows (BF16 blocks) or 48 rows (split blocks: two operand planes)
 // per workgroup, one workgroup per CU (the accumulators of a panel fill half the register
 // file); the inputs of a k step are loaded D steps ahead (a ring of D register sets): two
-// with one source set, one with two (a second set of two would spill; measured slower).
+// with one source set or pairs, one with two sets (a second set of two would spill;
+// measured slower).
 template <int PREC, int NS> struct OnePassShape {
   static constexpr int MT = PREC == 3 ? 3 : 4;     // 16-row tiles per panel
   static constexpr int SR = 16;                    // result slab rows
-  static constexpr int D = NS == 1 ? 2 : 1;
+  static constexpr int D = NS == 2 ? 1 : 2;
 };
 
-// PREC: GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: source sets loaded per k step (1: the two
-// blocks read the same inputs, or there is one block; 2: each block loads its own).  IN16:
-// the input rows hold BF16.  out16: the output rows hold BF16.
+// PREC: GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: how a k step's inputs are loaded
+// (OnePass::src_mode: 1, one set for both blocks; 2, one set per block; 3, one load of two
+// adjacent values per entry, the first for block 0, the second for block 1).  IN16: the
+// input rows hold BF16.  out16: the output rows hold BF16.
 template <int PREC, int NS, bool IN16>
 __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *__restrict__ in,
                                                           void *__restrict__ out, int64_t S, int out16) {
@@ -96,6 +112,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   constexpr int ESZ = IN16 ? 2 : 4;
   constexpr int SR = OnePassShape<PREC, NS>::SR;
   constexpr int ITEMS = (BM * 16 + kThreads - 1) / kThreads;         // (row, k pair) items
+  constexpr int NX = NS == 2 ? 2 : 1;                                // register sets per step
   __shared__ __attribute__((aligned(16))) int32_t sdesc[4 * kMaxEntries];
   __shared__ __attribute__((aligned(16))) char abuf[2 * 2 * PL * kPlane];
   __shared__ __attribute__((aligned(16))) float slab[SR * (1024 + 4)];
@@ -125,11 +142,11 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     }
     // ---- staging: inputs of k step kt into ring set q = kt mod D (loads only; consumed by
     // stage_store).  Steps past the end re-read the last step's inputs.
-    float sx[D][NS][ITEMS][2][2];
-    auto stage_load = [&](int kt, float (&x)[NS][ITEMS][2][2]) {
+    float sx[D][NX][ITEMS][2][2];
+    auto stage_load = [&](int kt, float (&x)[NX][ITEMS][2][2]) {
       kt = kt < P.nk ? kt : P.nk - 1;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
+      for (int s = 0; s < NX; ++s) {
         // the block whose entries give this set's offsets: with one set, block 0 while it
         // has k steps left, then block 1; k steps past a block's end re-read its last one
         const int b = NS == 2 ? s : (kt < P.nkc[0] || nb == 1 ? 0 : 1);
@@ -141,8 +158,12 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const u32x4 de = e == 0 ? d0 : d1;
-            x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
-            x[s][it][e][1] = load_in<IN16>(base, rowoff[it] + de[1]);
+            if constexpr (NS == 3) {
+              load_pair<IN16>(base, rowoff[it] + de[0], x[s][it][e][0], x[s][it][e][1]);
+            } else {
+              x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
+              x[s][it][e][1] = load_in<IN16>(base, rowoff[it] + de[1]);
+            }
           }
       }
     };
@@ -150,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     // past a block's end, so that its waves may multiply them in with no effect)
     // (both block slots always: with one block the second repeats the first into a plane
     // nothing reads, so that the staging is branch-free and can interleave with products)
-    auto stage_unit = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2], int b, int it) {
+    auto stage_unit = [&](int kt, int buf, const float (&x)[NX][ITEMS][2][2], int b, int it) {
       {
         const int bb = b < nb ? b : nb - 1;
         const bool live = kt < P.nkc[bb];
@@ -168,7 +189,11 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const u32x4 de = e == 0 ? d0 : d1;
-            v[e] = first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1]);
+            if constexpr (NS == 3)   // a copy: block b's value is element b (^ pair_swap) of the pair
+              v[e] = first_pass(__uint_as_float(de[2]), 0.0f, (b != 0) != (P.pair_swap != 0) ? x[0][it][e][1] : x[0][it][e][0],
+                                0.0f);
+            else
+              v[e] = first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1]);
           }
           const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
           *reinterpret_cast<uint32_t *>(plane + row * kARow + 4 * kp) = (h0 | (h1 << 16)) & keep;
@@ -180,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         }
       }
     };
-    auto stage_store = [&](int kt, int buf, const float (&x)[NS][ITEMS][2][2]) {
+    auto stage_store = [&](int kt, int buf, const float (&x)[NX][ITEMS][2][2]) {
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -356,22 +381,32 @@ int occupancy_op() {
   return blocks > 0 ? blocks : 1;
 }
 
-// The instance for a plan direction: one source set where the blocks share their inputs.
-template <int PREC>
-hipError_t launch_prec(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16, int grid,
-                       hipStream_t st) {
-  const bool one = P.same_src != 0;
-  if (in16)
-    return one ? launch_op<PREC, 1, true>(P, in, out, S, out16, grid, st)
-               : launch_op<PREC, 2, true>(P, in, out, S, out16, grid, st);
-  return one ? launch_op<PREC, 1, false>(P, in, out, S, out16, grid, st)
-             : launch_op<PREC, 2, false>(P, in, out, S, out16, grid, st);
+// The instance for a plan direction's source mode (OnePass::src_mode) and input storage.
+template <int PREC, bool IN16>
+hipError_t launch_mode(const OnePass &P, const void *in, void *out, int64_t S, bool out16, int grid, hipStream_t st) {
+  switch (P.src_mode) {
+    case 1: return launch_op<PREC, 1, IN16>(P, in, out, S, out16, grid, st);
+    case 3: return launch_op<PREC, 3, IN16>(P, in, out, S, out16, grid, st);
+    default: return launch_op<PREC, 2, IN16>(P, in, out, S, out16, grid, st);
+  }
 }
 
 template <int PREC>
-int occupancy_prec(bool same_src, bool in16) {
-  if (in16) return same_src ? occupancy_op<PREC, 1, true>() : occupancy_op<PREC, 2, true>();
-  return same_src ? occupancy_op<PREC, 1, false>() : occupancy_op<PREC, 2, false>();
+hipError_t launch_prec(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16, int grid,
+                       hipStream_t st) {
+  return in16 ? launch_mode<PREC, true>(P, in, out, S, out16, grid, st)
+              : launch_mode<PREC, false>(P, in, out, S, out16, grid, st);
+}
+
+template <int PREC, bool IN16>
+int occupancy_mode(int src_mode) {
+  return src_mode == 1 ? occupancy_op<PREC, 1, IN16>() : src_mode == 3 ? occupancy_op<PREC, 3, IN16>()
+                                                                       : occupancy_op<PREC, 2, IN16>();
+}
+
+template <int PREC>
+int occupancy_prec(int src_mode, bool in16) {
+  return in16 ? occupancy_mode<PREC, true>(src_mode) : occupancy_mode<PREC, false>(src_mode);
 }
 
 }  // namespace onepass

@@ -896,22 +896,49 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
     std::memcpy(&d[2], &x.c0, 4);
     std::memcpy(&d[3], &x.c1, 4);
   }
-  // one source set for both blocks where every valid entry of the second block has the
-  // first block's offsets at the same k
-  P.same_src = nb == 1 ? 1 : 0;
+  // how a k step's inputs are loaded (OnePass::src_mode): one set for both blocks where
+  // every valid entry of the second block has the first block's offsets at the same k;
+  // adjacent pairs where both blocks copy and the second block's source follows the first
+  // block's (an even position, not the row's last, so that the pair lies in the row);
+  // else one set per block
+  // (the pair starts at an even position below n - 1, so that it lies in the row; with the
+  // second block's source first, block 0's offsets move to the pair's start)
+  P.src_mode = nb == 1 ? 1 : 2;
+  P.pair_swap = 0;
   if (nb == 2) {
-    bool same = true;
-    for (int k = 0; k < 32 * P.nkc[1] && same; ++k) {
+    bool same = true, pair[2] = {true, true};   // pair[s]: block 1's source at block 0's +1 (s = 0) or -1
+    for (int k = 0; k < 32 * P.nkc[1] && (same || pair[0] || pair[1]); ++k) {
       const Src &b1 = src[P.desc_off[1] + k];
       if (b1.c0 == 0.0f) continue;   // padding
       if (k >= 32 * P.nkc[0]) {
-        same = false;
+        same = pair[0] = pair[1] = false;
         break;
       }
+      const Src &b0 = src[P.desc_off[0] + k];
       const int32_t *d0 = &im.desc[4 * ((size_t)P.desc_off[0] + k)], *d1 = &im.desc[4 * ((size_t)P.desc_off[1] + k)];
-      same = d0[0] == d1[0] && d0[1] == d1[1];
+      same = same && d0[0] == d1[0] && d0[1] == d1[1];
+      const bool copies = b0.c1 == 0.0f && b1.c1 == 0.0f && b0.s0 >= 0;
+      pair[0] = pair[0] && copies && b1.s0 == b0.s0 + 1;
+      pair[1] = pair[1] && copies && b1.s0 == b0.s0 - 1;
     }
-    P.same_src = same ? 1 : 0;
+    for (int s = 0; s < 2; ++s)
+      for (int k = 0; k < 32 * P.nkc[0] && pair[s]; ++k) {
+        const Src &b0 = src[P.desc_off[0] + k];
+        if (b0.c0 == 0.0f) continue;
+        const int start = s == 0 ? b0.s0 : b0.s0 - 1;
+        pair[s] = b0.c1 == 0.0f && start >= 0 && start % 2 == 0 && start + 1 < L.n;
+      }
+    if (same) {
+      P.src_mode = 1;
+    } else if (pair[0] || pair[1]) {
+      P.src_mode = 3;
+      P.pair_swap = pair[0] ? 0 : 1;
+      if (P.pair_swap)
+        for (int k = 0; k < 32 * P.nkc[0]; ++k) {
+          int32_t *d0 = &im.desc[4 * ((size_t)P.desc_off[0] + k)];
+          if (src[P.desc_off[0] + k].c0 != 0.0f) d0[0] -= esz;
+        }
+    }
   }
   P.desc_words = 4 * entries;
   // B fragments (forward and inverse alike: M[k][c] = Mt[c][k] of the stored transpose),
