@@ -7,9 +7,10 @@ same order, so the forms agree bit for bit (GFT_LARGE_FORM forces a form); both 
 the aligned FP64 oracle within the block precision's bound (BF16 <= 2e-2, split BF16 <=
 1e-5).  Cases: the weighted symmetric 1024-path (two 512-node blocks of the sums and
 differences of the same Haar units: one load per pair), the 1023-path (a V_Z node scaled by
-sqrt 2, blocks of 512 and 511), a 1000-cycle, and a 600-node path planned without a stage
-(one dense block); the inverse directions stage coefficients (a copy per block, two source
-sets) and run the Haar stage on the results in LDS.
+sqrt 2, blocks of 512 and 511), a uniform 1000-path (its inverse loads the two blocks'
+alternating coefficients in pairs), a 1000-cycle, and a 600-node path planned without a
+stage (one dense block); the inverse directions stage coefficients (a copy per block) and
+run the Haar stage on the results in LDS.
 """
 import ctypes
 
@@ -34,6 +35,9 @@ def _nostage_path(n):
 
 GRAPHS = {
     "wpath1024": wl.config5b_graph,
+    # uniform path: the sum and difference blocks' eigenvalues alternate strictly, so the
+    # inverse reads each pair of neighbouring coefficients with one load (pair mode)
+    "path1000": lambda: wl.path(1000),
     "wpath1023": lambda: wl.weighted_symmetric_path(1023, wl.rng_for(5, 8)),
     "cycle1000": lambda: wl.cycle(1000),
     "nostage600": lambda: _nostage_path(600),
