@@ -76,6 +76,43 @@ def test_onepass_bit_equal_to_three_passes_and_oracle(name, precision, monkeypat
     assert O.relative_error(to_np(xr), O.inverse(to_np(y).astype(np.float64), Ua)) <= TOL[precision]
 
 
+def _bipartite_nosym(n=400):
+    """A bipartite graph with no symmetry: under the normalized Laplacian its plan has no
+    left stage, n/2 right Haar units and two blocks (Sec. III), so the forward runs the right
+    stage on the result slab and the inverse stages sums and differences of coefficients."""
+    rng = np.random.default_rng(5)
+    a = n // 2
+    E = {}
+    for i in range(a):
+        for j in rng.choice(n - a, 6, replace=False):
+            E[(i, a + int(j))] = rng.uniform(0.5, 1.5)
+    for i in range(a - 1):                       # connected
+        E.setdefault((i, a + i), 1.0)
+        E.setdefault((i + 1, a + i), 1.0)
+    edges = list(E)
+    return wl._graph(n, edges, np.array([E[e] for e in edges]), None, [], "bipartite_nosym")
+
+
+@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+def test_onepass_right_haar_units(precision, monkeypatch):
+    dev = device()
+    g = _bipartite_nosym()
+    one = _plan(g, precision, "onepass", monkeypatch, laplacian="normalized")
+    three = _plan(g, precision, "passes", monkeypatch, laplacian="normalized")
+    st = one.info()
+    assert st["num_stages"] == 0 and st["num_right_units"] == g.n // 2 and st["num_blocks"] == 2
+    assert one.tuning()["variant"] == 2
+    X = wl.gaussian(777, g.n, wl.rng_for(5, g.n, 67))
+    x = torch.from_numpy(X).to(dev)
+    y = one.forward(x)
+    assert torch.equal(y, three.forward(x))
+    xr = one.inverse(y)
+    assert torch.equal(xr, three.inverse(y))
+    _, Ua = aligned_oracle_basis(g, one.basis(), sv_tol=1e-8, laplacian="normalized")
+    assert O.relative_error(to_np(y), O.forward(X.astype(np.float64), Ua)) <= TOL[precision]
+    assert O.relative_error(to_np(xr), O.inverse(to_np(y).astype(np.float64), Ua)) <= TOL[precision]
+
+
 @pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
 def test_onepass_epilogue_form_and_ragged_counts(precision, monkeypatch):
     """Signal counts around the panel heights (one partial panel, exact panels, a panel
