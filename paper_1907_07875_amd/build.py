@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libgft.so")
 
-SOURCES = ["gft_kernels.hip", "gft_batch16.hip", "gft_butterfly.hip", "gft_large.hip", "gft_onepass.hip", "gft_onepass3.hip", "gft_product.hip", "gft_product16.hip", "gft_copy.hip", "capi.cpp",
+SOURCES = ["gft_kernels.hip", "gft_batch16.hip", "gft_butterfly.hip", "gft_large.hip", "gft_onepass.hip", "gft_onepass0.hip", "gft_onepass3.hip", "gft_product.hip", "gft_product16.hip", "gft_copy.hip", "capi.cpp",
            "plan.cpp", "program.cpp", "eigen.cpp", "tune.cpp"]
 
 # Packed FP32 instructions stay disabled: hipcc emits them from plain float code and some

@@ -178,13 +178,17 @@ namespace gft {
 //     and their sources are neighbours: the inverse of one-stage plans whose two blocks'
 //     coefficients alternate), the first value to block pair_swap, the second to the other;
 //     2, one set per block;
-//   frag: the block matrices in MFMA B-operand order, one 16x16x32 fragment (32 k x 16
-//     columns, 16 bytes per lane: column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e)
-//     per (kc, nt), at fragment frag_off[b] + kc * ntl[b] + nt (split blocks: a hi and a lo
-//     fragment, 2 fragments per index); the rounding is the same as the three-pass GEMM's;
+//   frag: the block matrices in MFMA B-operand order, 16 bytes per lane per fragment, per
+//     (kc, nt) at index frag_off[b] + kc * ntl[b] + nt: BF16 blocks, one 16x16x32 fragment
+//     (column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e); split blocks, a hi and a lo
+//     fragment of that shape; FP32 blocks, two halves h = 0, 1 of four 16x16x4 k groups
+//     (k = 32 kc + 16 h + 4 (lane / 16) + e, e < 4: the k order of the three-pass FP32 GEMM);
+//     the rounding is the same as the three-pass GEMM's;
 //   the last pass: num_stages3 stages (stages3: offset, count pairs; ops3: i | j << 16,
 //     j = 0xffff: scale by sqrt 2) on workspace columns, 16 rows at a time, then output
-//     column c takes slab column gather3[c] (-1: zero).
+//     column c takes slab column gather3[c] (-1: zero); ops3 and gather3 are read from LDS
+//     copies, so that the last pass issues no global loads (their waits would also wait for
+//     the output stores before them).
 struct OnePass {
   int32_t n;              // input and output row length
   int32_t ldw;            // workspace columns
@@ -195,6 +199,7 @@ struct OnePass {
   int32_t pair_swap;      // src_mode 3: 1 when the second block's source comes first
   int32_t num_stages3;
   int32_t desc_words;     // int32 words of desc (copied to LDS)
+  int32_t ops3_words;     // entries of ops3 (copied to LDS, with gather3)
   int32_t K[2], col[2], nkc[2], ntl[2], desc_off[2], frag_off[2];
   int32_t wblk[8], wnt0[8], wcnt[8];
   const int32_t *desc;

@@ -57,6 +57,10 @@ int onepass_rows(int precision);
 int onepass_occupancy(const OnePass &P, int precision, bool in16);   // resident workgroups per CU
 hipError_t launch_onepass(const OnePass &P, int precision, const void *in, void *out, int64_t S, bool in16,
                           bool out16, int grid, hipStream_t stream);
+// FP32 instances (gft_onepass0.hip)
+int onepass_occupancy_f32(const OnePass &P, bool in16);
+hipError_t launch_onepass_f32(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16,
+                              int grid, hipStream_t st);
 // split-BF16 instances (gft_onepass3.hip)
 int onepass_occupancy_split(const OnePass &P, bool in16);
 hipError_t launch_onepass_split(const OnePass &P, const void *in, void *out, int64_t S, bool in16, bool out16,

@@ -1,5 +1,5 @@
 // Device code of the one-pass large-signal GFT (see OnePass in device_program.hpp); the
-// BF16 and split-BF16 kernels are instantiated in translation units of their own.
+// FP32, BF16 and split-BF16 kernels are instantiated in translation units of their own.
 //
 // The three-pass form moves every signal through a workspace twice: the first pass writes
 // the staged row, the GEMM reads it and writes the block outputs, the last pass gathers
@@ -8,13 +8,14 @@
 // columns of one workgroup, this kernel does all three in one visit of the signal:
 //
 //   * a workgroup owns 16*MT signal rows and every workspace column; its k loop runs over
-//     32-wide k steps of the blocks;
+//     32-wide k steps of the blocks (FP32 blocks: eight 16x16x4 products per k step, in
+//     two halves of 16 k);
 //   * staging: the inputs of a k step are loaded one or two steps ahead, while earlier
 //     steps' MFMAs run (32-bit byte offsets from the panel's first row: no 64-bit address
 //     arithmetic per value); the first-pass values (x_i + x_phi(i), x_i - x_phi(i), sqrt(2) x_c of a
 //     V_Z node, or a copy: a multiply and a fused multiply-add with the entry's
-//     coefficients) are rounded to BF16 (split: a hi and a lo part) into a double-buffered
-//     LDS tile, one barrier per k step;
+//     coefficients) are rounded to BF16 (split: a hi and a lo part; FP32 blocks: kept as
+//     they are) into a double-buffered LDS tile, one barrier per k step;
 //   * products: wave w holds the accumulators of its block's n-tiles for all the rows (up
 //     to 8 tiles of 16 columns x MT tiles of 16 rows) and reads its B fragments straight
 //     from global memory in MFMA operand order (the matrices are shared by every
@@ -46,9 +47,14 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;
 constexpr int kARow = 80;                 // LDS bytes of a staged row: 32 BF16 k + 16 of padding
+constexpr int kARow32 = 144;              // the same for FP32 blocks: 32 FP32 k + 16 of padding
 constexpr float kSqrt2f = 1.41421356237309504880f;
 // Largest tables (at most 1024 workspace columns: two blocks of at most 32 k steps).
 constexpr int kMaxEntries = 1088;
+constexpr int kMaxOps3 = 2048;            // last-pass Haar operations
+constexpr int kMaxN = 1024;               // row length
+// Word 3 of a raw (unswizzled, stride 0) buffer resource on gfx9-family GPUs.
+constexpr int kBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
   const uint32_t u = __float_as_uint(x);
@@ -86,18 +92,19 @@ __device__ __forceinline__ float first_pass(float c0, float c1, float x0, float 
   return c0 != 0.0f ? v : 0.0f;
 }
 
-// Shapes: a panel of 64 rows (BF16 blocks) or 48 rows (split blocks: two operand planes)
-// per workgroup, one workgroup per CU (the accumulators of a panel fill half the register
-// file); the inputs of a k step are loaded D steps ahead (a ring of D register sets): two
-// with one source set or pairs, one with two sets (a second set of two would spill;
-// measured slower).
+// Shapes: a panel of 64 rows (FP32 and BF16 blocks) or 48 rows (split blocks: two operand
+// planes) per workgroup, one workgroup per CU (the accumulators of a panel fill half the
+// register file); the inputs of a k step are loaded D steps ahead (a ring of D register
+// sets): two with one source set or pairs, one with two sets (a second set of two would
+// spill; measured slower) and with FP32 blocks (a k step is 256 products per wave, long
+// enough to cover the loads; two would spill).
 template <int PREC, int NS> struct OnePassShape {
   static constexpr int MT = PREC == 3 ? 3 : 4;     // 16-row tiles per panel
   static constexpr int SR = 16;                    // result slab rows
-  static constexpr int D = NS == 2 ? 1 : 2;
+  static constexpr int D = NS == 2 || PREC == 0 ? 1 : 2;
 };
 
-// PREC: GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: how a k step's inputs are loaded
+// PREC: GFT_FP32 (0), GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: how a k step's inputs are loaded
 // (OnePass::src_mode: 1, one set for both blocks; 2, one set per block; 3, one load of two
 // adjacent values per entry, the first for block 0, the second for block 1).  IN16: the
 // input rows hold BF16.  out16: the output rows hold BF16.
@@ -107,8 +114,10 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   constexpr int MT = OnePassShape<PREC, NS>::MT;
   constexpr int D = OnePassShape<PREC, NS>::D;
   constexpr int BM = 16 * MT;
-  constexpr int PL = PREC == 3 ? 2 : 1;                              // operand planes
-  constexpr int kPlane = BM * kARow;
+  constexpr int PL = PREC == 3 ? 2 : 1;                              // LDS operand planes
+  constexpr int PLB = PREC == 1 ? 1 : 2;                             // fragments per (kc, nt)
+  constexpr int AROW = PREC == 0 ? kARow32 : kARow;
+  constexpr int kPlane = BM * AROW;
   constexpr int ESZ = IN16 ? 2 : 4;
   constexpr int SR = OnePassShape<PREC, NS>::SR;
   constexpr int ITEMS = (BM * 16 + kThreads - 1) / kThreads;         // (row, k pair) items
@@ -116,19 +125,42 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   __shared__ __attribute__((aligned(16))) int32_t sdesc[4 * kMaxEntries];
   __shared__ __attribute__((aligned(16))) char abuf[2 * 2 * PL * kPlane];
   __shared__ __attribute__((aligned(16))) float slab[SR * (1024 + 4)];
+  __shared__ __attribute__((aligned(16))) int32_t sgather[kMaxN];
+  __shared__ uint32_t sops[kMaxOps3];
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15, kp = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: per-wave fields in SGPRs
   const int nb = P.nblocks, n = P.n;
   constexpr int buf_bytes = 2 * PL * kPlane;                        // room for two blocks
   const int sstr = P.slab_stride;
   for (int i = tid; i < P.desc_words; i += kThreads) sdesc[i] = P.desc[i];
+  for (int i = tid; i < n; i += kThreads) sgather[i] = P.gather3[i];
+  for (int i = tid; i < P.ops3_words; i += kThreads) sops[i] = P.ops3[i];
   __syncthreads();
 
   const int wb = P.wblk[wave], nt0 = P.wnt0[wave], wcnt = P.wcnt[wave];
   const int wbs = wb >= 0 ? wb : 0;
   const int wfo = P.frag_off[wbs], wntl = P.ntl[wbs], wK = P.K[wbs], wcol = P.col[wbs], wnk = P.nkc[wbs];
-  const u32x4 *frag = reinterpret_cast<const u32x4 *>(P.frag);
+  // the B fragments (a table of at most a few MB: 32-bit offsets; every index below is
+  // clamped to a valid fragment)
+  const __amdgpu_buffer_rsrc_t frsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(P.frag), (short)0, -1, kBufferWord3);
+  const uint32_t flane = 16u * (uint32_t)lane;
   const int64_t npanels = (S + BM - 1) / BM;
+  // (buffer loads: the fragment's byte offset is uniform and goes in a scalar register,
+  // the lane's 16-byte slot is one shared vector register; global loads would hold a
+  // 64-bit address per tile and step)
+  auto frag_at = [&](int kc, int j, int pl) {
+    const int nt = nt0 + (j < wcnt ? j : (wcnt > 0 ? wcnt - 1 : 0));   // always a valid tile
+    const int off = ((wfo + kc * wntl + nt) * PLB + pl) * 1024;
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(frsrc, flane, off, 0));
+  };
+  // the first k chunk's fragments; each panel's last k step loads them again for the next
+  u32x4 bh[8], bl[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    bh[j] = frag_at(0, j, 0);
+    if constexpr (PREC == 3) bl[j] = frag_at(0, j, 1);
+  }
 
   for (int64_t panel = blockIdx.x; panel < npanels; panel += gridDim.x) {
     const int64_t row0 = panel * BM;
@@ -195,12 +227,17 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
             else
               v[e] = first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1]);
           }
-          const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
-          *reinterpret_cast<uint32_t *>(plane + row * kARow + 4 * kp) = (h0 | (h1 << 16)) & keep;
-          if constexpr (PL == 2) {
-            const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
-            const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
-            *reinterpret_cast<uint32_t *>(plane + kPlane + row * kARow + 4 * kp) = (l0 | (l1 << 16)) & keep;
+          if constexpr (PREC == 0) {
+            *reinterpret_cast<u32x2 *>(plane + row * AROW + 8 * kp) =
+                u32x2{__float_as_uint(v[0]) & keep, __float_as_uint(v[1]) & keep};
+          } else {
+            const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
+            *reinterpret_cast<uint32_t *>(plane + row * AROW + 4 * kp) = (h0 | (h1 << 16)) & keep;
+            if constexpr (PL == 2) {
+              const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
+              const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
+              *reinterpret_cast<uint32_t *>(plane + kPlane + row * AROW + 4 * kp) = (l0 | (l1 << 16)) & keep;
+            }
           }
         }
       }
@@ -211,22 +248,12 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) stage_unit(kt, buf, x, b, it);
     };
-    auto frag_at = [&](int kc, int j, int pl) {
-      const int nt = nt0 + (j < wcnt ? j : (wcnt > 0 ? wcnt - 1 : 0));   // always a valid tile
-      return frag[(((size_t)wfo + (size_t)kc * wntl + nt) * PL + pl) * 64 + lane];
-    };
 
     floatx4 acc[MT][8];
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    u32x4 bh[8], bl[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      bh[j] = frag_at(0, j, 0);
-      if constexpr (PL == 2) bl[j] = frag_at(0, j, 1);
-    }
 #pragma unroll
     for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
     stage_store(0, 0, sx[0]);
@@ -243,37 +270,73 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       // wave's count (and every tile of an idle wave) repeat a valid fragment into
       // accumulators that are never stored.
       const char *ab = abuf + (kt & 1) * buf_bytes + wbs * PL * kPlane;
-      u32x4 ah[MT], al[MT];
+      // next k chunk; past the wave's last one, the first (the steps left multiply zero
+      // tiles, and the next panel starts with it)
+      const int kn = kt + 1 < wnk ? kt + 1 : 0;
+      if constexpr (PREC == 0) {
+        // FP32 blocks: two halves of 16 k, each four 16x16x4 products per tile (lane group g
+        // gives k = 16 h + 4 g + kk of MFMA kk: the three-pass FP32 GEMM's k order).  One
+        // fragment register per tile: the second half's fragment of this step is loaded
+        // right after the first half's last use, the next step's first half after the second.
+        // (the staging units go in the second half, so that this step's input loads, issued
+        // at its start, have had half a step to arrive)
+        const int kc = kt < wnk ? kt : wnk - 1;
+        constexpr int kUnits = 2 * ITEMS, kEvery = 8 / kUnits;
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        ah[i] = *reinterpret_cast<const u32x4 *>(ab + (16 * i + r) * kARow + 16 * g);
-        if constexpr (PL == 2) al[i] = *reinterpret_cast<const u32x4 *>(ab + kPlane + (16 * i + r) * kARow + 16 * g);
-      }
-      const int kn = kt + 1 < wnk ? kt + 1 : wnk - 1;   // next k chunk (the last one re-read)
-      // The staging of step kt + 1 into the other buffer (last read before the previous
-      // barrier; past the last step it writes zeros that nothing reads) is independent of
-      // this step's products: its 2 x ITEMS units go between the MFMA groups, fenced from
-      // the scheduler, so the matrix core runs each group while the wave issues the VALU
-      // work of a unit.
-      constexpr int kUnits = 2 * ITEMS, kEvery = 8 / kUnits;
+        for (int h = 0; h < 2; ++h) {
+          floatx4 af[MT];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+          for (int i = 0; i < MT; ++i)
+            af[i] = *reinterpret_cast<const floatx4 *>(ab + (16 * i + r) * AROW + 64 * h + 16 * g);
 #pragma unroll
-        for (int i = 0; i < MT; ++i) {
-          const bf16x8 a = __builtin_bit_cast(bf16x8, ah[i]), b = __builtin_bit_cast(bf16x8, bh[j]);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-          if constexpr (PL == 2) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]), b, acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 8; ++j) {
+            const floatx4 bf = __builtin_bit_cast(floatx4, bh[j]);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+              for (int i = 0; i < MT; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], bf[kk], acc[i][j], 0, 0, 0);
+            bh[j] = h == 0 ? frag_at(kc, j, 1) : frag_at(kn, j, 0);
+            if (h == 1 && j % kEvery == kEvery - 1) {
+              const int u = j / kEvery;
+              __builtin_amdgcn_sched_barrier(0);
+              stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
+              __builtin_amdgcn_sched_barrier(0);
+            }
           }
         }
-        bh[j] = frag_at(kn, j, 0);
-        if constexpr (PL == 2) bl[j] = frag_at(kn, j, 1);
-        if (j % kEvery == kEvery - 1) {
-          const int u = j / kEvery;
-          __builtin_amdgcn_sched_barrier(0);
-          stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
-          __builtin_amdgcn_sched_barrier(0);
+      } else {
+        u32x4 ah[MT], al[MT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          ah[i] = *reinterpret_cast<const u32x4 *>(ab + (16 * i + r) * AROW + 16 * g);
+          if constexpr (PL == 2) al[i] = *reinterpret_cast<const u32x4 *>(ab + kPlane + (16 * i + r) * AROW + 16 * g);
+        }
+        // The staging of step kt + 1 into the other buffer (last read before the previous
+        // barrier; past the last step it writes zeros that nothing reads) is independent of
+        // this step's products: its 2 x ITEMS units go between the MFMA groups, fenced from
+        // the scheduler, so the matrix core runs each group while the wave issues the VALU
+        // work of a unit.
+        constexpr int kUnits = 2 * ITEMS, kEvery = 8 / kUnits;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+#pragma unroll
+          for (int i = 0; i < MT; ++i) {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, ah[i]), b = __builtin_bit_cast(bf16x8, bh[j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            if constexpr (PL == 2) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]), b, acc[i][j], 0, 0, 0);
+            }
+          }
+          bh[j] = frag_at(kn, j, 0);
+          if constexpr (PL == 2) bl[j] = frag_at(kn, j, 1);
+          if (j % kEvery == kEvery - 1) {
+            const int u = j / kEvery;
+            __builtin_amdgcn_sched_barrier(0);
+            stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
       __syncthreads();
@@ -310,19 +373,28 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       for (int st = 0; st < P.num_stages3; ++st) {
         const int off = P.stages3[2 * st], cnt = P.stages3[2 * st + 1];
         for (int u = tid; u < cnt; u += kThreads) {
-          const uint32_t op = P.ops3[off + u];
+          const uint32_t op = sops[off + u];
           const int i = (int)(op & 0xffffu), j = (int)(op >> 16);
+          // every row's operands read before any is written (the rows do not alias, which
+          // the compiler cannot see: in one loop it would wait for each row in turn)
           if (j != 0xffff) {
-#pragma unroll 4
+            float a[SR], b[SR];
+#pragma unroll
             for (int rr = 0; rr < SR; ++rr) {
-              float *row = slab + rr * sstr;
-              const float a = row[i], b = row[j];
-              row[i] = a + b;
-              row[j] = a - b;
+              a[rr] = slab[rr * sstr + i];
+              b[rr] = slab[rr * sstr + j];
+            }
+#pragma unroll
+            for (int rr = 0; rr < SR; ++rr) {
+              slab[rr * sstr + i] = a[rr] + b[rr];
+              slab[rr * sstr + j] = a[rr] - b[rr];
             }
           } else {
-#pragma unroll 4
-            for (int rr = 0; rr < SR; ++rr) slab[rr * sstr + i] *= kSqrt2f;
+            float a[SR];
+#pragma unroll
+            for (int rr = 0; rr < SR; ++rr) a[rr] = slab[rr * sstr + i];
+#pragma unroll
+            for (int rr = 0; rr < SR; ++rr) slab[rr * sstr + i] = a[rr] * kSqrt2f;
           }
         }
         __syncthreads();
@@ -331,10 +403,11 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       const int nr = S - rb < SR ? (int)(S - rb) : SR;
       if ((n & 3) == 0) {
         const int nq = n >> 2;
+#pragma unroll 4
         for (int idx = tid; idx < SR * nq; idx += kThreads) {
           const int rr = idx / nq, q = idx - rr * nq;
           if (rr >= nr) continue;
-          const int4 gi = *reinterpret_cast<const int4 *>(P.gather3 + 4 * q);
+          const int4 gi = *reinterpret_cast<const int4 *>(sgather + 4 * q);
           const float *srow = slab + rr * sstr;
           floatx4 v;
           v[0] = gi.x >= 0 ? srow[gi.x] : 0.0f;
@@ -353,7 +426,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         for (int idx = tid; idx < SR * n; idx += kThreads) {
           const int rr = idx / n, c = idx - rr * n;
           if (rr >= nr) continue;
-          const int gi = P.gather3[c];
+          const int gi = sgather[c];
           const float v = gi >= 0 ? slab[rr * sstr + gi] : 0.0f;
           const int64_t o = (rb + rr) * n + c;
           if (out16) static_cast<uint16_t *>(out)[o] = (uint16_t)bf16_bits(v);

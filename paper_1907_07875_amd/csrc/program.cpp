@@ -820,11 +820,12 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
 namespace gft {
 
 bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out) {
-  if (precision != GFT_BF16 && precision != GFT_SPLIT_BF16) return false;
+  if (precision != GFT_FP32 && precision != GFT_BF16 && precision != GFT_SPLIT_BF16) return false;
   const PermPass &P1 = L.pass[0];
   const int nb = (int)L.blocks.size();
   const int esz = in16 ? 2 : 4;
-  if (P1.num_stages > 1 || nb < 1 || nb > 2 || L.ldw > 1024) return false;
+  if (P1.num_stages > 1 || nb < 1 || nb > 2 || L.ldw > 1024 || L.n > kOnePassMaxN) return false;
+  if (L.ops[1].size() > (size_t)kOnePassMaxOps3) return false;
   OnePassImage im;
   OnePass &P = im.P;
   im.mt = precision == GFT_SPLIT_BF16 ? 3 : 4;   // split: two operand planes, fewer rows
@@ -833,6 +834,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   P.slab_stride = L.ldw + 4;
   P.nblocks = nb;
   P.num_stages3 = L.pass[1].num_stages;
+  P.ops3_words = (int)L.ops[1].size();
   // waves: each block's 16-column tiles over the fewest waves of at most 8 tiles each
   int wave = 0, entries = 0, frags = 0;
   for (int w = 0; w < 8; ++w) P.wblk[w] = -1, P.wnt0[w] = 0, P.wcnt[w] = 0;
@@ -943,9 +945,26 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   P.desc_words = 4 * entries;
   // B fragments (forward and inverse alike: M[k][c] = Mt[c][k] of the stored transpose),
   // rounded as the three-pass GEMM rounds them
-  const int PL = precision == GFT_SPLIT_BF16 ? 2 : 1;
+  const int PL = precision == GFT_BF16 ? 1 : 2;
   im.frag.assign((size_t)frags * PL * 64 * 4, 0u);
-  for (int b = 0; b < nb; ++b) {
+  if (precision == GFT_FP32)
+    for (int b = 0; b < nb; ++b) {
+      const LBlock &B = L.blocks[b];
+      for (int kc = 0; kc < P.nkc[b]; ++kc)
+        for (int nt = 0; nt < P.ntl[b]; ++nt)
+          for (int h = 0; h < 2; ++h)
+            for (int lane = 0; lane < 64; ++lane)
+              for (int e = 0; e < 4; ++e) {
+                const int k = 32 * kc + 16 * h + 4 * (lane / 16) + e, c = 16 * nt + lane % 16;
+                float m = 0.0f;
+                if (k < B.size && c < B.size) m = L.mats[(size_t)B.mat + (size_t)c * B.ld + k];
+                uint32_t w;
+                std::memcpy(&w, &m, 4);
+                const size_t f = (size_t)P.frag_off[b] + (size_t)kc * P.ntl[b] + nt;
+                im.frag[((f * 2 + h) * 64 + lane) * 4 + e] = w;
+              }
+    }
+  for (int b = 0; b < nb && precision != GFT_FP32; ++b) {
     const LBlock &B = L.blocks[b];
     for (int kc = 0; kc < P.nkc[b]; ++kc)
       for (int nt = 0; nt < P.ntl[b]; ++nt)

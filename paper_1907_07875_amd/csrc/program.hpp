@@ -92,8 +92,10 @@ struct OnePassImage {
 // two blocks' k steps, and k steps.
 constexpr int kOnePassMaxEntries = 1088;
 constexpr int kOnePassMaxSteps = 32;
+constexpr int kOnePassMaxOps3 = 2048;   // last-pass Haar operations (all its stages)
+constexpr int kOnePassMaxN = 1024;      // row length (the output gather table)
 
-// The one-pass form of large image `L` (built for `precision`: GFT_BF16 or GFT_SPLIT_BF16,
+// The one-pass form of large image `L` (built for `precision`: GFT_FP32, GFT_BF16 or GFT_SPLIT_BF16,
 // with L's host matrices still present; in16: the direction's input rows hold BF16).
 // Returns false when the plan does not fit it: a first pass with more than one stage, more
 // than two leaf blocks, or more columns than eight waves hold.

@@ -4,8 +4,8 @@ output order) in LDS, all in one kernel with no workspace array.
 
 The one-pass form computes every value with the operations of the three-pass form in the
 same order, so the forms agree bit for bit (GFT_LARGE_FORM forces a form); both agree with
-the aligned FP64 oracle within the block precision's bound (BF16 <= 2e-2, split BF16 <=
-1e-5).  Cases: the weighted symmetric 1024-path (two 512-node blocks of the sums and
+the aligned FP64 oracle within the block precision's bound (FP32 and split BF16 <= 1e-5,
+BF16 <= 2e-2).  Cases: the weighted symmetric 1024-path (two 512-node blocks of the sums and
 differences of the same Haar units: one load per pair), the 1023-path (a V_Z node scaled by
 sqrt 2, blocks of 512 and 511), a uniform 1000-path (its inverse loads the two blocks'
 alternating coefficients in pairs), a 1000-cycle, and a 600-node path planned without a
@@ -24,7 +24,7 @@ from tests.gpu_helpers import aligned_oracle_basis, device, to_np, torch
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"bf16": 2e-2, "split_bf16": 1e-5}
+TOL = {"fp32": 1e-5, "bf16": 2e-2, "split_bf16": 1e-5}
 
 
 def _nostage_path(n):
@@ -52,7 +52,7 @@ def _plan(g, precision, form, monkeypatch, **kw):
     return plan
 
 
-@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split_bf16"])
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_onepass_bit_equal_to_three_passes_and_oracle(name, precision, monkeypatch):
     dev = device()
@@ -93,7 +93,7 @@ def _bipartite_nosym(n=400):
     return wl._graph(n, edges, np.array([E[e] for e in edges]), None, [], "bipartite_nosym")
 
 
-@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split_bf16"])
 def test_onepass_right_haar_units(precision, monkeypatch):
     dev = device()
     g = _bipartite_nosym()
@@ -113,7 +113,7 @@ def test_onepass_right_haar_units(precision, monkeypatch):
     assert O.relative_error(to_np(xr), O.inverse(to_np(y).astype(np.float64), Ua)) <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split_bf16"])
 def test_onepass_epilogue_form_and_ragged_counts(precision, monkeypatch):
     """Signal counts around the panel heights (one partial panel, exact panels, a panel
     plus one row) and an empty batch; the GEMM-epilogue form agrees too."""
@@ -132,14 +132,15 @@ def test_onepass_epilogue_form_and_ragged_counts(precision, monkeypatch):
     assert one.forward(torch.zeros((0, g.n), device=dev)).shape == (0, g.n)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("din,dout", [("bf16", "bf16"), ("bf16", "fp32"), ("fp32", "bf16")])
-def test_onepass_bf16_storage(din, dout, monkeypatch):
+def test_onepass_bf16_storage(din, dout, precision, monkeypatch):
     """BF16 signals and/or coefficients: bit-equal to the three-pass form with the same
     storage."""
     dev = device()
     g = wl.config5b_graph()
-    one = _plan(g, "bf16", "onepass", monkeypatch, in_dtype=din, out_dtype=dout)
-    three = _plan(g, "bf16", "passes", monkeypatch, in_dtype=din, out_dtype=dout)
+    one = _plan(g, precision, "onepass", monkeypatch, in_dtype=din, out_dtype=dout)
+    three = _plan(g, precision, "passes", monkeypatch, in_dtype=din, out_dtype=dout)
     assert one.tuning()["variant"] == 2
     td = {"bf16": torch.bfloat16, "fp32": torch.float32}
     X = wl.gaussian(333, g.n, wl.rng_for(5, 5, 333))

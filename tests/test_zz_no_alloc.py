@@ -28,10 +28,9 @@ def _noalloc(plan, x, out, direction):
 
 
 CASES = [
-    # (graph, precision, engine, signals of the two calls); with FP32 blocks the 1024-node
-    # path's forward writes the output order from the GEMM (W1 only) and its inverse runs
-    # the stage pass after the GEMM (W1 and W2): at most 8192 signals per call in both
-    # directions; with BF16 and split blocks it takes the one-pass form (no workspace)
+    # (graph, precision, engine, signals of the two calls); the 1024-node path's plans take
+    # the one-pass form (no workspace) or, as tuned, a three-pass form: with FP32 blocks
+    # at most 8192 signals per call fit the scratch in both directions
     ("wpath1024", "fp32", "auto", (8191, 4097)),         # large engine
     ("wpath1024", "bf16", "auto", (8192, 129)),          # one pass, or BF16 workspace
     ("wpath1024", "split_bf16", "auto", (5000, 1)),
@@ -74,13 +73,17 @@ def test_noalloc_matches_allocating_apply(case):
         assert torch.equal(outs[d][1], refs[d][1]), f"direction {d}: second (smaller) call differs"
 
 
-def test_noalloc_rejects_calls_beyond_the_scratch():
+def test_noalloc_rejects_calls_beyond_the_scratch(monkeypatch):
     dev = device()
     g = wl.config5b_graph()
-    plan = G.Plan.from_graph(g)
+    # a three-pass form (the one-pass form has no workspace and so no limit)
+    monkeypatch.setenv("GFT_LARGE_FORM", "passes")
+    plan = G.Plan.from_graph(g, autotune=False)
     plan.prepare()
-    # forward: W1 only when the GEMM writes the output order (the tuned variant), else W1, W2
-    per_signal = g.n * 4 * (1 if plan.tuning()["variant"] == 1 else 2)
+    monkeypatch.delenv("GFT_LARGE_FORM")
+    assert plan.tuning()["variant"] == 0
+    # the three passes' workspace: W1 and W2
+    per_signal = g.n * 4 * 2
     limit = SCRATCH_BYTES // per_signal
     x = torch.zeros((limit + 1, g.n), device=dev)
     y = torch.empty_like(x)
@@ -88,7 +91,6 @@ def test_noalloc_rejects_calls_beyond_the_scratch():
     st = _noalloc(plan, x, y, 0)
     assert G.STATUS[st] == "GFT_ERR_INVALID_ARG"
     assert f"at most {limit} signals" in G.load_library().gft_last_error().decode()
-    # the inverse runs its stage pass after the GEMM: W1 and W2
     inv = SCRATCH_BYTES // (g.n * 4 * 2)
     assert _noalloc(plan, x[:inv], y[:inv], 1) == 0
     st = _noalloc(plan, x[:inv + 1], y[:inv + 1], 1)
