@@ -202,51 +202,61 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     // ---- staging: first-pass values of k step kt into LDS buffer buf (zeros for k steps
     // past a block's end, so that its waves may multiply them in with no effect)
     // (both block slots always: with one block the second repeats the first into a plane
-    // nothing reads, so that the staging is branch-free and can interleave with products)
-    auto stage_unit = [&](int kt, int buf, const float (&x)[NX][ITEMS][2][2], int b, int it) {
-      {
-        const int bb = b < nb ? b : nb - 1;
-        const bool live = kt < P.nkc[bb];
-        const int kk = live ? kt : P.nkc[bb] - 1;
-        const uint32_t keep = live ? 0xffffffffu : 0u;   // zeros past the block's end (no branch)
-        const int s = NS == 2 ? b : 0;
-        const int32_t *d = sdesc + 4 * (P.desc_off[bb] + 32 * kk + 2 * kp);
-        const u32x4 d0 = *reinterpret_cast<const u32x4 *>(d), d1 = *reinterpret_cast<const u32x4 *>(d + 4);
-        char *plane = abuf + buf * buf_bytes + b * PL * kPlane;
-        {
-          const int idx = tid + kThreads * it;
-          if ((BM * 16) % kThreads != 0 && idx >= BM * 16) return;   // MT = 3: rows 48 .. 63 do not exist
-          const int row = idx >> 4;
-          float v[2];
+    // nothing reads, so that the staging is branch-free and can interleave with products).
+    // The coefficients of a block's entries at k step kt (the same for every row) are read
+    // from LDS at the start of the k step before, so that no unit waits for them.
+    struct Coef {
+      float c[4];      // c0, c1 of the lane's two entries
+      uint32_t keep;   // all ones, or zeros past the block's end (no branch)
+    };
+    auto stage_coef = [&](int kt, int b) {
+      const int bb = b < nb ? b : nb - 1;
+      const bool live = kt < P.nkc[bb];
+      const int kk = live ? kt : P.nkc[bb] - 1;
+      const int32_t *d = sdesc + 4 * (P.desc_off[bb] + 32 * kk + 2 * kp);
+      const u32x2 w0 = *reinterpret_cast<const u32x2 *>(d + 2), w1 = *reinterpret_cast<const u32x2 *>(d + 6);
+      Coef cf;
+      cf.c[0] = __uint_as_float(w0[0]);
+      cf.c[1] = __uint_as_float(w0[1]);
+      cf.c[2] = __uint_as_float(w1[0]);
+      cf.c[3] = __uint_as_float(w1[1]);
+      cf.keep = live ? 0xffffffffu : 0u;
+      return cf;
+    };
+    auto stage_unit = [&](const Coef &cf, int buf, const float (&x)[NX][ITEMS][2][2], int b, int it) {
+      const uint32_t keep = cf.keep;
+      const int s = NS == 2 ? b : 0;
+      char *plane = abuf + buf * buf_bytes + b * PL * kPlane;
+      const int idx = tid + kThreads * it;
+      if ((BM * 16) % kThreads != 0 && idx >= BM * 16) return;   // MT = 3: rows 48 .. 63 do not exist
+      const int row = idx >> 4;
+      float v[2];
 #pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const u32x4 de = e == 0 ? d0 : d1;
-            if constexpr (NS == 3)   // a copy: block b's value is element b (^ pair_swap) of the pair
-              v[e] = first_pass(__uint_as_float(de[2]), 0.0f, (b != 0) != (P.pair_swap != 0) ? x[0][it][e][1] : x[0][it][e][0],
-                                0.0f);
-            else
-              v[e] = first_pass(__uint_as_float(de[2]), __uint_as_float(de[3]), x[s][it][e][0], x[s][it][e][1]);
-          }
-          if constexpr (PREC == 0) {
-            *reinterpret_cast<u32x2 *>(plane + row * AROW + 8 * kp) =
-                u32x2{__float_as_uint(v[0]) & keep, __float_as_uint(v[1]) & keep};
-          } else {
-            const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
-            *reinterpret_cast<uint32_t *>(plane + row * AROW + 4 * kp) = (h0 | (h1 << 16)) & keep;
-            if constexpr (PL == 2) {
-              const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
-              const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
-              *reinterpret_cast<uint32_t *>(plane + kPlane + row * AROW + 4 * kp) = (l0 | (l1 << 16)) & keep;
-            }
-          }
+      for (int e = 0; e < 2; ++e) {
+        if constexpr (NS == 3)   // a copy: block b's value is element b (^ pair_swap) of the pair
+          v[e] = first_pass(cf.c[2 * e], 0.0f, (b != 0) != (P.pair_swap != 0) ? x[0][it][e][1] : x[0][it][e][0], 0.0f);
+        else
+          v[e] = first_pass(cf.c[2 * e], cf.c[2 * e + 1], x[s][it][e][0], x[s][it][e][1]);
+      }
+      if constexpr (PREC == 0) {
+        *reinterpret_cast<u32x2 *>(plane + row * AROW + 8 * kp) =
+            u32x2{__float_as_uint(v[0]) & keep, __float_as_uint(v[1]) & keep};
+      } else {
+        const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
+        *reinterpret_cast<uint32_t *>(plane + row * AROW + 4 * kp) = (h0 | (h1 << 16)) & keep;
+        if constexpr (PL == 2) {
+          const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
+          const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
+          *reinterpret_cast<uint32_t *>(plane + kPlane + row * AROW + 4 * kp) = (l0 | (l1 << 16)) & keep;
         }
       }
     };
     auto stage_store = [&](int kt, int buf, const float (&x)[NX][ITEMS][2][2]) {
+      const Coef cf[2] = {stage_coef(kt, 0), stage_coef(kt, 1)};
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int it = 0; it < ITEMS; ++it) stage_unit(kt, buf, x, b, it);
+        for (int it = 0; it < ITEMS; ++it) stage_unit(cf[b], buf, x, b, it);
     };
 
     floatx4 acc[MT][8];
@@ -263,6 +273,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     auto step = [&](int kt, auto Qc) {
       constexpr int Q = decltype(Qc)::value;
       stage_load(kt + D, sx[Q]);
+      const Coef cf[2] = {stage_coef(kt + 1, 0), stage_coef(kt + 1, 1)};
       // No branch around the products and the B reloads: a load under a branch makes the
       // compiler wait for every outstanding load where the paths join (which would expose
       // the next step's B fragments here), and accumulators under a branch get copied.
@@ -300,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
             if (h == 1 && j % kEvery == kEvery - 1) {
               const int u = j / kEvery;
               __builtin_amdgcn_sched_barrier(0);
-              stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
+              stage_unit(cf[u / ITEMS], (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
               __builtin_amdgcn_sched_barrier(0);
             }
           }
@@ -334,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
           if (j % kEvery == kEvery - 1) {
             const int u = j / kEvery;
             __builtin_amdgcn_sched_barrier(0);
-            stage_unit(kt + 1, (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
+            stage_unit(cf[u / ITEMS], (kt + 1) & 1, sx[(Q + 1) % D], u / ITEMS, u % ITEMS);
             __builtin_amdgcn_sched_barrier(0);
           }
         }
