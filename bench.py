@@ -32,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# block precision -> the library's precision number (GFT_FP32 .. GFT_SPLIT_BF16)
+PREC_ID = {"fp32": 0, "bf16": 1, "fp16": 2, "split_bf16": 3}
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0,
                     "split_bf16": 2500.0 / 3.0}   # split: three BF16 products per product
 METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM roofline"
@@ -264,6 +266,8 @@ def bench_single(args, graph, X_host, precision, workload_cfg, sample_rows, samp
     scopy_gbs = bytes_per_launch / (scopy_ms * 1e-3) / 1e9
     copy_gbs = bytes_per_launch / (copy_ms * 1e-3) / 1e9
     kname = (kernel_names or {}).get(eng, f"{eng} engine kernel")
+    if callable(kname):
+        kname = kname(launch)
 
     traffic = None
     try:
@@ -410,8 +414,11 @@ def _large_workload(args, graph, S, name, desc):
                   "launch": tuning,
                   "dense_flops_per_signal": 2.0 * graph.n * graph.n, "fast_flops_per_signal": flops},
                  256, "first 256 signals of the same workload",
-                 kernel_names={"large": "large engine: permute_stages + block_gemm (+ permute_stages "
-                                          "unless the output order is fused)",
+                 kernel_names={"large": lambda launch: {
+                                   0: "large engine, three passes: permute_stages + block_gemm + permute_stages",
+                                   1: "large engine: permute_stages + block_gemm writing the output order",
+                                   2: f"gft_onepass<{PREC_ID[precision]}> (large engine, one-pass form)"}
+                               .get(launch.get("variant"), "large engine"),
                                "product": "gft_product<64,64> (separable Kronecker leaves)"},
                  flops_per_signal=flops, make_plan=lambda: plan)
 
