@@ -177,7 +177,8 @@ namespace gft {
 //     load of two adjacent values per entry, at the first block's offset (both blocks copy
 //     and their sources are neighbours: the inverse of one-stage plans whose two blocks'
 //     coefficients alternate), the first value to block pair_swap, the second to the other;
-//     2, one set per block;
+//     4, one set per block of one value per entry (every entry a copy or a sqrt 2 scaling:
+//     the first pass has no stage, as in the inverse); 2, one set per block;
 //   frag: the block matrices in MFMA B-operand order, 16 bytes per lane per fragment, per
 //     (kc, nt) at index frag_off[b] + kc * ntl[b] + nt: BF16 blocks, one 16x16x32 fragment
 //     (column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e); split blocks, a hi and a lo

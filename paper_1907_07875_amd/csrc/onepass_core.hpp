@@ -106,7 +106,8 @@ template <int PREC, int NS> struct OnePassShape {
 
 // PREC: GFT_FP32 (0), GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: how a k step's inputs are loaded
 // (OnePass::src_mode: 1, one set for both blocks; 2, one set per block; 3, one load of two
-// adjacent values per entry, the first for block 0, the second for block 1).  IN16: the
+// adjacent values per entry, the first for block 0, the second for block 1; 4, one set per
+// block of one value per entry: every entry is a copy or a sqrt 2 scaling).  IN16: the
 // input rows hold BF16.  out16: the output rows hold BF16.
 template <int PREC, int NS, bool IN16>
 __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *__restrict__ in,
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   constexpr int ESZ = IN16 ? 2 : 4;
   constexpr int SR = OnePassShape<PREC, NS>::SR;
   constexpr int ITEMS = (BM * 16 + kThreads - 1) / kThreads;         // (row, k pair) items
-  constexpr int NX = NS == 2 ? 2 : 1;                                // register sets per step
+  constexpr int NX = NS == 2 || NS == 4 ? 2 : 1;                     // register sets per step
   __shared__ __attribute__((aligned(16))) int32_t sdesc[4 * kMaxEntries];
   __shared__ __attribute__((aligned(16))) char abuf[2 * 2 * PL * kPlane];
   __shared__ __attribute__((aligned(16))) float slab[SR * (1024 + 4)];
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       for (int s = 0; s < NX; ++s) {
         // the block whose entries give this set's offsets: with one set, block 0 while it
         // has k steps left, then block 1; k steps past a block's end re-read its last one
-        const int b = NS == 2 ? s : (kt < P.nkc[0] || nb == 1 ? 0 : 1);
+        const int b = NX == 2 ? s : (kt < P.nkc[0] || nb == 1 ? 0 : 1);
         const int kk = kt < P.nkc[b] ? kt : P.nkc[b] - 1;
         const int32_t *d = sdesc + 4 * (P.desc_off[b] + 32 * kk + 2 * kp);
         const u32x4 d0 = *reinterpret_cast<const u32x4 *>(d), d1 = *reinterpret_cast<const u32x4 *>(d + 4);
@@ -192,6 +193,8 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
             const u32x4 de = e == 0 ? d0 : d1;
             if constexpr (NS == 3) {
               load_pair<IN16>(base, rowoff[it] + de[0], x[s][it][e][0], x[s][it][e][1]);
+            } else if constexpr (NS == 4) {
+              x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
             } else {
               x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
               x[s][it][e][1] = load_in<IN16>(base, rowoff[it] + de[1]);
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     };
     auto stage_unit = [&](const Coef &cf, int buf, const float (&x)[NX][ITEMS][2][2], int b, int it) {
       const uint32_t keep = cf.keep;
-      const int s = NS == 2 ? b : 0;
+      const int s = NX == 2 ? b : 0;
       char *plane = abuf + buf * buf_bytes + b * PL * kPlane;
       const int idx = tid + kThreads * it;
       if ((BM * 16) % kThreads != 0 && idx >= BM * 16) return;   // MT = 3: rows 48 .. 63 do not exist
@@ -235,6 +238,8 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       for (int e = 0; e < 2; ++e) {
         if constexpr (NS == 3)   // a copy: block b's value is element b (^ pair_swap) of the pair
           v[e] = first_pass(cf.c[2 * e], 0.0f, (b != 0) != (P.pair_swap != 0) ? x[0][it][e][1] : x[0][it][e][0], 0.0f);
+        else if constexpr (NS == 4)
+          v[e] = first_pass(cf.c[2 * e], 0.0f, x[s][it][e][0], 0.0f);
         else
           v[e] = first_pass(cf.c[2 * e], cf.c[2 * e + 1], x[s][it][e][0], x[s][it][e][1]);
       }
@@ -471,6 +476,7 @@ hipError_t launch_mode(const OnePass &P, const void *in, void *out, int64_t S, b
   switch (P.src_mode) {
     case 1: return launch_op<PREC, 1, IN16>(P, in, out, S, out16, grid, st);
     case 3: return launch_op<PREC, 3, IN16>(P, in, out, S, out16, grid, st);
+    case 4: return launch_op<PREC, 4, IN16>(P, in, out, S, out16, grid, st);
     default: return launch_op<PREC, 2, IN16>(P, in, out, S, out16, grid, st);
   }
 }
@@ -484,8 +490,10 @@ hipError_t launch_prec(const OnePass &P, const void *in, void *out, int64_t S, b
 
 template <int PREC, bool IN16>
 int occupancy_mode(int src_mode) {
-  return src_mode == 1 ? occupancy_op<PREC, 1, IN16>() : src_mode == 3 ? occupancy_op<PREC, 3, IN16>()
-                                                                       : occupancy_op<PREC, 2, IN16>();
+  return src_mode == 1   ? occupancy_op<PREC, 1, IN16>()
+         : src_mode == 3 ? occupancy_op<PREC, 3, IN16>()
+         : src_mode == 4 ? occupancy_op<PREC, 4, IN16>()
+                         : occupancy_op<PREC, 2, IN16>();
 }
 
 template <int PREC>

@@ -902,7 +902,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   // every valid entry of the second block has the first block's offsets at the same k;
   // adjacent pairs where both blocks copy and the second block's source follows the first
   // block's (an even position, not the row's last, so that the pair lies in the row);
-  // else one set per block
+  // else one set per block, of one value per entry where no entry adds two values
   // (the pair starts at an even position below n - 1, so that it lies in the row; with the
   // second block's source first, block 0's offsets move to the pair's start)
   P.src_mode = nb == 1 ? 1 : 2;
@@ -930,6 +930,9 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
         const int start = s == 0 ? b0.s0 : b0.s0 - 1;
         pair[s] = b0.c1 == 0.0f && start >= 0 && start % 2 == 0 && start + 1 < L.n;
       }
+    // one value per entry in both blocks: copies and sqrt 2 scalings only (no sums or differences)
+    bool single = true;
+    for (int e = 0; e < entries && single; ++e) single = src[e].c1 == 0.0f;
     if (same) {
       P.src_mode = 1;
     } else if (pair[0] || pair[1]) {
@@ -940,6 +943,8 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
           int32_t *d0 = &im.desc[4 * ((size_t)P.desc_off[0] + k)];
           if (src[P.desc_off[0] + k].c0 != 0.0f) d0[0] -= esz;
         }
+    } else if (single) {
+      P.src_mode = 4;
     }
   }
   P.desc_words = 4 * entries;
