@@ -178,7 +178,11 @@ namespace gft {
 //     and their sources are neighbours: the inverse of one-stage plans whose two blocks'
 //     coefficients alternate), the first value to block pair_swap, the second to the other;
 //     4, one set per block of one value per entry (every entry a copy or a sqrt 2 scaling:
-//     the first pass has no stage, as in the inverse); 2, one set per block;
+//     the first pass has no stage, as in the inverse); 5, as 1, with each lane's two
+//     entries 2m, 2m + 1 read as two pairs: the first sources at word 0 of entry 2m and the
+//     next position (entry 2m + 1's), the second sources at word 1 of entry 2m + 1 and the
+//     next position (entry 2m's) — the units of a mirror involution in rank order; 2, one
+//     set per block;
 //   frag: the block matrices in MFMA B-operand order, 16 bytes per lane per fragment, per
 //     (kc, nt) at index frag_off[b] + kc * ntl[b] + nt: BF16 blocks, one 16x16x32 fragment
 //     (column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e); split blocks, a hi and a lo

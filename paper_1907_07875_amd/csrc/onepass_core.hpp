@@ -107,7 +107,8 @@ template <int PREC, int NS> struct OnePassShape {
 // PREC: GFT_FP32 (0), GFT_BF16 (1) or GFT_SPLIT_BF16 (3).  NS: how a k step's inputs are loaded
 // (OnePass::src_mode: 1, one set for both blocks; 2, one set per block; 3, one load of two
 // adjacent values per entry, the first for block 0, the second for block 1; 4, one set per
-// block of one value per entry: every entry is a copy or a sqrt 2 scaling).  IN16: the
+// block of one value per entry: every entry is a copy or a sqrt 2 scaling; 5, one set for
+// both blocks, each lane's two entries loaded as two pairs of adjacent values).  IN16: the
 // input rows hold BF16.  out16: the output rows hold BF16.
 template <int PREC, int NS, bool IN16>
 __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *__restrict__ in,
@@ -191,7 +192,14 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const u32x4 de = e == 0 ? d0 : d1;
-            if constexpr (NS == 3) {
+            if constexpr (NS == 5) {
+              // entries 2 kp and 2 kp + 1: their first sources are neighbours from the first
+              // entry's, their second sources neighbours from the second entry's, downwards
+              if (e == 0) {
+                load_pair<IN16>(base, rowoff[it] + d0[0], x[s][it][0][0], x[s][it][1][0]);
+                load_pair<IN16>(base, rowoff[it] + d1[1], x[s][it][1][1], x[s][it][0][1]);
+              }
+            } else if constexpr (NS == 3) {
               load_pair<IN16>(base, rowoff[it] + de[0], x[s][it][e][0], x[s][it][e][1]);
             } else if constexpr (NS == 4) {
               x[s][it][e][0] = load_in<IN16>(base, rowoff[it] + de[0]);
@@ -477,6 +485,7 @@ hipError_t launch_mode(const OnePass &P, const void *in, void *out, int64_t S, b
     case 1: return launch_op<PREC, 1, IN16>(P, in, out, S, out16, grid, st);
     case 3: return launch_op<PREC, 3, IN16>(P, in, out, S, out16, grid, st);
     case 4: return launch_op<PREC, 4, IN16>(P, in, out, S, out16, grid, st);
+    case 5: return launch_op<PREC, 5, IN16>(P, in, out, S, out16, grid, st);
     default: return launch_op<PREC, 2, IN16>(P, in, out, S, out16, grid, st);
   }
 }
@@ -493,6 +502,7 @@ int occupancy_mode(int src_mode) {
   return src_mode == 1   ? occupancy_op<PREC, 1, IN16>()
          : src_mode == 3 ? occupancy_op<PREC, 3, IN16>()
          : src_mode == 4 ? occupancy_op<PREC, 4, IN16>()
+         : src_mode == 5 ? occupancy_op<PREC, 5, IN16>()
                          : occupancy_op<PREC, 2, IN16>();
 }
 

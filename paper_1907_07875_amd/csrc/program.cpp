@@ -819,6 +819,31 @@ bool build_large(const GraphPlan &p, int direction, LargeImage &out) {
 
 namespace gft {
 
+// Whether a one-set plan's entries can be loaded as pairs (OnePass::src_mode 5): for every
+// lane's entries e = 2m and f = 2m + 1 of the block the kernel reads at that k (block 0
+// while it has k steps, then block 1), the pair at entry e's first offset holds e's and f's
+// first sources and the pair at entry f's second offset holds f's and e's second sources
+// (where those entries use them), both pairs aligned and inside the row.
+template <class Src>
+static bool onepass_mirror_pairs(const OnePass &P, const std::vector<Src> &src, const std::vector<int32_t> &desc,
+                                 int n, int esz) {
+  if (n % 2 != 0) return false;   // rows start on pair boundaries
+  for (int kt = 0; kt < P.nk; ++kt) {
+    const int b = kt < P.nkc[0] || P.nblocks == 1 ? 0 : 1;
+    for (int m = 0; m < 16; ++m) {
+      const size_t e = (size_t)P.desc_off[b] + 32 * kt + 2 * m, f = e + 1;
+      const int32_t *de = &desc[4 * e], *df = &desc[4 * f];
+      const int32_t a = de[0], c = df[1];   // the two pairs' byte offsets
+      if (a % (2 * esz) != 0 || c % (2 * esz) != 0 || a + 2 * esz > n * esz || c + 2 * esz > n * esz) return false;
+      if (src[f].c0 != 0.0f && df[0] != a + esz) return false;   // f's first source follows e's
+      if (src[e].c1 != 0.0f && de[1] != c + esz) return false;   // e's second source follows f's
+      if (src[e].c0 != 0.0f && de[0] != a) return false;
+      if (src[f].c1 != 0.0f && df[1] != c) return false;
+    }
+  }
+  return true;
+}
+
 bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out) {
   if (precision != GFT_FP32 && precision != GFT_BF16 && precision != GFT_SPLIT_BF16) return false;
   const PermPass &P1 = L.pass[0];
@@ -905,7 +930,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   // else one set per block, of one value per entry where no entry adds two values
   // (the pair starts at an even position below n - 1, so that it lies in the row; with the
   // second block's source first, block 0's offsets move to the pair's start)
-  P.src_mode = nb == 1 ? 1 : 2;
+  P.src_mode = nb == 1 ? (onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1) : 2;
   P.pair_swap = 0;
   if (nb == 2) {
     bool same = true, pair[2] = {true, true};   // pair[s]: block 1's source at block 0's +1 (s = 0) or -1
@@ -934,7 +959,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
     bool single = true;
     for (int e = 0; e < entries && single; ++e) single = src[e].c1 == 0.0f;
     if (same) {
-      P.src_mode = 1;
+      P.src_mode = onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1;
     } else if (pair[0] || pair[1]) {
       P.src_mode = 3;
       P.pair_swap = pair[0] ? 0 : 1;

@@ -6,7 +6,8 @@ The one-pass form computes every value with the operations of the three-pass for
 same order, so the forms agree bit for bit (GFT_LARGE_FORM forces a form); both agree with
 the aligned FP64 oracle within the block precision's bound (FP32 and split BF16 <= 1e-5,
 BF16 <= 2e-2).  Cases: the weighted symmetric 1024-path (two 512-node blocks of the sums and
-differences of the same Haar units: one load per pair), the 1023-path (a V_Z node scaled by
+differences of the same Haar units; the forward loads each lane's two units as two pairs of
+neighbouring values, the inverse one coefficient per entry), the 1023-path (a V_Z node scaled by
 sqrt 2, blocks of 512 and 511), a uniform 1000-path (its inverse loads the two blocks'
 alternating coefficients in pairs), a 1000-cycle, and a 600-node path planned without a
 stage (one dense block); the inverse directions stage coefficients (a copy per block) and
