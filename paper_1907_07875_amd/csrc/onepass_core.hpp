@@ -12,7 +12,9 @@
 //     two halves of 16 k);
 //   * staging: the inputs of a k step are loaded one or two steps ahead, while earlier
 //     steps' MFMAs run (32-bit byte offsets from the panel's first row: no 64-bit address
-//     arithmetic per value); the first-pass values (x_i + x_phi(i), x_i - x_phi(i), sqrt(2) x_c of a
+//     arithmetic per value; as few loads as the plan's source pattern allows: one value per
+//     entry where the first pass only copies, pairs of neighbours where two entries' sources
+//     are adjacent); the first-pass values (x_i + x_phi(i), x_i - x_phi(i), sqrt(2) x_c of a
 //     V_Z node, or a copy: a multiply and a fused multiply-add with the entry's
 //     coefficients) are rounded to BF16 (split: a hi and a lo part; FP32 blocks: kept as
 //     they are) into a double-buffered LDS tile, one barrier per k step;
@@ -23,7 +25,10 @@
 //     last use;
 //   * the last pass: 16-row slabs of the results are written to LDS at their workspace
 //     columns, the last pass's Haar stages (the inverse's left stage, the forward's right
-//     stage) run there, and the output rows leave in their final order as whole rows.
+//     stage) run there, and the output rows leave in their final order as whole rows (the
+//     gather table and the stages' operations are read from LDS copies).
+//
+// The built-in grid is persistent: one workgroup per CU takes panels in turn.
 //
 // Every value is computed with the same operations in the same order as in the three-pass
 // form (FP32 stage arithmetic, the same BF16 rounding, the same MFMA sequence per k chunk
