@@ -868,6 +868,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
                                     opi[d]))) {
         ooff[d][0] = blob.add(opi[d].desc.data(), opi[d].desc.size() * 4);
         ooff[d][1] = blob.add(opi[d].frag.data(), opi[d].frag.size() * 4);
+        if (!opi[d].omap.empty()) ooff[d][2] = blob.add(opi[d].omap.data(), opi[d].omap.size() * 4);
       }
   const size_t bytes = blob.bytes.size();
   auto img = std::make_unique<DeviceImage>();
@@ -938,6 +939,7 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
         O.gather3 = L.pass[1].gather;
         O.stages3 = L.pass[1].stages;
         O.ops3 = L.pass[1].ops;
+        O.omap3 = O.src_mode == 5 ? reinterpret_cast<const int32_t *>(base + ooff[d][2]) : nullptr;
         img->op_ok[d] = O.gather3 != nullptr;   // the last pass always gathers
         // built-in grid: the resident workgroups, each taking panels in turn (its LDS tables
         // are copied once; 1.5-6 % faster than one workgroup per panel at 16 panels per CU)

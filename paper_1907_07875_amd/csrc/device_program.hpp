@@ -181,8 +181,11 @@ namespace gft {
 //     the first pass has no stage, as in the inverse); 5, as 1, with each lane's two
 //     entries 2m, 2m + 1 read as two pairs: the first sources at word 0 of entry 2m and the
 //     next position (entry 2m + 1's), the second sources at word 1 of entry 2m + 1 and the
-//     next position (entry 2m's) — the units of a mirror involution in rank order; 2, one
-//     set per block;
+//     next position (entry 2m's) — the units of a mirror involution in rank order — and a
+//     last pass without stages that gathers no workspace column twice, whose results are
+//     written to the slab at their output columns (omap3[w]: output column of workspace
+//     column w, -1: none; the other columns hold zeros) and leave as they are; 2, one set
+//     per block;
 //   frag: the block matrices in MFMA B-operand order, 16 bytes per lane per fragment, per
 //     (kc, nt) at index frag_off[b] + kc * ntl[b] + nt: BF16 blocks, one 16x16x32 fragment
 //     (column 16 nt + lane % 16, k = 32 kc + 8 (lane / 16) + e); split blocks, a hi and a lo
@@ -212,6 +215,7 @@ struct OnePass {
   const int32_t *gather3;
   const int32_t *stages3;
   const uint32_t *ops3;
+  const int32_t *omap3;   // ldw entries (source mode 5)
 };
 
 }  // namespace gft

@@ -133,6 +133,8 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   __shared__ __attribute__((aligned(16))) char abuf[2 * 2 * PL * kPlane];
   __shared__ __attribute__((aligned(16))) float slab[SR * (1024 + 4)];
   __shared__ __attribute__((aligned(16))) int32_t sgather[kMaxN];
+  constexpr bool DIRECT = NS == 5;                                   // results to output columns
+  __shared__ int32_t somap[DIRECT ? kMaxN : 1];
   __shared__ uint32_t sops[kMaxOps3];
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15, kp = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: per-wave fields in SGPRs
@@ -140,7 +142,13 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
   constexpr int buf_bytes = 2 * PL * kPlane;                        // room for two blocks
   const int sstr = P.slab_stride;
   for (int i = tid; i < P.desc_words; i += kThreads) sdesc[i] = P.desc[i];
-  for (int i = tid; i < n; i += kThreads) sgather[i] = P.gather3[i];
+  if constexpr (DIRECT) {
+    // the results go to their output columns; the columns no workspace column feeds stay zero
+    for (int i = tid; i < P.ldw; i += kThreads) somap[i] = P.omap3[i];
+    for (int i = tid; i < SR * sstr; i += kThreads) slab[i] = 0.0f;
+  } else {
+    for (int i = tid; i < n; i += kThreads) sgather[i] = P.gather3[i];
+  }
   for (int i = tid; i < P.ops3_words; i += kThreads) sops[i] = P.ops3[i];
   __syncthreads();
 
@@ -379,12 +387,33 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     }
     if (D == 2 && kt < P.nk) step(kt, std::integral_constant<int, 0>{});
 
-    // ---- last pass, one slab of SR rows at a time (row tile s, half h when SR = 8)
+    // ---- last pass, one slab of SR rows at a time (row tile s, half h when SR = 8); each
+    // result column goes to its workspace column, or (DIRECT) its output column (-1: none)
+    [[maybe_unused]] int dcol[8];
+    if constexpr (DIRECT) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = 16 * (nt0 + j) + r;
+        dcol[j] = wb >= 0 && j < wcnt && c < wK ? somap[wcol + c] : -1;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < MT; ++s)
 #pragma unroll
     for (int h = 0; h < 16 / SR; ++h) {
-      if (wb >= 0) {
+      if constexpr (DIRECT) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (dcol[j] >= 0) {
+            float *dst = slab + dcol[j];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lr = 4 * g + v - SR * h;   // the lanes of this half write
+              if (lr >= 0 && lr < SR) dst[lr * sstr] = acc[s][j][v];
+            }
+          }
+        }
+      } else if (wb >= 0) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int c = 16 * (nt0 + j) + r;
@@ -392,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
             float *dst = slab + wcol + c;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int lr = 4 * g + v - SR * h;   // the lanes of this half write
+              const int lr = 4 * g + v - SR * h;
               if (lr >= 0 && lr < SR) dst[lr * sstr] = acc[s][j][v];
             }
           }
@@ -436,13 +465,17 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         for (int idx = tid; idx < SR * nq; idx += kThreads) {
           const int rr = idx / nq, q = idx - rr * nq;
           if (rr >= nr) continue;
-          const int4 gi = *reinterpret_cast<const int4 *>(sgather + 4 * q);
           const float *srow = slab + rr * sstr;
           floatx4 v;
-          v[0] = gi.x >= 0 ? srow[gi.x] : 0.0f;
-          v[1] = gi.y >= 0 ? srow[gi.y] : 0.0f;
-          v[2] = gi.z >= 0 ? srow[gi.z] : 0.0f;
-          v[3] = gi.w >= 0 ? srow[gi.w] : 0.0f;
+          if constexpr (DIRECT) {
+            v = *reinterpret_cast<const floatx4 *>(srow + 4 * q);
+          } else {
+            const int4 gi = *reinterpret_cast<const int4 *>(sgather + 4 * q);
+            v[0] = gi.x >= 0 ? srow[gi.x] : 0.0f;
+            v[1] = gi.y >= 0 ? srow[gi.y] : 0.0f;
+            v[2] = gi.z >= 0 ? srow[gi.z] : 0.0f;
+            v[3] = gi.w >= 0 ? srow[gi.w] : 0.0f;
+          }
           const int64_t o = (rb + rr) * n + 4 * q;
           if (out16)
             __builtin_nontemporal_store(
@@ -455,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         for (int idx = tid; idx < SR * n; idx += kThreads) {
           const int rr = idx / n, c = idx - rr * n;
           if (rr >= nr) continue;
-          const int gi = sgather[c];
+          const int gi = DIRECT ? c : sgather[c];
           const float v = gi >= 0 ? slab[rr * sstr + gi] : 0.0f;
           const int64_t o = (rb + rr) * n + c;
           if (out16) static_cast<uint16_t *>(out)[o] = (uint16_t)bf16_bits(v);

@@ -860,6 +860,18 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   P.nblocks = nb;
   P.num_stages3 = L.pass[1].num_stages;
   P.ops3_words = (int)L.ops[1].size();
+  // source mode 5 also writes the results straight to their output columns: a last pass
+  // without stages whose gather takes every workspace column at most once
+  bool direct = P.num_stages3 == 0 && (int)L.gather[1].size() == L.n;
+  if (direct) {
+    im.omap.assign((size_t)L.ldw, -1);
+    for (int c = 0; c < L.n && direct; ++c) {
+      const int w = L.gather[1][c];
+      if (w < 0) continue;
+      if (w >= L.ldw || im.omap[w] >= 0) direct = false;
+      else im.omap[w] = c;
+    }
+  }
   // waves: each block's 16-column tiles over the fewest waves of at most 8 tiles each
   int wave = 0, entries = 0, frags = 0;
   for (int w = 0; w < 8; ++w) P.wblk[w] = -1, P.wnt0[w] = 0, P.wcnt[w] = 0;
@@ -930,7 +942,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   // else one set per block, of one value per entry where no entry adds two values
   // (the pair starts at an even position below n - 1, so that it lies in the row; with the
   // second block's source first, block 0's offsets move to the pair's start)
-  P.src_mode = nb == 1 ? (onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1) : 2;
+  P.src_mode = nb == 1 ? (direct && onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1) : 2;
   P.pair_swap = 0;
   if (nb == 2) {
     bool same = true, pair[2] = {true, true};   // pair[s]: block 1's source at block 0's +1 (s = 0) or -1
@@ -959,7 +971,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
     bool single = true;
     for (int e = 0; e < entries && single; ++e) single = src[e].c1 == 0.0f;
     if (same) {
-      P.src_mode = onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1;
+      P.src_mode = direct && onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1;
     } else if (pair[0] || pair[1]) {
       P.src_mode = 3;
       P.pair_swap = pair[0] ? 0 : 1;
@@ -972,6 +984,7 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
       P.src_mode = 4;
     }
   }
+  if (P.src_mode != 5) im.omap.clear();
   P.desc_words = 4 * entries;
   // B fragments (forward and inverse alike: M[k][c] = Mt[c][k] of the stored transpose),
   // rounded as the three-pass GEMM rounds them

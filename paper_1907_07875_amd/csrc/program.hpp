@@ -86,6 +86,7 @@ struct OnePassImage {
   int mt = 4;                    // 16-signal row tiles per workgroup
   std::vector<int32_t> desc;
   std::vector<uint32_t> frag;
+  std::vector<int32_t> omap;     // OnePass::omap3 (source mode 5)
 };
 
 // Table limits of the one-pass kernel (its LDS arrays are sized for them): entries of the
