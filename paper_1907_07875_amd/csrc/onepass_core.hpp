@@ -177,19 +177,29 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     if constexpr (PREC == 3) bl[j] = frag_at(0, j, 1);
   }
 
-  for (int64_t panel = blockIdx.x; panel < npanels; panel += gridDim.x) {
-    const int64_t row0 = panel * BM;
-    const char *base = static_cast<const char *>(in) + row0 * n * ESZ;   // uniform
-    const int last = (S - row0 < BM ? (int)(S - row0) : BM) - 1;        // rows past it: clamped, never stored
-    uint32_t rowoff[ITEMS];
+  // the input rows the staging loads read: panel p's first row (uniform) and each item's
+  // row offset (rows past the last signal: clamped, never stored)
+  const char *base = nullptr;
+  uint32_t rowoff[ITEMS];
+  auto set_panel = [&](int64_t p) {
+    const int64_t r0 = p * BM;
+    base = static_cast<const char *>(in) + r0 * n * ESZ;
+    const int last = (S - r0 < BM ? (int)(S - r0) : BM) - 1;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       const int row = (tid >> 4) + 32 * it;
       rowoff[it] = (uint32_t)((row < last ? row : last) * n * ESZ);
     }
-    // ---- staging: inputs of k step kt into ring set q = kt mod D (loads only; consumed by
-    // stage_store).  Steps past the end re-read the last step's inputs.
-    float sx[D][NX][ITEMS][2][2];
+  };
+  // ---- staging: inputs of k step kt into ring set q = kt mod D (loads only; consumed by
+  // stage_store).  Steps past the end re-read the last step's inputs.
+  float sx[D][NX][ITEMS][2][2];
+  // split blocks: their registers have no room for the next panel's inputs during the last
+  // pass (held there they spill, and the forward measured no faster)
+  constexpr bool kPrefetchPanel = PREC != 3;
+
+  for (int64_t panel = blockIdx.x; panel < npanels; panel += gridDim.x) {
+    const int64_t row0 = panel * BM;
     auto stage_load = [&](int kt, float (&x)[NX][ITEMS][2][2]) {
       kt = kt < P.nk ? kt : P.nk - 1;
 #pragma unroll
@@ -290,8 +300,13 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     for (int i = 0; i < MT; ++i)
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the first steps' inputs: loaded here for the first panel (and every panel with split
+    // blocks), before the last pass of the panel before for the others
+    if (!kPrefetchPanel || panel == (int64_t)blockIdx.x) {
+      set_panel(panel);
 #pragma unroll
-    for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
+      for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
+    }
     stage_store(0, 0, sx[0]);
     __syncthreads();
     // one k step (kt = Q mod D): the loads of step kt + D into the set that step kt used,
@@ -386,6 +401,14 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
       if constexpr (D == 2) step(kt + 1, std::integral_constant<int, 1 % D>{});
     }
     if (D == 2 && kt < P.nk) step(kt, std::integral_constant<int, 0>{});
+    if constexpr (kPrefetchPanel) {
+      // the next panel's first steps, loaded ahead of this panel's last pass so that their
+      // latency passes during it (past the last panel: this one again, never used)
+      const int64_t nx = panel + gridDim.x;
+      set_panel(nx < npanels ? nx : panel);
+#pragma unroll
+      for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
+    }
 
     // ---- last pass, one slab of SR rows at a time (row tile s, half h when SR = 8); each
     // result column goes to its workspace column, or (DIRECT) its output column (-1: none)
