@@ -403,11 +403,13 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
     if (D == 2 && kt < P.nk) step(kt, std::integral_constant<int, 0>{});
     if constexpr (kPrefetchPanel) {
       // the next panel's first steps, loaded ahead of this panel's last pass so that their
-      // latency passes during it (past the last panel: this one again, never used)
+      // latency passes during it (past the last panel: this panel's last step again, still
+      // in L2, never used)
       const int64_t nx = panel + gridDim.x;
-      set_panel(nx < npanels ? nx : panel);
+      const bool more = nx < npanels;
+      set_panel(more ? nx : panel);
 #pragma unroll
-      for (int q = 0; q < D; ++q) stage_load(q, sx[q]);
+      for (int q = 0; q < D; ++q) stage_load(more ? q : P.nk - 1, sx[q]);
     }
 
     // ---- last pass, one slab of SR rows at a time (row tile s, half h when SR = 8); each
