@@ -100,9 +100,9 @@ __device__ __forceinline__ float first_pass(float c0, float c1, float x0, float 
 // Shapes: a panel of 64 rows (FP32 and BF16 blocks) or 48 rows (split blocks: two operand
 // planes) per workgroup, one workgroup per CU (the accumulators of a panel fill half the
 // register file); the inputs of a k step are loaded D steps ahead (a ring of D register
-// sets): two with one source set or pairs, one with two sets (a second set of two would
-// spill; measured slower) and with FP32 blocks (a k step is 256 products per wave, long
-// enough to cover the loads; two would spill).
+// sets): two with one source set, pairs, or two sets of one value per entry; one with two
+// sets of two values (a second ring slot would spill; measured slower) and with FP32 blocks
+// (a k step is 256 products per wave, long enough to cover the loads; two would spill).
 template <int PREC, int NS> struct OnePassShape {
   static constexpr int MT = PREC == 3 ? 3 : 4;     // 16-row tiles per panel
   static constexpr int SR = 16;                    // result slab rows
@@ -113,8 +113,9 @@ template <int PREC, int NS> struct OnePassShape {
 // (OnePass::src_mode: 1, one set for both blocks; 2, one set per block; 3, one load of two
 // adjacent values per entry, the first for block 0, the second for block 1; 4, one set per
 // block of one value per entry: every entry is a copy or a sqrt 2 scaling; 5, one set for
-// both blocks, each lane's two entries loaded as two pairs of adjacent values).  IN16: the
-// input rows hold BF16.  out16: the output rows hold BF16.
+// both blocks, each lane's two entries loaded as two pairs of adjacent values, and the
+// results written to the slab at their output columns).  IN16: the input rows hold BF16.
+// out16: the output rows hold BF16.
 template <int PREC, int NS, bool IN16>
 __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *__restrict__ in,
                                                           void *__restrict__ out, int64_t S, int out16) {
