@@ -201,17 +201,26 @@ typedef struct {
   int32_t engine;          /* gft_engine the plan runs on                             */
   int32_t fwd_tile;        /* signals per tile: generic engine 16 * m (tuned), butterfly */
   int32_t inv_tile;        /* 16 (per wave), product 1 (per wave), large 0, batch 0    */
-  int32_t grid_fwd;        /* butterfly and product engines: most workgroups launched */
-  int32_t grid_inv;        /* (tuned; the tile loop strides over the rest); else 0    */
-  int32_t variant;         /* product: 1 staged factors, 0 dense; large: 1 forward    */
-                           /* output order written by the GEMM epilogue, 0 by a third */
-                           /* pass (tuned where both exist); else 0                   */
+  int32_t grid_fwd;        /* butterfly and product engines, and the large engine's   */
+  int32_t grid_inv;        /* one-pass form: most workgroups launched (tuned; the tile */
+                           /* or panel loop strides over the rest; 0: one per tile or */
+                           /* panel); else 0                                          */
+  int32_t variant;         /* product: 1 staged factors, 0 dense; large: 2 one-pass   */
+                           /* form, 1 forward output order written by the GEMM        */
+                           /* epilogue, 0 three passes (tuned where several exist);   */
+                           /* else 0                                                  */
   int32_t batch_rounds;    /* batch: rounds of resident workgroups (tuned)            */
   int32_t batch_cost16;    /* batch: register-phase fixed cost per signal in          */
                            /* sixteenths of the padded slot count (tuned)             */
   int32_t large_tile_kb;   /* large: stage-pass tile size in KB (tuned)               */
   int32_t source;          /* gft_tune_source                                         */
   double tune_ms;          /* host milliseconds spent timing candidates (0 if none)   */
+  int32_t onepass_fwd;     /* large engine, one-pass form (where the plan fits it):   */
+  int32_t onepass_inv;     /* how a k step's inputs are loaded, per direction: 1 one  */
+                           /* set for both blocks, 2 one set per block, 3 pairs split */
+                           /* between the blocks, 4 one value per entry and block, 5  */
+                           /* pairs of neighbours, results at their output columns;  */
+                           /* 0 without the form                                      */
 } gft_tuning;
 
 typedef struct {

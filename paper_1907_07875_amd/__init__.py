@@ -71,7 +71,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("fwd_tile", ctypes.c_int32), ("inv_tile", ctypes.c_int32),
                 ("grid_fwd", ctypes.c_int32), ("grid_inv", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("batch_rounds", ctypes.c_int32), ("batch_cost16", ctypes.c_int32),
-                ("large_tile_kb", ctypes.c_int32), ("source", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+                ("large_tile_kb", ctypes.c_int32), ("source", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("onepass_fwd", ctypes.c_int32), ("onepass_inv", ctypes.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

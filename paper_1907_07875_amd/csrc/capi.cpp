@@ -860,12 +860,15 @@ gft_status device_image(gft_plan_s *plan, DeviceImage **out) {
   // the one-pass form where the plan fits it (its tables and B fragments)
   OnePassImage opi[2];
   bool op_ok[2] = {false, false};
+  // GFT_ONEPASS_GENERAL=1: the one-pass form with its general source modes only (testing)
+  const char *gen_env = std::getenv("GFT_ONEPASS_GENERAL");
+  const bool onepass_general = gen_env && std::strcmp(gen_env, "1") == 0;
   size_t ooff[2][3] = {};
   if (use_large)
     for (int d = 0; d < 2; ++d)
       if ((op_ok[d] = build_onepass(lgi[d], plan->opts.precision,
                                     (d == 0 ? plan->opts.in_dtype : plan->opts.out_dtype) == GFT_DTYPE_BF16,
-                                    opi[d]))) {
+                                    opi[d], onepass_general))) {
         ooff[d][0] = blob.add(opi[d].desc.data(), opi[d].desc.size() * 4);
         ooff[d][1] = blob.add(opi[d].frag.data(), opi[d].frag.size() * 4);
         if (!opi[d].omap.empty()) ooff[d][2] = blob.add(opi[d].omap.data(), opi[d].omap.size() * 4);
@@ -1494,6 +1497,8 @@ gft_status gft_plan_tuning(gft_plan_t plan, gft_tuning *out) {
     t.large_tile_kb = img->ltile_kb[0];
     t.grid_fwd = img->op_grid[0];
     t.grid_inv = img->op_grid[1];
+    t.onepass_fwd = img->op_ok[0] ? img->op[0].src_mode : 0;
+    t.onepass_inv = img->op_ok[1] ? img->op[1].src_mode : 0;
   } else if (!plan->batch) {
     t.fwd_tile = 16 * img->fwd[0].mt;
     t.inv_tile = 16 * img->inv[0].mt;

@@ -844,7 +844,7 @@ static bool onepass_mirror_pairs(const OnePass &P, const std::vector<Src> &src, 
   return true;
 }
 
-bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out) {
+bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out, bool general) {
   if (precision != GFT_FP32 && precision != GFT_BF16 && precision != GFT_SPLIT_BF16) return false;
   const PermPass &P1 = L.pass[0];
   const int nb = (int)L.blocks.size();
@@ -942,9 +942,9 @@ bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &
   // else one set per block, of one value per entry where no entry adds two values
   // (the pair starts at an even position below n - 1, so that it lies in the row; with the
   // second block's source first, block 0's offsets move to the pair's start)
-  P.src_mode = nb == 1 ? (direct && onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1) : 2;
+  P.src_mode = nb == 1 ? (!general && direct && onepass_mirror_pairs(P, src, im.desc, L.n, esz) ? 5 : 1) : 2;
   P.pair_swap = 0;
-  if (nb == 2) {
+  if (nb == 2 && !general) {
     bool same = true, pair[2] = {true, true};   // pair[s]: block 1's source at block 0's +1 (s = 0) or -1
     for (int k = 0; k < 32 * P.nkc[1] && (same || pair[0] || pair[1]); ++k) {
       const Src &b1 = src[P.desc_off[1] + k];

@@ -99,7 +99,9 @@ constexpr int kOnePassMaxN = 1024;      // row length (the output gather table)
 // The one-pass form of large image `L` (built for `precision`: GFT_FP32, GFT_BF16 or GFT_SPLIT_BF16,
 // with L's host matrices still present; in16: the direction's input rows hold BF16).
 // Returns false when the plan does not fit it: a first pass with more than one stage, more
-// than two leaf blocks, or more columns than eight waves hold.
-bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out);
+// than two leaf blocks, or more columns than eight waves hold.  general: the general source
+// modes only (1 with one block, 2 with two: each entry's two sources loaded as they are),
+// for testing the specialised modes against them.
+bool build_onepass(const LargeImage &L, int precision, bool in16, OnePassImage &out, bool general = false);
 
 }  // namespace gft

@@ -77,6 +77,49 @@ def test_onepass_bit_equal_to_three_passes_and_oracle(name, precision, monkeypat
     assert O.relative_error(to_np(xr), O.inverse(to_np(y).astype(np.float64), Ua)) <= TOL[precision]
 
 
+def test_onepass_source_modes():
+    """The specialised ways the kernel loads a k step's inputs (OnePass::src_mode 1, 3, 4,
+    5, reported by gft_plan_tuning) are exercised by the graphs above, in one direction or
+    the other (mode 2, the general two-block mode, by GFT_ONEPASS_GENERAL below); the
+    symmetric 1024-path loads its forward as pairs of neighbours and its inverse one
+    coefficient per entry."""
+    device()
+    seen = {}
+    cases = dict(GRAPHS)
+    cases["bipartite_nosym"] = _bipartite_nosym
+    for name, make in cases.items():
+        kw = {"laplacian": "normalized"} if name == "bipartite_nosym" else {}
+        plan = G.Plan.from_graph(make(), engine="large", precision="bf16", autotune=False, **kw)
+        plan.prepare()
+        t = plan.tuning()
+        seen[name] = (t["onepass_fwd"], t["onepass_inv"])
+    assert seen["wpath1024"] == (5, 4), seen
+    modes = {m for pair in seen.values() for m in pair}
+    assert {1, 3, 4, 5} <= modes, seen
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "split_bf16"])
+def test_onepass_general_modes_agree(precision, monkeypatch):
+    """GFT_ONEPASS_GENERAL=1 builds the one-pass form with its general source modes only
+    (each entry's sources loaded as they are: mode 2 with two blocks); the specialised modes
+    compute the same values with fewer loads, so the two agree bit for bit."""
+    dev = device()
+    for name in ("wpath1024", "path1000", "bipartite_nosym"):
+        g = _bipartite_nosym() if name == "bipartite_nosym" else GRAPHS[name]()
+        kw = {"laplacian": "normalized"} if name == "bipartite_nosym" else {}
+        spec = _plan(g, precision, "onepass", monkeypatch, **kw)
+        monkeypatch.setenv("GFT_ONEPASS_GENERAL", "1")
+        gen = _plan(g, precision, "onepass", monkeypatch, **kw)
+        monkeypatch.delenv("GFT_ONEPASS_GENERAL")
+        ts, tg = spec.tuning(), gen.tuning()
+        assert tg["variant"] == 2 and tg["onepass_fwd"] == 2 and tg["onepass_inv"] == 2, (name, tg)
+        assert (ts["onepass_fwd"], ts["onepass_inv"]) != (2, 2), (name, ts)
+        x = torch.from_numpy(wl.gaussian(1001, g.n, wl.rng_for(5, g.n, 71))).to(dev)
+        y = spec.forward(x)
+        assert torch.equal(y, gen.forward(x)), name
+        assert torch.equal(spec.inverse(y), gen.inverse(y)), name
+
+
 def _bipartite_nosym(n=400):
     """A bipartite graph with no symmetry: under the normalized Laplacian its plan has no
     left stage, n/2 right Haar units and two blocks (Sec. III), so the forward runs the right
