@@ -67,6 +67,15 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+// Two values rounded to BF16 in one gfx950 conversion (v_cvt_pk_bf16_f32; nearest even,
+// FP32 denormals preserved: as bf16_bits for every value but NaN payloads): a in the low
+// half, b in the high half.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{a, b}, bf16x2));
+}
+
 // Value `off` bytes past `base` (FP32, or BF16 widened exactly).
 template <bool IN16>
 __device__ __forceinline__ float load_in(const char *base, uint32_t off) {
@@ -279,12 +288,11 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
         *reinterpret_cast<u32x2 *>(plane + row * AROW + 8 * kp) =
             u32x2{__float_as_uint(v[0]) & keep, __float_as_uint(v[1]) & keep};
       } else {
-        const uint32_t h0 = bf16_bits(v[0]), h1 = bf16_bits(v[1]);
-        *reinterpret_cast<uint32_t *>(plane + row * AROW + 4 * kp) = (h0 | (h1 << 16)) & keep;
+        const uint32_t hw = bf16_pair(v[0], v[1]);
+        *reinterpret_cast<uint32_t *>(plane + row * AROW + 4 * kp) = hw & keep;
         if constexpr (PL == 2) {
-          const uint32_t l0 = bf16_bits(v[0] - __uint_as_float(h0 << 16));
-          const uint32_t l1 = bf16_bits(v[1] - __uint_as_float(h1 << 16));
-          *reinterpret_cast<uint32_t *>(plane + kPlane + row * AROW + 4 * kp) = (l0 | (l1 << 16)) & keep;
+          const uint32_t lw = bf16_pair(v[0] - __uint_as_float(hw << 16), v[1] - __uint_as_float(hw & 0xffff0000u));
+          *reinterpret_cast<uint32_t *>(plane + kPlane + row * AROW + 4 * kp) = lw & keep;
         }
       }
     };
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void gft_onepass(OnePass P, const void *_
           const int64_t o = (rb + rr) * n + 4 * q;
           if (out16)
             __builtin_nontemporal_store(
-                u32x2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)},
+                u32x2{bf16_pair(v[0], v[1]), bf16_pair(v[2], v[3])},
                 reinterpret_cast<u32x2 *>(static_cast<uint16_t *>(out) + o));
           else
             __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(static_cast<float *>(out) + o));
