@@ -28,10 +28,15 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-__device__ __forceinline__ bf16x4 pack_bf16(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-  const u32x2 w = {a | (b << 16), c | (d << 16)};
-  return __builtin_bit_cast(bf16x4, w);
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float floatx2_t __attribute__((ext_vector_type(2)));
+// Two values rounded to BF16 in one gfx950 conversion (v_cvt_pk_bf16_f32; nearest even,
+// FP32 denormals preserved: as the bit arithmetic above for every value but NaN
+// payloads): a in the low half, b in the high half.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2_t{a, b}, bf16x2_t));
 }
+
 
 constexpr int kThreads = 256;
 constexpr float kSqrt2f = 1.41421356237309504880f;
@@ -195,8 +200,7 @@ __device__ __forceinline__ void store_tile(const float *lds, int count, int n, i
       }
     }
     if constexpr (B16)
-      __builtin_nontemporal_store(u32x2v{bf16_bits(q[0]) | (bf16_bits(q[1]) << 16),
-                                         bf16_bits(q[2]) | (bf16_bits(q[3]) << 16)},
+      __builtin_nontemporal_store(u32x2v{bf16_pair(q[0], q[1]), bf16_pair(q[2], q[3])},
                                   static_cast<u32x2v *>(g) + v);
     else
       __builtin_nontemporal_store(floatx4{q[0], q[1], q[2], q[3]}, static_cast<floatx4 *>(g) + v);
@@ -287,17 +291,14 @@ __device__ __forceinline__ void block_products(const DevProgram &P, const LdsTab
             acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, __builtin_bit_cast(halfx4, bw),
                                                            acc[m], 0, 0, 0);
           } else {
-            uint32_t h[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) h[j] = bf16_bits(x[j]);
-            const bf16x4 ahi = pack_bf16(h[0], h[1], h[2], h[3]);
+            const uint32_t w0 = bf16_pair(x[0], x[1]), w1 = bf16_pair(x[2], x[3]);
+            const bf16x4 ahi = __builtin_bit_cast(bf16x4, u32x2{w0, w1});
             const bf16x4 bhi = __builtin_bit_cast(bf16x4, bw);
             acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[m], 0, 0, 0);
             if constexpr (PREC == kSPLIT) {
-              uint32_t l[4];
-#pragma unroll
-              for (int j = 0; j < 4; ++j) l[j] = bf16_bits(x[j] - __uint_as_float(h[j] << 16));
-              const bf16x4 alo = pack_bf16(l[0], l[1], l[2], l[3]);
+              const u32x2 lw = {bf16_pair(x[0] - __uint_as_float(w0 << 16), x[1] - __uint_as_float(w0 & 0xffff0000u)),
+                                bf16_pair(x[2] - __uint_as_float(w1 << 16), x[3] - __uint_as_float(w1 & 0xffff0000u))};
+              const bf16x4 alo = __builtin_bit_cast(bf16x4, lw);
               const u32x2 bwl = {fw[2], fw[3]};
               const bf16x4 blo = __builtin_bit_cast(bf16x4, bwl);
               acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[m], 0, 0, 0);

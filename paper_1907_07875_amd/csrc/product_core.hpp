@@ -31,18 +31,26 @@ __device__ __forceinline__ uint32_t bf16_rne(float x) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float floatx2_t __attribute__((ext_vector_type(2)));
+// Two values rounded to BF16 in one gfx950 conversion (v_cvt_pk_bf16_f32; nearest even,
+// FP32 denormals preserved: as bf16_rne for every value but NaN
+// payloads): a in the low half, b in the high half.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2_t{a, b}, bf16x2_t));
+}
+
 // Four values as a 16x16x16 BF16 MFMA operand: hi = BF16(x), lo = BF16(x - hi) (the split
 // form; lo unused with plain BF16 blocks).
 struct Frag16 {
   u32x2 hi, lo;
 };
 __device__ __forceinline__ Frag16 pack16(float a, float b, float c, float d) {
-  const uint32_t h0 = bf16_rne(a), h1 = bf16_rne(b), h2 = bf16_rne(c), h3 = bf16_rne(d);
+  const uint32_t w0 = bf16_pair(a, b), w1 = bf16_pair(c, d);
   Frag16 f;
-  f.hi = u32x2{h0 | (h1 << 16), h2 | (h3 << 16)};
-  const uint32_t l0 = bf16_rne(a - __uint_as_float(h0 << 16)), l1 = bf16_rne(b - __uint_as_float(h1 << 16));
-  const uint32_t l2 = bf16_rne(c - __uint_as_float(h2 << 16)), l3 = bf16_rne(d - __uint_as_float(h3 << 16));
-  f.lo = u32x2{l0 | (l1 << 16), l2 | (l3 << 16)};
+  f.hi = u32x2{w0, w1};
+  f.lo = u32x2{bf16_pair(a - __uint_as_float(w0 << 16), b - __uint_as_float(w0 & 0xffff0000u)),
+               bf16_pair(c - __uint_as_float(w1 << 16), d - __uint_as_float(w1 & 0xffff0000u))};
   return f;
 }
 
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(64 * kPWaves) __attribute__((amdgpu_waves_per_eu(2)
         u32x4 o;
 #pragma unroll
         for (int h = 0; h < 4; ++h)
-          o[h] = bf16_rne(T[lds_out(e + 2 * h)]) | (bf16_rne(T[lds_out(e + 2 * h + 1)]) << 16);
+          o[h] = bf16_pair(T[lds_out(e + 2 * h)], T[lds_out(e + 2 * h + 1)]);
         __builtin_nontemporal_store(o, dst + v);
       }
     } else if (IO16) {
