@@ -306,7 +306,11 @@ gft_status gft_plan_product(const gft_graph *graph_a, const gft_pairing *pairing
  * x: device, num_signals x n values of options.in_dtype (FP32 unless set), 16-byte
  * aligned.  y: device, num_signals x n values of options.out_dtype, 16-byte aligned;
  * y == x (in place) is allowed when the two types are equal, other overlaps are rejected.
- * num_signals == 0 is a no-op.  Single-graph plans only. */
+ * num_signals == 0 is a no-op.  Single-graph plans only.  The large-signal engine's
+ * three-pass and GEMM-epilogue forms (gft_plan_tuning variant 0 or 1) take a workspace from
+ * the stream-ordered pool per call and return GFT_ERR_UNSUPPORTED on a stream under capture
+ * (gft_apply_noalloc serves such callers); its one-pass form (variant 2) and every other
+ * engine allocate nothing per call. */
 gft_status gft_forward(gft_plan_t plan, const void *x, void *y, int64_t num_signals,
                        void *stream);
 

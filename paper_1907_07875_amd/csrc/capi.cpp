@@ -1071,6 +1071,15 @@ gft_status launch_image(gft_plan_t plan, DeviceImage *img, int dir, const void *
   } else if (img->large) {
     const int mode = img->lmode[dir];
     const bool pooled = ws == nullptr && mode != 2;
+    if (pooled && st != nullptr) {
+      // a stream-ordered allocation would become part of a captured graph: refuse it
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return set_error(GFT_ERR_UNSUPPORTED,
+                         "this plan's large-signal form takes a workspace per call, which is not "
+                         "allocated under stream capture; use gft_apply_noalloc (static scratch) "
+                         "or a plan whose large form is the one-pass form");
+    }
     if (pooled) {
       e = hipMallocAsync(&ws, large_ws_bytes(img->lg[dir], mode, S), st);
       if (e != hipSuccess) return set_error(GFT_ERR_OOM, "hipMallocAsync of the large-signal workspace failed");

@@ -211,3 +211,57 @@ def test_onepass_needs_no_workspace(monkeypatch):
                                    S, G._stream_ptr(None))
         assert st == 0, lib.gft_last_error()
         assert torch.equal(out, fn(plan, x))
+
+
+def test_onepass_captured_graph_replays_equal_eager(monkeypatch):
+    """hipGraph capture of the large engine: one-pass plans with FP32 and BF16 blocks
+    (forward and inverse) replay bit-equal to eager, with eager work between replays.  A
+    plan forced to the three-pass form, whose workspace comes from the stream-ordered pool
+    per call, is refused under capture (GFT_ERR_UNSUPPORTED) without disturbing the capture,
+    and the allocation-free apply records it in the same graph instead."""
+    dev = device()
+    g = wl.config5b_graph()
+    rng = wl.rng_for(5, 12)
+    one32 = _plan(g, "fp32", "onepass", monkeypatch)
+    one16 = _plan(g, "bf16", "onepass", monkeypatch)
+    three = _plan(g, "fp32", "passes", monkeypatch)
+    assert one32.tuning()["variant"] == 2 and one16.tuning()["variant"] == 2
+    assert three.tuning()["variant"] == 0
+    x = torch.from_numpy(wl.gaussian(3001, g.n, rng)).to(dev)
+    x3 = torch.from_numpy(wl.gaussian(700, g.n, rng)).to(dev)
+    y32, r32, y16, y3 = (torch.empty_like(x), torch.empty_like(x), torch.empty_like(x), torch.empty_like(x3))
+    eager = [one32.forward(x).clone(), None, one16.forward(x).clone(), three.forward(x3).clone()]
+    eager[1] = one32.inverse(eager[0]).clone()
+    lib = G.load_library()
+
+    def record(stream):
+        one32.forward(x, out=y32, stream=stream)
+        one32.inverse(y32, out=r32, stream=stream)
+        one16.forward(x, out=y16, stream=stream)
+        st = lib.gft_apply_noalloc(three.handle, 0, ctypes.c_void_p(x3.data_ptr()), ctypes.c_void_p(y3.data_ptr()),
+                                   x3.shape[0], G._stream_ptr(stream))
+        assert st == 0, lib.gft_last_error()
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        record(None)                                     # warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        with pytest.raises(G.GFTError, match="stream capture"):
+            three.forward(x3, out=y3)
+        record(None)
+    outs = (y32, r32, y16, y3)
+    for _ in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e)
+        one16.inverse(one16.forward(x))                  # eager work between replays
+        three.forward(x3)
+        torch.cuda.synchronize()
