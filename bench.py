@@ -45,7 +45,7 @@ METRIC = "GFT coeffs/sec, fast vs dense GFT on 1 GPU at stated rel. err; % HBM r
 PROFILED_TRAFFIC = {"sources": ["paper_1907_07875_amd/csrc/gft_butterfly.hip",
                                 "paper_1907_07875_amd/csrc/butterfly_core.hpp",
                                 "paper_1907_07875_amd/csrc/device_program.hpp"],
-                    "sha256_16": "5cfef7152b1b8935",
+                    "sha256_16": "fc5dea449a1a5f30",
                     "bytes_per_launch": 2.0 * 131161.1 * 1024 + 262149.2 * 1024}
 
 
