@@ -375,7 +375,7 @@ gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile)
  * 80 KB) and keeps the fastest (3% better than the built-in choice at least), unless the
  * tuning cache holds a choice for the same device kind and plan image.  The cache lives in
  * memory and in the text file named by the environment variable GFT_TUNE_CACHE (default
- * $HOME/.cache/libgft/tuning-v1.txt; empty or "off": memory only).  Needs a GPU. */
+ * $HOME/.cache/libgft/tuning-v2.txt; empty or "off": memory only).  Needs a GPU. */
 gft_status gft_plan_tuning(gft_plan_t plan, gft_tuning *out);
 
 /* Statistics of graph `index` of a plan (0 for single-graph plans). */

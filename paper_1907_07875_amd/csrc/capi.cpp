@@ -515,7 +515,13 @@ bool tune_large(gft_plan_s *plan, DeviceImage *img, std::vector<int32_t> &choice
         img->num_cus * (img->op_ok[dir] ? onepass_occupancy(img->op[dir], plan->opts.precision, in16) : 1);
     for (int m = 0; m < 3; ++m) {
       if (!large_mode_ok(img, dir, m) || (img->lforce[dir] >= 0 && m != img->lforce[dir])) continue;
-      const std::vector<int> args = m == 2 ? std::vector<int>{0, resident} : std::vector<int>{20, 40, 80};
+      // one-pass grids: the resident workgroups, and one workgroup per panel where the
+      // timed signals hold more panels than that (else the two are the same launch, and
+      // a pick between them would follow timing noise, not the full-size behaviour)
+      const int64_t panels = (S + onepass_rows(plan->opts.precision) - 1) / onepass_rows(plan->opts.precision);
+      const std::vector<int> args = m != 2 ? std::vector<int>{20, 40, 80}
+                                    : panels > resident ? std::vector<int>{0, resident}
+                                                        : std::vector<int>{resident};
       for (int a : args) {
         if (m == img->lmode[dir] && a == (m == 2 ? img->op_grid[dir] : img->ltile_kb[dir])) base = (int)cand.size();
         cand.push_back({m, a});

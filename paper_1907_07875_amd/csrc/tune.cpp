@@ -48,7 +48,7 @@ std::string cache_path() {
   if (env) return (!*env || !std::strcmp(env, "off")) ? std::string() : std::string(env);
   const char *home = std::getenv("HOME");
   if (!home || !*home) return std::string();
-  return std::string(home) + "/.cache/libgft/tuning-v1.txt";
+  return std::string(home) + "/.cache/libgft/tuning-v2.txt";
 }
 
 void make_parent_dirs(const std::string &path) {
