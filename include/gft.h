@@ -372,7 +372,9 @@ gft_status gft_plan_tiles(gft_plan_t plan, int32_t *fwd_tile, int32_t *inv_tile)
  * fits in LDS; butterfly and product: grids of 1/2, 3/4, 1 and 2 times the resident
  * workgroups; batch: 1 to 4 rounds of resident workgroups x register-phase cost 8, 11 or
  * 14 sixteenths; large: fused or three-pass output order x stage-pass tiles of 20, 40 or
- * 80 KB) and keeps the fastest (3% better than the built-in choice at least), unless the
+ * 80 KB, and the one-pass form with the resident workgroups or, where the timed batch holds
+ * more panels than that, one workgroup per panel) and keeps the fastest (3% better than
+ * the built-in choice at least), unless the
  * tuning cache holds a choice for the same device kind and plan image.  The cache lives in
  * memory and in the text file named by the environment variable GFT_TUNE_CACHE (default
  * $HOME/.cache/libgft/tuning-v2.txt; empty or "off": memory only).  Needs a GPU. */
